@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark of the SG-WLS hot path on one MI355X.
+
+Workload: one 1080x1920 RGB float32 image (synthetic: 200 random rectangles,
+a sinusoidal gradient and Gaussian noise, seed 1000), luma guidance, r = 1,
+T = 3 iterations (6 passes), stride 1, lambda = 4, omega^exp with
+sigma_s = 1, sigma_r = 0.1.  One step = one full filter call (all 2T passes,
+all channels) with the inputs resident in HBM.
+
+Prints ONE JSON line:
+  value      MPixel/s = M*N / (time of one filter call)
+  roofline   the dominant kernel's algorithmic bytes per launch / its mean
+             duration (HIP events around launches of that kernel alone), vs
+             the 8 TB/s HBM peak
+  cpu_baseline  the FP64 oracle on the host cores, same workload
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--stride", type=int, default=1)
+    return ap.parse_args()
+
+
+def time_events(torch, fn, reps):
+    """Mean milliseconds of fn() over reps calls, HIP events on the current stream."""
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(reps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / reps
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    from paper_1705_01674_amd import _native as nat
+    from paper_1705_01674_amd import ops, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = synth.rgb1080p(stride=args.stride)
+    C, M, N = w.f.shape
+    p = ops.Params(**w.params)
+    f = torch.from_numpy(w.f).to(dev)
+    g = torch.from_numpy(w.g).to(dev)
+    u = torch.empty_like(f)
+    ws = torch.empty(ops.workspace_bytes(C, M, N, p), dtype=torch.uint8, device=dev)
+
+    def step():
+        ops.sgwls_filter(f, g, p, out=u, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ms = time_events(torch, step, args.steps)
+    mpix = M * N / (ms * 1e-3) / 1e6
+
+    # Per-kernel timing: each stage of each pass direction launched alone on
+    # the current stream, between HIP events.
+    cp = p.c()
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    y = torch.empty_like(f)
+    stage_names = {1: "k_reduce", 2: "k_interface", 4: "k_expand"}
+    per_filter_ms = {}
+    stage_ms = {}
+    for direction in (0, 1):
+        def run(mask):
+            nat.check(nat.lib.sgwls_pass_stages(mask, direction, ctypes.c_void_p(f.data_ptr()),
+                                                ctypes.c_void_p(g.data_ptr()),
+                                                ctypes.c_void_p(y.data_ptr()), C, M, N,
+                                                ctypes.byref(cp), None,
+                                                ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                                stream), "sgwls_pass_stages")
+        run(7)
+        for mask, name in stage_names.items():
+            for _ in range(3):
+                run(mask)
+            t = time_events(torch, lambda: run(mask), max(10, args.steps))
+            stage_ms[(direction, name)] = t
+            per_filter_ms[name] = per_filter_ms.get(name, 0.0) + t * p.iters
+    dom = max(per_filter_ms, key=per_filter_ms.get)
+    dom_launch_ms = per_filter_ms[dom] / (2 * p.iters)   # mean over column and row launches
+    px = M * N
+    alg_bytes = {"k_expand": (8 * C + 4) * px, "k_reduce": (4 * C + 4) * px}
+    alg = alg_bytes.get(dom)
+    achieved = alg / (dom_launch_ms * 1e-3) / 1e9 if alg else None
+
+    # Accuracy of this very output against the oracle, and the CPU baseline.
+    step()
+    torch.cuda.synchronize()
+    gpu_out = u.cpu().numpy().astype(np.float64)
+    cpu = None
+    max_rel = None
+    if not args.no_cpu_baseline:
+        import oracle
+        P = oracle.OracleParams(**w.params)
+        f64, g64 = w.f.astype(np.float64), w.g.astype(np.float64)
+        times = []
+        ref = None
+        for _ in range(args.cpu_reps):
+            t0 = time.perf_counter()
+            ref = oracle.filter(f64, g64, P)
+            times.append(time.perf_counter() - t0)
+        tmed = sorted(times)[len(times) // 2]
+        cpu = {"value": round(px / tmed / 1e6, 4), "unit": "MPixel/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"the full workload (one {M}x{N}x{C} filter, T={p.iters}), "
+                         f"median of {args.cpu_reps} runs, {tmed:.2f} s each"}
+        max_rel = float(np.abs(gpu_out - ref).max() / np.abs(ref).max())
+
+    line = {
+        "metric": "MPixel/s per SG-WLS filter (1080p RGB, r=1, tau=3) fwd",
+        "value": round(mpix, 2),
+        "unit": "MPixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "M": M, "N": N, "C": C, "r": p.r, "iters": p.iters,
+                   "stride": p.stride, "lambda": p.lam, "weight": p.kind,
+                   "sigma_s": float(p.r), "sigma_r": p.sigma_r},
+        "roofline": {"bound": "hbm", "kernel": dom,
+                     "achieved": round(achieved, 1) if achieved else None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                     "traffic": None},
+        "kernels_ms_per_launch": {f"{'col' if d == 0 else 'row'}:{n}": round(t, 5)
+                                  for (d, n), t in stage_ms.items()},
+        "filter_alg_GBps": round((8 * C + 4) * px * 2 * p.iters / (ms * 1e-3) / 1e9, 1),
+        "max_rel_err_vs_oracle": max_rel,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

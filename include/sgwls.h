@@ -1,0 +1,187 @@
+/*
+ * sgwls.h -- C ABI of the MI355X (gfx950) SG-WLS filtering library.
+ *
+ * Semi-Global Weighted Least Squares (SG-WLS): W. Liu, X. Chen, C. Shen,
+ * Z. Liu, J. Yang, "Semi-Global Weighted Least Squares in Image Filtering",
+ * ICCV 2017, arXiv 1705.01674.
+ *
+ * The filter approximates the weighted-least-squares smoothing of Eq. (1),
+ * min_U sum (U-F)^2 + lambda sum w_ij (U_i-U_j)^2 with guidance weights of
+ * Eq. (2), by many one-dimensional WLS subsystems (Sec. 2.1-2.3):
+ *   - for every strip of 2r+1 columns centred at k = r, r+tau, ... (and the
+ *     last centre N-1-r), the strip's rows are concatenated head to end with
+ *     every second row reversed (Sec. 2.1), giving a vector of s = (2r+1)M
+ *     pixels;
+ *   - its subsystem A_s u = f (Eq. 5), A_s = I + lambda*L over pairs at most r
+ *     apart on the vector, weights of Eq. (2) with |i-j| the distance along
+ *     the vector, is solved exactly (Sec. 2.2; the library uses an exact
+ *     partitioned banded LDL^T, not the paper's r-band LU);
+ *   - solutions are scattered back and pixels covered by several strips are
+ *     averaged with equal weights (Sec. 2.3);
+ *   - a column pass and then a row pass (the same on the transposed image)
+ *     make one iteration; T iterations are run (Sec. 2.3).
+ *
+ * Conventions for every entry point:
+ *   - images are planar C x M x N float32, contiguous, row-major (CHW); a
+ *     batch of such images is N C H W.  The guidance g is one M x N float32
+ *     plane shared by all C channels.
+ *   - every image, workspace and gradient pointer is a DEVICE pointer owned
+ *     by the caller.  Parameter structs and image tables are HOST memory.
+ *     The library allocates no device memory in any entry point.
+ *   - `stream` is a hipStream_t passed as an opaque pointer (NULL = the
+ *     default stream).  Work is enqueued asynchronously on it; results are
+ *     ready when the stream is synchronised.
+ *   - all arguments are validated on the host before anything is enqueued;
+ *     on any error nothing is enqueued and outputs are untouched.  HIP launch
+ *     errors are reported as SGWLS_E_HIP.  No entry point aborts or exits.
+ *   - NaN or Inf in f propagate to the outputs of the strips that read them;
+ *     NaN or Inf in g make the affected weights NaN (not trapped).
+ */
+#ifndef SGWLS_H
+#define SGWLS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SGWLS_OK = 0,
+  SGWLS_E_ARG = 1,          /* a parameter is out of range, or a required pointer is NULL */
+  SGWLS_E_SHAPE = 2,        /* C < 1, or M or N smaller than 2r+1, or too large */
+  SGWLS_E_WORKSPACE = 3,    /* the workspace is NULL or smaller than required */
+  SGWLS_E_UNSUPPORTED = 4,  /* a valid request this build does not implement (e.g. r > 4) */
+  SGWLS_E_HIP = 5           /* a HIP runtime call or kernel launch failed */
+} sgwls_status;
+
+/* Guidance weight of Eq. (2). */
+typedef enum {
+  SGWLS_W_EXP = 0,   /* exp(-d^2/(2 sigma_s^2)) * exp(-(G_i-G_j)^2/(2 sigma_r^2)) */
+  SGWLS_W_FRAC = 1   /* 1/(d^alpha_s + eps) * 1/(|G_i-G_j|^alpha_r + eps) */
+} sgwls_weight;
+
+/* Arithmetic of the elimination (not in the paper).  FP32: all arithmetic in
+ * float32.  FP64_PIVOT: weights are computed in float32, but the diagonal
+ * sums, the pivots, the elimination and the running recurrences are carried
+ * in float64 (for large lambda*w, where float32 pivots lose digits to
+ * cancellation).  Loads and stores stay float32 in both modes. */
+typedef enum {
+  SGWLS_P_FP32 = 0,
+  SGWLS_P_FP64_PIVOT = 1
+} sgwls_precision;
+
+/* Filter parameters.  lambda: Eq. (1).  r: the neighbourhood is
+ * (2r+1)x(2r+1) (Eq. 1), 1 <= r <= 4 in this build.  iters: T >= 1 column+row
+ * iterations (Sec. 2.3).  stride: the sliding step tau between strip centres
+ * (Sec. 2.3), 1 <= stride <= 2r+1.  sigma_s, sigma_r > 0 for SGWLS_W_EXP;
+ * alpha_s, alpha_r >= 0 and eps > 0 for SGWLS_W_FRAC (the paper uses
+ * eps = 1e-4, Sec. 1). */
+typedef struct {
+  float lambda;
+  int r;
+  int iters;
+  int stride;
+  sgwls_weight kind;
+  float sigma_s, sigma_r;
+  float alpha_s, alpha_r;
+  float eps;
+  sgwls_precision prec;
+} sgwls_params;
+
+/* Human-readable name of a status code (static storage; never NULL). */
+const char* sgwls_status_str(sgwls_status s);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int sgwls_version(void);
+
+/* Host-only validation of a (C, M, N, params) request, exactly as the
+ * filter entry points perform it.  Makes no HIP call, so it can be used
+ * without a GPU. */
+sgwls_status sgwls_validate(int C, int M, int N, const sgwls_params* p);
+
+/* Device workspace bytes needed by sgwls_filter / sgwls_pass /
+ * sgwls_backward for one C x M x N image with parameters p; 0 if the
+ * request is invalid.  save_for_backward is accepted for symmetry and does
+ * not change the size (the saved pass inputs live in the caller's `saved`
+ * buffer).  Makes no HIP call. */
+size_t sgwls_workspace_bytes(int C, int M, int N, const sgwls_params* p);
+
+/* One pass of Sec. 2.3 (steps 1-4) on a C x M x N image: direction 0 is
+ * the column direction (strips of 2r+1 columns, Sec. 2.1), 1 the row
+ * direction (the column pass of the transposed image).  x: input, y: output
+ * (must not alias x or g).  lambda_dev: optional device float that, when
+ * non-NULL, overrides p->lambda (read by the kernels, no host sync). */
+sgwls_status sgwls_pass(int direction, const float* x, const float* g, float* y,
+                        int C, int M, int N, const sgwls_params* p,
+                        const float* lambda_dev, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* The kernels of one pass, for timing them one at a time.  A pass runs
+ * three stages in order: 1 = reduce (every chunk of every subsystem is
+ * eliminated and contributes to the Schur complement on the chunk
+ * separators), 2 = interface (the separator system of every subsystem is
+ * solved), 4 = expand (every chunk is solved with its separators known, and
+ * the pixels covered by several subsystems are averaged into y).  `stages`
+ * is a bit mask (1..7); stage 2 reads what stage 1 left in ws and stage 4
+ * what stage 2 left there, so calling masks 1, 2 and 4 in order on the same
+ * ws and stream computes exactly sgwls_pass.  Other arguments as sgwls_pass. */
+sgwls_status sgwls_pass_stages(int stages, int direction, const float* x, const float* g,
+                               float* y, int C, int M, int N, const sgwls_params* p,
+                               const float* lambda_dev, void* ws, size_t ws_bytes,
+                               void* stream);
+
+/* The SG-WLS filter of Sec. 2.3: T iterations of (column pass, row pass).
+ * f: input C x M x N; g: guidance M x N; u: output C x M x N, may alias f
+ * (must not alias g).  lambda_dev: optional device override of p->lambda.
+ * saved: NULL, or a device buffer of 2T*C*M*N floats that receives the
+ * input of every pass in order (pass 2t = column pass of iteration t, 2t+1
+ * its row pass) for sgwls_backward.  ws: workspace of
+ * sgwls_workspace_bytes(C, M, N, p) bytes. */
+sgwls_status sgwls_filter(const float* f, const float* g, float* u,
+                          int C, int M, int N, const sgwls_params* p,
+                          const float* lambda_dev, float* saved,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of sgwls_filter (not in the paper): for a scalar loss with
+ * gradient grad_u (C x M x N) with respect to the filter output, writes
+ * grad_f (C x M x N), and, when non-NULL, grad_g (M x N) and grad_lambda
+ * (one device double).  saved: the 2T pass inputs written by sgwls_filter
+ * with the same g and parameters.  Per pass, in reverse order, the adjoint
+ * of the exact solve is the same SPD solve applied to the scattered
+ * gradient; the weight terms -(ubar_p - ubar_q)(u_p - u_q) give the guidance
+ * and lambda gradients with the weights recomputed from g.  ws: workspace of
+ * sgwls_workspace_bytes(C, M, N, p) bytes plus 2*C*M*N floats plus
+ * sgwls_backward_extra_bytes(C, M, N, p). */
+sgwls_status sgwls_backward(const float* g, const float* saved, const float* grad_u,
+                            float* grad_f, float* grad_g, double* grad_lambda,
+                            int C, int M, int N, const sgwls_params* p,
+                            const float* lambda_dev, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* Workspace bytes for sgwls_backward (0 if the request is invalid). */
+size_t sgwls_backward_workspace_bytes(int C, int M, int N, const sgwls_params* p);
+
+/* One image of a batch: device pointers and its shape. */
+typedef struct {
+  const float* f;
+  const float* g;
+  float* u;
+  int C, M, N;
+} sgwls_image;
+
+/* Workspace bytes for sgwls_filter_batched over B images (0 if invalid). */
+size_t sgwls_batched_workspace_bytes(const sgwls_image* imgs, const sgwls_params* p, int B);
+
+/* Batched SG-WLS over B images of uneven sizes with per-image parameters
+ * p[b] (imgs and p are host arrays of B entries; every p[b].iters must be
+ * equal).  All images are processed together by one launch per step of a
+ * pass.  u may alias f per image. */
+sgwls_status sgwls_filter_batched(const sgwls_image* imgs, const sgwls_params* p, int B,
+                                  void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGWLS_H */

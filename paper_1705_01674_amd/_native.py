@@ -1,0 +1,77 @@
+"""ctypes binding of the C ABI in ``include/sgwls.h`` (argument marshalling only).
+
+Loads the in-tree ``libsgwls.so``.  There is no fallback: if the library is
+missing or fails to load, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsgwls.so")
+
+STATUS = {0: "SGWLS_OK", 1: "SGWLS_E_ARG", 2: "SGWLS_E_SHAPE", 3: "SGWLS_E_WORKSPACE",
+          4: "SGWLS_E_UNSUPPORTED", 5: "SGWLS_E_HIP"}
+
+# Every symbol include/sgwls.h declares.
+EXPORTS = ["sgwls_status_str", "sgwls_version", "sgwls_validate", "sgwls_workspace_bytes",
+           "sgwls_pass", "sgwls_pass_stages", "sgwls_filter", "sgwls_backward", "sgwls_backward_workspace_bytes",
+           "sgwls_batched_workspace_bytes", "sgwls_filter_batched"]
+
+
+class SgwlsParams(ctypes.Structure):
+    _fields_ = [("lam", ctypes.c_float), ("r", ctypes.c_int), ("iters", ctypes.c_int),
+                ("stride", ctypes.c_int), ("kind", ctypes.c_int),
+                ("sigma_s", ctypes.c_float), ("sigma_r", ctypes.c_float),
+                ("alpha_s", ctypes.c_float), ("alpha_r", ctypes.c_float),
+                ("eps", ctypes.c_float), ("prec", ctypes.c_int)]
+
+
+class SgwlsImage(ctypes.Structure):
+    _fields_ = [("f", ctypes.c_void_p), ("g", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("C", ctypes.c_int), ("M", ctypes.c_int), ("N", ctypes.c_int)]
+
+
+class SgwlsError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {STATUS.get(code, code)}")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"SG-WLS HIP library not built: {LIB_PATH} is missing "
+                          "(run paper_1705_01674_amd/build.py or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, sz, i, P = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(SgwlsParams)
+    lib.sgwls_status_str.restype = ctypes.c_char_p
+    lib.sgwls_status_str.argtypes = [i]
+    lib.sgwls_version.restype = i
+    lib.sgwls_validate.restype = i
+    lib.sgwls_validate.argtypes = [i, i, i, P]
+    lib.sgwls_workspace_bytes.restype = sz
+    lib.sgwls_workspace_bytes.argtypes = [i, i, i, P]
+    lib.sgwls_pass.restype = i
+    lib.sgwls_pass.argtypes = [i, vp, vp, vp, i, i, i, P, vp, vp, sz, vp]
+    lib.sgwls_pass_stages.restype = i
+    lib.sgwls_pass_stages.argtypes = [i, i, vp, vp, vp, i, i, i, P, vp, vp, sz, vp]
+    lib.sgwls_filter.restype = i
+    lib.sgwls_filter.argtypes = [vp, vp, vp, i, i, i, P, vp, vp, vp, sz, vp]
+    lib.sgwls_backward.restype = i
+    lib.sgwls_backward.argtypes = [vp, vp, vp, vp, vp, vp, i, i, i, P, vp, vp, sz, vp]
+    lib.sgwls_backward_workspace_bytes.restype = sz
+    lib.sgwls_backward_workspace_bytes.argtypes = [i, i, i, P]
+    lib.sgwls_batched_workspace_bytes.restype = sz
+    lib.sgwls_batched_workspace_bytes.argtypes = [ctypes.POINTER(SgwlsImage), P, i]
+    lib.sgwls_filter_batched.restype = i
+    lib.sgwls_filter_batched.argtypes = [ctypes.POINTER(SgwlsImage), P, i, vp, sz, vp]
+    return lib
+
+
+lib = _load()
+
+
+def check(code: int, what: str) -> None:
+    if code != 0:
+        raise SgwlsError(code, what)

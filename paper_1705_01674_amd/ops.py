@@ -1,0 +1,159 @@
+"""PyTorch-facing calls of the SG-WLS library.
+
+Torch supplies device memory and the current HIP stream; every step of the
+filter runs in the HIP kernels behind the C ABI (``include/sgwls.h``).  The
+names follow the paper (Liu et al., ICCV 2017): ``lam`` is lambda of Eq. (1),
+``r`` the neighbourhood radius, ``iters`` the iteration count T and ``stride``
+the sliding step tau of Sec. 2.3; ``kind`` selects omega^exp or omega^frac of
+Eq. (2).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, replace
+from typing import Optional
+
+import torch
+
+from . import _native as nat
+
+_KIND = {"exp": 0, "frac": 1}
+_PREC = {"fp32": 0, "fp64_pivot": 1}
+
+
+@dataclass(frozen=True)
+class Params:
+    lam: float = 1.0
+    r: int = 1
+    iters: int = 1
+    stride: int = 1
+    kind: str = "exp"
+    sigma_s: Optional[float] = None     # default: r (the paper's setting, Sec. 3)
+    sigma_r: float = 0.1
+    alpha_s: float = 1.2
+    alpha_r: float = 1.2
+    eps: float = 1e-4
+    prec: str = "fp32"
+
+    def c(self) -> nat.SgwlsParams:
+        if self.kind not in _KIND:
+            raise ValueError(f"kind must be one of {list(_KIND)}")
+        if self.prec not in _PREC:
+            raise ValueError(f"prec must be one of {list(_PREC)}")
+        ss = float(self.r) if self.sigma_s is None else float(self.sigma_s)
+        return nat.SgwlsParams(float(self.lam), int(self.r), int(self.iters), int(self.stride),
+                               _KIND[self.kind], ss, float(self.sigma_r), float(self.alpha_s),
+                               float(self.alpha_r), float(self.eps), _PREC[self.prec])
+
+    def with_(self, **kw) -> "Params":
+        return replace(self, **kw)
+
+
+def params(**kw) -> Params:
+    """Params from keyword arguments; unknown keys raise."""
+    return Params(**kw)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(dev: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _image(x: torch.Tensor, name: str):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if x.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if x.dim() == 2:
+        return 1, x.shape[0], x.shape[1]
+    if x.dim() == 3:
+        return x.shape[0], x.shape[1], x.shape[2]
+    raise ValueError(f"{name} must be (M, N) or (C, M, N)")
+
+
+def _guidance(g: torch.Tensor, M: int, N: int, dev: torch.device):
+    _image(g, "g")
+    if g.dim() != 2 or g.shape != (M, N):
+        raise ValueError(f"g must be ({M}, {N})")
+    if g.device != dev:
+        raise ValueError("g must be on the same device as f")
+
+
+def _lambda(lambda_dev: Optional[torch.Tensor], dev):
+    if lambda_dev is None:
+        return None
+    if not lambda_dev.is_cuda or lambda_dev.dtype != torch.float32 or lambda_dev.numel() != 1:
+        raise TypeError("lambda_dev must be a one-element float32 CUDA tensor")
+    if lambda_dev.device != dev:
+        raise ValueError("lambda_dev must be on the device of f")
+    return lambda_dev
+
+
+def workspace_bytes(C: int, M: int, N: int, p: Params) -> int:
+    n = nat.lib.sgwls_workspace_bytes(C, M, N, ctypes.byref(p.c()))
+    if n == 0:
+        nat.check(nat.lib.sgwls_validate(C, M, N, ctypes.byref(p.c())), "sgwls_workspace_bytes")
+    return int(n)
+
+
+def validate(C: int, M: int, N: int, p: Params) -> int:
+    return int(nat.lib.sgwls_validate(C, M, N, ctypes.byref(p.c())))
+
+
+def _workspace(nbytes: int, dev) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=dev)
+
+
+def sgwls_filter(f: torch.Tensor, g: torch.Tensor, p: Params, *,
+                 lambda_dev: Optional[torch.Tensor] = None,
+                 saved: Optional[torch.Tensor] = None,
+                 out: Optional[torch.Tensor] = None,
+                 workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """SG-WLS filter of f (C x M x N or M x N) guided by g (M x N), Sec. 2.3.
+
+    ``saved`` (optional, 2T x C x M x N float32) receives every pass input for
+    the backward call.  ``out`` may be f itself (in-place filtering)."""
+    C, M, N = _image(f, "f")
+    dev = f.device
+    _guidance(g, M, N, dev)
+    lam = _lambda(lambda_dev, dev)
+    if out is None:
+        out = torch.empty_like(f)
+    elif out.shape != f.shape or out.dtype != f.dtype or not out.is_contiguous() or out.device != dev:
+        raise ValueError("out must match f")
+    if saved is not None:
+        if (saved.dtype != torch.float32 or not saved.is_contiguous() or saved.device != dev
+                or saved.numel() != 2 * p.iters * C * M * N):
+            raise ValueError("saved must be a contiguous float32 tensor of 2T*C*M*N elements")
+    nbytes = workspace_bytes(C, M, N, p)
+    ws = workspace if workspace is not None else _workspace(nbytes, dev)
+    if ws.numel() < nbytes or ws.device != dev:
+        raise ValueError("workspace too small")
+    cp = p.c()
+    nat.check(nat.lib.sgwls_filter(_ptr(f), _ptr(g), _ptr(out), C, M, N, ctypes.byref(cp),
+                                   _ptr(lam), _ptr(saved), _ptr(ws), ws.numel(), _stream(dev)),
+              "sgwls_filter")
+    return out
+
+
+def sgwls_pass(direction: int, x: torch.Tensor, g: torch.Tensor, p: Params, *,
+               lambda_dev: Optional[torch.Tensor] = None,
+               out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """One pass of Sec. 2.3: direction 0 = column direction, 1 = row direction."""
+    C, M, N = _image(x, "x")
+    dev = x.device
+    _guidance(g, M, N, dev)
+    lam = _lambda(lambda_dev, dev)
+    out = torch.empty_like(x) if out is None else out
+    nbytes = workspace_bytes(C, M, N, p)
+    ws = _workspace(nbytes, dev)
+    cp = p.c()
+    nat.check(nat.lib.sgwls_pass(int(direction), _ptr(x), _ptr(g), _ptr(out), C, M, N,
+                                 ctypes.byref(cp), _ptr(lam), _ptr(ws), ws.numel(), _stream(dev)),
+              "sgwls_pass")
+    return out

@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol the header declares, and validates arguments before enqueueing
+anything (so error paths return codes without touching HIP)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def nat():
+    from paper_1705_01674_amd import _native
+    return _native
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "sgwls.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sgwls_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol(nat):
+    syms = header_symbols()
+    assert syms, "no declarations found"
+    assert set(syms) == set(nat.EXPORTS)
+    for s in syms:
+        assert hasattr(nat.lib, s), s
+
+
+def test_status_strings(nat):
+    for code in range(6):
+        assert nat.lib.sgwls_status_str(code)
+    assert nat.lib.sgwls_status_str(99) == b"unknown status"
+    assert nat.lib.sgwls_version() >= 100
+
+
+def P(nat, **kw):
+    d = dict(lam=4.0, r=1, iters=3, stride=1, kind=0, sigma_s=1.0, sigma_r=0.1, alpha_s=1.2,
+             alpha_r=1.2, eps=1e-4, prec=0)
+    d.update(kw)
+    return nat.SgwlsParams(*[d[k] for k, _ in nat.SgwlsParams._fields_])
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(), 0), (dict(r=0), 1), (dict(iters=0), 1), (dict(stride=0), 1), (dict(stride=4), 1),
+    (dict(r=2, stride=5), 0), (dict(lam=-1.0), 1), (dict(lam=float("nan")), 1),
+    (dict(lam=float("inf")), 1), (dict(sigma_s=0.0), 1), (dict(sigma_r=-1.0), 1),
+    (dict(kind=1, eps=0.0), 1), (dict(kind=1, alpha_r=-0.5), 1), (dict(kind=1, sigma_r=0.0), 0),
+    (dict(kind=2), 1), (dict(prec=2), 1), (dict(prec=1), 0), (dict(r=5), 4), (dict(r=4), 0),
+])
+def test_validate_parameters(nat, kw, code):
+    assert nat.lib.sgwls_validate(3, 64, 64, ctypes.byref(P(nat, **kw))) == code
+
+
+@pytest.mark.parametrize("C,M,N,code", [(0, 64, 64, 2), (3, 2, 64, 2), (3, 64, 2, 2), (1, 3, 3, 0),
+                                        (1, 70000, 8, 2), (5, 9, 11, 0)])
+def test_validate_shapes(nat, C, M, N, code):
+    assert nat.lib.sgwls_validate(C, M, N, ctypes.byref(P(nat))) == code
+
+
+def test_validate_null_params(nat):
+    assert nat.lib.sgwls_validate(1, 8, 8, None) == 1
+
+
+def test_workspace_bytes(nat):
+    p = P(nat)
+    n = nat.lib.sgwls_workspace_bytes(3, 1080, 1920, ctypes.byref(p))
+    assert n >= 4 * 3 * 1080 * 1920
+    assert nat.lib.sgwls_workspace_bytes(3, 2, 2, ctypes.byref(p)) == 0
+    assert nat.lib.sgwls_workspace_bytes(3, 64, 64, None) == 0
+
+
+def test_filter_error_paths_return_before_any_launch(nat):
+    p = ctypes.byref(P(nat))
+    f, g, u, ws = (ctypes.c_void_p(a) for a in (0x1000, 0x2000, 0x3000, 0x4000))
+    big = 1 << 30
+    lib = nat.lib
+    # invalid parameters / shapes / pointers / workspace: nothing is enqueued
+    assert lib.sgwls_filter(f, g, u, 3, 2, 64, p, None, None, ws, big, None) == 2
+    assert lib.sgwls_filter(None, g, u, 3, 64, 64, p, None, None, ws, big, None) == 1
+    assert lib.sgwls_filter(f, None, u, 3, 64, 64, p, None, None, ws, big, None) == 1
+    assert lib.sgwls_filter(f, g, None, 3, 64, 64, p, None, None, ws, big, None) == 1
+    assert lib.sgwls_filter(f, g, u, 3, 64, 64, p, None, None, None, big, None) == 3
+    assert lib.sgwls_filter(f, g, u, 3, 64, 64, p, None, None, ws, 16, None) == 3
+    assert lib.sgwls_filter(f, g, g, 3, 64, 64, p, None, None, ws, big, None) == 1   # u aliases g
+    assert lib.sgwls_filter(f, g, u, 3, 64, 64, None, None, None, ws, big, None) == 1
+    assert lib.sgwls_pass(2, f, g, u, 3, 64, 64, p, None, ws, big, None) == 1       # direction
+    assert lib.sgwls_pass(0, f, g, f, 3, 64, 64, p, None, ws, big, None) == 1       # y aliases x
+    assert lib.sgwls_pass(0, f, g, u, 3, 64, 64, p, None, ws, 16, None) == 3

@@ -1,0 +1,168 @@
+"""GPU parity: the HIP library against the FP64 CPU oracle, element by element.
+
+Error measure: normwise relative, max|gpu - oracle| / max|oracle| per output
+(the mean is printed beside it).  Bar: 1e-5 for float32 arithmetic.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_1705_01674_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ops():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1705_01674_amd import ops as _ops
+    return _ops
+
+
+def rel_err(gpu, ref):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    scale = np.abs(ref).max()
+    d = np.abs(gpu - ref)
+    return d.max() / scale, d.mean() / scale
+
+
+def run_filter(ops, f, g, pd, prec="fp32", **kw):
+    p = ops.Params(**pd, prec=prec)
+    ft = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+    gt = torch.from_numpy(np.ascontiguousarray(g)).cuda()
+    u = ops.sgwls_filter(ft, gt, p, **kw)
+    torch.cuda.synchronize()
+    return u.cpu().numpy()
+
+
+def oracle_filter(f, g, pd):
+    return oracle.filter(f.astype(np.float64), g.astype(np.float64), oracle.OracleParams(**pd))
+
+
+def pdict(lam=1.0, r=1, iters=1, stride=1, kind="exp", sigma_r=0.1, alpha=1.2):
+    return dict(lam=lam, r=r, iters=iters, stride=stride, kind=kind, sigma_s=float(r),
+                sigma_r=sigma_r, alpha_s=alpha, alpha_r=alpha, eps=1e-4)
+
+
+def check(name, gpu, ref, tol=TOL):
+    mx, mean = rel_err(gpu, ref)
+    print(f"[parity] {name}: max {mx:.3e} mean {mean:.3e}", flush=True)
+    assert mx <= tol, f"{name}: {mx:.3e} > {tol:.1e}"
+
+
+def test_grey256_r1_T1(ops):
+    w = synth.grey256()
+    check("grey256 r1 T1", run_filter(ops, w.f, w.g, w.params), oracle_filter(w.f, w.g, w.params))
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("r,stride", [(1, 1), (1, 3), (2, 1), (2, 4), (3, 1), (3, 7), (4, 1), (4, 5)])
+@pytest.mark.parametrize("C", [1, 3])
+def test_single_pass_small(ops, direction, r, stride, C):
+    # several chunks and a ragged last chunk in both directions
+    rng = np.random.default_rng(100 * r + 10 * stride + C + direction)
+    M, N = 37 + 2 * r, 53 + 3 * r
+    f = rng.uniform(0, 1, (C, M, N)).astype(np.float32)
+    g = rng.uniform(0, 1, (M, N)).astype(np.float32)
+    pd = pdict(lam=5.0, r=r, stride=stride, sigma_r=0.2)
+    p = ops.Params(**pd)
+    out = ops.sgwls_pass(direction, torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda(), p)
+    torch.cuda.synchronize()
+    fn = oracle.col_pass if direction == 0 else oracle.row_pass
+    ref = fn(f.astype(np.float64), g.astype(np.float64), oracle.OracleParams(**pd))[0]
+    check(f"pass dir{direction} r{r} s{stride} C{C}", out.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("shape", [(3, 3), (3, 4), (4, 3), (5, 200), (200, 5), (7, 7), (2, 9, 9),
+                                   (4, 33, 65), (5, 31, 17), (1, 130, 3)])
+@pytest.mark.parametrize("r", [1, 2])
+def test_edge_shapes(ops, shape, r):
+    if len(shape) == 2:
+        C, (M, N) = 1, shape
+    else:
+        C, M, N = shape
+    if min(M, N) < 2 * r + 1:
+        pytest.skip("smaller than one window")
+    rng = np.random.default_rng(M * 1000 + N + C + r)
+    f = rng.uniform(0, 1, (C, M, N)).astype(np.float32)
+    g = rng.uniform(0, 1, (M, N)).astype(np.float32)
+    pd = pdict(lam=3.0, r=r, iters=2, sigma_r=0.2)
+    check(f"shape {shape} r{r}", run_filter(ops, f, g, pd), oracle_filter(f, g, pd))
+
+
+@pytest.mark.parametrize("kind,lam", [("exp", 0.5), ("exp", 30.0), ("frac", 1.0), ("frac", 5.0)])
+@pytest.mark.parametrize("prec", ["fp32", "fp64_pivot"])
+def test_kinds_and_precisions(ops, kind, lam, prec):
+    rng = np.random.default_rng(7)
+    f = synth.image(96, 80, 3, 30, 0.05, seed=11)
+    g = synth.luma(f)
+    pd = pdict(lam=lam, r=2, iters=2, kind=kind, sigma_r=0.1, alpha=1.2)
+    check(f"{kind} lam{lam} {prec}", run_filter(ops, f, g, pd, prec=prec), oracle_filter(f, g, pd))
+    del rng
+
+
+def test_rgb768x1024_r1_T3(ops):
+    w = synth.rgb768x1024()
+    check("rgb768x1024 r1 T3", run_filter(ops, w.f, w.g, w.params), oracle_filter(w.f, w.g, w.params))
+
+
+def test_rgb1080p_r1_T3_bench_config(ops):
+    # the configuration bench.py times (1080p RGB, r=1, T=3, lambda=4, stride 1)
+    w = synth.rgb1080p()
+    check("rgb1080p r1 T3", run_filter(ops, w.f, w.g, w.params), oracle_filter(w.f, w.g, w.params))
+
+
+@pytest.mark.parametrize("r", [2, 3])
+@pytest.mark.parametrize("lam", [1.0, 16.0, 64.0])
+def test_rgb1080p_large_radius_fp64_pivot(ops, r, lam):
+    w = synth.rgb1080p(r=r, lam=lam, seed=1002)
+    ref = oracle_filter(w.f, w.g, w.params)
+    check(f"rgb1080p r{r} lam{lam} fp64_pivot", run_filter(ops, w.f, w.g, w.params, "fp64_pivot"), ref)
+    mx, mean = rel_err(run_filter(ops, w.f, w.g, w.params, "fp32"), ref)
+    print(f"[parity] rgb1080p r{r} lam{lam} fp32: max {mx:.3e} mean {mean:.3e}", flush=True)
+    assert mx <= 1e-4
+
+
+def test_invariants_on_gpu(ops):
+    rng = np.random.default_rng(3)
+    M, N = 70, 90
+    g = rng.uniform(0, 1, (M, N)).astype(np.float32)
+    const = np.full((3, M, N), 0.625, dtype=np.float32)
+    u = run_filter(ops, const, g, pdict(lam=20.0, r=2, iters=2))
+    assert np.abs(u - 0.625).max() <= 1e-6
+    f = rng.uniform(0, 1, (2, M, N)).astype(np.float32)
+    u0 = run_filter(ops, f, g, pdict(lam=0.0, r=1, iters=2))
+    assert np.abs(u0 - f).max() <= 1e-7
+
+
+def test_deterministic_and_in_place(ops):
+    w = synth.single("t", 200, 300, 3, 40, 0.05, 5, 4.0, 1, 2)
+    a = run_filter(ops, w.f, w.g, w.params)
+    b = run_filter(ops, w.f, w.g, w.params)
+    assert np.array_equal(a, b)
+    ft = torch.from_numpy(w.f.copy()).cuda()
+    gt = torch.from_numpy(w.g).cuda()
+    p = ops.Params(**w.params)
+    ops.sgwls_filter(ft, gt, p, out=ft)
+    torch.cuda.synchronize()
+    assert np.array_equal(ft.cpu().numpy(), a)
+
+
+def test_lambda_on_device_and_saved_inputs(ops):
+    w = synth.single("t", 64, 96, 3, 20, 0.05, 9, 6.0, 1, 2)
+    p = ops.Params(**{**w.params, "lam": 123.0})        # overridden by lambda_dev
+    ft = torch.from_numpy(w.f).cuda()
+    gt = torch.from_numpy(w.g).cuda()
+    lam = torch.tensor([6.0], device="cuda")
+    saved = torch.empty(2 * p.iters * w.f.size, device="cuda")
+    u = ops.sgwls_filter(ft, gt, p, lambda_dev=lam, saved=saved)
+    torch.cuda.synchronize()
+    ref, ref_saved = oracle.filter(w.f.astype(np.float64), w.g.astype(np.float64),
+                                   oracle.OracleParams(**w.params), save=True)
+    check("lambda_dev", u.cpu().numpy(), ref)
+    check("saved pass inputs", saved.cpu().numpy().reshape(ref_saved.shape), ref_saved)
