@@ -37,7 +37,10 @@ WeightParams weight_params(const sgwls_params& p) {
     }
     wp.spatial[d] = (float)s;
   }
-  wp.range_c = p.kind == SGWLS_W_EXP ? (float)(1.0 / (2.0 * (double)p.sigma_r * p.sigma_r)) : 0.0f;
+  // exp range factor as a power of two: exp(-x) = 2^(-x log2(e))
+  wp.range_c2 = p.kind == SGWLS_W_EXP
+                    ? (float)(1.4426950408889634 / (2.0 * (double)p.sigma_r * p.sigma_r))
+                    : 0.0f;
   wp.alpha_r = p.alpha_r;
   wp.eps = p.eps;
   return wp;

@@ -9,13 +9,13 @@
 namespace sgwls {
 
 constexpr int kMaxR = 4;     // largest neighbourhood radius compiled in
-constexpr int kWave = 64;    // CDNA wavefront width; every kernel uses one-wave blocks
+constexpr int kWave = 64;    // CDNA wavefront width
 
 // Guidance-weight constants of Eq. (2), prepared on the host.
 struct WeightParams {
   int kind;                    // 0: omega^exp, 1: omega^frac
   float spatial[kMaxR + 1];    // spatial factor S(d) for d = 1..r (index d)
-  float range_c;               // exp: log2(e) / (2 sigma_r^2)
+  float range_c2;              // exp: log2(e) / (2 sigma_r^2), so R = 2^(-dG^2 * range_c2)
   float alpha_r;               // frac: exponent of |G_i - G_j|
   float eps;                   // frac: epsilon
 };
@@ -36,19 +36,21 @@ struct PassGeom {
   int P;            // chunks per subsystem = ceil(L / R)
 };
 
-// Launch configuration chosen for one (r, channel block, precision) case.
+// Launch configuration of one (r, channel block, precision, stride) case.
 struct PassPlan {
   int R;            // rows per chunk
+  int Q;            // chunks per reduce / expand block (one wave each)
   int P;            // chunks per subsystem
   int nK;           // strip centres
   int OW;           // output columns owned by one expand block
-  int accw;         // LDS accumulator width (columns) of one expand block
-  size_t sum_elems, g_elems, u_elems;   // interface buffer sizes (elements)
+  int TB;           // LDS tile width (columns across the pass)
+  int pitch;        // LDS row pitch (odd)
+  int iface_m;      // separators per lane of the wave interface solver (0: serial solver)
+  size_t sum_elems, u_elems;   // interface buffer sizes (elements)
   int acc_bytes;    // 4 (float) or 8 (double) interface element size
 };
 
 // Host-side helpers (sgwls_kernels.hip).
-int rows_per_chunk(int r, int cb, int fp64);
 int strip_count(int W, int r, int stride);
 PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64);
 size_t interface_bytes(const PassPlan& pl);

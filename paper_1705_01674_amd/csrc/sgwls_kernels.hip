@@ -12,44 +12,58 @@
 // serial sweep per subsystem would leave the GPU idle (a 1080p column pass has
 // 1918 subsystems of 3240 elements), so every subsystem is cut into chunks of
 // R rows (R(2r+1) elements) and solved exactly by a partitioned (Schur
-// complement) method:
+// complement) method in three kernels:
 //
-//   k_reduce    one lane per (strip, chunk): the last r elements of every
-//               chunk but the last are a separator block S_j.  The lane
-//               eliminates its chunk's interior I_j (banded LDL^T, right-looking
-//               (r+1)x(r+1) window) while carrying the previous separator
-//               S_{j-1} as a border; the result is the chunk's contribution to
-//               the Schur complement on the separators: the blocks
-//               A_{SS} - A_{S I} A_I^{-1} A_{I S} and the matching RHS terms.
-//   k_interface one lane per strip: block-tridiagonal (r x r blocks) Cholesky
-//               solve of the separator system, one block per chunk boundary.
-//   k_expand    one wave per (64 strips, chunk): each lane re-solves its
-//               chunk interior with both separators known (they move to the
-//               right-hand side), back-substitutes, and the wave averages the
-//               strips covering each pixel in LDS in a fixed order (no
-//               atomics, bitwise reproducible), then writes its owned pixels.
+//   k_reduce     lanes = 64 adjacent strips, waves = Q consecutive chunks.  The
+//                last r elements of every chunk but the last are a separator
+//                block S_j.  Each lane eliminates its chunk interior I_j
+//                (banded LDL^T with a right-looking (r+1)x(r+1) window) while
+//                carrying the previous separator S_{j-1} as a border, and emits
+//                the chunk's contribution to the Schur complement on the
+//                separators.
+//   k_interface  one wave per strip: the separator system is block tridiagonal
+//                (r x r blocks, one per chunk boundary).  Each lane eliminates
+//                a run of m consecutive separator blocks (the same bordered
+//                elimination, one level up), the 64 remaining blocks are solved
+//                by block parallel cyclic reduction across the lanes, and each
+//                lane back-substitutes its run.  (A serial one-lane-per-strip
+//                solver covers runs too long for registers.)
+//   k_expand     same block shape as k_reduce: each lane re-solves its chunk
+//                with both separators known, and the block averages the strips
+//                covering each pixel in LDS in a fixed order (no atomics,
+//                bitwise reproducible) before writing the pixels it owns.
 //
-// The weights and the band of A_s are recomputed from the guidance in every
-// kernel; nothing of size O(pixels) is stored besides the output.
-// Lanes of a wave are adjacent strips, so in the column pass consecutive lanes
-// read consecutive pixels of a row.
+// Image tiles are staged through LDS so that global loads and stores are
+// contiguous in both pass directions; lanes then read their strip's pixels
+// from LDS.  Weights and the band of A_s are recomputed from the guidance; no
+// per-pixel intermediate goes to memory.
 #include "sgwls_internal.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace sgwls {
 namespace {
 
 #define DEV __device__ __forceinline__
 
-// Range factor of Eq. (2).  exp: exp(-dG^2 / (2 sigma_r^2)); frac:
-// 1 / (|dG|^alpha_r + eps).  The spatial factor is folded into lambda*S(d).
+// ---------------------------------------------------------------------------
+// Arithmetic helpers.
+
+// Range factor of Eq. (2); the spatial factor is folded into lambda*S(d).
+// exp: 2^(-dG^2 * log2(e)/(2 sigma_r^2)); frac: 1/(|dG|^alpha_r + eps) with
+// |dG|^alpha_r = 2^(alpha_r log2|dG|).  Hardware exp2/log2/rcp (about 1 ulp).
 DEV float range_weight(float dg, const WeightParams& wp) {
-  if (wp.kind == 0) return expf(-(dg * dg) * wp.range_c);
+  if (wp.kind == 0) return __builtin_amdgcn_exp2f(-(dg * dg) * wp.range_c2);
   const float ad = fabsf(dg);
-  const float pw = (wp.alpha_r == 0.0f) ? 1.0f : (ad > 0.0f ? powf(ad, wp.alpha_r) : 0.0f);
-  return 1.0f / (pw + wp.eps);
+  float pw;
+  if (wp.alpha_r == 0.0f) pw = 1.0f;
+  else pw = ad > 0.0f ? __builtin_amdgcn_exp2f(wp.alpha_r * __builtin_amdgcn_logf(ad)) : 0.0f;
+  return __builtin_amdgcn_rcpf(pw + wp.eps);
 }
+
+DEV float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+DEV double recip(double x) { return 1.0 / x; }
 
 // Element m of a chunk (local index; negative = the previous chunk's tail)
 // lies in chunk row floor(m / (2r+1)) at position q = m mod (2r+1).  Chunks
@@ -60,64 +74,13 @@ template <int r>
 DEV constexpr int row_of(int m) {
   return m >= 0 ? m / (2 * r + 1) : -1 - ((-m - 1) / (2 * r + 1));
 }
-
-template <int r, int R>
-struct Chunk {
-  static constexpr int w = 2 * r + 1;
-  static constexpr int E = R * w;          // elements per full chunk
-  static_assert(R >= 2 && R % 2 == 0, "chunks must start on even rows");
-  long long base;                          // offset of pixel (a0, k)
-  long long sa, sb;
-  int a0, L;
-  DEV long long off(int m) const {
-    const int rho = row_of<r>(m);
-    const int q = m - rho * w;
-    const int db = (rho & 1) ? (r - q) : (q - r);
-    return base + (long long)rho * sa + (long long)db * sb;
-  }
-  DEV bool ok(int m) const {
-    const int a = a0 + row_of<r>(m);
-    return a >= 0 && a < L;
-  }
-};
-
-// lambda * w(m, m+d) for local m in [-r, E) and d = 1..r, at lw[m + r][d - 1];
-// zero where either end lies outside the subsystem.
-template <int r, int R>
-DEV void chunk_weights(const Chunk<r, R>& ch, const float* __restrict__ G,
-                       const WeightParams& wp, const float (&lamS)[r + 1],
-                       float (&lw)[Chunk<r, R>::E + r][r]) {
-  constexpr int E = Chunk<r, R>::E;
-  float gv[E + 2 * r];
-  bool okv[E + 2 * r];
-#pragma unroll
-  for (int m = -r; m < E + r; ++m) {
-    okv[m + r] = ch.ok(m);
-    gv[m + r] = okv[m + r] ? G[ch.off(m)] : 0.0f;
-  }
-#pragma unroll
-  for (int m = -r; m < E; ++m) {
-#pragma unroll
-    for (int d = 1; d <= r; ++d) {
-      lw[m + r][d - 1] = (okv[m + r] && okv[m + d + r])
-                             ? lamS[d] * range_weight(gv[m + r] - gv[m + d + r], wp)
-                             : 0.0f;
-    }
-  }
+template <int r>
+DEV constexpr int col_of(int m) {  // offset from the centre column k
+  return (row_of<r>(m) & 1) ? (r - (m - row_of<r>(m) * (2 * r + 1)))
+                            : ((m - row_of<r>(m) * (2 * r + 1)) - r);
 }
 
-// Diagonal of A_s at local element m: 1 + lambda * (sum of its edge weights).
-template <int r, int R, typename Acc>
-DEV Acc diag_at(const float (&lw)[Chunk<r, R>::E + r][r], int m) {
-  Acc s = Acc(1);
-#pragma unroll
-  for (int d = 1; d <= r; ++d) s += Acc(lw[m + r][d - 1]) + Acc(lw[m - d + r][d - 1]);
-  return s;
-}
-
-template <typename Acc> DEV Acc rcp_exact(Acc x) { return Acc(1) / x; }
-
-// In-place Cholesky of a small SPD matrix (lower triangle used) and solves.
+// Small dense helpers on r x r blocks.
 template <int n, typename Acc>
 DEV void chol(Acc (&A)[n][n]) {
 #pragma unroll
@@ -159,6 +122,75 @@ DEV void chol_solve(const Acc (&Lc)[n][n], Acc (&B)[n][m]) {
   }
 }
 
+// Inverse of a small SPD matrix through its Cholesky factor.
+template <int n, typename Acc>
+DEV void spd_inverse(const Acc (&A)[n][n], Acc (&Ai)[n][n]) {
+  Acc Lc[n][n];
+#pragma unroll
+  for (int i = 0; i < n; ++i)
+#pragma unroll
+    for (int j = 0; j < n; ++j) Lc[i][j] = A[i][j];
+  chol<n, Acc>(Lc);
+#pragma unroll
+  for (int i = 0; i < n; ++i)
+#pragma unroll
+    for (int j = 0; j < n; ++j) Ai[i][j] = (i == j) ? Acc(1) : Acc(0);
+  chol_solve<n, n, Acc>(Lc, Ai);
+}
+
+// C = A * B (n x k times k x m), C must not alias.
+template <int n, int k, int m, typename Acc>
+DEV void mm(const Acc (&A)[n][k], const Acc (&B)[k][m], Acc (&C)[n][m]) {
+#pragma unroll
+  for (int i = 0; i < n; ++i)
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
+      Acc v = Acc(0);
+#pragma unroll
+      for (int t = 0; t < k; ++t) v += A[i][t] * B[t][j];
+      C[i][j] = v;
+    }
+}
+
+// C -= A^T * B.
+template <int n, int k, int m, typename Acc>
+DEV void sub_AtB(const Acc (&A)[k][n], const Acc (&B)[k][m], Acc (&C)[n][m]) {
+#pragma unroll
+  for (int i = 0; i < n; ++i)
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
+      Acc v = C[i][j];
+#pragma unroll
+      for (int t = 0; t < k; ++t) v -= A[t][i] * B[t][j];
+      C[i][j] = v;
+    }
+}
+
+template <int n, int m, typename Acc>
+DEV void shfl_up_blk(const Acc (&src)[n][m], Acc (&dst)[n][m], int delta, int lane) {
+#pragma unroll
+  for (int i = 0; i < n; ++i)
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
+      const Acc v = __shfl_up(src[i][j], delta, kWave);
+      dst[i][j] = lane >= delta ? v : Acc(0);
+    }
+}
+
+template <int n, int m, typename Acc>
+DEV void shfl_down_blk(const Acc (&src)[n][m], Acc (&dst)[n][m], int delta, int lane) {
+#pragma unroll
+  for (int i = 0; i < n; ++i)
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
+      const Acc v = __shfl_down(src[i][j], delta, kWave);
+      dst[i][j] = lane + delta < kWave ? v : Acc(0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Layout of the per-chunk Schur complement contributions written by k_reduce
+// (strip-major: sum[(ki * P + j) * F + f]).
 template <int r, int CB>
 struct IfaceLayout {
   static constexpr int T2 = r * (r + 1) / 2;
@@ -166,7 +198,7 @@ struct IfaceLayout {
   static constexpr int oRf = T2;                // f_S - A_SI A_I^-1 f_I of S_j
   static constexpr int oTT = T2 + r * CB;       // A_TI A_I^-1 A_IT of T = S_{j-1} (lower)
   static constexpr int oRT = 2 * T2 + r * CB;   // A_TI A_I^-1 f_I
-  static constexpr int oTB = 2 * T2 + 2 * r * CB;  // coupling S_j <-> S_{j-1} after elimination
+  static constexpr int oTB = 2 * T2 + 2 * r * CB;  // S_j <-> S_{j-1} coupling after elimination
   static constexpr int F = 2 * T2 + 2 * r * CB + r * r;
 };
 
@@ -174,165 +206,532 @@ DEV float load_lambda(const float* lam_dev, float lam_host) {
   return lam_dev ? *lam_dev : lam_host;
 }
 
-// ---------------------------------------------------------------------------
-// k_reduce: Schur complement contributions of one chunk of one subsystem.
-template <int r, int CB, int R, typename Acc>
-__global__ __launch_bounds__(kWave) void k_reduce(
-    const float* __restrict__ X, const float* __restrict__ G, PassGeom geo, WeightParams wp,
-    const float* __restrict__ lam_dev, float lam_host, int c0, Acc* __restrict__ sum) {
-  using CK = Chunk<r, R>;
-  using LY = IfaceLayout<r, CB>;
-  constexpr int E = CK::E;
-  const int ki = blockIdx.x * kWave + threadIdx.x;
-  const int j = blockIdx.y;
-  if (ki >= geo.nK) return;
-  const float lam = load_lambda(lam_dev, lam_host);
-  float lamS[r + 1];
-#pragma unroll
-  for (int d = 0; d <= r; ++d) lamS[d] = lam * wp.spatial[d];
-  const int k = min(r + ki * geo.stride, geo.W - 1 - r);
-  CK ch;
-  ch.a0 = j * R;
-  ch.L = geo.L;
-  ch.sa = geo.sa;
-  ch.sb = geo.sb;
-  ch.base = (long long)ch.a0 * geo.sa + (long long)k * geo.sb;
-  const bool hasT = j > 0, hasB = j + 1 < geo.P;
-  float lw[E + r][r];
-  chunk_weights<r, R>(ch, G, wp, lamS, lw);
-  const float* Xc = X + (long long)c0 * geo.plane;
-  auto fval = [&](int m, int c) -> Acc {
-    return ch.ok(m) ? Acc(Xc[(long long)c * geo.plane + ch.off(m)]) : Acc(0);
-  };
+DEV int centre_of(int ki, const PassGeom& geo, int r) {
+  return min(r + ki * geo.stride, geo.W - 1 - r);
+}
 
+// Number of strip centres whose 2r+1 columns cover column b.
+DEV int cover_count(int b, const PassGeom& geo, int r) {
+  const int lo = max(r, b - r), hi = min(geo.W - 1 - r, b + r);
+  const int t = geo.stride;
+  const int first = (lo - r + t - 1) / t, last = (hi - r) / t;
+  int c = max(0, last - first + 1);
+  const int span = geo.W - 1 - 2 * r;
+  if (span % t != 0 && geo.W - 1 - r >= lo && geo.W - 1 - r <= hi) c += 1;
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// LDS tile of a block: rows a in [a_lo - 1, a_lo + Q*R + 1) of the pass, columns
+// b in [colbase, colbase + TB), planes: guidance then CB image channels.  Rows
+// or columns outside the image hold 0 (never used as pixels).
+template <int CB>
+DEV void load_tile(float* lds, const float* __restrict__ G, const float* __restrict__ X,
+                   const PassGeom& geo, int c0, int a_lo, int colbase, int TA, int TB,
+                   int pitch, int tid, int nthr) {
+#pragma unroll
+  for (int p = 0; p <= CB; ++p) {
+    const float* src = p == 0 ? G : X + (long long)(c0 + p - 1) * geo.plane;
+    float* dst = lds + p * TA * pitch;
+    if (geo.sb == 1) {   // column pass: b is contiguous in memory
+      for (int idx = tid; idx < TA * TB; idx += nthr) {
+        const int ta = idx / TB, tb = idx - ta * TB;
+        const int a = a_lo - 1 + ta, b = colbase + tb;
+        float v = 0.0f;
+        if (a >= 0 && a < geo.L && b < geo.W) v = src[(long long)a * geo.sa + b];
+        dst[ta * pitch + tb] = v;
+      }
+    } else {             // row pass: a is contiguous in memory
+      for (int idx = tid; idx < TA * TB; idx += nthr) {
+        const int tb = idx / TA, ta = idx - tb * TA;
+        const int a = a_lo - 1 + ta, b = colbase + tb;
+        float v = 0.0f;
+        if (a >= 0 && a < geo.L && b < geo.W) v = src[a + (long long)b * geo.sb];
+        dst[ta * pitch + tb] = v;
+      }
+    }
+  }
+}
+
+// The chunk of one lane: element values come from the LDS tile.
+template <int r, int R, bool S1>
+struct ChunkView {
+  static constexpr int w = 2 * r + 1;
+  static constexpr int E = R * w;
+  static constexpr int PITCH1 = kWave + 2 * r + 1;   // pitch of stride-1 tiles
+  static_assert(R >= 2 && R % 2 == 0, "chunks must start on even rows");
+  const float* base;   // plane 0 at (tile row of the chunk's first row, column k)
+  int pitch, plane, a0, L;
+  DEV int off(int m) const {
+    const int p = S1 ? PITCH1 : pitch;
+    return row_of<r>(m) * p + col_of<r>(m);
+  }
+  DEV bool ok(int m) const {
+    const int a = a0 + row_of<r>(m);
+    return a >= 0 && a < L;
+  }
+  DEV float g(int m) const { return base[off(m)]; }
+  DEV float f(int m, int c) const { return base[(c + 1) * plane + off(m)]; }
+};
+
+// lambda * w(m, m+d) for local m in [-r, E) and d = 1..r, at lw[m + r][d - 1];
+// zero where either end lies outside the subsystem.
+template <int r, int R, bool S1>
+DEV void chunk_weights(const ChunkView<r, R, S1>& cv, const WeightParams& wp,
+                       const float (&lamS)[r + 1],
+                       float (&lw)[ChunkView<r, R, S1>::E + r][r]) {
+  constexpr int E = ChunkView<r, R, S1>::E;
+  float gv[E + 2 * r];
+#pragma unroll
+  for (int m = -r; m < E + r; ++m) gv[m + r] = cv.g(m);
+#pragma unroll
+  for (int m = -r; m < E; ++m) {
+#pragma unroll
+    for (int d = 1; d <= r; ++d) {
+      lw[m + r][d - 1] = (cv.ok(m) && cv.ok(m + d))
+                             ? lamS[d] * range_weight(gv[m + r] - gv[m + d + r], wp)
+                             : 0.0f;
+    }
+  }
+}
+
+// Diagonal of A_s at local element m: 1 + lambda * (sum of its edge weights).
+template <int r, int E, typename Acc>
+DEV Acc diag_at(const float (&lw)[E + r][r], int m) {
+  Acc s = Acc(1);
+#pragma unroll
+  for (int d = 1; d <= r; ++d) s += Acc(lw[m + r][d - 1]) + Acc(lw[m - d + r][d - 1]);
+  return s;
+}
+
+template <int r>
+DEV int tile_width(int stride) { return stride == 1 ? kWave + 2 * r : (kWave - 1) * stride + 2 * r + 1; }
+
+// ---------------------------------------------------------------------------
+// k_reduce: Schur complement contributions of every chunk of 64 strips.
+template <int r, int CB, int R, int Q, bool S1, typename Acc>
+__global__ __launch_bounds__(kWave* Q) void k_reduce(
+    const float* __restrict__ X, const float* __restrict__ G, PassGeom geo, WeightParams wp,
+    const float* __restrict__ lam_dev, float lam_host, int c0, int pitch,
+    Acc* __restrict__ sum) {
+  using CV = ChunkView<r, R, S1>;
+  using LY = IfaceLayout<r, CB>;
+  constexpr int E = CV::E;
+  constexpr int TA = Q * R + 2;
+  extern __shared__ float smem[];
+  const int lane = threadIdx.x % kWave, wq = threadIdx.x / kWave;
+  const int ki_lo = blockIdx.x * kWave;
+  const int j0 = blockIdx.y * Q, j = j0 + wq;
+  const int a_lo = j0 * R;
+  const int colbase = centre_of(ki_lo, geo, r) - r;
+  const int TB = S1 ? kWave + 2 * r : tile_width<r>(geo.stride);
+  const int pch = S1 ? CV::PITCH1 : pitch;
+  load_tile<CB>(smem, G, X, geo, c0, a_lo, colbase, TA, TB, pch, threadIdx.x, kWave * Q);
+  __syncthreads();
+
+  const int ki = ki_lo + lane;
+  const bool active = ki < geo.nK && j < geo.P;
+  const bool hasT = j > 0, hasB = j + 1 < geo.P;
   Acc W[r + 1][r + 1];   // Schur complement on the window, lower triangle
   Acc Bt[r + 1][r];      // window couplings to the previous separator
   Acc Rw[r + 1][CB];     // window right-hand sides
   Acc TT[r][r], RT[r][CB];
+  if (active) {
+    const float lam = load_lambda(lam_dev, lam_host);
+    float lamS[r + 1];
 #pragma unroll
-  for (int a = 0; a < r; ++a) {
-#pragma unroll
-    for (int b = 0; b < r; ++b) TT[a][b] = Acc(0);
-#pragma unroll
-    for (int c = 0; c < CB; ++c) RT[a][c] = Acc(0);
-  }
-#pragma unroll
-  for (int a = 0; a < r; ++a) {
-    W[a][a] = diag_at<r, R, Acc>(lw, a);
-#pragma unroll
-    for (int b = 0; b < a; ++b) W[a][b] = -Acc(lw[b + r][a - b - 1]);
-#pragma unroll
-    for (int c = 0; c < r; ++c) Bt[a][c] = (c >= a) ? -Acc(lw[c][a + r - c - 1]) : Acc(0);
-#pragma unroll
-    for (int c = 0; c < CB; ++c) Rw[a][c] = fval(a, c);
-  }
-
-  auto step = [&](const int m) {
-    const int n = m + r;                 // element entering the window
-    if (n < E) {
-      W[r][r] = diag_at<r, R, Acc>(lw, n);
-#pragma unroll
-      for (int b = 0; b < r; ++b) W[r][b] = -Acc(lw[m + b + r][r - b - 1]);
-#pragma unroll
-      for (int c = 0; c < CB; ++c) Rw[r][c] = fval(n, c);
-    } else {                             // past the end of the subsystem
-      W[r][r] = Acc(1);
-#pragma unroll
-      for (int b = 0; b < r; ++b) W[r][b] = Acc(0);
-#pragma unroll
-      for (int c = 0; c < CB; ++c) Rw[r][c] = Acc(0);
-    }
-#pragma unroll
-    for (int c = 0; c < r; ++c) Bt[r][c] = Acc(0);
-
-    const Acc invD = rcp_exact(W[0][0]);
-    Acc l[r + 1];
-#pragma unroll
-    for (int a = 1; a <= r; ++a) l[a] = W[a][0] * invD;
-#pragma unroll
-    for (int a = 1; a <= r; ++a)
-#pragma unroll
-      for (int b = 1; b <= a; ++b) W[a][b] -= l[a] * W[b][0];
-#pragma unroll
-    for (int a = 1; a <= r; ++a)
-#pragma unroll
-      for (int c = 0; c < r; ++c) Bt[a][c] -= l[a] * Bt[0][c];
-#pragma unroll
-    for (int c = 0; c < r; ++c) {
-      const Acc bs = Bt[0][c] * invD;
-#pragma unroll
-      for (int c2 = 0; c2 <= c; ++c2) TT[c][c2] += bs * Bt[0][c2];
-#pragma unroll
-      for (int h = 0; h < CB; ++h) RT[c][h] += bs * Rw[0][h];
-    }
-#pragma unroll
-    for (int a = 1; a <= r; ++a)
-#pragma unroll
-      for (int h = 0; h < CB; ++h) Rw[a][h] -= l[a] * Rw[0][h];
+    for (int d = 0; d <= r; ++d) lamS[d] = lam * wp.spatial[d];
+    const int k = centre_of(ki, geo, r);
+    CV cv;
+    cv.base = smem + (wq * R + 1) * pch + (k - colbase);
+    cv.pitch = pch;
+    cv.plane = TA * pch;
+    cv.a0 = j * R;
+    cv.L = geo.L;
+    float lw[E + r][r];
+    chunk_weights<r, R, S1>(cv, wp, lamS, lw);
+    auto fval = [&](int m, int c) -> Acc { return cv.ok(m) ? Acc(cv.f(m, c)) : Acc(0); };
 #pragma unroll
     for (int a = 0; a < r; ++a) {
 #pragma unroll
-      for (int b = 0; b <= a; ++b) W[a][b] = W[a + 1][b + 1];
+      for (int b = 0; b < r; ++b) TT[a][b] = Acc(0);
 #pragma unroll
-      for (int c = 0; c < r; ++c) Bt[a][c] = Bt[a + 1][c];
-#pragma unroll
-      for (int h = 0; h < CB; ++h) Rw[a][h] = Rw[a + 1][h];
+      for (int c = 0; c < CB; ++c) RT[a][c] = Acc(0);
     }
-  };
-  // Interior elements of a chunk with a separator: 0..E-r-1.  The last chunk
-  // has no separator and eliminates all E (padding past the end is inert).
 #pragma unroll
-  for (int m = 0; m < E - r; ++m) step(m);
-  if (!hasB) {
+    for (int a = 0; a < r; ++a) {
+      W[a][a] = diag_at<r, E, Acc>(lw, a);
 #pragma unroll
-    for (int m = E - r; m < E; ++m) step(m);
+      for (int b = 0; b < a; ++b) W[a][b] = -Acc(lw[b + r][a - b - 1]);
+#pragma unroll
+      for (int c = 0; c < r; ++c) Bt[a][c] = (c >= a) ? -Acc(lw[c][a + r - c - 1]) : Acc(0);
+#pragma unroll
+      for (int c = 0; c < CB; ++c) Rw[a][c] = fval(a, c);
+    }
+    auto step = [&](const int m) {
+      const int n = m + r;   // element entering the window
+      if (n < E) {
+        W[r][r] = diag_at<r, E, Acc>(lw, n);
+#pragma unroll
+        for (int b = 0; b < r; ++b) W[r][b] = -Acc(lw[m + b + r][r - b - 1]);
+#pragma unroll
+        for (int c = 0; c < CB; ++c) Rw[r][c] = fval(n, c);
+      } else {               // past the end of the subsystem
+        W[r][r] = Acc(1);
+#pragma unroll
+        for (int b = 0; b < r; ++b) W[r][b] = Acc(0);
+#pragma unroll
+        for (int c = 0; c < CB; ++c) Rw[r][c] = Acc(0);
+      }
+#pragma unroll
+      for (int c = 0; c < r; ++c) Bt[r][c] = Acc(0);
+      const Acc invD = recip(W[0][0]);
+      Acc l[r + 1];
+#pragma unroll
+      for (int a = 1; a <= r; ++a) l[a] = W[a][0] * invD;
+#pragma unroll
+      for (int a = 1; a <= r; ++a)
+#pragma unroll
+        for (int b = 1; b <= a; ++b) W[a][b] -= l[a] * W[b][0];
+#pragma unroll
+      for (int a = 1; a <= r; ++a)
+#pragma unroll
+        for (int c = 0; c < r; ++c) Bt[a][c] -= l[a] * Bt[0][c];
+#pragma unroll
+      for (int c = 0; c < r; ++c) {
+        const Acc bs = Bt[0][c] * invD;
+#pragma unroll
+        for (int c2 = 0; c2 <= c; ++c2) TT[c][c2] += bs * Bt[0][c2];
+#pragma unroll
+        for (int h = 0; h < CB; ++h) RT[c][h] += bs * Rw[0][h];
+      }
+#pragma unroll
+      for (int a = 1; a <= r; ++a)
+#pragma unroll
+        for (int h = 0; h < CB; ++h) Rw[a][h] -= l[a] * Rw[0][h];
+#pragma unroll
+      for (int a = 0; a < r; ++a) {
+#pragma unroll
+        for (int b = 0; b <= a; ++b) W[a][b] = W[a + 1][b + 1];
+#pragma unroll
+        for (int c = 0; c < r; ++c) Bt[a][c] = Bt[a + 1][c];
+#pragma unroll
+        for (int h = 0; h < CB; ++h) Rw[a][h] = Rw[a + 1][h];
+      }
+    };
+    // Interior of a chunk with a separator: elements 0..E-r-1.  The last chunk
+    // has no separator and eliminates all E (padding past the end is inert).
+#pragma unroll
+    for (int m = 0; m < E - r; ++m) step(m);
+    if (!hasB) {
+#pragma unroll
+      for (int m = E - r; m < E; ++m) step(m);
+    }
   }
+  __syncthreads();   // tile reads done: the LDS now stages the block's output
 
-  Acc* out = sum + (size_t)j * LY::F * geo.nK + ki;
-  const size_t fs = geo.nK;
-  if (hasB) {
+  Acc* st = reinterpret_cast<Acc*>(smem) + (lane * Q + wq) * LY::F;
+  if (active) {
     int t = 0;
 #pragma unroll
     for (int a = 0; a < r; ++a)
 #pragma unroll
-      for (int b = 0; b <= a; ++b) out[(LY::oW + t++) * fs] = W[a][b];
+      for (int b = 0; b <= a; ++b) {
+        st[LY::oW + t] = hasB ? W[a][b] : Acc(0);
+        st[LY::oTT + t] = hasT ? TT[a][b] : Acc(0);
+        ++t;
+      }
 #pragma unroll
     for (int a = 0; a < r; ++a)
 #pragma unroll
-      for (int h = 0; h < CB; ++h) out[(LY::oRf + a * CB + h) * fs] = Rw[a][h];
+      for (int h = 0; h < CB; ++h) {
+        st[LY::oRf + a * CB + h] = hasB ? Rw[a][h] : Acc(0);
+        st[LY::oRT + a * CB + h] = hasT ? RT[a][h] : Acc(0);
+      }
+#pragma unroll
+    for (int a = 0; a < r; ++a)
+#pragma unroll
+      for (int c = 0; c < r; ++c) st[LY::oTB + a * r + c] = (hasT && hasB) ? Bt[a][c] : Acc(0);
   }
-  if (hasT) {
-    int t = 0;
-#pragma unroll
-    for (int a = 0; a < r; ++a)
-#pragma unroll
-      for (int b = 0; b <= a; ++b) out[(LY::oTT + t++) * fs] = TT[a][b];
-#pragma unroll
-    for (int a = 0; a < r; ++a)
-#pragma unroll
-      for (int h = 0; h < CB; ++h) out[(LY::oRT + a * CB + h) * fs] = RT[a][h];
-  }
-  if (hasT && hasB) {
-#pragma unroll
-    for (int a = 0; a < r; ++a)
-#pragma unroll
-      for (int c = 0; c < r; ++c) out[(LY::oTB + a * r + c) * fs] = Bt[a][c];
+  __syncthreads();
+  // strip-major output: Q*F consecutive values per strip
+  const int qv = min(Q, geo.P - j0);
+  const Acc* stg = reinterpret_cast<const Acc*>(smem);
+  for (int idx = threadIdx.x; idx < kWave * Q * LY::F; idx += kWave * Q) {
+    const int s = idx / (Q * LY::F), t = idx - s * (Q * LY::F);
+    if (ki_lo + s < geo.nK && t < qv * LY::F)
+      sum[((size_t)(ki_lo + s) * geo.P + j0) * LY::F + t] = stg[idx];
   }
 }
 
 // ---------------------------------------------------------------------------
-// k_interface: block-tridiagonal separator system of one subsystem.
-// Sigma_jj = W_j - TT_{j+1},  Sigma_{j,j+1}[a][c] = TB_{j+1}[c][a],
-// rhs_j = Rf_j - RT_{j+1};  block Cholesky forward sweep, then back sweep.
-// U receives u on every separator: U[(j*r*CB + a*CB + h) * nK + ki].
+// Separator system of one strip: Sigma_jj = W_j - TT_{j+1},
+// Sigma_{j,j+1}[a][c] = TB_{j+1}[c][a], rhs_j = Rf_j - RT_{j+1}, j = 0..P-2.
 template <int r, int CB, typename Acc>
-__global__ __launch_bounds__(kWave) void k_interface(const Acc* __restrict__ sum,
-                                                     Acc* __restrict__ Gb, Acc* __restrict__ U,
-                                                     int nK, int P) {
+struct SepReader {
   using LY = IfaceLayout<r, CB>;
+  const Acc* S;   // this strip's contributions
+  int P;
+  DEV Acc at(int j, int f) const { return S[(size_t)j * LY::F + f]; }
+  DEV void diag(int j, Acc (&A)[r][r]) const {
+    int t = 0;
+#pragma unroll
+    for (int a = 0; a < r; ++a)
+#pragma unroll
+      for (int b = 0; b <= a; ++b) {
+        A[a][b] = at(j, LY::oW + t) - at(j + 1, LY::oTT + t);
+        A[b][a] = A[a][b];
+        ++t;
+      }
+  }
+  DEV void rhs(int j, Acc (&y)[r][CB]) const {
+#pragma unroll
+    for (int a = 0; a < r; ++a)
+#pragma unroll
+      for (int h = 0; h < CB; ++h)
+        y[a][h] = at(j, LY::oRf + a * CB + h) - at(j + 1, LY::oRT + a * CB + h);
+  }
+  DEV void off(int j, Acc (&U)[r][r]) const {   // Sigma_{j,j+1}; zero past the last
+#pragma unroll
+    for (int a = 0; a < r; ++a)
+#pragma unroll
+      for (int c = 0; c < r; ++c) U[a][c] = (j + 1 < P - 1) ? at(j + 1, LY::oTB + c * r + a) : Acc(0);
+  }
+};
+
+// k_interface_pcr: one wave per strip, lane l owns separator blocks
+// [l*m, min(l*m + m, P-1)); MM is the compiled maximum of m.
+// U receives the separator solutions strip-major: U[(ki*(P-1) + j)*r*CB + a*CB + h].
+template <int r, int CB, int MM, typename Acc>
+__global__ __launch_bounds__(kWave) void k_interface_pcr(const Acc* __restrict__ sum,
+                                                         Acc* __restrict__ U, int nK, int P,
+                                                         int m) {
+  using LY = IfaceLayout<r, CB>;
+  const int ki = blockIdx.x, lane = threadIdx.x;
+  const int n = P - 1;
+  const int s = lane * m, e = min(s + m, n);
+  const bool active = s < n;
+  SepReader<r, CB, Acc> rd{sum + (size_t)ki * P * LY::F, P};
+
+  // Local bordered elimination of blocks s .. e-2 (T = block s-1 of the
+  // previous lane, B = block e-1 is this lane's unknown at the PCR level).
+  Acc Ls[MM][r][r], Ub[MM][r][r], Btb[MM][r][r], Rb[MM][r][CB];
+  Acc S[r][r], Bt[r][r], Rr[r][CB], TT[r][r], RT[r][CB];
+#pragma unroll
+  for (int a = 0; a < r; ++a) {
+#pragma unroll
+    for (int c = 0; c < r; ++c) { TT[a][c] = Acc(0); S[a][c] = Acc(0); Bt[a][c] = Acc(0); }
+#pragma unroll
+    for (int h = 0; h < CB; ++h) { RT[a][h] = Acc(0); Rr[a][h] = Acc(0); }
+  }
+  if (active) {
+    rd.diag(s, S);
+    rd.rhs(s, Rr);
+    if (s > 0) {
+      Acc U0[r][r];
+      rd.off(s - 1, U0);
+#pragma unroll
+      for (int a = 0; a < r; ++a)
+#pragma unroll
+        for (int c = 0; c < r; ++c) Bt[a][c] = U0[c][a];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < MM - 1; ++i) {
+    const int b = s + i;
+    if (active && b < e - 1) {
+      Acc Lc[r][r];
+#pragma unroll
+      for (int a = 0; a < r; ++a)
+#pragma unroll
+        for (int c = 0; c < r; ++c) Lc[a][c] = S[a][c];
+      chol<r, Acc>(Lc);
+      Acc Uc[r][r];
+      rd.off(b, Uc);
+      Acc V[r][r], Y[r][r], wv[r][CB];
+#pragma unroll
+      for (int a = 0; a < r; ++a) {
+#pragma unroll
+        for (int c = 0; c < r; ++c) { V[a][c] = Uc[a][c]; Y[a][c] = Bt[a][c]; }
+#pragma unroll
+        for (int h = 0; h < CB; ++h) wv[a][h] = Rr[a][h];
+      }
+      chol_solve<r, r, Acc>(Lc, V);    // S^-1 U
+      chol_solve<r, r, Acc>(Lc, Y);    // S^-1 Bt
+      chol_solve<r, CB, Acc>(Lc, wv);  // S^-1 R
+      // TT += Bt^T S^-1 Bt, RT += Bt^T S^-1 R
+#pragma unroll
+      for (int a = 0; a < r; ++a) {
+#pragma unroll
+        for (int c = 0; c < r; ++c) {
+          Acc v = Acc(0);
+#pragma unroll
+          for (int t = 0; t < r; ++t) v += Bt[t][a] * Y[t][c];
+          TT[a][c] += v;
+        }
+#pragma unroll
+        for (int h = 0; h < CB; ++h) {
+          Acc v = Acc(0);
+#pragma unroll
+          for (int t = 0; t < r; ++t) v += Bt[t][a] * wv[t][h];
+          RT[a][h] += v;
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < r; ++a) {
+#pragma unroll
+        for (int c = 0; c < r; ++c) { Ls[i][a][c] = Lc[a][c]; Ub[i][a][c] = Uc[a][c]; Btb[i][a][c] = Bt[a][c]; }
+#pragma unroll
+        for (int h = 0; h < CB; ++h) Rb[i][a][h] = Rr[a][h];
+      }
+      // next block
+      Acc Sn[r][r], Rn[r][CB], Bn[r][r];
+      rd.diag(b + 1, Sn);
+      rd.rhs(b + 1, Rn);
+#pragma unroll
+      for (int a = 0; a < r; ++a)
+#pragma unroll
+        for (int c = 0; c < r; ++c) Bn[a][c] = Acc(0);
+      sub_AtB<r, r, r, Acc>(Uc, V, Sn);
+      sub_AtB<r, r, r, Acc>(Uc, Y, Bn);
+      sub_AtB<r, r, CB, Acc>(Uc, wv, Rn);
+#pragma unroll
+      for (int a = 0; a < r; ++a) {
+#pragma unroll
+        for (int c = 0; c < r; ++c) { S[a][c] = Sn[a][c]; Bt[a][c] = Bn[a][c]; }
+#pragma unroll
+        for (int h = 0; h < CB; ++h) Rr[a][h] = Rn[a][h];
+      }
+    }
+  }
+
+  // PCR level: lane l's unknown X_l = x_{e-1}:
+  //   A_l X_{l-1} + B_l X_l + C_l X_{l+1} = d_l with
+  //   A_l = Bt_l, B_l = S_l - TT_{l+1}, C_l = Bt_{l+1}^T, d_l = R_l - RT_{l+1}.
+  Acc A[r][r], B[r][r], Cc[r][r], d[r][CB];
+  {
+    Acc TTn[r][r], RTn[r][CB], Btn[r][r];
+    shfl_down_blk<r, r, Acc>(TT, TTn, 1, lane);
+    shfl_down_blk<r, CB, Acc>(RT, RTn, 1, lane);
+    shfl_down_blk<r, r, Acc>(Bt, Btn, 1, lane);
+    const bool nextActive = (lane + 1) * m < n;
+#pragma unroll
+    for (int a = 0; a < r; ++a) {
+#pragma unroll
+      for (int c = 0; c < r; ++c) {
+        A[a][c] = active ? Bt[a][c] : Acc(0);
+        B[a][c] = active ? S[a][c] - (nextActive ? TTn[a][c] : Acc(0)) : (a == c ? Acc(1) : Acc(0));
+        Cc[a][c] = (active && nextActive) ? Btn[c][a] : Acc(0);
+      }
+#pragma unroll
+      for (int h = 0; h < CB; ++h) d[a][h] = active ? Rr[a][h] - (nextActive ? RTn[a][h] : Acc(0)) : Acc(0);
+    }
+  }
+#pragma unroll
+  for (int delta = 1; delta < kWave; delta *= 2) {
+    Acc Bi[r][r];
+    spd_inverse<r, Acc>(B, Bi);
+    Acc Bim[r][r], Am[r][r], Cm[r][r], dm[r][CB];
+    Acc Bip[r][r], Ap[r][r], Cp[r][r], dp[r][CB];
+    shfl_up_blk<r, r, Acc>(Bi, Bim, delta, lane);
+    shfl_up_blk<r, r, Acc>(A, Am, delta, lane);
+    shfl_up_blk<r, r, Acc>(Cc, Cm, delta, lane);
+    shfl_up_blk<r, CB, Acc>(d, dm, delta, lane);
+    shfl_down_blk<r, r, Acc>(Bi, Bip, delta, lane);
+    shfl_down_blk<r, r, Acc>(A, Ap, delta, lane);
+    shfl_down_blk<r, r, Acc>(Cc, Cp, delta, lane);
+    shfl_down_blk<r, CB, Acc>(d, dp, delta, lane);
+    Acc al[r][r], ga[r][r];
+    mm<r, r, r, Acc>(A, Bim, al);
+    mm<r, r, r, Acc>(Cc, Bip, ga);
+    Acc An[r][r], Cn[r][r], t1[r][r], t2[r][r], e1[r][CB], e2[r][CB];
+    mm<r, r, r, Acc>(al, Am, An);
+    mm<r, r, r, Acc>(ga, Cp, Cn);
+    mm<r, r, r, Acc>(al, Cm, t1);
+    mm<r, r, r, Acc>(ga, Ap, t2);
+    mm<r, r, CB, Acc>(al, dm, e1);
+    mm<r, r, CB, Acc>(ga, dp, e2);
+#pragma unroll
+    for (int a = 0; a < r; ++a) {
+#pragma unroll
+      for (int c = 0; c < r; ++c) {
+        A[a][c] = -An[a][c];
+        Cc[a][c] = -Cn[a][c];
+        B[a][c] = B[a][c] - t1[a][c] - t2[a][c];
+      }
+#pragma unroll
+      for (int h = 0; h < CB; ++h) d[a][h] = d[a][h] - e1[a][h] - e2[a][h];
+    }
+  }
+  Acc X[r][CB];
+  {
+    Acc Bc[r][r];
+#pragma unroll
+    for (int a = 0; a < r; ++a)
+#pragma unroll
+      for (int c = 0; c < r; ++c) Bc[a][c] = B[a][c];
+    chol<r, Acc>(Bc);
+#pragma unroll
+    for (int a = 0; a < r; ++a)
+#pragma unroll
+      for (int h = 0; h < CB; ++h) X[a][h] = d[a][h];
+    chol_solve<r, CB, Acc>(Bc, X);
+  }
+  Acc XT[r][CB];
+  shfl_up_blk<r, CB, Acc>(X, XT, 1, lane);
+  if (!active) return;
+  Acc* out = U + (size_t)ki * n * r * CB;
+#pragma unroll
+  for (int a = 0; a < r; ++a)
+#pragma unroll
+    for (int h = 0; h < CB; ++h) out[(size_t)(e - 1) * r * CB + a * CB + h] = X[a][h];
+  // back substitution: x_b = S_b^-1 (R_b - U_b x_{b+1} - Bt_b x_T)
+  Acc xn[r][CB];
+#pragma unroll
+  for (int a = 0; a < r; ++a)
+#pragma unroll
+    for (int h = 0; h < CB; ++h) xn[a][h] = X[a][h];
+#pragma unroll
+  for (int i = MM - 2; i >= 0; --i) {
+    const int b = s + i;
+    if (b < e - 1) {
+      Acc v[r][CB];
+#pragma unroll
+      for (int a = 0; a < r; ++a)
+#pragma unroll
+        for (int h = 0; h < CB; ++h) {
+          Acc t = Rb[i][a][h];
+#pragma unroll
+          for (int c = 0; c < r; ++c) t -= Ub[i][a][c] * xn[c][h] + Btb[i][a][c] * XT[c][h];
+          v[a][h] = t;
+        }
+      chol_solve<r, CB, Acc>(Ls[i], v);
+#pragma unroll
+      for (int a = 0; a < r; ++a)
+#pragma unroll
+        for (int h = 0; h < CB; ++h) {
+          out[(size_t)b * r * CB + a * CB + h] = v[a][h];
+          xn[a][h] = v[a][h];
+        }
+    }
+  }
+}
+
+// k_interface_serial: one lane per strip, block Cholesky over all separators
+// (for runs too long for the wave solver).  Uses U as scratch for h_j and
+// gb for the G_j blocks.
+template <int r, int CB, typename Acc>
+__global__ __launch_bounds__(kWave) void k_interface_serial(const Acc* __restrict__ sum,
+                                                            Acc* __restrict__ U,
+                                                            Acc* __restrict__ Gb, int nK,
+                                                            int P) {
   const int ki = blockIdx.x * kWave + threadIdx.x;
   if (ki >= nK) return;
-  auto S = [&](int j, int f) -> Acc { return sum[((size_t)j * LY::F + f) * nK + ki]; };
+  using LY = IfaceLayout<r, CB>;
+  SepReader<r, CB, Acc> rd{sum + (size_t)ki * P * LY::F, P};
+  const int n = P - 1;
+  Acc* out = U + (size_t)ki * n * r * CB;
+  Acc* gb = Gb + (size_t)ki * n * r * r;
   Acc Gp[r][r], hp[r][CB];
 #pragma unroll
   for (int a = 0; a < r; ++a) {
@@ -341,91 +740,51 @@ __global__ __launch_bounds__(kWave) void k_interface(const Acc* __restrict__ sum
 #pragma unroll
     for (int h = 0; h < CB; ++h) hp[a][h] = Acc(0);
   }
-  for (int j = 0; j < P - 1; ++j) {
+  for (int j = 0; j < n; ++j) {
     Acc A[r][r], y[r][CB];
-    int t = 0;
-#pragma unroll
-    for (int a = 0; a < r; ++a)
-#pragma unroll
-      for (int b = 0; b <= a; ++b) {
-        A[a][b] = S(j, LY::oW + t) - S(j + 1, LY::oTT + t);
-        A[b][a] = A[a][b];
-        ++t;
-      }
-#pragma unroll
-    for (int a = 0; a < r; ++a)
-#pragma unroll
-      for (int h = 0; h < CB; ++h)
-        y[a][h] = S(j, LY::oRf + a * CB + h) - S(j + 1, LY::oRT + a * CB + h);
+    rd.diag(j, A);
+    rd.rhs(j, y);
     if (j > 0) {
-      Acc Up[r][r];   // Sigma_{j-1,j}
-#pragma unroll
-      for (int a = 0; a < r; ++a)
-#pragma unroll
-        for (int c = 0; c < r; ++c) Up[a][c] = S(j, LY::oTB + c * r + a);
-#pragma unroll
-      for (int a = 0; a < r; ++a) {
-#pragma unroll
-        for (int b = 0; b < r; ++b) {
-          Acc v = A[a][b];
-#pragma unroll
-          for (int c = 0; c < r; ++c) v -= Up[c][a] * Gp[c][b];
-          A[a][b] = v;
-        }
-#pragma unroll
-        for (int h = 0; h < CB; ++h) {
-          Acc v = y[a][h];
-#pragma unroll
-          for (int c = 0; c < r; ++c) v -= Up[c][a] * hp[c][h];
-          y[a][h] = v;
-        }
-      }
+      Acc Up[r][r];
+      rd.off(j - 1, Up);
+      sub_AtB<r, r, r, Acc>(Up, Gp, A);
+      sub_AtB<r, r, CB, Acc>(Up, hp, y);
     }
     chol<r, Acc>(A);
     Acc Gn[r][r];
-    if (j + 1 < P - 1) {
-#pragma unroll
-      for (int a = 0; a < r; ++a)
-#pragma unroll
-        for (int c = 0; c < r; ++c) Gn[a][c] = S(j + 1, LY::oTB + c * r + a);
-      chol_solve<r, r, Acc>(A, Gn);
-    } else {
-#pragma unroll
-      for (int a = 0; a < r; ++a)
-#pragma unroll
-        for (int c = 0; c < r; ++c) Gn[a][c] = Acc(0);
-    }
+    rd.off(j, Gn);
+    chol_solve<r, r, Acc>(A, Gn);
     chol_solve<r, CB, Acc>(A, y);
 #pragma unroll
     for (int a = 0; a < r; ++a) {
 #pragma unroll
       for (int c = 0; c < r; ++c) {
-        Gb[((size_t)j * r * r + a * r + c) * nK + ki] = Gn[a][c];
+        gb[(size_t)j * r * r + a * r + c] = Gn[a][c];
         Gp[a][c] = Gn[a][c];
       }
 #pragma unroll
       for (int h = 0; h < CB; ++h) {
-        U[((size_t)j * r * CB + a * CB + h) * nK + ki] = y[a][h];
+        out[(size_t)j * r * CB + a * CB + h] = y[a][h];
         hp[a][h] = y[a][h];
       }
     }
   }
-  for (int j = P - 3; j >= 0; --j) {
+  for (int j = n - 2; j >= 0; --j) {
     Acc u[r][CB];
 #pragma unroll
     for (int a = 0; a < r; ++a)
 #pragma unroll
       for (int h = 0; h < CB; ++h) {
-        Acc v = U[((size_t)j * r * CB + a * CB + h) * nK + ki];
+        Acc v = out[(size_t)j * r * CB + a * CB + h];
 #pragma unroll
-        for (int c = 0; c < r; ++c) v -= Gb[((size_t)j * r * r + a * r + c) * nK + ki] * hp[c][h];
+        for (int c = 0; c < r; ++c) v -= gb[(size_t)j * r * r + a * r + c] * hp[c][h];
         u[a][h] = v;
       }
 #pragma unroll
     for (int a = 0; a < r; ++a)
 #pragma unroll
       for (int h = 0; h < CB; ++h) {
-        U[((size_t)j * r * CB + a * CB + h) * nK + ki] = u[a][h];
+        out[(size_t)j * r * CB + a * CB + h] = u[a][h];
         hp[a][h] = u[a][h];
       }
   }
@@ -433,19 +792,18 @@ __global__ __launch_bounds__(kWave) void k_interface(const Acc* __restrict__ sum
 
 // ---------------------------------------------------------------------------
 // k_expand: final solve of every chunk with its separators known, scatter and
-// average.  Block x owns output columns [x*OW, x*OW + OW) of the pass; its
-// 64 lanes are the strips whose 2r+1 columns touch them.
-template <int r, int CB, int R, typename Acc>
-__global__ __launch_bounds__(kWave) void k_expand(
+// average.  Block (x, y) owns pass columns [x*OW, x*OW + OW) and rows of chunks
+// [y*Q, y*Q + Q); its 64 lanes are the strips whose columns touch them.
+template <int r, int CB, int R, int Q, bool S1, typename Acc>
+__global__ __launch_bounds__(kWave* Q) void k_expand(
     const float* __restrict__ X, const float* __restrict__ G, float* __restrict__ Y,
     PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
-    const Acc* __restrict__ U, int OW, int accw, int row_major_out) {
-  using CK = Chunk<r, R>;
-  constexpr int E = CK::E, w = CK::w;
+    const Acc* __restrict__ Us, int OW, int pitch) {
+  using CV = ChunkView<r, R, S1>;
+  constexpr int E = CV::E, w = CV::w;
+  constexpr int TA = Q * R + 2;
   extern __shared__ float smem[];
-  float* acc = smem;                                   // [CB][R][accw]
-  int* cnt = reinterpret_cast<int*>(smem + CB * R * accw);   // [accw]
-  const int lane = threadIdx.x, j = blockIdx.y;
+  const int lane = threadIdx.x % kWave, wq = threadIdx.x / kWave;
   const int b_lo = blockIdx.x * OW, b_hi = min(b_lo + OW, geo.W);
   int ki_lo;
   if (geo.stride == 1) {
@@ -455,48 +813,51 @@ __global__ __launch_bounds__(kWave) void k_expand(
     ki_lo = t <= 0 ? 0 : (t + geo.stride - 1) / geo.stride;
   }
   ki_lo = min(ki_lo, geo.nK - 1);
-  const int colbase = min(r + ki_lo * geo.stride, geo.W - 1 - r) - r;
-  const int ki = ki_lo + lane;
-  const bool active = ki < geo.nK;
-  const int k = active ? min(r + ki * geo.stride, geo.W - 1 - r) : colbase + r;
-  for (int i = lane; i < CB * R * accw; i += kWave) acc[i] = 0.0f;
-  for (int i = lane; i < accw; i += kWave) cnt[i] = 0;
+  const int colbase = centre_of(ki_lo, geo, r) - r;
+  const int j0 = blockIdx.y * Q, j = j0 + wq;
+  const int a_lo = j0 * R;
+  const int TB = S1 ? kWave + 2 * r : tile_width<r>(geo.stride);
+  const int pch = S1 ? CV::PITCH1 : pitch;
+  load_tile<CB>(smem, G, X, geo, c0, a_lo, colbase, TA, TB, pch, threadIdx.x, kWave * Q);
   __syncthreads();
 
-  const float lam = load_lambda(lam_dev, lam_host);
-  float lamS[r + 1];
-#pragma unroll
-  for (int d = 0; d <= r; ++d) lamS[d] = lam * wp.spatial[d];
-  CK ch;
-  ch.a0 = j * R;
-  ch.L = geo.L;
-  ch.sa = geo.sa;
-  ch.sb = geo.sb;
-  ch.base = (long long)ch.a0 * geo.sa + (long long)k * geo.sb;
+  const int ki = ki_lo + lane;
+  const bool active = ki < geo.nK && j < geo.P;
   const bool hasT = j > 0, hasB = j + 1 < geo.P;
-  const float* Xc = X + (long long)c0 * geo.plane;
+  const int k = active ? centre_of(ki, geo, r) : colbase + r;
+  const int rows = max(0, min(R, geo.L - j * R));
 
   Acc Z[E][CB];     // z = D^{-1} L^{-1} f, overwritten by the solution u
   if (active) {
+    const float lam = load_lambda(lam_dev, lam_host);
+    float lamS[r + 1];
+#pragma unroll
+    for (int d = 0; d <= r; ++d) lamS[d] = lam * wp.spatial[d];
+    CV cv;
+    cv.base = smem + (wq * R + 1) * pch + (k - colbase);
+    cv.pitch = pch;
+    cv.plane = TA * pch;
+    cv.a0 = j * R;
+    cv.L = geo.L;
     float lw[E + r][r];
-    chunk_weights<r, R>(ch, G, wp, lamS, lw);
-    auto fval = [&](int m, int c) -> Acc {
-      return ch.ok(m) ? Acc(Xc[(long long)c * geo.plane + ch.off(m)]) : Acc(0);
-    };
+    chunk_weights<r, R, S1>(cv, wp, lamS, lw);
+    auto fval = [&](int m, int c) -> Acc { return cv.ok(m) ? Acc(cv.f(m, c)) : Acc(0); };
+    const int n_sep = geo.P - 1;
+    const Acc* us = Us + (size_t)ki * n_sep * r * CB;
     Acc uT[r][CB], uB[r][CB];
 #pragma unroll
     for (int a = 0; a < r; ++a)
 #pragma unroll
       for (int h = 0; h < CB; ++h) {
-        uT[a][h] = hasT ? U[((size_t)(j - 1) * r * CB + a * CB + h) * geo.nK + ki] : Acc(0);
-        uB[a][h] = hasB ? U[((size_t)j * r * CB + a * CB + h) * geo.nK + ki] : Acc(0);
+        uT[a][h] = hasT ? us[(size_t)(j - 1) * r * CB + a * CB + h] : Acc(0);
+        uB[a][h] = hasB ? us[(size_t)j * r * CB + a * CB + h] : Acc(0);
       }
     Acc Lf[E][r];   // Lf[m][a-1] = L(m+a, m)
     Acc W[r + 1][r + 1];
     Acc Rw[r + 1][CB];
 #pragma unroll
     for (int a = 0; a < r; ++a) {
-      W[a][a] = diag_at<r, R, Acc>(lw, a);
+      W[a][a] = diag_at<r, E, Acc>(lw, a);
 #pragma unroll
       for (int b = 0; b < a; ++b) W[a][b] = -Acc(lw[b + r][a - b - 1]);
 #pragma unroll
@@ -511,7 +872,7 @@ __global__ __launch_bounds__(kWave) void k_expand(
       const int n = m + r;
       bool dummy = true;
       if (hasB && n >= E - r) {
-        // n belongs to the known separator S_j: move its coupling to the RHS.
+        // n belongs to the known separator S_j: its coupling moves to the RHS.
         const int bi = n - (E - r);
 #pragma unroll
         for (int b = 0; b < r; ++b)
@@ -519,7 +880,7 @@ __global__ __launch_bounds__(kWave) void k_expand(
           for (int h = 0; h < CB; ++h) Rw[b][h] += Acc(lw[m + b + r][r - b - 1]) * uB[bi][h];
       } else if (n < E) {
         dummy = false;
-        W[r][r] = diag_at<r, R, Acc>(lw, n);
+        W[r][r] = diag_at<r, E, Acc>(lw, n);
 #pragma unroll
         for (int b = 0; b < r; ++b) W[r][b] = -Acc(lw[m + b + r][r - b - 1]);
 #pragma unroll
@@ -532,7 +893,7 @@ __global__ __launch_bounds__(kWave) void k_expand(
 #pragma unroll
         for (int h = 0; h < CB; ++h) Rw[r][h] = Acc(0);
       }
-      const Acc invD = rcp_exact(W[0][0]);
+      const Acc invD = recip(W[0][0]);
       Acc l[r + 1];
 #pragma unroll
       for (int a = 1; a <= r; ++a) {
@@ -562,33 +923,39 @@ __global__ __launch_bounds__(kWave) void k_expand(
     if (!hasB) {
 #pragma unroll
       for (int m = E - r; m < E; ++m) step(m);
-    }
-    if (hasB) {
+    } else {
 #pragma unroll
-      for (int a = 0; a < r; ++a)
+      for (int a = 0; a < r; ++a) {
 #pragma unroll
         for (int h = 0; h < CB; ++h) Z[E - r + a][h] = uB[a][h];
 #pragma unroll
-      for (int a = 0; a < r; ++a)
-#pragma unroll
         for (int t = 0; t < r; ++t) Lf[E - r + a][t] = Acc(0);
+      }
     }
     // back substitution u_m = z_m - sum_a L(m+a, m) u_{m+a}
 #pragma unroll
     for (int m = E - 1; m >= 0; --m) {
+      if (m < E - r || !hasB) {
 #pragma unroll
-      for (int h = 0; h < CB; ++h) {
-        Acc v = Z[m][h];
+        for (int h = 0; h < CB; ++h) {
+          Acc v = Z[m][h];
 #pragma unroll
-        for (int a = 1; a <= r; ++a)
-          if (m + a < E) v -= Lf[m][a - 1] * Z[m + a][h];
-        Z[m][h] = v;
+          for (int a = 1; a <= r; ++a)
+            if (m + a < E) v -= Lf[m][a - 1] * Z[m + a][h];
+          Z[m][h] = v;
+        }
       }
     }
   }
-
+  __syncthreads();   // all tile reads done: the image planes become accumulators
+  const int nrow = Q * R;
+  for (int p = 1; p <= CB; ++p)
+    for (int idx = threadIdx.x; idx < nrow * TB; idx += kWave * Q) {
+      const int ta = 1 + idx / TB, tb = idx - (ta - 1) * TB;
+      smem[p * TA * pch + ta * pch + tb] = 0.0f;
+    }
+  __syncthreads();
   // Average over the strips covering each pixel, in a fixed order (q = 0..2r).
-  const int rows = min(R, geo.L - ch.a0);
 #pragma unroll
   for (int q = 0; q < w; ++q) {
     if (active) {
@@ -596,65 +963,92 @@ __global__ __launch_bounds__(kWave) void k_expand(
       for (int rho = 0; rho < R; ++rho) {
         if (rho < rows) {
           const int col = ((rho & 1) ? (k + r - q) : (k - r + q)) - colbase;
+          float* cell = smem + TA * pch + (wq * R + 1 + rho) * pch + col;
 #pragma unroll
-          for (int h = 0; h < CB; ++h) acc[(h * R + rho) * accw + col] += float(Z[rho * w + q][h]);
+          for (int h = 0; h < CB; ++h) cell[h * TA * pch] += float(Z[rho * w + q][h]);
         }
       }
-      cnt[k - r + q - colbase] += 1;
     }
     __syncthreads();
   }
   const int ncols = b_hi - b_lo;
-  const int total = rows * ncols;
+  const int arows = max(0, min(nrow, geo.L - a_lo));
   float* Yc = Y + (long long)c0 * geo.plane;
-  for (int idx = lane; idx < total; idx += kWave) {
-    int rho, b;
-    if (row_major_out) {
-      rho = idx % rows;
-      b = b_lo + idx / rows;
-    } else {
-      rho = idx / ncols;
-      b = b_lo + idx % ncols;
-    }
-    const float inv = 1.0f / float(cnt[b - colbase]);
-    const long long o = (long long)(ch.a0 + rho) * geo.sa + (long long)b * geo.sb;
+  if (geo.sb == 1) {   // column pass: b contiguous
+    for (int idx = threadIdx.x; idx < arows * ncols; idx += kWave * Q) {
+      const int tr = idx / ncols, bc = idx - tr * ncols;
+      const int b = b_lo + bc, a = a_lo + tr;
+      const float inv = 1.0f / float(cover_count(b, geo, r));
+      const float* cell = smem + TA * pch + (tr + 1) * pch + (b - colbase);
 #pragma unroll
-    for (int h = 0; h < CB; ++h)
-      Yc[(long long)h * geo.plane + o] = acc[(h * R + rho) * accw + (b - colbase)] * inv;
+      for (int h = 0; h < CB; ++h)
+        Yc[(long long)h * geo.plane + (long long)a * geo.sa + b] = cell[h * TA * pch] * inv;
+    }
+  } else {             // row pass: a contiguous
+    for (int idx = threadIdx.x; idx < arows * ncols; idx += kWave * Q) {
+      const int bc = idx / arows, tr = idx - bc * arows;
+      const int b = b_lo + bc, a = a_lo + tr;
+      const float inv = 1.0f / float(cover_count(b, geo, r));
+      const float* cell = smem + TA * pch + (tr + 1) * pch + (b - colbase);
+#pragma unroll
+      for (int h = 0; h < CB; ++h)
+        Yc[(long long)h * geo.plane + a + (long long)b * geo.sb] = cell[h * TA * pch] * inv;
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Rows per chunk: the expand kernel keeps (r + CB) values per element in
-// registers, so R shrinks as r and the channel block grow.
-constexpr int rows_table(int r, int cb, int fp64) {
-  return fp64 ? (r == 1 ? (cb == 1 ? 8 : 4) : (r == 2 ? (cb == 1 ? 4 : 2) : 2))
-              : (r == 1 ? (cb == 1 ? 16 : 8)
-                        : (r == 2 ? (cb == 1 ? 6 : 4) : (r == 3 ? (cb == 1 ? 4 : 2) : 2)));
+// Tuning table.  R: rows per chunk (the expand kernel keeps r + CB values per
+// element in registers); Q: chunks per block; MM: the wave interface solver's
+// maximum separators per lane (0 = always use the serial solver).
+struct Tune {
+  int R, Q, MM;
+};
+constexpr Tune tune_of(int r, int cb, int fp64) {
+  return fp64 ? (r == 1 ? Tune{cb == 1 ? 8 : 4, 4, 4}
+                        : (r == 2 ? Tune{cb == 1 ? 4 : 2, 4, 4} : Tune{2, 2, 0}))
+              : (r == 1 ? Tune{cb == 1 ? 16 : 8, 4, 4}
+                        : (r == 2 ? Tune{cb == 1 ? 6 : 4, 4, 8}
+                                  : (r == 3 ? Tune{cb == 1 ? 4 : 2, 2, 0} : Tune{2, 2, 0})));
 }
 
-template <int r, int CB, int fp64>
+template <int r, int CB, int fp64, bool S1>
 hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const PassGeom& geo,
                        const PassPlan& pl, const WeightParams& wp, const float* lam_dev,
                        float lam_host, void* iface, hipStream_t stream, int stages) {
   using Acc = typename std::conditional<fp64 != 0, double, float>::type;
-  constexpr int R = rows_table(r, CB, fp64);
+  constexpr Tune T = tune_of(r, CB, fp64);
+  // Tiles of strided passes are (kWave-1)*stride + 2r + 1 columns wide: one
+  // chunk per block keeps them within 64 KB of LDS.
+  constexpr int R = T.R, Q = S1 ? T.Q : 1;
+  using LY = IfaceLayout<r, CB>;
   Acc* sum = reinterpret_cast<Acc*>(iface);
-  Acc* gb = sum + pl.sum_elems;
-  Acc* u = gb + pl.g_elems;
-  const int gx = (geo.nK + kWave - 1) / kWave;
-  if (geo.P > 1 && (stages & kStageReduce))
-    hipLaunchKernelGGL((k_reduce<r, CB, R, Acc>), dim3(gx, geo.P), dim3(kWave), 0, stream, x, g,
-                       geo, wp, lam_dev, lam_host, c0, sum);
-  if (geo.P > 1 && (stages & kStageInterface))
-    hipLaunchKernelGGL((k_interface<r, CB, Acc>), dim3(gx), dim3(kWave), 0, stream,
-                       (const Acc*)sum, gb, u, geo.nK, geo.P);
+  Acc* us = sum + pl.sum_elems;
+  Acc* gb = us + pl.u_elems;
+  const size_t tile = sizeof(float) * (size_t)(CB + 1) * (Q * R + 2) * pl.pitch;
+  const size_t stage_out = sizeof(Acc) * (size_t)kWave * Q * LY::F;
+  const int gy = (geo.P + Q - 1) / Q;
+  if (geo.P > 1 && (stages & kStageReduce)) {
+    const int gx = (geo.nK + kWave - 1) / kWave;
+    hipLaunchKernelGGL((k_reduce<r, CB, R, Q, S1, Acc>), dim3(gx, gy), dim3(kWave * Q),
+                       std::max(tile, stage_out), stream, x, g, geo, wp, lam_dev, lam_host, c0,
+                       pl.pitch, sum);
+  }
+  if (geo.P > 1 && (stages & kStageInterface)) {
+    if (T.MM > 0 && pl.iface_m > 0 && pl.iface_m <= T.MM) {
+      constexpr int MM = T.MM > 0 ? T.MM : 1;
+      hipLaunchKernelGGL((k_interface_pcr<r, CB, MM, Acc>), dim3(geo.nK), dim3(kWave), 0,
+                         stream, (const Acc*)sum, us, geo.nK, geo.P, pl.iface_m);
+    } else {
+      hipLaunchKernelGGL((k_interface_serial<r, CB, Acc>), dim3((geo.nK + kWave - 1) / kWave),
+                         dim3(kWave), 0, stream, (const Acc*)sum, us, gb, geo.nK, geo.P);
+    }
+  }
   if (stages & kStageExpand) {
     const int ex = (geo.W + pl.OW - 1) / pl.OW;
-    const size_t lds = sizeof(float) * ((size_t)CB * R * pl.accw + pl.accw);
-    hipLaunchKernelGGL((k_expand<r, CB, R, Acc>), dim3(ex, geo.P), dim3(kWave), lds, stream, x,
-                       g, y, geo, wp, lam_dev, lam_host, c0, (const Acc*)u, pl.OW, pl.accw,
-                       geo.sa == 1 ? 1 : 0);
+    hipLaunchKernelGGL((k_expand<r, CB, R, Q, S1, Acc>), dim3(ex, gy), dim3(kWave * Q), tile,
+                       stream, x, g, y, geo, wp, lam_dev, lam_host, c0, (const Acc*)us, pl.OW,
+                       pl.pitch);
   }
   return hipGetLastError();
 }
@@ -664,8 +1058,12 @@ hipError_t launch_prec(int fp64, const float* x, const float* g, float* y, int c
                        const PassGeom& geo, const PassPlan& pl, const WeightParams& wp,
                        const float* lam_dev, float lam_host, void* iface, hipStream_t s,
                        int st) {
-  return fp64 ? launch_impl<r, CB, 1>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st)
-              : launch_impl<r, CB, 0>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
+  const bool s1 = geo.stride == 1;
+  if (fp64)
+    return s1 ? launch_impl<r, CB, 1, true>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st)
+              : launch_impl<r, CB, 1, false>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
+  return s1 ? launch_impl<r, CB, 0, true>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st)
+            : launch_impl<r, CB, 0, false>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
 }
 
 template <int r>
@@ -679,33 +1077,38 @@ hipError_t launch_cb(int cb, int fp64, const float* x, const float* g, float* y,
 
 }  // namespace
 
-int rows_per_chunk(int r, int cb, int fp64) { return rows_table(r, cb, fp64); }
-
 int strip_count(int W, int r, int stride) {
   if (r < 1 || stride < 1 || W < 2 * r + 1) return 0;
-  const int span = W - 1 - 2 * r;          // last regular centre offset
+  const int span = W - 1 - 2 * r;          // offset of the last regular centre
   const int regular = span / stride + 1;
   return regular + ((span % stride) != 0 ? 1 : 0);
 }
 
 PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64) {
   PassPlan pl{};
-  pl.R = rows_table(r, cb, fp64);
+  const Tune T = tune_of(r, cb, fp64);
+  pl.R = T.R;
+  pl.Q = stride == 1 ? T.Q : 1;
   pl.P = (L + pl.R - 1) / pl.R;
   pl.nK = strip_count(W, r, stride);
   pl.OW = stride == 1 ? kWave - 2 * r : (kWave - 2) * stride - 2 * r;
-  pl.accw = stride == 1 ? kWave + 2 * r : (kWave - 1) * stride + 2 * r + 1;
+  pl.TB = stride == 1 ? kWave + 2 * r : (kWave - 1) * stride + 2 * r + 1;
+  pl.pitch = pl.TB | 1;
+  const int n = pl.P - 1;
+  const int m = (n + kWave - 1) / kWave;
+  pl.iface_m = (T.MM > 0 && m <= T.MM) ? std::max(m, 1) : 0;
   const int T2 = r * (r + 1) / 2;
   const int F = 2 * T2 + 2 * r * cb + r * r;
   pl.acc_bytes = fp64 ? 8 : 4;
   pl.sum_elems = (size_t)pl.P * F * pl.nK;
-  pl.g_elems = (size_t)std::max(pl.P - 1, 1) * r * r * pl.nK;
-  pl.u_elems = (size_t)std::max(pl.P - 1, 1) * r * cb * pl.nK;
+  pl.u_elems = (size_t)std::max(n, 1) * r * cb * pl.nK;
   return pl;
 }
 
 size_t interface_bytes(const PassPlan& pl) {
-  return (pl.sum_elems + pl.g_elems + pl.u_elems) * (size_t)pl.acc_bytes + 256;
+  // sum, separator solutions, and (serial solver) the G_j blocks
+  const size_t g_elems = (size_t)std::max(pl.P - 1, 1) * kMaxR * kMaxR * pl.nK;
+  return (pl.sum_elems + pl.u_elems + g_elems) * (size_t)pl.acc_bytes + 256;
 }
 
 hipError_t launch_pass(int r, int cb, int fp64, const float* x, const float* g, float* y,
