@@ -49,7 +49,7 @@ extern "C" {
 typedef enum {
   SGWLS_OK = 0,
   SGWLS_E_ARG = 1,          /* a parameter is out of range, or a required pointer is NULL */
-  SGWLS_E_SHAPE = 2,        /* C < 1, or M or N smaller than 2r+1, or too large */
+  SGWLS_E_SHAPE = 2,        /* C < 1, M or N < 2r+1 or > 65536, or C*M*N >= 2^31 */
   SGWLS_E_WORKSPACE = 3,    /* the workspace is NULL or smaller than required */
   SGWLS_E_UNSUPPORTED = 4,  /* a valid request this build does not implement (e.g. r > 4) */
   SGWLS_E_HIP = 5           /* a HIP runtime call or kernel launch failed */

@@ -130,7 +130,8 @@ sgwls_status sgwls_validate(int C, int M, int N, const sgwls_params* p) {
   }
   if (p->prec != SGWLS_P_FP32 && p->prec != SGWLS_P_FP64_PIVOT) return SGWLS_E_ARG;
   if (C < 1 || M < 2 * p->r + 1 || N < 2 * p->r + 1) return SGWLS_E_SHAPE;
-  if (M > kMaxSide || N > kMaxSide || (long long)C * M * N > (1LL << 40)) return SGWLS_E_SHAPE;
+  // kernels address pixels with 32-bit element offsets
+  if (M > kMaxSide || N > kMaxSide || (long long)C * M * N > 0x7fffffffLL) return SGWLS_E_SHAPE;
   if (p->r > kMaxR) return SGWLS_E_UNSUPPORTED;
   return SGWLS_OK;
 }

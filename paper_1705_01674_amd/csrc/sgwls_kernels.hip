@@ -53,8 +53,9 @@ namespace {
 // Range factor of Eq. (2); the spatial factor is folded into lambda*S(d).
 // exp: 2^(-dG^2 * log2(e)/(2 sigma_r^2)); frac: 1/(|dG|^alpha_r + eps) with
 // |dG|^alpha_r = 2^(alpha_r log2|dG|).  Hardware exp2/log2/rcp (about 1 ulp).
+template <int KIND>
 DEV float range_weight(float dg, const WeightParams& wp) {
-  if (wp.kind == 0) return __builtin_amdgcn_exp2f(-(dg * dg) * wp.range_c2);
+  if (KIND == 0) return __builtin_amdgcn_exp2f(-(dg * dg) * wp.range_c2);
   const float ad = fabsf(dg);
   float pw;
   if (wp.alpha_r == 0.0f) pw = 1.0f;
@@ -221,35 +222,58 @@ DEV int cover_count(int b, const PassGeom& geo, int r) {
   return c;
 }
 
+// Guidance value of tile rows outside the subsystem (see load_tile).
+constexpr float kSentinel = 1.0e30f;
+
 // ---------------------------------------------------------------------------
 // LDS tile of a block: rows a in [a_lo - 1, a_lo + Q*R + 1) of the pass, columns
 // b in [colbase, colbase + TB), planes: guidance then CB image channels.  Rows
-// or columns outside the image hold 0 (never used as pixels).
-template <int CB>
+// or columns outside the image hold 0 (never used as pixels).  Loads are
+// issued in batches of BATCH per thread before any LDS store, so one memory
+// latency covers the batch; consecutive threads read consecutive addresses
+// (b in the column pass, a in the row pass).
+template <int CB, int TA, int NT, int BATCH>
 DEV void load_tile(float* lds, const float* __restrict__ G, const float* __restrict__ X,
-                   const PassGeom& geo, int c0, int a_lo, int colbase, int TA, int TB,
-                   int pitch, int tid, int nthr) {
+                   const PassGeom& geo, int c0, int a_lo, int colbase, int TB, int pitch,
+                   int tid) {
+  const int total = TA * TB;
+  const bool colpass = geo.sb == 1;
+  const float* xc = X + c0 * (int)geo.plane;
+  for (int base = 0; base < total; base += NT * BATCH) {
+    float v[CB + 1][BATCH];
+    int dst[BATCH];
 #pragma unroll
-  for (int p = 0; p <= CB; ++p) {
-    const float* src = p == 0 ? G : X + (long long)(c0 + p - 1) * geo.plane;
-    float* dst = lds + p * TA * pitch;
-    if (geo.sb == 1) {   // column pass: b is contiguous in memory
-      for (int idx = tid; idx < TA * TB; idx += nthr) {
-        const int ta = idx / TB, tb = idx - ta * TB;
-        const int a = a_lo - 1 + ta, b = colbase + tb;
-        float v = 0.0f;
-        if (a >= 0 && a < geo.L && b < geo.W) v = src[(long long)a * geo.sa + b];
-        dst[ta * pitch + tb] = v;
+    for (int u = 0; u < BATCH; ++u) {
+      const int idx = base + u * NT + tid;
+      int ta, tb;
+      if (colpass) {
+        ta = idx / TB;
+        tb = idx - ta * TB;
+      } else {
+        tb = idx / TA;
+        ta = idx - tb * TA;
       }
-    } else {             // row pass: a is contiguous in memory
-      for (int idx = tid; idx < TA * TB; idx += nthr) {
-        const int tb = idx / TA, ta = idx - tb * TA;
-        const int a = a_lo - 1 + ta, b = colbase + tb;
-        float v = 0.0f;
-        if (a >= 0 && a < geo.L && b < geo.W) v = src[a + (long long)b * geo.sb];
-        dst[ta * pitch + tb] = v;
+      const int a = a_lo - 1 + ta, b = colbase + tb;
+      const bool rowok = a >= 0 && a < geo.L;
+      const bool in = idx < total && rowok && b < geo.W;
+      const int o = in ? (colpass ? a * (int)geo.sa + b : a + b * (int)geo.sb) : 0;
+      dst[u] = idx < total ? ta * pitch + tb : -1;
+      const float gv = G[o];
+      // Rows outside the subsystem hold a sentinel guidance value: every edge
+      // to them gets weight 0 (exp underflows, frac is below 1e-30).
+      v[0][u] = in ? gv : (rowok ? 0.0f : kSentinel);
+#pragma unroll
+      for (int p = 1; p <= CB; ++p) {
+        const float xv = xc[(p - 1) * (int)geo.plane + o];
+        v[p][u] = in ? xv : 0.0f;
       }
     }
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u)
+      if (dst[u] >= 0) {
+#pragma unroll
+        for (int p = 0; p <= CB; ++p) lds[p * TA * pitch + dst[u]] = v[p][u];
+      }
   }
 }
 
@@ -274,9 +298,10 @@ struct ChunkView {
   DEV float f(int m, int c) const { return base[(c + 1) * plane + off(m)]; }
 };
 
-// lambda * w(m, m+d) for local m in [-r, E) and d = 1..r, at lw[m + r][d - 1];
-// zero where either end lies outside the subsystem.
-template <int r, int R, bool S1>
+// lambda * w(m, m+d) for local m in [-r, E) and d = 1..r, at lw[m + r][d - 1].
+// Ends outside the subsystem read the sentinel guidance, so their edges
+// weigh 0 and the padding elements are decoupled from the subsystem.
+template <int r, int R, bool S1, int KIND>
 DEV void chunk_weights(const ChunkView<r, R, S1>& cv, const WeightParams& wp,
                        const float (&lamS)[r + 1],
                        float (&lw)[ChunkView<r, R, S1>::E + r][r]) {
@@ -288,9 +313,7 @@ DEV void chunk_weights(const ChunkView<r, R, S1>& cv, const WeightParams& wp,
   for (int m = -r; m < E; ++m) {
 #pragma unroll
     for (int d = 1; d <= r; ++d) {
-      lw[m + r][d - 1] = (cv.ok(m) && cv.ok(m + d))
-                             ? lamS[d] * range_weight(gv[m + r] - gv[m + d + r], wp)
-                             : 0.0f;
+      lw[m + r][d - 1] = lamS[d] * range_weight<KIND>(gv[m + r] - gv[m + d + r], wp);
     }
   }
 }
@@ -307,9 +330,15 @@ DEV Acc diag_at(const float (&lw)[E + r][r], int m) {
 template <int r>
 DEV int tile_width(int stride) { return stride == 1 ? kWave + 2 * r : (kWave - 1) * stride + 2 * r + 1; }
 
+// Loads per thread per batch: the whole stride-1 tile in one batch, else 8.
+template <int r, int TA>
+constexpr int tile_batch(int nthr, bool s1) {
+  return s1 ? (TA * (kWave + 2 * r) + nthr - 1) / nthr : 8;
+}
+
 // ---------------------------------------------------------------------------
 // k_reduce: Schur complement contributions of every chunk of 64 strips.
-template <int r, int CB, int R, int Q, bool S1, typename Acc>
+template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc>
 __global__ __launch_bounds__(kWave* Q) void k_reduce(
     const float* __restrict__ X, const float* __restrict__ G, PassGeom geo, WeightParams wp,
     const float* __restrict__ lam_dev, float lam_host, int c0, int pitch,
@@ -319,14 +348,16 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce(
   constexpr int E = CV::E;
   constexpr int TA = Q * R + 2;
   extern __shared__ float smem[];
-  const int lane = threadIdx.x % kWave, wq = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int ki_lo = blockIdx.x * kWave;
   const int j0 = blockIdx.y * Q, j = j0 + wq;
   const int a_lo = j0 * R;
   const int colbase = centre_of(ki_lo, geo, r) - r;
   const int TB = S1 ? kWave + 2 * r : tile_width<r>(geo.stride);
   const int pch = S1 ? CV::PITCH1 : pitch;
-  load_tile<CB>(smem, G, X, geo, c0, a_lo, colbase, TA, TB, pch, threadIdx.x, kWave * Q);
+  load_tile<CB, TA, kWave * Q, tile_batch<r, Q * R + 2>(kWave * Q, S1)>(
+      smem, G, X, geo, c0, a_lo, colbase, TB, pch, threadIdx.x);
   __syncthreads();
 
   const int ki = ki_lo + lane;
@@ -349,8 +380,8 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce(
     cv.a0 = j * R;
     cv.L = geo.L;
     float lw[E + r][r];
-    chunk_weights<r, R, S1>(cv, wp, lamS, lw);
-    auto fval = [&](int m, int c) -> Acc { return cv.ok(m) ? Acc(cv.f(m, c)) : Acc(0); };
+    chunk_weights<r, R, S1, KIND>(cv, wp, lamS, lw);
+    auto fval = [&](int m, int c) -> Acc { return Acc(cv.f(m, c)); };   // 0 outside
 #pragma unroll
     for (int a = 0; a < r; ++a) {
 #pragma unroll
@@ -794,7 +825,7 @@ __global__ __launch_bounds__(kWave) void k_interface_serial(const Acc* __restric
 // k_expand: final solve of every chunk with its separators known, scatter and
 // average.  Block (x, y) owns pass columns [x*OW, x*OW + OW) and rows of chunks
 // [y*Q, y*Q + Q); its 64 lanes are the strips whose columns touch them.
-template <int r, int CB, int R, int Q, bool S1, typename Acc>
+template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc>
 __global__ __launch_bounds__(kWave* Q) void k_expand(
     const float* __restrict__ X, const float* __restrict__ G, float* __restrict__ Y,
     PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
@@ -803,7 +834,8 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
   constexpr int E = CV::E, w = CV::w;
   constexpr int TA = Q * R + 2;
   extern __shared__ float smem[];
-  const int lane = threadIdx.x % kWave, wq = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int b_lo = blockIdx.x * OW, b_hi = min(b_lo + OW, geo.W);
   int ki_lo;
   if (geo.stride == 1) {
@@ -818,7 +850,8 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
   const int a_lo = j0 * R;
   const int TB = S1 ? kWave + 2 * r : tile_width<r>(geo.stride);
   const int pch = S1 ? CV::PITCH1 : pitch;
-  load_tile<CB>(smem, G, X, geo, c0, a_lo, colbase, TA, TB, pch, threadIdx.x, kWave * Q);
+  load_tile<CB, TA, kWave * Q, tile_batch<r, Q * R + 2>(kWave * Q, S1)>(
+      smem, G, X, geo, c0, a_lo, colbase, TB, pch, threadIdx.x);
   __syncthreads();
 
   const int ki = ki_lo + lane;
@@ -840,8 +873,8 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
     cv.a0 = j * R;
     cv.L = geo.L;
     float lw[E + r][r];
-    chunk_weights<r, R, S1>(cv, wp, lamS, lw);
-    auto fval = [&](int m, int c) -> Acc { return cv.ok(m) ? Acc(cv.f(m, c)) : Acc(0); };
+    chunk_weights<r, R, S1, KIND>(cv, wp, lamS, lw);
+    auto fval = [&](int m, int c) -> Acc { return Acc(cv.f(m, c)); };   // 0 outside
     const int n_sep = geo.P - 1;
     const Acc* us = Us + (size_t)ki * n_sep * r * CB;
     Acc uT[r][CB], uB[r][CB];
@@ -947,52 +980,105 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
       }
     }
   }
-  __syncthreads();   // all tile reads done: the image planes become accumulators
   const int nrow = Q * R;
-  for (int p = 1; p <= CB; ++p)
-    for (int idx = threadIdx.x; idx < nrow * TB; idx += kWave * Q) {
-      const int ta = 1 + idx / TB, tb = idx - (ta - 1) * TB;
-      smem[p * TA * pch + ta * pch + tb] = 0.0f;
+  const int arows = max(0, min(nrow, geo.L - a_lo));
+  float* Yc = Y + c0 * (int)geo.plane;
+  if constexpr (S1) {
+    // Lane l outputs column b = colbase + l.  The strips covering it are the
+    // lanes l-2r..l (centres b+r..b-r); lane l-t holds column b at row-vector
+    // position t on even rows and 2r-t on odd rows.  Lanes without a strip
+    // contribute 0.  Sums run t = 0..2r in a fixed order.
+    if (!active) {
+#pragma unroll
+      for (int m = 0; m < E; ++m)
+#pragma unroll
+        for (int h = 0; h < CB; ++h) Z[m][h] = Acc(0);
     }
-  __syncthreads();
-  // Average over the strips covering each pixel, in a fixed order (q = 0..2r).
+    const int b = colbase + lane;
+    const bool own = b >= b_lo && b < b_hi && j < geo.P;
+    const int cnt = min(geo.W - 1 - r, b + r) - max(r, b - r) + 1;
+    const float inv = __builtin_amdgcn_rcpf(float(max(cnt, 1)));
+    float out[R][CB];
 #pragma unroll
-  for (int q = 0; q < w; ++q) {
-    if (active) {
+    for (int rho = 0; rho < R; ++rho)
 #pragma unroll
-      for (int rho = 0; rho < R; ++rho) {
-        if (rho < rows) {
-          const int col = ((rho & 1) ? (k + r - q) : (k - r + q)) - colbase;
-          float* cell = smem + TA * pch + (wq * R + 1 + rho) * pch + col;
+      for (int h = 0; h < CB; ++h) {
+        float acc = float(Z[rho * w + ((rho & 1) ? 2 * r : 0)][h]);
 #pragma unroll
-          for (int h = 0; h < CB; ++h) cell[h * TA * pch] += float(Z[rho * w + q][h]);
+        for (int t = 1; t <= 2 * r; ++t) {
+          const float v = __shfl_up(float(Z[rho * w + ((rho & 1) ? 2 * r - t : t)][h]), t, kWave);
+          acc += lane >= t ? v : 0.0f;
         }
+        out[rho][h] = acc * inv;
+      }
+    if (geo.sb == 1) {   // column pass: lanes write consecutive columns of each row
+      if (own) {
+#pragma unroll
+        for (int rho = 0; rho < R; ++rho)
+          if (rho < rows)
+#pragma unroll
+            for (int h = 0; h < CB; ++h)
+              Yc[h * (int)geo.plane + (j * R + rho) * (int)geo.sa + b] = out[rho][h];
+      }
+    } else {             // row pass: transpose through the (consumed) image planes
+      if (own) {
+#pragma unroll
+        for (int rho = 0; rho < R; ++rho)
+#pragma unroll
+          for (int h = 0; h < CB; ++h)
+            smem[(h + 1) * TA * pch + (wq * R + 1 + rho) * pch + lane] = out[rho][h];
+      }
+      __syncthreads();
+      const int ncols = b_hi - b_lo;
+      for (int idx = threadIdx.x; idx < arows * ncols; idx += kWave * Q) {
+        const int bc = idx / arows, tr = idx - bc * arows;
+        const int bb = b_lo + bc, a = a_lo + tr;
+        const float* cell = smem + TA * pch + (tr + 1) * pch + (bb - colbase);
+#pragma unroll
+        for (int h = 0; h < CB; ++h)
+          Yc[h * (int)geo.plane + a + bb * (int)geo.sb] = cell[h * TA * pch];
       }
     }
+  } else {
+    __syncthreads();   // all tile reads done: the image planes become accumulators
+    for (int p = 1; p <= CB; ++p)
+      for (int idx = threadIdx.x; idx < nrow * TB; idx += kWave * Q) {
+        const int ta = 1 + idx / TB, tb = idx - (ta - 1) * TB;
+        smem[p * TA * pch + ta * pch + tb] = 0.0f;
+      }
     __syncthreads();
-  }
-  const int ncols = b_hi - b_lo;
-  const int arows = max(0, min(nrow, geo.L - a_lo));
-  float* Yc = Y + (long long)c0 * geo.plane;
-  if (geo.sb == 1) {   // column pass: b contiguous
-    for (int idx = threadIdx.x; idx < arows * ncols; idx += kWave * Q) {
-      const int tr = idx / ncols, bc = idx - tr * ncols;
-      const int b = b_lo + bc, a = a_lo + tr;
-      const float inv = 1.0f / float(cover_count(b, geo, r));
-      const float* cell = smem + TA * pch + (tr + 1) * pch + (b - colbase);
+    // Average over the strips covering each pixel, in a fixed order (q = 0..2r).
 #pragma unroll
-      for (int h = 0; h < CB; ++h)
-        Yc[(long long)h * geo.plane + (long long)a * geo.sa + b] = cell[h * TA * pch] * inv;
+    for (int q = 0; q < w; ++q) {
+      if (active) {
+#pragma unroll
+        for (int rho = 0; rho < R; ++rho) {
+          if (rho < rows) {
+            const int col = ((rho & 1) ? (k + r - q) : (k - r + q)) - colbase;
+            float* cell = smem + TA * pch + (wq * R + 1 + rho) * pch + col;
+#pragma unroll
+            for (int h = 0; h < CB; ++h) cell[h * TA * pch] += float(Z[rho * w + q][h]);
+          }
+        }
+      }
+      __syncthreads();
     }
-  } else {             // row pass: a contiguous
+    const int ncols = b_hi - b_lo;
     for (int idx = threadIdx.x; idx < arows * ncols; idx += kWave * Q) {
-      const int bc = idx / arows, tr = idx - bc * arows;
-      const int b = b_lo + bc, a = a_lo + tr;
-      const float inv = 1.0f / float(cover_count(b, geo, r));
-      const float* cell = smem + TA * pch + (tr + 1) * pch + (b - colbase);
+      int tr, bc;
+      if (geo.sb == 1) {
+        tr = idx / ncols;
+        bc = idx - tr * ncols;
+      } else {
+        bc = idx / arows;
+        tr = idx - bc * arows;
+      }
+      const int bb = b_lo + bc, a = a_lo + tr;
+      const float inv = 1.0f / float(cover_count(bb, geo, r));
+      const float* cell = smem + TA * pch + (tr + 1) * pch + (bb - colbase);
+      const int o = geo.sb == 1 ? a * (int)geo.sa + bb : a + bb * (int)geo.sb;
 #pragma unroll
-      for (int h = 0; h < CB; ++h)
-        Yc[(long long)h * geo.plane + a + (long long)b * geo.sb] = cell[h * TA * pch] * inv;
+      for (int h = 0; h < CB; ++h) Yc[h * (int)geo.plane + o] = cell[h * TA * pch] * inv;
     }
   }
 }
@@ -1012,7 +1098,7 @@ constexpr Tune tune_of(int r, int cb, int fp64) {
                                   : (r == 3 ? Tune{cb == 1 ? 4 : 2, 2, 0} : Tune{2, 2, 0})));
 }
 
-template <int r, int CB, int fp64, bool S1>
+template <int r, int CB, int fp64, bool S1, int KIND>
 hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const PassGeom& geo,
                        const PassPlan& pl, const WeightParams& wp, const float* lam_dev,
                        float lam_host, void* iface, hipStream_t stream, int stages) {
@@ -1030,7 +1116,7 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
   const int gy = (geo.P + Q - 1) / Q;
   if (geo.P > 1 && (stages & kStageReduce)) {
     const int gx = (geo.nK + kWave - 1) / kWave;
-    hipLaunchKernelGGL((k_reduce<r, CB, R, Q, S1, Acc>), dim3(gx, gy), dim3(kWave * Q),
+    hipLaunchKernelGGL((k_reduce<r, CB, R, Q, S1, KIND, Acc>), dim3(gx, gy), dim3(kWave * Q),
                        std::max(tile, stage_out), stream, x, g, geo, wp, lam_dev, lam_host, c0,
                        pl.pitch, sum);
   }
@@ -1046,11 +1132,20 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
   }
   if (stages & kStageExpand) {
     const int ex = (geo.W + pl.OW - 1) / pl.OW;
-    hipLaunchKernelGGL((k_expand<r, CB, R, Q, S1, Acc>), dim3(ex, gy), dim3(kWave * Q), tile,
+    hipLaunchKernelGGL((k_expand<r, CB, R, Q, S1, KIND, Acc>), dim3(ex, gy), dim3(kWave * Q), tile,
                        stream, x, g, y, geo, wp, lam_dev, lam_host, c0, (const Acc*)us, pl.OW,
                        pl.pitch);
   }
   return hipGetLastError();
+}
+
+template <int r, int CB, int fp64, bool S1>
+hipError_t launch_kind(const float* x, const float* g, float* y, int c0, const PassGeom& geo,
+                       const PassPlan& pl, const WeightParams& wp, const float* lam_dev,
+                       float lam_host, void* iface, hipStream_t s, int st) {
+  return wp.kind == 0
+             ? launch_impl<r, CB, fp64, S1, 0>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st)
+             : launch_impl<r, CB, fp64, S1, 1>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
 }
 
 template <int r, int CB>
@@ -1060,10 +1155,10 @@ hipError_t launch_prec(int fp64, const float* x, const float* g, float* y, int c
                        int st) {
   const bool s1 = geo.stride == 1;
   if (fp64)
-    return s1 ? launch_impl<r, CB, 1, true>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st)
-              : launch_impl<r, CB, 1, false>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
-  return s1 ? launch_impl<r, CB, 0, true>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st)
-            : launch_impl<r, CB, 0, false>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
+    return s1 ? launch_kind<r, CB, 1, true>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st)
+              : launch_kind<r, CB, 1, false>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
+  return s1 ? launch_kind<r, CB, 0, true>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st)
+            : launch_kind<r, CB, 0, false>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
 }
 
 template <int r>

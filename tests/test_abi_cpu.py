@@ -56,7 +56,7 @@ def test_validate_parameters(nat, kw, code):
 
 
 @pytest.mark.parametrize("C,M,N,code", [(0, 64, 64, 2), (3, 2, 64, 2), (3, 64, 2, 2), (1, 3, 3, 0),
-                                        (1, 70000, 8, 2), (5, 9, 11, 0)])
+                                        (1, 70000, 8, 2), (5, 9, 11, 0), (600, 60000, 60000, 2)])
 def test_validate_shapes(nat, C, M, N, code):
     assert nat.lib.sgwls_validate(C, M, N, ctypes.byref(P(nat))) == code
 
