@@ -76,6 +76,9 @@ def main():
     u = torch.empty_like(f)
     ws = torch.empty(ops.workspace_bytes(C, M, N, p), dtype=torch.uint8, device=dev)
 
+    # kernel variants chosen by the autotuner for this shape
+    tuned = ops.autotune(f, g, p, reps=20)
+
     def step():
         ops.sgwls_filter(f, g, p, out=u, workspace=ws)
 
@@ -153,7 +156,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "M": M, "N": N, "C": C, "r": p.r, "iters": p.iters,
                    "stride": p.stride, "lambda": p.lam, "weight": p.kind,
-                   "sigma_s": float(p.r), "sigma_r": p.sigma_r},
+                   "sigma_s": float(p.r), "sigma_r": p.sigma_r,
+                   "variants": {f"{'col' if d == 0 else 'row'}_c{cb}": v
+                                for (d, cb), v in sorted(tuned.items())}},
         "roofline": {"bound": "hbm", "kernel": dom,
                      "achieved": round(achieved, 1) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -143,6 +143,51 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u,
                           const float* lambda_dev, float* saved,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Kernel variants and autotuning (not in the paper) ----
+ * Stride-1 passes can run several compiled kernel variants that differ in
+ * how a subsystem is cut into chunks (rows per chunk) and how many chunks
+ * one workgroup processes; all variants compute the same result up to
+ * float rounding.  A process-wide tuning table maps (radius, channel block,
+ * precision, weight kind, direction, size bucket) to a variant; absent
+ * entries use variant 0.  The size bucket is round(2 log2(L*W)) of the
+ * pass (L = rows along the pass, W = extent across).  The table is guarded
+ * by a mutex; concurrent filter calls read it. */
+
+/* Number of compiled variants for radius r, channel block 1 or 3 and
+ * precision prec (0 if the triple is invalid). */
+int sgwls_variant_count(int r, int channel_block, int prec);
+
+/* Set the variant used for stride-1 passes of this direction, channel block
+ * width (1 or 3), image size and parameters.  SGWLS_E_ARG for an unknown
+ * variant. */
+sgwls_status sgwls_tune_pin(int direction, int channel_block, int M, int N,
+                            const sgwls_params* p, int variant);
+
+/* The variant such a pass uses now (-1 for invalid arguments). */
+int sgwls_tune_query(int direction, int channel_block, int M, int N, const sgwls_params* p);
+
+/* Forget every tuning entry / number of entries. */
+void sgwls_tune_clear(void);
+int sgwls_tune_size(void);
+
+/* Time every variant of both pass directions on the given image (each
+ * channel block width present in C), `reps` launches each with HIP events
+ * on `stream`, and store the fastest in the tuning table.  Synchronises the
+ * stream.  x, g, y as for sgwls_pass (y is overwritten); ws of
+ * sgwls_workspace_bytes(C, M, N, p) bytes.  chosen (nullable, 4 ints)
+ * receives the variant per (direction 0/1) x (channel block 3/1), -1 where
+ * nothing was tuned.  Strided passes have nothing to tune (SGWLS_OK). */
+sgwls_status sgwls_autotune(const float* x, const float* g, float* y, int C, int M, int N,
+                            const sgwls_params* p, void* ws, size_t ws_bytes, void* stream,
+                            int reps, int* chosen);
+
+/* Persist / restore the tuning table as text, tagged with the library
+ * version and the caller's device architecture name (e.g. "gfx950").  Load
+ * rejects (SGWLS_E_ARG, table unchanged) a file with another version or
+ * architecture or any malformed line. */
+sgwls_status sgwls_tune_save(const char* path, const char* arch);
+sgwls_status sgwls_tune_load(const char* path, const char* arch);
+
 /* Adjoint of sgwls_filter (not in the paper): for a scalar loss with
  * gradient grad_u (C x M x N) with respect to the filter output, writes
  * grad_f (C x M x N), and, when non-NULL, grad_g (M x N) and grad_lambda

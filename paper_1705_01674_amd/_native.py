@@ -17,7 +17,9 @@ STATUS = {0: "SGWLS_OK", 1: "SGWLS_E_ARG", 2: "SGWLS_E_SHAPE", 3: "SGWLS_E_WORKS
 # Every symbol include/sgwls.h declares.
 EXPORTS = ["sgwls_status_str", "sgwls_version", "sgwls_validate", "sgwls_workspace_bytes",
            "sgwls_pass", "sgwls_pass_stages", "sgwls_filter", "sgwls_backward", "sgwls_backward_workspace_bytes",
-           "sgwls_batched_workspace_bytes", "sgwls_filter_batched"]
+           "sgwls_batched_workspace_bytes", "sgwls_filter_batched", "sgwls_variant_count",
+           "sgwls_tune_pin", "sgwls_tune_query", "sgwls_tune_clear", "sgwls_tune_size",
+           "sgwls_autotune", "sgwls_tune_save", "sgwls_tune_load"]
 
 
 class SgwlsParams(ctypes.Structure):
@@ -66,6 +68,22 @@ def _load():
     lib.sgwls_batched_workspace_bytes.argtypes = [ctypes.POINTER(SgwlsImage), P, i]
     lib.sgwls_filter_batched.restype = i
     lib.sgwls_filter_batched.argtypes = [ctypes.POINTER(SgwlsImage), P, i, vp, sz, vp]
+    lib.sgwls_variant_count.restype = i
+    lib.sgwls_variant_count.argtypes = [i, i, i]
+    lib.sgwls_tune_pin.restype = i
+    lib.sgwls_tune_pin.argtypes = [i, i, i, i, P, i]
+    lib.sgwls_tune_query.restype = i
+    lib.sgwls_tune_query.argtypes = [i, i, i, i, P]
+    lib.sgwls_tune_clear.restype = None
+    lib.sgwls_tune_clear.argtypes = []
+    lib.sgwls_tune_size.restype = i
+    lib.sgwls_tune_size.argtypes = []
+    lib.sgwls_autotune.restype = i
+    lib.sgwls_autotune.argtypes = [vp, vp, vp, i, i, i, P, vp, sz, vp, i, ctypes.POINTER(ctypes.c_int)]
+    lib.sgwls_tune_save.restype = i
+    lib.sgwls_tune_save.argtypes = [ctypes.c_char_p, ctypes.c_char_p]
+    lib.sgwls_tune_load.restype = i
+    lib.sgwls_tune_load.argtypes = [ctypes.c_char_p, ctypes.c_char_p]
     return lib
 
 

@@ -10,7 +10,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsgwls.so")
-SOURCES = ["sgwls_kernels.hip", "sgwls_api.cpp"]
+SOURCES = ["sgwls_pass_r1.hip", "sgwls_pass_r2.hip", "sgwls_pass_r3.hip", "sgwls_pass_r4.hip",
+           "sgwls_plan.cpp", "sgwls_api.cpp"]
 ARCH = os.environ.get("SGWLS_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled for all device code.
@@ -25,18 +26,38 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found; the SG-WLS library needs ROCm's hipcc to build")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile the library (always recompiles) and return its path."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", *HIP_FLAGS, "-shared",
-           "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp,
-           *[os.path.join(CSRC, s) for s in SOURCES]]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
+    return subprocess.run(cmd, capture_output=True, text=True)
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile the library (always recompiles) and return its path.  The
+    translation units (one per neighbourhood radius) compile in parallel."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    jobs = jobs or max(1, min(len(SOURCES), os.cpu_count() or 1, 8))
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    objs, cmds = [], []
+    for src in SOURCES:
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        objs.append(obj)
+        cmds.append([hipcc(), f"--offload-arch={ARCH}", *HIP_FLAGS, *inc, "-c",
+                     os.path.join(CSRC, src), "-o", obj])
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(lambda c: _run(c, verbose), cmds))
+    for cmd, res in zip(cmds, results):
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError(f"hipcc failed on {cmd[-3]} with code {res.returncode}")
+    tmp = LIB + ".tmp"
+    res = _run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError(f"hipcc failed with code {res.returncode}")
+        raise RuntimeError(f"hipcc link failed with code {res.returncode}")
     os.replace(tmp, LIB)
     return LIB
 

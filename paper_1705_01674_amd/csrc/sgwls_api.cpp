@@ -8,6 +8,12 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
 
 using namespace sgwls;
 
@@ -23,6 +29,33 @@ bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
 
 // Channel blocks: the kernels are compiled for 3 and 1 channels at a time.
 int channel_block(int remaining) { return remaining >= 3 ? 3 : 1; }
+
+// ---------------------------------------------------------------------------
+// Tuning table: the kernel variant (rows per chunk, chunks per block) chosen
+// for a pass, keyed by radius, channel block, precision, weight kind,
+// direction and a size bucket (half-octaves of L*W).  Entries come from
+// sgwls_autotune, sgwls_tune_pin or sgwls_tune_load; absent keys use
+// variant 0.  Only stride-1 passes have variants.
+using TuneKey = std::tuple<int, int, int, int, int, int>;
+std::map<TuneKey, int>& tune_table() {
+  static std::map<TuneKey, int> t;
+  return t;
+}
+std::mutex& tune_mutex() {
+  static std::mutex m;
+  return m;
+}
+int size_bucket(int L, int W) {
+  return (int)std::lround(2.0 * std::log2((double)L * (double)W));
+}
+TuneKey tune_key(int r, int cb, int fp64, int kind, int dir, int L, int W) {
+  return TuneKey(r, cb, fp64, kind, dir, size_bucket(L, W));
+}
+int tuned_variant(int r, int cb, int fp64, int kind, int dir, int L, int W) {
+  std::lock_guard<std::mutex> lk(tune_mutex());
+  auto it = tune_table().find(tune_key(r, cb, fp64, kind, dir, L, W));
+  return it == tune_table().end() ? 0 : it->second;
+}
 
 WeightParams weight_params(const sgwls_params& p) {
   WeightParams wp{};
@@ -61,13 +94,14 @@ PassGeom pass_geom(int direction, int M, int N, const PassPlan& pl, int stride) 
   return g;
 }
 
-// Interface bytes needed by one pass direction over all channel blocks.
+// Interface bytes needed by one pass direction over all channel blocks and
+// all kernel variants (so a tuned variant never outgrows the workspace).
 size_t pass_iface_bytes(int direction, int C, int M, int N, const sgwls_params& p) {
   const int L = direction == 0 ? M : N, W = direction == 0 ? N : M;
   size_t need = 0;
   for (int c0 = 0; c0 < C;) {
     const int cb = channel_block(C - c0);
-    need = std::max(need, interface_bytes(make_plan(L, W, p.r, cb, p.stride, p.prec)));
+    need = std::max(need, interface_bytes_max(L, W, p.r, cb, p.stride, p.prec));
     c0 += cb;
   }
   return align_up(need);
@@ -79,14 +113,17 @@ size_t iface_bytes_all(int C, int M, int N, const sgwls_params& p) {
 
 size_t image_bytes(int C, int M, int N) { return align_up(sizeof(float) * (size_t)C * M * N); }
 
+// variant < 0: the tuned variant of the case (variant 0 when none is tuned).
 sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* y, int C, int M,
                           int N, const sgwls_params& p, const float* lam_dev, void* iface,
-                          hipStream_t stream, int stages = kStageAll) {
+                          hipStream_t stream, int stages = kStageAll, int variant = -1) {
   const int L = direction == 0 ? M : N, W = direction == 0 ? N : M;
   const WeightParams wp = weight_params(p);
   for (int c0 = 0; c0 < C;) {
     const int cb = channel_block(C - c0);
-    const PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec);
+    const int v = variant >= 0 ? variant
+                               : tuned_variant(p.r, cb, p.prec, (int)p.kind, direction, L, W);
+    const PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, v);
     const PassGeom geo = pass_geom(direction, M, N, pl, p.stride);
     hipError_t e = launch_pass(p.r, cb, p.prec, x, g, y, c0, geo, pl, wp, lam_dev, p.lambda,
                                iface, stream, stages);
@@ -194,6 +231,150 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u, int C, int M
     if (st != SGWLS_OK) return st;
     x = y;
   }
+  return SGWLS_OK;
+}
+
+int sgwls_variant_count(int r, int channel_block, int prec) {
+  if (r < 1 || r > kMaxR || (channel_block != 1 && channel_block != 3) || (prec != 0 && prec != 1))
+    return 0;
+  return variants_of(r, channel_block, prec).n;
+}
+
+sgwls_status sgwls_tune_pin(int direction, int channel_block, int M, int N,
+                            const sgwls_params* p, int variant) {
+  sgwls_status st = sgwls_validate(channel_block, M, N, p);
+  if (st != SGWLS_OK) return st;
+  if (direction != 0 && direction != 1) return SGWLS_E_ARG;
+  if (channel_block != 1 && channel_block != 3) return SGWLS_E_ARG;
+  if (variant < 0 || variant >= variants_of(p->r, channel_block, p->prec).n) return SGWLS_E_ARG;
+  const int L = direction == 0 ? M : N, W = direction == 0 ? N : M;
+  std::lock_guard<std::mutex> lk(tune_mutex());
+  tune_table()[tune_key(p->r, channel_block, p->prec, (int)p->kind, direction, L, W)] = variant;
+  return SGWLS_OK;
+}
+
+int sgwls_tune_query(int direction, int channel_block, int M, int N, const sgwls_params* p) {
+  if (!p || (direction != 0 && direction != 1)) return -1;
+  const int L = direction == 0 ? M : N, W = direction == 0 ? N : M;
+  return tuned_variant(p->r, channel_block, p->prec, (int)p->kind, direction, L, W);
+}
+
+void sgwls_tune_clear(void) {
+  std::lock_guard<std::mutex> lk(tune_mutex());
+  tune_table().clear();
+}
+
+int sgwls_tune_size(void) {
+  std::lock_guard<std::mutex> lk(tune_mutex());
+  return (int)tune_table().size();
+}
+
+sgwls_status sgwls_autotune(const float* x, const float* g, float* y, int C, int M, int N,
+                            const sgwls_params* p, void* ws, size_t ws_bytes, void* stream,
+                            int reps, int* chosen) {
+  sgwls_status st = sgwls_validate(C, M, N, p);
+  if (st != SGWLS_OK) return st;
+  if (!x || !g || !y || y == x || (const float*)y == g || reps < 1) return SGWLS_E_ARG;
+  const size_t need = std::max(pass_iface_bytes(0, C, M, N, *p), pass_iface_bytes(1, C, M, N, *p));
+  if (!ws || ws_bytes < need) return SGWLS_E_WORKSPACE;
+  if (chosen)
+    for (int i = 0; i < 4; ++i) chosen[i] = -1;
+  if (p->stride != 1) return SGWLS_OK;   // strided passes have a single kernel
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return SGWLS_E_HIP;
+  }
+  const WeightParams wp = weight_params(*p);
+  sgwls_status result = SGWLS_OK;
+  for (int dir = 0; dir < 2 && result == SGWLS_OK; ++dir) {
+    const int L = dir == 0 ? M : N, W = dir == 0 ? N : M;
+    for (int cbi = 0; cbi < 2 && result == SGWLS_OK; ++cbi) {
+      const int cb = cbi == 0 ? 3 : 1;
+      int c0 = -1;   // first channel block of this width
+      for (int c = 0; c < C;) {
+        const int b = channel_block(C - c);
+        if (b == cb) { c0 = c; break; }
+        c += b;
+      }
+      if (c0 < 0) continue;
+      const int nv = variants_of(p->r, cb, p->prec).n;
+      int best = 0;
+      float best_ms = 0.0f;
+      for (int v = 0; v < nv && result == SGWLS_OK; ++v) {
+        const PassPlan pl = make_plan(L, W, p->r, cb, p->stride, p->prec, v);
+        const PassGeom geo = pass_geom(dir, M, N, pl, p->stride);
+        auto run = [&]() {
+          return launch_pass(p->r, cb, p->prec, x, g, y, c0, geo, pl, wp, nullptr, p->lambda,
+                             ws, s, kStageAll);
+        };
+        if (run() != hipSuccess || hipEventRecord(e0, s) != hipSuccess) { result = SGWLS_E_HIP; break; }
+        for (int i = 0; i < reps; ++i)
+          if (run() != hipSuccess) { result = SGWLS_E_HIP; break; }
+        float ms = 0.0f;
+        if (result != SGWLS_OK || hipEventRecord(e1, s) != hipSuccess ||
+            hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          result = SGWLS_E_HIP;
+          break;
+        }
+        if (v == 0 || ms < best_ms) { best = v; best_ms = ms; }
+      }
+      if (result != SGWLS_OK) break;
+      {
+        std::lock_guard<std::mutex> lk(tune_mutex());
+        tune_table()[tune_key(p->r, cb, p->prec, (int)p->kind, dir, L, W)] = best;
+      }
+      if (chosen) chosen[dir * 2 + cbi] = best;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return result;
+}
+
+sgwls_status sgwls_tune_save(const char* path, const char* arch) {
+  if (!path || !arch || !arch[0] || std::strchr(arch, ' ') || std::strchr(arch, '\n'))
+    return SGWLS_E_ARG;
+  FILE* fp = std::fopen(path, "w");
+  if (!fp) return SGWLS_E_ARG;
+  std::lock_guard<std::mutex> lk(tune_mutex());
+  std::fprintf(fp, "sgwls-tune %d %s\n", kVersion, arch);
+  for (const auto& kv : tune_table()) {
+    int r, cb, fp64, kind, dir, bucket;
+    std::tie(r, cb, fp64, kind, dir, bucket) = kv.first;
+    std::fprintf(fp, "%d %d %d %d %d %d %d\n", r, cb, fp64, kind, dir, bucket, kv.second);
+  }
+  const bool ok = std::fclose(fp) == 0;
+  return ok ? SGWLS_OK : SGWLS_E_ARG;
+}
+
+sgwls_status sgwls_tune_load(const char* path, const char* arch) {
+  if (!path || !arch) return SGWLS_E_ARG;
+  FILE* fp = std::fopen(path, "r");
+  if (!fp) return SGWLS_E_ARG;
+  char tag[32] = {0}, farch[128] = {0};
+  int version = -1;
+  std::map<TuneKey, int> entries;
+  bool ok = std::fscanf(fp, "%31s %d %127s", tag, &version, farch) == 3 &&
+            std::strcmp(tag, "sgwls-tune") == 0 && version == kVersion &&
+            std::strcmp(farch, arch) == 0;
+  while (ok) {
+    int r, cb, fp64, kind, dir, bucket, v;
+    const int got = std::fscanf(fp, "%d %d %d %d %d %d %d", &r, &cb, &fp64, &kind, &dir, &bucket, &v);
+    if (got == EOF) break;
+    if (got != 7 || r < 1 || r > kMaxR || (cb != 1 && cb != 3) || (fp64 != 0 && fp64 != 1) ||
+        (kind != 0 && kind != 1) || (dir != 0 && dir != 1) || v < 0 ||
+        v >= variants_of(r, cb, fp64).n) {
+      ok = false;
+      break;
+    }
+    entries[TuneKey(r, cb, fp64, kind, dir, bucket)] = v;
+  }
+  std::fclose(fp);
+  if (!ok) return SGWLS_E_ARG;   // stale or corrupt: the table is left unchanged
+  std::lock_guard<std::mutex> lk(tune_mutex());
+  for (const auto& kv : entries) tune_table()[kv.first] = kv.second;
   return SGWLS_OK;
 }
 

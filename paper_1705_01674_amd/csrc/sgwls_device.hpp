@@ -1,4 +1,5 @@
-// HIP kernels for one SG-WLS pass on gfx950 (MI355X).
+// HIP kernels for one SG-WLS pass on gfx950 (MI355X), included by one
+// translation unit per neighbourhood radius (sgwls_pass_r<r>.hip).
 //
 // One pass (Sec. 2.3 of Liu et al., ICCV 2017) solves, for every strip centre
 // k, the subsystem A_s u = f of Eq. (5): A_s = I + lambda*L on the vector of
@@ -37,6 +38,8 @@
 // contiguous in both pass directions; lanes then read their strip's pixels
 // from LDS.  Weights and the band of A_s are recomputed from the guidance; no
 // per-pixel intermediate goes to memory.
+#pragma once
+
 #include "sgwls_internal.hpp"
 
 #include <algorithm>
@@ -277,6 +280,111 @@ DEV void load_tile(float* lds, const float* __restrict__ G, const float* __restr
   }
 }
 
+
+// Stride-1 tiles (TB = 64 + 2r columns), loaded with wave-uniform row or
+// column bases so that every load is a uniform pointer plus a fixed lane
+// offset.  Column pass: wave wq loads tile rows wq, wq+Q, ... (contiguous in
+// memory), lane l columns l and l+64.  Row pass: wave wq loads tile columns
+// wq, wq+Q, ... (contiguous along a), lane l rows l and l+64.  All loads of a
+// thread are issued before its LDS stores.
+template <int r, int CB, int TA, int Q>
+DEV void load_tile_s1(float* lds, const float* __restrict__ G, const float* __restrict__ X,
+                      const PassGeom& geo, int c0, int a_lo, int colbase, int pitch, int lane,
+                      int wq) {
+  constexpr int TB = kWave + 2 * r;
+  const int plane = (int)geo.plane;
+  const float* xc = X + c0 * plane;
+  if (geo.sb == 1) {
+    constexpr int NR = (TA + Q - 1) / Q, NH = (TB + kWave - 1) / kWave;
+    const int sa = (int)geo.sa;
+    int lo[NH];
+    bool lv[NH], cok[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      const int tb = lane + kWave * h, b = colbase + tb;
+      lv[h] = tb < TB;
+      cok[h] = lv[h] && b < geo.W;
+      lo[h] = cok[h] ? b : colbase;
+    }
+    float v[NR][NH][CB + 1];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int ta = wq + i * Q, a = a_lo - 1 + ta;
+      if (ta < TA && a >= 0 && a < geo.L) {
+        const float* gr = G + a * sa;
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          v[i][h][0] = gr[lo[h]];
+#pragma unroll
+          for (int c = 0; c < CB; ++c) v[i][h][c + 1] = (xc + c * plane + a * sa)[lo[h]];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int ta = wq + i * Q, a = a_lo - 1 + ta;
+      if (ta < TA) {
+        const bool rowok = a >= 0 && a < geo.L;
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+          if (lv[h]) {
+            float* d = lds + ta * pitch + lane + kWave * h;
+            d[0] = rowok ? (cok[h] ? v[i][h][0] : 0.0f) : kSentinel;
+#pragma unroll
+            for (int c = 0; c < CB; ++c) d[(c + 1) * TA * pitch] = (rowok && cok[h]) ? v[i][h][c + 1] : 0.0f;
+          }
+      }
+    }
+  } else {
+    constexpr int NC = (TB + Q - 1) / Q, NH = (TA + kWave - 1) / kWave;
+    const int sb = (int)geo.sb;
+    int lo[NH];
+    bool lv[NH], aok[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      const int ta = lane + kWave * h, a = a_lo - 1 + ta;
+      lv[h] = ta < TA;
+      aok[h] = lv[h] && a >= 0 && a < geo.L;
+      lo[h] = aok[h] ? a : 0;
+    }
+    float v[NC][NH][CB + 1];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      const int tb = wq + i * Q, b = colbase + tb;
+      if (tb < TB && b < geo.W) {
+        const float* gc = G + b * sb;
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          v[i][h][0] = gc[lo[h]];
+#pragma unroll
+          for (int c = 0; c < CB; ++c) v[i][h][c + 1] = (xc + c * plane + b * sb)[lo[h]];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      const int tb = wq + i * Q, b = colbase + tb;
+      if (tb < TB) {
+        const bool bok = b < geo.W;
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+          if (lv[h]) {
+            float* d = lds + (lane + kWave * h) * pitch + tb;
+            d[0] = aok[h] ? (bok ? v[i][h][0] : 0.0f) : kSentinel;
+#pragma unroll
+            for (int c = 0; c < CB; ++c) d[(c + 1) * TA * pitch] = (aok[h] && bok) ? v[i][h][c + 1] : 0.0f;
+          }
+      }
+    }
+  }
+}
+
+// v shifted up by one lane across the wave (lane 0 receives 0).
+DEV float lane_shr1(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                               0x138, 0xf, 0xf, false));
+}
+
 // The chunk of one lane: element values come from the LDS tile.
 template <int r, int R, bool S1>
 struct ChunkView {
@@ -330,12 +438,6 @@ DEV Acc diag_at(const float (&lw)[E + r][r], int m) {
 template <int r>
 DEV int tile_width(int stride) { return stride == 1 ? kWave + 2 * r : (kWave - 1) * stride + 2 * r + 1; }
 
-// Loads per thread per batch: the whole stride-1 tile in one batch, else 8.
-template <int r, int TA>
-constexpr int tile_batch(int nthr, bool s1) {
-  return s1 ? (TA * (kWave + 2 * r) + nthr - 1) / nthr : 8;
-}
-
 // ---------------------------------------------------------------------------
 // k_reduce: Schur complement contributions of every chunk of 64 strips.
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc>
@@ -356,8 +458,10 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce(
   const int colbase = centre_of(ki_lo, geo, r) - r;
   const int TB = S1 ? kWave + 2 * r : tile_width<r>(geo.stride);
   const int pch = S1 ? CV::PITCH1 : pitch;
-  load_tile<CB, TA, kWave * Q, tile_batch<r, Q * R + 2>(kWave * Q, S1)>(
-      smem, G, X, geo, c0, a_lo, colbase, TB, pch, threadIdx.x);
+  if constexpr (S1)
+    load_tile_s1<r, CB, TA, Q>(smem, G, X, geo, c0, a_lo, colbase, pch, lane, wq);
+  else
+    load_tile<CB, TA, kWave * Q, 8>(smem, G, X, geo, c0, a_lo, colbase, TB, pch, threadIdx.x);
   __syncthreads();
 
   const int ki = ki_lo + lane;
@@ -850,8 +954,10 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
   const int a_lo = j0 * R;
   const int TB = S1 ? kWave + 2 * r : tile_width<r>(geo.stride);
   const int pch = S1 ? CV::PITCH1 : pitch;
-  load_tile<CB, TA, kWave * Q, tile_batch<r, Q * R + 2>(kWave * Q, S1)>(
-      smem, G, X, geo, c0, a_lo, colbase, TB, pch, threadIdx.x);
+  if constexpr (S1)
+    load_tile_s1<r, CB, TA, Q>(smem, G, X, geo, c0, a_lo, colbase, pch, lane, wq);
+  else
+    load_tile<CB, TA, kWave * Q, 8>(smem, G, X, geo, c0, a_lo, colbase, TB, pch, threadIdx.x);
   __syncthreads();
 
   const int ki = ki_lo + lane;
@@ -987,7 +1093,8 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
     // Lane l outputs column b = colbase + l.  The strips covering it are the
     // lanes l-2r..l (centres b+r..b-r); lane l-t holds column b at row-vector
     // position t on even rows and 2r-t on odd rows.  Lanes without a strip
-    // contribute 0.  Sums run t = 0..2r in a fixed order.
+    // contribute 0 (including those left of lane 0).  The sum is a fixed
+    // nesting of one-lane wave shifts, so it is reproducible.
     if (!active) {
 #pragma unroll
       for (int m = 0; m < E; ++m)
@@ -1003,12 +1110,11 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
     for (int rho = 0; rho < R; ++rho)
 #pragma unroll
       for (int h = 0; h < CB; ++h) {
-        float acc = float(Z[rho * w + ((rho & 1) ? 2 * r : 0)][h]);
+        // sum_t shift_t(v_t) evaluated as v_0 + shift(v_1 + shift(v_2 + ...))
+        float acc = float(Z[rho * w + ((rho & 1) ? 0 : 2 * r)][h]);
 #pragma unroll
-        for (int t = 1; t <= 2 * r; ++t) {
-          const float v = __shfl_up(float(Z[rho * w + ((rho & 1) ? 2 * r - t : t)][h]), t, kWave);
-          acc += lane >= t ? v : 0.0f;
-        }
+        for (int t = 2 * r - 1; t >= 0; --t)
+          acc = float(Z[rho * w + ((rho & 1) ? 2 * r - t : t)][h]) + lane_shr1(acc);
         out[rho][h] = acc * inv;
       }
     if (geo.sb == 1) {   // column pass: lanes write consecutive columns of each row
@@ -1084,29 +1190,14 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
 }
 
 // ---------------------------------------------------------------------------
-// Tuning table.  R: rows per chunk (the expand kernel keeps r + CB values per
-// element in registers); Q: chunks per block; MM: the wave interface solver's
-// maximum separators per lane (0 = always use the serial solver).
-struct Tune {
-  int R, Q, MM;
-};
-constexpr Tune tune_of(int r, int cb, int fp64) {
-  return fp64 ? (r == 1 ? Tune{cb == 1 ? 8 : 4, 4, 4}
-                        : (r == 2 ? Tune{cb == 1 ? 4 : 2, 4, 4} : Tune{2, 2, 0}))
-              : (r == 1 ? Tune{cb == 1 ? 16 : 8, 4, 4}
-                        : (r == 2 ? Tune{cb == 1 ? 6 : 4, 4, 8}
-                                  : (r == 3 ? Tune{cb == 1 ? 4 : 2, 2, 0} : Tune{2, 2, 0})));
-}
-
-template <int r, int CB, int fp64, bool S1, int KIND>
+// Launch of one pass for one (r, channel block, precision, stride class,
+// weight kind, variant).
+template <int r, int CB, int fp64, bool S1, int KIND, int R, int Q>
 hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const PassGeom& geo,
                        const PassPlan& pl, const WeightParams& wp, const float* lam_dev,
                        float lam_host, void* iface, hipStream_t stream, int stages) {
   using Acc = typename std::conditional<fp64 != 0, double, float>::type;
-  constexpr Tune T = tune_of(r, CB, fp64);
-  // Tiles of strided passes are (kWave-1)*stride + 2r + 1 columns wide: one
-  // chunk per block keeps them within 64 KB of LDS.
-  constexpr int R = T.R, Q = S1 ? T.Q : 1;
+  constexpr VariantSet VS = variants_of(r, CB, fp64);
   using LY = IfaceLayout<r, CB>;
   Acc* sum = reinterpret_cast<Acc*>(iface);
   Acc* us = sum + pl.sum_elems;
@@ -1121,8 +1212,8 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
                        pl.pitch, sum);
   }
   if (geo.P > 1 && (stages & kStageInterface)) {
-    if (T.MM > 0 && pl.iface_m > 0 && pl.iface_m <= T.MM) {
-      constexpr int MM = T.MM > 0 ? T.MM : 1;
+    if (VS.MM > 0 && pl.iface_m > 0 && pl.iface_m <= VS.MM) {
+      constexpr int MM = VS.MM > 0 ? VS.MM : 1;
       hipLaunchKernelGGL((k_interface_pcr<r, CB, MM, Acc>), dim3(geo.nK), dim3(kWave), 0,
                          stream, (const Acc*)sum, us, geo.nK, geo.P, pl.iface_m);
     } else {
@@ -1139,84 +1230,67 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
   return hipGetLastError();
 }
 
-template <int r, int CB, int fp64, bool S1>
+// Runtime selection of the compiled variant (stride-1 passes) or of the
+// strided kernel (variant 0's R, one chunk per block).
+template <int r, int CB, int fp64, int KIND, int VI>
+hipError_t launch_variant(int vi, const float* x, const float* g, float* y, int c0,
+                          const PassGeom& geo, const PassPlan& pl, const WeightParams& wp,
+                          const float* lam_dev, float lam_host, void* iface, hipStream_t s,
+                          int st) {
+  constexpr VariantSet VS = variants_of(r, CB, fp64);
+  if constexpr (VI < VS.n) {
+    if (vi == VI)
+      return launch_impl<r, CB, fp64, true, KIND, VS.v[VI].R, VS.v[VI].Q>(
+          x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
+    return launch_variant<r, CB, fp64, KIND, VI + 1>(vi, x, g, y, c0, geo, pl, wp, lam_dev,
+                                                     lam_host, iface, s, st);
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int r, int CB, int fp64, int KIND>
 hipError_t launch_kind(const float* x, const float* g, float* y, int c0, const PassGeom& geo,
                        const PassPlan& pl, const WeightParams& wp, const float* lam_dev,
                        float lam_host, void* iface, hipStream_t s, int st) {
-  return wp.kind == 0
-             ? launch_impl<r, CB, fp64, S1, 0>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st)
-             : launch_impl<r, CB, fp64, S1, 1>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
+  constexpr VariantSet VS = variants_of(r, CB, fp64);
+  if (geo.stride != 1)
+    return launch_impl<r, CB, fp64, false, KIND, VS.v[0].R, 1>(x, g, y, c0, geo, pl, wp,
+                                                                lam_dev, lam_host, iface, s, st);
+  return launch_variant<r, CB, fp64, KIND, 0>(pl.variant, x, g, y, c0, geo, pl, wp, lam_dev,
+                                              lam_host, iface, s, st);
 }
 
-template <int r, int CB>
-hipError_t launch_prec(int fp64, const float* x, const float* g, float* y, int c0,
-                       const PassGeom& geo, const PassPlan& pl, const WeightParams& wp,
-                       const float* lam_dev, float lam_host, void* iface, hipStream_t s,
-                       int st) {
-  const bool s1 = geo.stride == 1;
-  if (fp64)
-    return s1 ? launch_kind<r, CB, 1, true>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st)
-              : launch_kind<r, CB, 1, false>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
-  return s1 ? launch_kind<r, CB, 0, true>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st)
-            : launch_kind<r, CB, 0, false>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
+template <int r, int CB, int fp64>
+hipError_t launch_prec(const float* x, const float* g, float* y, int c0, const PassGeom& geo,
+                       const PassPlan& pl, const WeightParams& wp, const float* lam_dev,
+                       float lam_host, void* iface, hipStream_t s, int st) {
+  return wp.kind == 0
+             ? launch_kind<r, CB, fp64, 0>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st)
+             : launch_kind<r, CB, fp64, 1>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
 }
 
 template <int r>
-hipError_t launch_cb(int cb, int fp64, const float* x, const float* g, float* y, int c0,
-                     const PassGeom& geo, const PassPlan& pl, const WeightParams& wp,
-                     const float* lam_dev, float lam_host, void* iface, hipStream_t s, int st) {
-  return cb == 3
-             ? launch_prec<r, 3>(fp64, x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st)
-             : launch_prec<r, 1>(fp64, x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
+hipError_t launch_r(int cb, int fp64, const float* x, const float* g, float* y, int c0,
+                    const PassGeom& geo, const PassPlan& pl, const WeightParams& wp,
+                    const float* lam_dev, float lam_host, void* iface, hipStream_t s, int st) {
+  if (cb == 3)
+    return fp64 ? launch_prec<r, 3, 1>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st)
+                : launch_prec<r, 3, 0>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
+  return fp64 ? launch_prec<r, 1, 1>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st)
+              : launch_prec<r, 1, 0>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
 }
 
 }  // namespace
 
-int strip_count(int W, int r, int stride) {
-  if (r < 1 || stride < 1 || W < 2 * r + 1) return 0;
-  const int span = W - 1 - 2 * r;          // offset of the last regular centre
-  const int regular = span / stride + 1;
-  return regular + ((span % stride) != 0 ? 1 : 0);
-}
-
-PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64) {
-  PassPlan pl{};
-  const Tune T = tune_of(r, cb, fp64);
-  pl.R = T.R;
-  pl.Q = stride == 1 ? T.Q : 1;
-  pl.P = (L + pl.R - 1) / pl.R;
-  pl.nK = strip_count(W, r, stride);
-  pl.OW = stride == 1 ? kWave - 2 * r : (kWave - 2) * stride - 2 * r;
-  pl.TB = stride == 1 ? kWave + 2 * r : (kWave - 1) * stride + 2 * r + 1;
-  pl.pitch = pl.TB | 1;
-  const int n = pl.P - 1;
-  const int m = (n + kWave - 1) / kWave;
-  pl.iface_m = (T.MM > 0 && m <= T.MM) ? std::max(m, 1) : 0;
-  const int T2 = r * (r + 1) / 2;
-  const int F = 2 * T2 + 2 * r * cb + r * r;
-  pl.acc_bytes = fp64 ? 8 : 4;
-  pl.sum_elems = (size_t)pl.P * F * pl.nK;
-  pl.u_elems = (size_t)std::max(n, 1) * r * cb * pl.nK;
-  return pl;
-}
-
-size_t interface_bytes(const PassPlan& pl) {
-  // sum, separator solutions, and (serial solver) the G_j blocks
-  const size_t g_elems = (size_t)std::max(pl.P - 1, 1) * kMaxR * kMaxR * pl.nK;
-  return (pl.sum_elems + pl.u_elems + g_elems) * (size_t)pl.acc_bytes + 256;
-}
-
-hipError_t launch_pass(int r, int cb, int fp64, const float* x, const float* g, float* y,
-                       int c0, const PassGeom& geo, const PassPlan& plan,
-                       const WeightParams& wp, const float* lam_dev, float lam_host,
-                       void* iface, hipStream_t stream, int st) {
-  switch (r) {
-    case 1: return launch_cb<1>(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface, stream, st);
-    case 2: return launch_cb<2>(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface, stream, st);
-    case 3: return launch_cb<3>(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface, stream, st);
-    case 4: return launch_cb<4>(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface, stream, st);
-    default: return hipErrorInvalidValue;
+// Defines launch_pass_r<RR> in the translation unit that instantiates radius RR.
+#define SGWLS_DEFINE_LAUNCH(RR)                                                              \
+  hipError_t launch_pass_r##RR(int cb, int fp64, const float* x, const float* g, float* y,  \
+                               int c0, const PassGeom& geo, const PassPlan& plan,           \
+                               const WeightParams& wp, const float* lam_dev,                \
+                               float lam_host, void* iface, hipStream_t stream, int stages) { \
+    return launch_r<RR>(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface,     \
+                        stream, stages);                                                     \
   }
-}
 
 }  // namespace sgwls

@@ -1,5 +1,5 @@
-// Internal declarations shared by the kernels (sgwls_kernels.hip) and the
-// C ABI (sgwls_api.cpp).  Nothing here is part of the public interface.
+// Internal declarations shared by the kernel translation units and the C ABI.
+// Nothing here is part of the public interface.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,8 +36,43 @@ struct PassGeom {
   int P;            // chunks per subsystem = ceil(L / R)
 };
 
-// Launch configuration of one (r, channel block, precision, stride) case.
+// Kernel variants: rows per chunk R (even) and chunks per block Q.  Stride-1
+// passes may use any variant of their case; strided passes always use
+// variant 0's R with Q = 1 (their tiles are wider).
+struct Variant {
+  int R, Q;
+};
+constexpr int kMaxVariants = 8;
+struct VariantSet {
+  int n;
+  Variant v[kMaxVariants];
+  int MM;   // separators per lane handled by the wave interface solver
+};
+
+// The expand kernel keeps (r + CB) values per chunk element in registers, so
+// R shrinks as r, the channel block and the precision grow.
+constexpr VariantSet variants_of(int r, int cb, int fp64) {
+  if (fp64) {
+    if (r == 1) return cb == 1 ? VariantSet{2, {{8, 4}, {4, 4}}, 8} : VariantSet{2, {{4, 4}, {4, 2}}, 8};
+    if (r == 2) return cb == 1 ? VariantSet{1, {{4, 4}}, 4} : VariantSet{1, {{2, 4}}, 4};
+    return VariantSet{1, {{2, 2}}, 0};
+  }
+  // Variant 0 first; the row-pass tile loader keeps a lane per tile row, so
+  // Q*R + 2 close to (and not above) 64 uses the lanes best.  Every tile
+  // stays within 64 KB of LDS.
+  if (r == 1)
+    return cb == 1 ? VariantSet{6, {{16, 4}, {16, 3}, {8, 7}, {12, 5}, {8, 4}, {16, 2}}, 8}
+                   : VariantSet{8, {{8, 4}, {8, 7}, {6, 9}, {4, 14}, {10, 5}, {8, 2}, {6, 4}, {4, 4}}, 8};
+  if (r == 2)
+    return cb == 1 ? VariantSet{4, {{6, 4}, {6, 9}, {4, 14}, {4, 4}}, 8}
+                   : VariantSet{4, {{4, 4}, {4, 14}, {4, 8}, {4, 2}}, 8};
+  if (r == 3) return cb == 1 ? VariantSet{1, {{4, 2}}, 0} : VariantSet{1, {{2, 2}}, 0};
+  return VariantSet{1, {{2, 2}}, 0};
+}
+
+// Launch configuration of one (r, channel block, precision, stride, variant).
 struct PassPlan {
+  int variant;      // index into variants_of(r, cb, fp64)
   int R;            // rows per chunk
   int Q;            // chunks per reduce / expand block (one wave each)
   int P;            // chunks per subsystem
@@ -50,10 +85,12 @@ struct PassPlan {
   int acc_bytes;    // 4 (float) or 8 (double) interface element size
 };
 
-// Host-side helpers (sgwls_kernels.hip).
+// Host-side planning (sgwls_plan.cpp).
 int strip_count(int W, int r, int stride);
-PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64);
+PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64, int variant);
 size_t interface_bytes(const PassPlan& pl);
+// Largest interface_bytes over every variant of the case.
+size_t interface_bytes_max(int L, int W, int r, int cb, int stride, int fp64);
 
 // Stages of one pass (bit mask): reduce, interface solve, expand.
 constexpr int kStageReduce = 1, kStageInterface = 2, kStageExpand = 4, kStageAll = 7;
@@ -64,5 +101,17 @@ hipError_t launch_pass(int r, int cb, int fp64, const float* x, const float* g, 
                        int c0, const PassGeom& geo, const PassPlan& plan,
                        const WeightParams& wp, const float* lam_dev, float lam_host,
                        void* iface, hipStream_t stream, int stages);
+
+// Per-radius entry points (one translation unit each).
+#define SGWLS_DECLARE_LAUNCH(RR)                                                            \
+  hipError_t launch_pass_r##RR(int cb, int fp64, const float* x, const float* g, float* y, \
+                               int c0, const PassGeom& geo, const PassPlan& plan,          \
+                               const WeightParams& wp, const float* lam_dev,               \
+                               float lam_host, void* iface, hipStream_t stream, int stages);
+SGWLS_DECLARE_LAUNCH(1)
+SGWLS_DECLARE_LAUNCH(2)
+SGWLS_DECLARE_LAUNCH(3)
+SGWLS_DECLARE_LAUNCH(4)
+#undef SGWLS_DECLARE_LAUNCH
 
 }  // namespace sgwls

@@ -1,0 +1,66 @@
+// Host-side planning of a pass: chunking, block geometry, interface buffers,
+// and dispatch to the per-radius kernel translation units.
+#include "sgwls_internal.hpp"
+
+#include <algorithm>
+
+namespace sgwls {
+
+int strip_count(int W, int r, int stride) {
+  if (r < 1 || stride < 1 || W < 2 * r + 1) return 0;
+  const int span = W - 1 - 2 * r;          // offset of the last regular centre
+  const int regular = span / stride + 1;
+  return regular + ((span % stride) != 0 ? 1 : 0);
+}
+
+PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64, int variant) {
+  PassPlan pl{};
+  const VariantSet vs = variants_of(r, cb, fp64);
+  if (stride != 1 || variant < 0 || variant >= vs.n) variant = 0;
+  pl.variant = variant;
+  pl.R = vs.v[variant].R;
+  pl.Q = stride == 1 ? vs.v[variant].Q : 1;
+  pl.P = (L + pl.R - 1) / pl.R;
+  pl.nK = strip_count(W, r, stride);
+  pl.OW = stride == 1 ? kWave - 2 * r : (kWave - 2) * stride - 2 * r;
+  pl.TB = stride == 1 ? kWave + 2 * r : (kWave - 1) * stride + 2 * r + 1;
+  pl.pitch = pl.TB | 1;
+  const int n = pl.P - 1;
+  const int m = (n + kWave - 1) / kWave;
+  pl.iface_m = (vs.MM > 0 && m <= vs.MM) ? std::max(m, 1) : 0;
+  const int T2 = r * (r + 1) / 2;
+  const int F = 2 * T2 + 2 * r * cb + r * r;
+  pl.acc_bytes = fp64 ? 8 : 4;
+  pl.sum_elems = (size_t)pl.P * F * pl.nK;
+  pl.u_elems = (size_t)std::max(n, 1) * r * cb * pl.nK;
+  return pl;
+}
+
+size_t interface_bytes(const PassPlan& pl) {
+  // chunk summaries, separator solutions, and (serial solver) the G_j blocks
+  const size_t g_elems = (size_t)std::max(pl.P - 1, 1) * kMaxR * kMaxR * pl.nK;
+  return (pl.sum_elems + pl.u_elems + g_elems) * (size_t)pl.acc_bytes + 256;
+}
+
+size_t interface_bytes_max(int L, int W, int r, int cb, int stride, int fp64) {
+  const VariantSet vs = variants_of(r, cb, fp64);
+  size_t need = 0;
+  for (int v = 0; v < (stride == 1 ? vs.n : 1); ++v)
+    need = std::max(need, interface_bytes(make_plan(L, W, r, cb, stride, fp64, v)));
+  return need;
+}
+
+hipError_t launch_pass(int r, int cb, int fp64, const float* x, const float* g, float* y,
+                       int c0, const PassGeom& geo, const PassPlan& plan,
+                       const WeightParams& wp, const float* lam_dev, float lam_host,
+                       void* iface, hipStream_t stream, int st) {
+  switch (r) {
+    case 1: return launch_pass_r1(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface, stream, st);
+    case 2: return launch_pass_r2(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface, stream, st);
+    case 3: return launch_pass_r3(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface, stream, st);
+    case 4: return launch_pass_r4(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface, stream, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace sgwls

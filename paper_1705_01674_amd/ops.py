@@ -157,3 +157,61 @@ def sgwls_pass(direction: int, x: torch.Tensor, g: torch.Tensor, p: Params, *,
                                  ctypes.byref(cp), _ptr(lam), _ptr(ws), ws.numel(), _stream(dev)),
               "sgwls_pass")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Kernel variants and autotuning (stride-1 passes).
+
+def variant_count(r: int, channel_block: int, prec: str = "fp32") -> int:
+    return int(nat.lib.sgwls_variant_count(int(r), int(channel_block), _PREC[prec]))
+
+
+def tune_pin(direction: int, channel_block: int, M: int, N: int, p: Params, variant: int) -> None:
+    nat.check(nat.lib.sgwls_tune_pin(int(direction), int(channel_block), int(M), int(N),
+                                     ctypes.byref(p.c()), int(variant)), "sgwls_tune_pin")
+
+
+def tune_query(direction: int, channel_block: int, M: int, N: int, p: Params) -> int:
+    return int(nat.lib.sgwls_tune_query(int(direction), int(channel_block), int(M), int(N),
+                                        ctypes.byref(p.c())))
+
+
+def tune_clear() -> None:
+    nat.lib.sgwls_tune_clear()
+
+
+def device_arch(dev=None) -> str:
+    name = torch.cuda.get_device_properties(dev or torch.cuda.current_device()).gcnArchName
+    return name.split(":")[0]
+
+
+def autotune(f: torch.Tensor, g: torch.Tensor, p: Params, reps: int = 10):
+    """Time every compiled kernel variant of both pass directions on this image
+    and keep the fastest for its shape (synchronises the current stream).
+    Returns {(direction, channel_block): variant}."""
+    C, M, N = _image(f, "f")
+    dev = f.device
+    _guidance(g, M, N, dev)
+    y = torch.empty_like(f)
+    ws = _workspace(workspace_bytes(C, M, N, p), dev)
+    chosen = (ctypes.c_int * 4)()
+    nat.check(nat.lib.sgwls_autotune(_ptr(f), _ptr(g), _ptr(y), C, M, N, ctypes.byref(p.c()),
+                                     _ptr(ws), ws.numel(), _stream(dev), int(reps), chosen),
+              "sgwls_autotune")
+    out = {}
+    for d in (0, 1):
+        for i, cb in enumerate((3, 1)):
+            if chosen[2 * d + i] >= 0:
+                out[(d, cb)] = chosen[2 * d + i]
+    return out
+
+
+def tune_save(path: str, arch: Optional[str] = None) -> None:
+    nat.check(nat.lib.sgwls_tune_save(path.encode(), (arch or device_arch()).encode()),
+              "sgwls_tune_save")
+
+
+def tune_load(path: str, arch: Optional[str] = None) -> bool:
+    """Merge a saved tuning table; False (table unchanged) if the file is
+    missing, malformed, or from another library version or architecture."""
+    return nat.lib.sgwls_tune_load(path.encode(), (arch or device_arch()).encode()) == 0

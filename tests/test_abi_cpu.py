@@ -90,3 +90,58 @@ def test_filter_error_paths_return_before_any_launch(nat):
     assert lib.sgwls_pass(2, f, g, u, 3, 64, 64, p, None, ws, big, None) == 1       # direction
     assert lib.sgwls_pass(0, f, g, f, 3, 64, 64, p, None, ws, big, None) == 1       # y aliases x
     assert lib.sgwls_pass(0, f, g, u, 3, 64, 64, p, None, ws, 16, None) == 3
+
+
+def test_variant_counts(nat):
+    assert nat.lib.sgwls_variant_count(1, 3, 0) >= 2
+    assert nat.lib.sgwls_variant_count(1, 1, 0) >= 2
+    assert nat.lib.sgwls_variant_count(4, 3, 1) >= 1
+    assert nat.lib.sgwls_variant_count(5, 3, 0) == 0
+    assert nat.lib.sgwls_variant_count(1, 2, 0) == 0
+
+
+def test_tune_table_pin_query_save_load(nat, tmp_path):
+    lib = nat.lib
+    lib.sgwls_tune_clear()
+    p = ctypes.byref(P(nat))
+    assert lib.sgwls_tune_query(0, 3, 1080, 1920, p) == 0
+    assert lib.sgwls_tune_pin(0, 3, 1080, 1920, p, 2) == 0
+    assert lib.sgwls_tune_pin(1, 3, 1080, 1920, p, 1) == 0
+    assert lib.sgwls_tune_query(0, 3, 1080, 1920, p) == 2
+    assert lib.sgwls_tune_query(1, 3, 1080, 1920, p) == 1
+    assert lib.sgwls_tune_query(0, 1, 1080, 1920, p) == 0          # other channel block
+    assert lib.sgwls_tune_query(0, 3, 1082, 1920, p) == 2          # same size bucket
+    assert lib.sgwls_tune_query(0, 3, 2160, 3840, p) == 0          # other bucket
+    assert lib.sgwls_tune_pin(0, 3, 1080, 1920, p, 99) == 1         # unknown variant
+    assert lib.sgwls_tune_pin(2, 3, 1080, 1920, p, 0) == 1          # bad direction
+    path = str(tmp_path / "tune.txt").encode()
+    assert lib.sgwls_tune_save(path, b"gfx950") == 0
+    assert lib.sgwls_tune_size() == 2
+    lib.sgwls_tune_clear()
+    assert lib.sgwls_tune_size() == 0
+    assert lib.sgwls_tune_load(path, b"gfx942") == 1                # other architecture
+    assert lib.sgwls_tune_size() == 0
+    assert lib.sgwls_tune_load(path, b"gfx950") == 0
+    assert lib.sgwls_tune_query(0, 3, 1080, 1920, p) == 2
+    lines = open(path.decode()).read().splitlines()
+    bad = tmp_path / "bad.txt"
+    bad.write_text("\n".join(lines + ["1 3 0 0 0 41 77"]) + "\n")   # variant out of range
+    lib.sgwls_tune_clear()
+    assert lib.sgwls_tune_load(str(bad).encode(), b"gfx950") == 1
+    assert lib.sgwls_tune_size() == 0
+    stale = tmp_path / "stale.txt"
+    stale.write_text(lines[0].replace("sgwls-tune 100", "sgwls-tune 1") + "\n")
+    assert lib.sgwls_tune_load(str(stale).encode(), b"gfx950") == 1
+    assert lib.sgwls_tune_load(str(tmp_path / "missing.txt").encode(), b"gfx950") == 1
+    lib.sgwls_tune_clear()
+
+
+def test_autotune_error_paths_return_before_any_launch(nat):
+    lib = nat.lib
+    f, g, u, ws = (ctypes.c_void_p(a) for a in (0x1000, 0x2000, 0x3000, 0x4000))
+    p = ctypes.byref(P(nat))
+    chosen = (ctypes.c_int * 4)()
+    assert lib.sgwls_autotune(f, g, u, 3, 2, 64, p, ws, 1 << 30, None, 5, chosen) == 2
+    assert lib.sgwls_autotune(f, g, f, 3, 64, 64, p, ws, 1 << 30, None, 5, chosen) == 1
+    assert lib.sgwls_autotune(f, g, u, 3, 64, 64, p, ws, 1 << 30, None, 0, chosen) == 1
+    assert lib.sgwls_autotune(f, g, u, 3, 64, 64, p, ws, 16, None, 5, chosen) == 3

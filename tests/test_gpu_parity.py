@@ -173,3 +173,40 @@ def test_lambda_on_device_and_saved_inputs(ops):
                                    oracle.OracleParams(**w.params), save=True)
     check("lambda_dev", u.cpu().numpy(), ref)
     check("saved pass inputs", saved.cpu().numpy().reshape(ref_saved.shape), ref_saved)
+
+
+@pytest.mark.parametrize("r,C", [(1, 3), (1, 1), (2, 3), (2, 1)])
+@pytest.mark.parametrize("direction", [0, 1])
+def test_every_kernel_variant_matches_oracle(ops, r, C, direction):
+    rng = np.random.default_rng(10 * r + C + direction)
+    M, N = 133, 157                       # several chunks of every variant, ragged
+    f = rng.uniform(0, 1, (C, M, N)).astype(np.float32)
+    g = rng.uniform(0, 1, (M, N)).astype(np.float32)
+    pd = pdict(lam=6.0, r=r, sigma_r=0.2)
+    p = ops.Params(**pd)
+    ref = (oracle.col_pass if direction == 0 else oracle.row_pass)(
+        f.astype(np.float64), g.astype(np.float64), oracle.OracleParams(**pd))[0]
+    ft, gt = torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda()
+    try:
+        for v in range(ops.variant_count(r, C)):
+            ops.tune_pin(direction, C, M, N, p, v)
+            out = ops.sgwls_pass(direction, ft, gt, p)
+            torch.cuda.synchronize()
+            check(f"variant {v} r{r} C{C} dir{direction}", out.cpu().numpy(), ref)
+    finally:
+        ops.tune_clear()
+
+
+def test_autotune_picks_a_variant_and_keeps_parity(ops):
+    w = synth.single("t", 300, 420, 3, 40, 0.05, 21, 4.0, 1, 2)
+    p = ops.Params(**w.params)
+    ft, gt = torch.from_numpy(w.f).cuda(), torch.from_numpy(w.g).cuda()
+    try:
+        chosen = ops.autotune(ft, gt, p, reps=3)
+        assert set(chosen) == {(0, 3), (1, 3)}
+        assert ops.tune_query(0, 3, 300, 420, p) == chosen[(0, 3)]
+        u = ops.sgwls_filter(ft, gt, p)
+        torch.cuda.synchronize()
+        check("autotuned filter", u.cpu().numpy(), oracle_filter(w.f, w.g, w.params))
+    finally:
+        ops.tune_clear()
