@@ -188,24 +188,45 @@ sgwls_status sgwls_autotune(const float* x, const float* g, float* y, int C, int
 sgwls_status sgwls_tune_save(const char* path, const char* arch);
 sgwls_status sgwls_tune_load(const char* path, const char* arch);
 
-/* Adjoint of sgwls_filter (not in the paper): for a scalar loss with
- * gradient grad_u (C x M x N) with respect to the filter output, writes
- * grad_f (C x M x N), and, when non-NULL, grad_g (M x N) and grad_lambda
- * (one device double).  saved: the 2T pass inputs written by sgwls_filter
- * with the same g and parameters.  Per pass, in reverse order, the adjoint
- * of the exact solve is the same SPD solve applied to the scattered
- * gradient; the weight terms -(ubar_p - ubar_q)(u_p - u_q) give the guidance
- * and lambda gradients with the weights recomputed from g.  ws: workspace of
- * sgwls_workspace_bytes(C, M, N, p) bytes plus 2*C*M*N floats plus
- * sgwls_backward_extra_bytes(C, M, N, p). */
+/* ---- Gradients (not in the paper) ----
+ * A pass maps x to y = (1/cnt) sum_k scatter_k(A_k^-1 gather_k(x)) (Sec.
+ * 2.3, Eq. 5).  For a scalar loss with output gradient ybar, its adjoint is,
+ * per strip k: v = gather_k(ybar / cnt); ubar = A_k^-1 v (A_k is symmetric,
+ * so the adjoint solve is the same solve); xbar += scatter_k(ubar).  With
+ * dA_k/dw_pq = lambda (e_p - e_q)(e_p - e_q)^T and u = A_k^-1 gather_k(x)
+ * (recomputed, not stored), every edge (p, q) of Eq. (2) contributes
+ * t_pq = -sum_c (ubar_p - ubar_q)(u_p - u_q): lambda t_pq dw_pq/dG to the
+ * guidance gradient at both pixels of the edge and w_pq t_pq to the lambda
+ * gradient.  Weights are recomputed from g.  omega^frac is not differentiable
+ * in G where G_p = G_q and alpha_r <= 1; its derivative is taken as 0 there.
+ * The lambda gradient is summed in float64 in a fixed order (deterministic). */
+
+/* Device workspace bytes of sgwls_backward and sgwls_pass_backward for one
+ * C x M x N image (0 if the request is invalid).  Makes no HIP call. */
+size_t sgwls_backward_workspace_bytes(int C, int M, int N, const sgwls_params* p);
+
+/* Adjoint of one sgwls_pass.  x: the pass input; ybar: gradient of the pass
+ * output (C x M x N); xbar (written): gradient of the pass input, must not
+ * alias x, ybar or g.  gbar (nullable, M x N, written): guidance gradient.
+ * grad_lambda (nullable, one device double, written): lambda gradient.  ws:
+ * sgwls_backward_workspace_bytes(C, M, N, p) bytes. */
+sgwls_status sgwls_pass_backward(int direction, const float* x, const float* g,
+                                 const float* ybar, float* xbar, float* gbar,
+                                 double* grad_lambda, int C, int M, int N,
+                                 const sgwls_params* p, const float* lambda_dev, void* ws,
+                                 size_t ws_bytes, void* stream);
+
+/* Adjoint of sgwls_filter.  saved: the 2T pass inputs that sgwls_filter wrote
+ * with the same g, parameters and lambda; grad_u: gradient of the filter
+ * output (C x M x N).  Writes grad_f (C x M x N; may alias grad_u, must not
+ * alias g or saved) and, when non-NULL, grad_g (M x N) and grad_lambda (one
+ * device double), each overwritten.  The passes are traversed in reverse
+ * order.  ws: sgwls_backward_workspace_bytes(C, M, N, p) bytes. */
 sgwls_status sgwls_backward(const float* g, const float* saved, const float* grad_u,
                             float* grad_f, float* grad_g, double* grad_lambda,
                             int C, int M, int N, const sgwls_params* p,
                             const float* lambda_dev, void* ws, size_t ws_bytes,
                             void* stream);
-
-/* Workspace bytes for sgwls_backward (0 if the request is invalid). */
-size_t sgwls_backward_workspace_bytes(int C, int M, int N, const sgwls_params* p);
 
 /* One image of a batch: device pointers and its shape. */
 typedef struct {

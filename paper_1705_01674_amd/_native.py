@@ -16,7 +16,8 @@ STATUS = {0: "SGWLS_OK", 1: "SGWLS_E_ARG", 2: "SGWLS_E_SHAPE", 3: "SGWLS_E_WORKS
 
 # Every symbol include/sgwls.h declares.
 EXPORTS = ["sgwls_status_str", "sgwls_version", "sgwls_validate", "sgwls_workspace_bytes",
-           "sgwls_pass", "sgwls_pass_stages", "sgwls_filter", "sgwls_backward", "sgwls_backward_workspace_bytes",
+           "sgwls_pass", "sgwls_pass_stages", "sgwls_filter", "sgwls_backward",
+           "sgwls_pass_backward", "sgwls_backward_workspace_bytes",
            "sgwls_batched_workspace_bytes", "sgwls_filter_batched", "sgwls_variant_count",
            "sgwls_tune_pin", "sgwls_tune_query", "sgwls_tune_clear", "sgwls_tune_size",
            "sgwls_autotune", "sgwls_tune_save", "sgwls_tune_load"]
@@ -62,6 +63,8 @@ def _load():
     lib.sgwls_filter.argtypes = [vp, vp, vp, i, i, i, P, vp, vp, vp, sz, vp]
     lib.sgwls_backward.restype = i
     lib.sgwls_backward.argtypes = [vp, vp, vp, vp, vp, vp, i, i, i, P, vp, vp, sz, vp]
+    lib.sgwls_pass_backward.restype = i
+    lib.sgwls_pass_backward.argtypes = [i, vp, vp, vp, vp, vp, vp, i, i, i, P, vp, vp, sz, vp]
     lib.sgwls_backward_workspace_bytes.restype = sz
     lib.sgwls_backward_workspace_bytes.argtypes = [i, i, i, P]
     lib.sgwls_batched_workspace_bytes.restype = sz

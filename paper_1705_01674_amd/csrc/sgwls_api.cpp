@@ -76,6 +76,7 @@ WeightParams weight_params(const sgwls_params& p) {
                     : 0.0f;
   wp.alpha_r = p.alpha_r;
   wp.eps = p.eps;
+  wp.inv_sr2 = p.kind == SGWLS_W_EXP ? (float)(1.0 / ((double)p.sigma_r * p.sigma_r)) : 0.0f;
   return wp;
 }
 
@@ -128,6 +129,72 @@ sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* 
     hipError_t e = launch_pass(p.r, cb, p.prec, x, g, y, c0, geo, pl, wp, lam_dev, p.lambda,
                                iface, stream, stages);
     if (e != hipSuccess) return SGWLS_E_HIP;
+    c0 += cb;
+  }
+  return SGWLS_OK;
+}
+
+// Backward workspace: the gradient ping-pong image, the interface buffers of
+// the backward plans (two right-hand sides per channel), the side terms of
+// chunk-boundary edges (P x W floats) and the per-block lambda partials.
+struct BwdLayout {
+  size_t img_off, iface_off, side_off, lpart_off, total;
+};
+
+BwdLayout bwd_layout(int C, int M, int N, const sgwls_params& p) {
+  size_t iface = 0, side = 0, blocks = 0;
+  for (int dir = 0; dir < 2; ++dir) {
+    const int L = dir == 0 ? M : N, W = dir == 0 ? N : M;
+    for (int c0 = 0; c0 < C;) {
+      const int cb = channel_block(C - c0);
+      iface = std::max(iface, interface_bytes_max(L, W, p.r, cb, p.stride, p.prec, kModeBackward));
+      const VariantSet vs = variants_for(kModeBackward, p.r, cb, p.prec);
+      for (int v = 0; v < (p.stride == 1 ? vs.n : 1); ++v) {
+        const PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, v, kModeBackward);
+        const PassGeom geo = pass_geom(dir, M, N, pl, p.stride);
+        side = std::max(side, (size_t)pl.P * W);
+        blocks = std::max(blocks, (size_t)expand_blocks(geo, pl));
+      }
+      c0 += cb;
+    }
+  }
+  BwdLayout l{};
+  l.img_off = 0;
+  l.iface_off = image_bytes(C, M, N);
+  l.side_off = l.iface_off + align_up(iface);
+  l.lpart_off = l.side_off + align_up(side * sizeof(float));
+  l.total = l.lpart_off + align_up(blocks * sizeof(double));
+  return l;
+}
+
+// One backward pass over all channel blocks.  `first` is true for the first
+// launch of a backward call: it overwrites gbar and *grad_lambda, later
+// launches add to them.
+sgwls_status enqueue_pass_backward(int direction, const float* x, const float* g,
+                                   const float* ybar, float* xbar, float* gbar,
+                                   double* grad_lambda, int C, int M, int N,
+                                   const sgwls_params& p, const float* lam_dev, void* ws,
+                                   const BwdLayout& lay, hipStream_t stream, bool& first) {
+  const int L = direction == 0 ? M : N, W = direction == 0 ? N : M;
+  const WeightParams wp = weight_params(p);
+  char* base = reinterpret_cast<char*>(ws);
+  BwdArgs bw{};
+  bw.ybar = ybar;
+  bw.gbar = gbar;
+  bw.side = reinterpret_cast<float*>(base + lay.side_off);
+  bw.lpart = grad_lambda ? reinterpret_cast<double*>(base + lay.lpart_off) : nullptr;
+  for (int c0 = 0; c0 < C;) {
+    const int cb = channel_block(C - c0);
+    const PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, 0, kModeBackward);
+    const PassGeom geo = pass_geom(direction, M, N, pl, p.stride);
+    bw.gacc = first ? 0 : 1;
+    hipError_t e = launch_pass(p.r, cb, p.prec, x, g, xbar, c0, geo, pl, wp, lam_dev, p.lambda,
+                               base + lay.iface_off, stream, kStageAll, &bw);
+    if (e != hipSuccess) return SGWLS_E_HIP;
+    e = launch_bwd_fixup(bw.side, gbar, geo, bw.lpart, expand_blocks(geo, pl), grad_lambda,
+                         first ? 0 : 1, stream);
+    if (e != hipSuccess) return SGWLS_E_HIP;
+    first = false;
     c0 += cb;
   }
   return SGWLS_OK;
@@ -379,17 +446,61 @@ sgwls_status sgwls_tune_load(const char* path, const char* arch) {
 }
 
 size_t sgwls_backward_workspace_bytes(int C, int M, int N, const sgwls_params* p) {
-  (void)C; (void)M; (void)N; (void)p;
-  return 0;
+  if (sgwls_validate(C, M, N, p) != SGWLS_OK) return 0;
+  return bwd_layout(C, M, N, *p).total;
+}
+
+sgwls_status sgwls_pass_backward(int direction, const float* x, const float* g,
+                                 const float* ybar, float* xbar, float* gbar,
+                                 double* grad_lambda, int C, int M, int N,
+                                 const sgwls_params* p, const float* lambda_dev, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  sgwls_status st = sgwls_validate(C, M, N, p);
+  if (st != SGWLS_OK) return st;
+  if (direction != 0 && direction != 1) return SGWLS_E_ARG;
+  if (!x || !g || !ybar || !xbar || xbar == x || xbar == ybar || (const float*)xbar == g)
+    return SGWLS_E_ARG;
+  if (gbar && ((const float*)gbar == g || gbar == xbar || (const float*)gbar == x ||
+               (const float*)gbar == ybar))
+    return SGWLS_E_ARG;
+  const BwdLayout lay = bwd_layout(C, M, N, *p);
+  if (!ws || ws_bytes < lay.total) return SGWLS_E_WORKSPACE;
+  bool first = true;
+  return enqueue_pass_backward(direction, x, g, ybar, xbar, gbar, grad_lambda, C, M, N, *p,
+                               lambda_dev, ws, lay, (hipStream_t)stream, first);
 }
 
 sgwls_status sgwls_backward(const float* g, const float* saved, const float* grad_u,
                             float* grad_f, float* grad_g, double* grad_lambda, int C, int M,
                             int N, const sgwls_params* p, const float* lambda_dev, void* ws,
                             size_t ws_bytes, void* stream) {
-  (void)g; (void)saved; (void)grad_u; (void)grad_f; (void)grad_g; (void)grad_lambda;
-  (void)C; (void)M; (void)N; (void)p; (void)lambda_dev; (void)ws; (void)ws_bytes; (void)stream;
-  return SGWLS_E_UNSUPPORTED;
+  sgwls_status st = sgwls_validate(C, M, N, p);
+  if (st != SGWLS_OK) return st;
+  if (!g || !saved || !grad_u || !grad_f || (const float*)grad_f == g ||
+      (const float*)grad_f == saved)
+    return SGWLS_E_ARG;
+  if (grad_g && ((const float*)grad_g == g || grad_g == grad_f || (const float*)grad_g == grad_u ||
+                 (const float*)grad_g == saved))
+    return SGWLS_E_ARG;
+  const BwdLayout lay = bwd_layout(C, M, N, *p);
+  if (!ws || ws_bytes < lay.total) return SGWLS_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  float* tmp = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + lay.img_off);
+  const size_t plane = (size_t)C * M * N;
+  const int passes = 2 * p->iters;
+  // Passes in reverse order.  Pass q reads the gradient of its output (grad_u
+  // for the last pass) and writes that of its input: into grad_f for even q,
+  // tmp for odd q, so pass 0 ends in grad_f and grad_u may alias grad_f.
+  const float* ybar = grad_u;
+  bool first = true;
+  for (int q = passes - 1; q >= 0; --q) {
+    float* xbar = (q % 2 == 0) ? grad_f : tmp;
+    st = enqueue_pass_backward(q % 2, saved + (size_t)q * plane, g, ybar, xbar, grad_g,
+                               grad_lambda, C, M, N, *p, lambda_dev, ws, lay, s, first);
+    if (st != SGWLS_OK) return st;
+    ybar = xbar;
+  }
+  return SGWLS_OK;
 }
 
 size_t sgwls_batched_workspace_bytes(const sgwls_image* imgs, const sgwls_params* p, int B) {

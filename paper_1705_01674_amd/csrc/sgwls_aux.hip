@@ -1,0 +1,55 @@
+// Radius-independent kernels: the fix-up step of a backward pass.
+#include "sgwls_internal.hpp"
+
+namespace sgwls {
+namespace {
+
+constexpr int kFixThreads = 256;
+
+// Blocks [0, nfix): side terms of chunk j (guidance-gradient terms of edges
+// from chunk j-1's last r elements into chunk j, gathered per pixel by the
+// expand kernel) are added to the pixels of row jR - 1.  Block nfix (when
+// lpart is set): fixed-order reduction of the per-block lambda partials.
+__global__ __launch_bounds__(kFixThreads) void k_bwd_fixup(const float* __restrict__ side,
+                                                           float* __restrict__ gbar,
+                                                           PassGeom geo, int nfix,
+                                                           const double* __restrict__ lpart,
+                                                           int nparts, double* glam,
+                                                           int lam_acc) {
+  if ((int)blockIdx.x < nfix) {
+    const int idx = blockIdx.x * kFixThreads + threadIdx.x;
+    const int n = (geo.P - 1) * geo.W;
+    if (idx < n) {
+      const int j = 1 + idx / geo.W, b = idx - (j - 1) * geo.W;
+      const int a = j * geo.R - 1;
+      const long long o = a * geo.sa + b * geo.sb;
+      gbar[o] += side[(size_t)j * geo.W + b];
+    }
+    return;
+  }
+  __shared__ double red[kFixThreads];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kFixThreads) s += lpart[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = kFixThreads / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *glam = lam_acc ? *glam + red[0] : red[0];
+}
+
+}  // namespace
+
+hipError_t launch_bwd_fixup(const float* side, float* gbar, const PassGeom& geo,
+                            const double* lpart, int nparts, double* glam, int lam_acc,
+                            hipStream_t stream) {
+  const int nfix = gbar && geo.P > 1 ? ((geo.P - 1) * geo.W + kFixThreads - 1) / kFixThreads : 0;
+  const int nlam = (lpart && glam) ? 1 : 0;
+  if (nfix + nlam == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bwd_fixup, dim3(nfix + nlam), dim3(kFixThreads), 0, stream, side, gbar,
+                     geo, nfix, lpart, nparts, glam, lam_acc);
+  return hipGetLastError();
+}
+
+}  // namespace sgwls

@@ -229,21 +229,32 @@ DEV int cover_count(int b, const PassGeom& geo, int r) {
 constexpr float kSentinel = 1.0e30f;
 
 // ---------------------------------------------------------------------------
+// Source planes of a tile: NX channels of X, then channels of X2, both from
+// channel c0 on (`plane` floats apart).  The forward kernels read X only; the
+// backward ones read the saved pass input (X) and the output gradient (X2).
+template <int NX>
+struct PlaneSrc {
+  const float* X;
+  const float* X2;
+  int c0, plane;
+  DEV const float* at(int p) const {
+    return p < NX ? X + (c0 + p) * plane : X2 + (c0 + p - NX) * plane;
+  }
+};
+
 // LDS tile of a block: rows a in [a_lo - 1, a_lo + Q*R + 1) of the pass, columns
-// b in [colbase, colbase + TB), planes: guidance then CB image channels.  Rows
+// b in [colbase, colbase + TB), planes: guidance then NP image planes.  Rows
 // or columns outside the image hold 0 (never used as pixels).  Loads are
 // issued in batches of BATCH per thread before any LDS store, so one memory
 // latency covers the batch; consecutive threads read consecutive addresses
 // (b in the column pass, a in the row pass).
-template <int CB, int TA, int NT, int BATCH>
-DEV void load_tile(float* lds, const float* __restrict__ G, const float* __restrict__ X,
-                   const PassGeom& geo, int c0, int a_lo, int colbase, int TB, int pitch,
-                   int tid) {
+template <int NP, int NX, int TA, int NT, int BATCH>
+DEV void load_tile(float* lds, const float* __restrict__ G, const PlaneSrc<NX>& src,
+                   const PassGeom& geo, int a_lo, int colbase, int TB, int pitch, int tid) {
   const int total = TA * TB;
   const bool colpass = geo.sb == 1;
-  const float* xc = X + c0 * (int)geo.plane;
   for (int base = 0; base < total; base += NT * BATCH) {
-    float v[CB + 1][BATCH];
+    float v[NP + 1][BATCH];
     int dst[BATCH];
 #pragma unroll
     for (int u = 0; u < BATCH; ++u) {
@@ -266,8 +277,8 @@ DEV void load_tile(float* lds, const float* __restrict__ G, const float* __restr
       // to them gets weight 0 (exp underflows, frac is below 1e-30).
       v[0][u] = in ? gv : (rowok ? 0.0f : kSentinel);
 #pragma unroll
-      for (int p = 1; p <= CB; ++p) {
-        const float xv = xc[(p - 1) * (int)geo.plane + o];
+      for (int p = 1; p <= NP; ++p) {
+        const float xv = src.at(p - 1)[o];
         v[p][u] = in ? xv : 0.0f;
       }
     }
@@ -275,7 +286,7 @@ DEV void load_tile(float* lds, const float* __restrict__ G, const float* __restr
     for (int u = 0; u < BATCH; ++u)
       if (dst[u] >= 0) {
 #pragma unroll
-        for (int p = 0; p <= CB; ++p) lds[p * TA * pitch + dst[u]] = v[p][u];
+        for (int p = 0; p <= NP; ++p) lds[p * TA * pitch + dst[u]] = v[p][u];
       }
   }
 }
@@ -287,13 +298,10 @@ DEV void load_tile(float* lds, const float* __restrict__ G, const float* __restr
 // memory), lane l columns l and l+64.  Row pass: wave wq loads tile columns
 // wq, wq+Q, ... (contiguous along a), lane l rows l and l+64.  All loads of a
 // thread are issued before its LDS stores.
-template <int r, int CB, int TA, int Q>
-DEV void load_tile_s1(float* lds, const float* __restrict__ G, const float* __restrict__ X,
-                      const PassGeom& geo, int c0, int a_lo, int colbase, int pitch, int lane,
-                      int wq) {
+template <int r, int NP, int NX, int TA, int Q>
+DEV void load_tile_s1(float* lds, const float* __restrict__ G, const PlaneSrc<NX>& src,
+                      const PassGeom& geo, int a_lo, int colbase, int pitch, int lane, int wq) {
   constexpr int TB = kWave + 2 * r;
-  const int plane = (int)geo.plane;
-  const float* xc = X + c0 * plane;
   if (geo.sb == 1) {
     constexpr int NR = (TA + Q - 1) / Q, NH = (TB + kWave - 1) / kWave;
     const int sa = (int)geo.sa;
@@ -306,7 +314,7 @@ DEV void load_tile_s1(float* lds, const float* __restrict__ G, const float* __re
       cok[h] = lv[h] && b < geo.W;
       lo[h] = cok[h] ? b : colbase;
     }
-    float v[NR][NH][CB + 1];
+    float v[NR][NH][NP + 1];
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
       const int ta = wq + i * Q, a = a_lo - 1 + ta;
@@ -316,7 +324,7 @@ DEV void load_tile_s1(float* lds, const float* __restrict__ G, const float* __re
         for (int h = 0; h < NH; ++h) {
           v[i][h][0] = gr[lo[h]];
 #pragma unroll
-          for (int c = 0; c < CB; ++c) v[i][h][c + 1] = (xc + c * plane + a * sa)[lo[h]];
+          for (int c = 0; c < NP; ++c) v[i][h][c + 1] = (src.at(c) + a * sa)[lo[h]];
         }
       }
     }
@@ -331,7 +339,7 @@ DEV void load_tile_s1(float* lds, const float* __restrict__ G, const float* __re
             float* d = lds + ta * pitch + lane + kWave * h;
             d[0] = rowok ? (cok[h] ? v[i][h][0] : 0.0f) : kSentinel;
 #pragma unroll
-            for (int c = 0; c < CB; ++c) d[(c + 1) * TA * pitch] = (rowok && cok[h]) ? v[i][h][c + 1] : 0.0f;
+            for (int c = 0; c < NP; ++c) d[(c + 1) * TA * pitch] = (rowok && cok[h]) ? v[i][h][c + 1] : 0.0f;
           }
       }
     }
@@ -347,7 +355,7 @@ DEV void load_tile_s1(float* lds, const float* __restrict__ G, const float* __re
       aok[h] = lv[h] && a >= 0 && a < geo.L;
       lo[h] = aok[h] ? a : 0;
     }
-    float v[NC][NH][CB + 1];
+    float v[NC][NH][NP + 1];
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
       const int tb = wq + i * Q, b = colbase + tb;
@@ -357,7 +365,7 @@ DEV void load_tile_s1(float* lds, const float* __restrict__ G, const float* __re
         for (int h = 0; h < NH; ++h) {
           v[i][h][0] = gc[lo[h]];
 #pragma unroll
-          for (int c = 0; c < CB; ++c) v[i][h][c + 1] = (xc + c * plane + b * sb)[lo[h]];
+          for (int c = 0; c < NP; ++c) v[i][h][c + 1] = (src.at(c) + b * sb)[lo[h]];
         }
       }
     }
@@ -372,7 +380,7 @@ DEV void load_tile_s1(float* lds, const float* __restrict__ G, const float* __re
             float* d = lds + (lane + kWave * h) * pitch + tb;
             d[0] = aok[h] ? (bok ? v[i][h][0] : 0.0f) : kSentinel;
 #pragma unroll
-            for (int c = 0; c < CB; ++c) d[(c + 1) * TA * pitch] = (aok[h] && bok) ? v[i][h][c + 1] : 0.0f;
+            for (int c = 0; c < NP; ++c) d[(c + 1) * TA * pitch] = (aok[h] && bok) ? v[i][h][c + 1] : 0.0f;
           }
       }
     }
@@ -438,15 +446,73 @@ DEV Acc diag_at(const float (&lw)[E + r][r], int m) {
 template <int r>
 DEV int tile_width(int stride) { return stride == 1 ? kWave + 2 * r : (kWave - 1) * stride + 2 * r + 1; }
 
+// Reciprocal cover counts of the 2r+1 columns k-r..k+r of strip k: the
+// adjoint of the averaging of Sec. 2.3 divides the output gradient by them.
+template <int r, bool S1>
+DEV void inv_counts(int k, const PassGeom& geo, float (&ic)[2 * r + 1]) {
+#pragma unroll
+  for (int q = 0; q <= 2 * r; ++q) {
+    const int b = k - r + q;
+    const int c = S1 ? min(geo.W - 1 - r, b + r) - max(r, b - r) + 1 : cover_count(b, geo, r);
+    ic[q] = 1.0f / float(max(c, 1));
+  }
+}
+
+// First strip of expand block bx (blocks own OW pass columns each; the strips
+// of a block are those whose columns touch the columns it owns).
+DEV int expand_first_strip(int bx, int OW, const PassGeom& geo, int r) {
+  const int b_lo = bx * OW;
+  int ki;
+  if (geo.stride == 1) {
+    ki = max(0, b_lo - 2 * r);
+  } else {
+    const int t = b_lo - 2 * r;
+    ki = t <= 0 ? 0 : (t + geo.stride - 1) / geo.stride;
+  }
+  return min(ki, geo.nK - 1);
+}
+
+// Guidance of the chunk elements m in [-r, E + r) (gv[m + r]) and the weights
+// omega(m, m+d) of Eq. (2) without lambda (om[m + r][d - 1], m in [-r, E)).
+template <int r, int R, bool S1, int KIND>
+DEV void chunk_omega(const ChunkView<r, R, S1>& cv, const WeightParams& wp,
+                     float (&gv)[ChunkView<r, R, S1>::E + 2 * r],
+                     float (&om)[ChunkView<r, R, S1>::E + r][r]) {
+  constexpr int E = ChunkView<r, R, S1>::E;
+#pragma unroll
+  for (int m = -r; m < E + r; ++m) gv[m + r] = cv.g(m);
+#pragma unroll
+  for (int m = -r; m < E; ++m)
+#pragma unroll
+    for (int d = 1; d <= r; ++d)
+      om[m + r][d - 1] = wp.spatial[d] * range_weight<KIND>(gv[m + r] - gv[m + d + r], wp);
+}
+
+// d omega / d dG for dG = G_p - G_q, given omega.  exp: -omega dG / sigma_r^2.
+// frac: -omega alpha_r |dG|^alpha_r / (dG (|dG|^alpha_r + eps)), taken as 0 at
+// dG = 0 where it is not differentiable for alpha_r <= 1.
+template <int KIND>
+DEV float domega(float w, float dg, const WeightParams& wp) {
+  if (KIND == 0) return -w * dg * wp.inv_sr2;
+  const float ad = fabsf(dg);
+  if (!(ad > 0.0f) || wp.alpha_r == 0.0f) return 0.0f;
+  const float pw = __builtin_amdgcn_exp2f(wp.alpha_r * __builtin_amdgcn_logf(ad));
+  return -w * wp.alpha_r * pw * __builtin_amdgcn_rcpf(pw + wp.eps) / dg;
+}
+
 // ---------------------------------------------------------------------------
 // k_reduce: Schur complement contributions of every chunk of 64 strips.
-template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc>
+// Forward: the right-hand sides are the CB channels of X.  Backward: also the
+// CB channels of the output gradient X2 divided by the cover counts, so the
+// pass solution and the adjoint solve share one elimination (NR = 2 CB).
+template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE>
 __global__ __launch_bounds__(kWave* Q) void k_reduce(
-    const float* __restrict__ X, const float* __restrict__ G, PassGeom geo, WeightParams wp,
-    const float* __restrict__ lam_dev, float lam_host, int c0, int pitch,
-    Acc* __restrict__ sum) {
+    const float* __restrict__ X, const float* __restrict__ X2, const float* __restrict__ G,
+    PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
+    int pitch, Acc* __restrict__ sum) {
+  constexpr int NR = MODE == kModeBackward ? 2 * CB : CB;
   using CV = ChunkView<r, R, S1>;
-  using LY = IfaceLayout<r, CB>;
+  using LY = IfaceLayout<r, NR>;
   constexpr int E = CV::E;
   constexpr int TA = Q * R + 2;
   extern __shared__ float smem[];
@@ -458,10 +524,11 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce(
   const int colbase = centre_of(ki_lo, geo, r) - r;
   const int TB = S1 ? kWave + 2 * r : tile_width<r>(geo.stride);
   const int pch = S1 ? CV::PITCH1 : pitch;
+  const PlaneSrc<CB> src{X, X2, c0, (int)geo.plane};
   if constexpr (S1)
-    load_tile_s1<r, CB, TA, Q>(smem, G, X, geo, c0, a_lo, colbase, pch, lane, wq);
+    load_tile_s1<r, NR, CB, TA, Q>(smem, G, src, geo, a_lo, colbase, pch, lane, wq);
   else
-    load_tile<CB, TA, kWave * Q, 8>(smem, G, X, geo, c0, a_lo, colbase, TB, pch, threadIdx.x);
+    load_tile<NR, CB, TA, kWave * Q, 8>(smem, G, src, geo, a_lo, colbase, TB, pch, threadIdx.x);
   __syncthreads();
 
   const int ki = ki_lo + lane;
@@ -469,8 +536,8 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce(
   const bool hasT = j > 0, hasB = j + 1 < geo.P;
   Acc W[r + 1][r + 1];   // Schur complement on the window, lower triangle
   Acc Bt[r + 1][r];      // window couplings to the previous separator
-  Acc Rw[r + 1][CB];     // window right-hand sides
-  Acc TT[r][r], RT[r][CB];
+  Acc Rw[r + 1][NR];     // window right-hand sides
+  Acc TT[r][r], RT[r][NR];
   if (active) {
     const float lam = load_lambda(lam_dev, lam_host);
     float lamS[r + 1];
@@ -485,13 +552,18 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce(
     cv.L = geo.L;
     float lw[E + r][r];
     chunk_weights<r, R, S1, KIND>(cv, wp, lamS, lw);
-    auto fval = [&](int m, int c) -> Acc { return Acc(cv.f(m, c)); };   // 0 outside
+    float ic[2 * r + 1];
+    if constexpr (MODE == kModeBackward) inv_counts<r, S1>(k, geo, ic);
+    auto fval = [&](int m, int c) -> Acc {   // 0 outside the subsystem
+      if (MODE == kModeBackward && c >= CB) return Acc(cv.f(m, c) * ic[col_of<r>(m) + r]);
+      return Acc(cv.f(m, c));
+    };
 #pragma unroll
     for (int a = 0; a < r; ++a) {
 #pragma unroll
       for (int b = 0; b < r; ++b) TT[a][b] = Acc(0);
 #pragma unroll
-      for (int c = 0; c < CB; ++c) RT[a][c] = Acc(0);
+      for (int c = 0; c < NR; ++c) RT[a][c] = Acc(0);
     }
 #pragma unroll
     for (int a = 0; a < r; ++a) {
@@ -501,7 +573,7 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce(
 #pragma unroll
       for (int c = 0; c < r; ++c) Bt[a][c] = (c >= a) ? -Acc(lw[c][a + r - c - 1]) : Acc(0);
 #pragma unroll
-      for (int c = 0; c < CB; ++c) Rw[a][c] = fval(a, c);
+      for (int c = 0; c < NR; ++c) Rw[a][c] = fval(a, c);
     }
     auto step = [&](const int m) {
       const int n = m + r;   // element entering the window
@@ -510,13 +582,13 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce(
 #pragma unroll
         for (int b = 0; b < r; ++b) W[r][b] = -Acc(lw[m + b + r][r - b - 1]);
 #pragma unroll
-        for (int c = 0; c < CB; ++c) Rw[r][c] = fval(n, c);
+        for (int c = 0; c < NR; ++c) Rw[r][c] = fval(n, c);
       } else {               // past the end of the subsystem
         W[r][r] = Acc(1);
 #pragma unroll
         for (int b = 0; b < r; ++b) W[r][b] = Acc(0);
 #pragma unroll
-        for (int c = 0; c < CB; ++c) Rw[r][c] = Acc(0);
+        for (int c = 0; c < NR; ++c) Rw[r][c] = Acc(0);
       }
 #pragma unroll
       for (int c = 0; c < r; ++c) Bt[r][c] = Acc(0);
@@ -538,12 +610,12 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce(
 #pragma unroll
         for (int c2 = 0; c2 <= c; ++c2) TT[c][c2] += bs * Bt[0][c2];
 #pragma unroll
-        for (int h = 0; h < CB; ++h) RT[c][h] += bs * Rw[0][h];
+        for (int h = 0; h < NR; ++h) RT[c][h] += bs * Rw[0][h];
       }
 #pragma unroll
       for (int a = 1; a <= r; ++a)
 #pragma unroll
-        for (int h = 0; h < CB; ++h) Rw[a][h] -= l[a] * Rw[0][h];
+        for (int h = 0; h < NR; ++h) Rw[a][h] -= l[a] * Rw[0][h];
 #pragma unroll
       for (int a = 0; a < r; ++a) {
 #pragma unroll
@@ -551,7 +623,7 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce(
 #pragma unroll
         for (int c = 0; c < r; ++c) Bt[a][c] = Bt[a + 1][c];
 #pragma unroll
-        for (int h = 0; h < CB; ++h) Rw[a][h] = Rw[a + 1][h];
+        for (int h = 0; h < NR; ++h) Rw[a][h] = Rw[a + 1][h];
       }
     };
     // Interior of a chunk with a separator: elements 0..E-r-1.  The last chunk
@@ -579,9 +651,9 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce(
 #pragma unroll
     for (int a = 0; a < r; ++a)
 #pragma unroll
-      for (int h = 0; h < CB; ++h) {
-        st[LY::oRf + a * CB + h] = hasB ? Rw[a][h] : Acc(0);
-        st[LY::oRT + a * CB + h] = hasT ? RT[a][h] : Acc(0);
+      for (int h = 0; h < NR; ++h) {
+        st[LY::oRf + a * NR + h] = hasB ? Rw[a][h] : Acc(0);
+        st[LY::oRT + a * NR + h] = hasT ? RT[a][h] : Acc(0);
       }
 #pragma unroll
     for (int a = 0; a < r; ++a)
@@ -929,11 +1001,27 @@ __global__ __launch_bounds__(kWave) void k_interface_serial(const Acc* __restric
 // k_expand: final solve of every chunk with its separators known, scatter and
 // average.  Block (x, y) owns pass columns [x*OW, x*OW + OW) and rows of chunks
 // [y*Q, y*Q + Q); its 64 lanes are the strips whose columns touch them.
-template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc>
+//
+// Backward (MODE = kModeBackward): the chunk is solved for the pass solution u
+// (right-hand sides X) and the adjoint solution ubar (right-hand sides X2 /
+// cover count) together.  Y receives the scattered sum of ubar (the input
+// gradient; the averaging was already applied to X2).  Every edge (p, q) of
+// the subsystem with q in the chunk (p may be one of the previous chunk's
+// last r elements, known from the separator solve) contributes
+// t = -sum_c (ubar_p - ubar_q)(u_p - u_q): omega t to the lambda gradient and
+// lambda t d omega / d(G_p - G_q) (+ at p, - at q) to the guidance gradient.
+// Terms of the previous chunk's elements go to bw.side (added by the fix-up
+// kernel); lambda partials go to bw.lpart, one per block, from the strips
+// the block owns (a strip is solved by the two blocks whose columns it
+// touches, and owned by the first).
+template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE>
 __global__ __launch_bounds__(kWave* Q) void k_expand(
     const float* __restrict__ X, const float* __restrict__ G, float* __restrict__ Y,
     PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
-    const Acc* __restrict__ Us, int OW, int pitch) {
+    const Acc* __restrict__ Us, int OW, int pitch, BwdArgs bw) {
+  constexpr bool BWD = MODE == kModeBackward;
+  constexpr int NR = BWD ? 2 * CB : CB;   // right-hand sides
+  constexpr int NO = BWD ? CB + 1 : CB;   // output planes (backward: + guidance gradient)
   using CV = ChunkView<r, R, S1>;
   constexpr int E = CV::E, w = CV::w;
   constexpr int TA = Q * R + 2;
@@ -941,23 +1029,17 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
   const int lane = threadIdx.x % kWave;
   const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int b_lo = blockIdx.x * OW, b_hi = min(b_lo + OW, geo.W);
-  int ki_lo;
-  if (geo.stride == 1) {
-    ki_lo = max(0, b_lo - 2 * r);
-  } else {
-    const int t = b_lo - 2 * r;
-    ki_lo = t <= 0 ? 0 : (t + geo.stride - 1) / geo.stride;
-  }
-  ki_lo = min(ki_lo, geo.nK - 1);
+  const int ki_lo = expand_first_strip(blockIdx.x, OW, geo, r);
   const int colbase = centre_of(ki_lo, geo, r) - r;
   const int j0 = blockIdx.y * Q, j = j0 + wq;
   const int a_lo = j0 * R;
   const int TB = S1 ? kWave + 2 * r : tile_width<r>(geo.stride);
   const int pch = S1 ? CV::PITCH1 : pitch;
+  const PlaneSrc<CB> src{X, bw.ybar, c0, (int)geo.plane};
   if constexpr (S1)
-    load_tile_s1<r, CB, TA, Q>(smem, G, X, geo, c0, a_lo, colbase, pch, lane, wq);
+    load_tile_s1<r, NR, CB, TA, Q>(smem, G, src, geo, a_lo, colbase, pch, lane, wq);
   else
-    load_tile<CB, TA, kWave * Q, 8>(smem, G, X, geo, c0, a_lo, colbase, TB, pch, threadIdx.x);
+    load_tile<NR, CB, TA, kWave * Q, 8>(smem, G, src, geo, a_lo, colbase, TB, pch, threadIdx.x);
   __syncthreads();
 
   const int ki = ki_lo + lane;
@@ -965,13 +1047,15 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
   const bool hasT = j > 0, hasB = j + 1 < geo.P;
   const int k = active ? centre_of(ki, geo, r) : colbase + r;
   const int rows = max(0, min(R, geo.L - j * R));
+  const bool want_edges = BWD && (bw.gbar != nullptr || bw.lpart != nullptr);
 
-  Acc Z[E][CB];     // z = D^{-1} L^{-1} f, overwritten by the solution u
+  Acc Z[E][NR];     // z = D^{-1} L^{-1} f, overwritten by the solution u
+  Acc uT[r][NR], uB[r][NR];
+  float gv[E + 2 * r];
+  float om[E + r][r];
+  float lam = 0.0f;
   if (active) {
-    const float lam = load_lambda(lam_dev, lam_host);
-    float lamS[r + 1];
-#pragma unroll
-    for (int d = 0; d <= r; ++d) lamS[d] = lam * wp.spatial[d];
+    lam = load_lambda(lam_dev, lam_host);
     CV cv;
     cv.base = smem + (wq * R + 1) * pch + (k - colbase);
     cv.pitch = pch;
@@ -979,28 +1063,43 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
     cv.a0 = j * R;
     cv.L = geo.L;
     float lw[E + r][r];
-    chunk_weights<r, R, S1, KIND>(cv, wp, lamS, lw);
-    auto fval = [&](int m, int c) -> Acc { return Acc(cv.f(m, c)); };   // 0 outside
+    if constexpr (BWD) {
+      chunk_omega<r, R, S1, KIND>(cv, wp, gv, om);
+#pragma unroll
+      for (int m = 0; m < E + r; ++m)
+#pragma unroll
+        for (int d = 0; d < r; ++d) lw[m][d] = lam * om[m][d];
+    } else {
+      float lamS[r + 1];
+#pragma unroll
+      for (int d = 0; d <= r; ++d) lamS[d] = lam * wp.spatial[d];
+      chunk_weights<r, R, S1, KIND>(cv, wp, lamS, lw);
+    }
+    float ic[2 * r + 1];
+    if constexpr (BWD) inv_counts<r, S1>(k, geo, ic);
+    auto fval = [&](int m, int c) -> Acc {   // 0 outside the subsystem
+      if (BWD && c >= CB) return Acc(cv.f(m, c) * ic[col_of<r>(m) + r]);
+      return Acc(cv.f(m, c));
+    };
     const int n_sep = geo.P - 1;
-    const Acc* us = Us + (size_t)ki * n_sep * r * CB;
-    Acc uT[r][CB], uB[r][CB];
+    const Acc* us = Us + (size_t)ki * n_sep * r * NR;
 #pragma unroll
     for (int a = 0; a < r; ++a)
 #pragma unroll
-      for (int h = 0; h < CB; ++h) {
-        uT[a][h] = hasT ? us[(size_t)(j - 1) * r * CB + a * CB + h] : Acc(0);
-        uB[a][h] = hasB ? us[(size_t)j * r * CB + a * CB + h] : Acc(0);
+      for (int h = 0; h < NR; ++h) {
+        uT[a][h] = hasT ? us[(size_t)(j - 1) * r * NR + a * NR + h] : Acc(0);
+        uB[a][h] = hasB ? us[(size_t)j * r * NR + a * NR + h] : Acc(0);
       }
     Acc Lf[E][r];   // Lf[m][a-1] = L(m+a, m)
     Acc W[r + 1][r + 1];
-    Acc Rw[r + 1][CB];
+    Acc Rw[r + 1][NR];
 #pragma unroll
     for (int a = 0; a < r; ++a) {
       W[a][a] = diag_at<r, E, Acc>(lw, a);
 #pragma unroll
       for (int b = 0; b < a; ++b) W[a][b] = -Acc(lw[b + r][a - b - 1]);
 #pragma unroll
-      for (int h = 0; h < CB; ++h) {
+      for (int h = 0; h < NR; ++h) {
         Acc v = fval(a, h);
 #pragma unroll
         for (int c = a; c < r; ++c) v += Acc(lw[c][a + r - c - 1]) * uT[c][h];
@@ -1016,21 +1115,21 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
 #pragma unroll
         for (int b = 0; b < r; ++b)
 #pragma unroll
-          for (int h = 0; h < CB; ++h) Rw[b][h] += Acc(lw[m + b + r][r - b - 1]) * uB[bi][h];
+          for (int h = 0; h < NR; ++h) Rw[b][h] += Acc(lw[m + b + r][r - b - 1]) * uB[bi][h];
       } else if (n < E) {
         dummy = false;
         W[r][r] = diag_at<r, E, Acc>(lw, n);
 #pragma unroll
         for (int b = 0; b < r; ++b) W[r][b] = -Acc(lw[m + b + r][r - b - 1]);
 #pragma unroll
-        for (int h = 0; h < CB; ++h) Rw[r][h] = fval(n, h);
+        for (int h = 0; h < NR; ++h) Rw[r][h] = fval(n, h);
       }
       if (dummy) {
         W[r][r] = Acc(1);
 #pragma unroll
         for (int b = 0; b < r; ++b) W[r][b] = Acc(0);
 #pragma unroll
-        for (int h = 0; h < CB; ++h) Rw[r][h] = Acc(0);
+        for (int h = 0; h < NR; ++h) Rw[r][h] = Acc(0);
       }
       const Acc invD = recip(W[0][0]);
       Acc l[r + 1];
@@ -1040,7 +1139,7 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
         Lf[m][a - 1] = l[a];
       }
 #pragma unroll
-      for (int h = 0; h < CB; ++h) Z[m][h] = Rw[0][h] * invD;
+      for (int h = 0; h < NR; ++h) Z[m][h] = Rw[0][h] * invD;
 #pragma unroll
       for (int a = 1; a <= r; ++a)
 #pragma unroll
@@ -1048,13 +1147,13 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
 #pragma unroll
       for (int a = 1; a <= r; ++a)
 #pragma unroll
-        for (int h = 0; h < CB; ++h) Rw[a][h] -= l[a] * Rw[0][h];
+        for (int h = 0; h < NR; ++h) Rw[a][h] -= l[a] * Rw[0][h];
 #pragma unroll
       for (int a = 0; a < r; ++a) {
 #pragma unroll
         for (int b = 0; b <= a; ++b) W[a][b] = W[a + 1][b + 1];
 #pragma unroll
-        for (int h = 0; h < CB; ++h) Rw[a][h] = Rw[a + 1][h];
+        for (int h = 0; h < NR; ++h) Rw[a][h] = Rw[a + 1][h];
       }
     };
 #pragma unroll
@@ -1066,7 +1165,7 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
 #pragma unroll
       for (int a = 0; a < r; ++a) {
 #pragma unroll
-        for (int h = 0; h < CB; ++h) Z[E - r + a][h] = uB[a][h];
+        for (int h = 0; h < NR; ++h) Z[E - r + a][h] = uB[a][h];
 #pragma unroll
         for (int t = 0; t < r; ++t) Lf[E - r + a][t] = Acc(0);
       }
@@ -1076,7 +1175,7 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
     for (int m = E - 1; m >= 0; --m) {
       if (m < E - r || !hasB) {
 #pragma unroll
-        for (int h = 0; h < CB; ++h) {
+        for (int h = 0; h < NR; ++h) {
           Acc v = Z[m][h];
 #pragma unroll
           for (int a = 1; a <= r; ++a)
@@ -1085,54 +1184,124 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
         }
       }
     }
+  } else {
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+#pragma unroll
+      for (int h = 0; h < NR; ++h) Z[m][h] = Acc(0);
   }
+
+  // Backward edge terms (guidance gradient per element, lambda partial).
+  float Gv[BWD ? E + r : 1];
+  double lsum = 0.0;
+  if constexpr (BWD) {
+#pragma unroll
+    for (int m = 0; m < E + r; ++m) Gv[m] = 0.0f;
+    const int ki_next = blockIdx.x + 1 < gridDim.x
+                            ? expand_first_strip(blockIdx.x + 1, OW, geo, r) : geo.nK;
+    const bool owns = ki < ki_next;
+    if (active && want_edges) {
+#pragma unroll
+      for (int q = 0; q < E; ++q)
+#pragma unroll
+        for (int d = 1; d <= r; ++d) {
+          const int p = q - d;
+          if (p >= -r) {
+            Acc t = Acc(0);
+#pragma unroll
+            for (int h = 0; h < CB; ++h) {
+              const Acc up = p < 0 ? uT[p + r][h] : Z[p][h];
+              const Acc bp = p < 0 ? uT[p + r][CB + h] : Z[p][CB + h];
+              t -= (bp - Z[q][CB + h]) * (up - Z[q][h]);
+            }
+            const float wpq = om[p + r][d - 1];
+            if (owns) lsum += double(wpq) * double(t);
+            const float kap = float(Acc(lam) * t) * domega<KIND>(wpq, gv[p + r] - gv[q + r], wp);
+            Gv[p + r] += kap;
+            Gv[q + r] -= kap;
+          }
+        }
+    }
+    if (bw.lpart) {
+      __shared__ double lred[16];
+      double v = lsum;
+#pragma unroll
+      for (int off = kWave / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+      if (lane == 0) lred[wq] = v;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < Q; ++i) s += lred[i];
+        bw.lpart[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+      }
+    }
+  }
+  const bool wantg = BWD && bw.gbar != nullptr;
+  // value of output plane o at element m of this lane's strip
+  auto outval = [&](int m, int o) -> float {
+    if constexpr (BWD) return o < CB ? float(Z[m][CB + o]) : Gv[m + r];
+    return float(Z[m][o]);
+  };
+
   const int nrow = Q * R;
   const int arows = max(0, min(nrow, geo.L - a_lo));
-  float* Yc = Y + c0 * (int)geo.plane;
+  const int plane = (int)geo.plane;
+  float* Yc = Y + c0 * plane;
   if constexpr (S1) {
     // Lane l outputs column b = colbase + l.  The strips covering it are the
     // lanes l-2r..l (centres b+r..b-r); lane l-t holds column b at row-vector
     // position t on even rows and 2r-t on odd rows.  Lanes without a strip
     // contribute 0 (including those left of lane 0).  The sum is a fixed
     // nesting of one-lane wave shifts, so it is reproducible.
-    if (!active) {
-#pragma unroll
-      for (int m = 0; m < E; ++m)
-#pragma unroll
-        for (int h = 0; h < CB; ++h) Z[m][h] = Acc(0);
-    }
     const int b = colbase + lane;
     const bool own = b >= b_lo && b < b_hi && j < geo.P;
-    const int cnt = min(geo.W - 1 - r, b + r) - max(r, b - r) + 1;
-    const float inv = __builtin_amdgcn_rcpf(float(max(cnt, 1)));
-    float out[R][CB];
+    float inv = 1.0f;
+    if constexpr (!BWD) {
+      const int cnt = min(geo.W - 1 - r, b + r) - max(r, b - r) + 1;
+      inv = __builtin_amdgcn_rcpf(float(max(cnt, 1)));
+    }
+    float out[R][NO];
 #pragma unroll
     for (int rho = 0; rho < R; ++rho)
 #pragma unroll
-      for (int h = 0; h < CB; ++h) {
+      for (int o = 0; o < NO; ++o) {
         // sum_t shift_t(v_t) evaluated as v_0 + shift(v_1 + shift(v_2 + ...))
-        float acc = float(Z[rho * w + ((rho & 1) ? 0 : 2 * r)][h]);
+        float acc = outval(rho * w + ((rho & 1) ? 0 : 2 * r), o);
 #pragma unroll
         for (int t = 2 * r - 1; t >= 0; --t)
-          acc = float(Z[rho * w + ((rho & 1) ? 2 * r - t : t)][h]) + lane_shr1(acc);
-        out[rho][h] = acc * inv;
+          acc = outval(rho * w + ((rho & 1) ? 2 * r - t : t), o) + lane_shr1(acc);
+        out[rho][o] = acc * inv;
       }
+    if constexpr (BWD) {
+      // The previous chunk's last row is odd: its element -r+i (i < r) lies in
+      // column k-1-i, so column b gathers element -r+i of lane l-r+1+i.
+      if (wantg) {
+        float sacc = Gv[0];
+#pragma unroll
+        for (int i = 1; i < r; ++i) sacc = Gv[i] + lane_shr1(sacc);
+        if (own && hasT) bw.side[(size_t)j * geo.W + b] = sacc;
+      }
+    }
     if (geo.sb == 1) {   // column pass: lanes write consecutive columns of each row
       if (own) {
 #pragma unroll
         for (int rho = 0; rho < R; ++rho)
-          if (rho < rows)
+          if (rho < rows) {
+            const int o = (j * R + rho) * (int)geo.sa + b;
 #pragma unroll
-            for (int h = 0; h < CB; ++h)
-              Yc[h * (int)geo.plane + (j * R + rho) * (int)geo.sa + b] = out[rho][h];
+            for (int h = 0; h < CB; ++h) Yc[h * plane + o] = out[rho][h];
+            if constexpr (BWD) {
+              if (wantg) bw.gbar[o] = (bw.gacc ? bw.gbar[o] : 0.0f) + out[rho][CB];
+            }
+          }
       }
     } else {             // row pass: transpose through the (consumed) image planes
       if (own) {
 #pragma unroll
         for (int rho = 0; rho < R; ++rho)
 #pragma unroll
-          for (int h = 0; h < CB; ++h)
-            smem[(h + 1) * TA * pch + (wq * R + 1 + rho) * pch + lane] = out[rho][h];
+          for (int o = 0; o < NO; ++o)
+            smem[(o + 1) * TA * pch + (wq * R + 1 + rho) * pch + lane] = out[rho][o];
       }
       __syncthreads();
       const int ncols = b_hi - b_lo;
@@ -1140,20 +1309,24 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
         const int bc = idx / arows, tr = idx - bc * arows;
         const int bb = b_lo + bc, a = a_lo + tr;
         const float* cell = smem + TA * pch + (tr + 1) * pch + (bb - colbase);
+        const int o = a + bb * (int)geo.sb;
 #pragma unroll
-        for (int h = 0; h < CB; ++h)
-          Yc[h * (int)geo.plane + a + bb * (int)geo.sb] = cell[h * TA * pch];
+        for (int h = 0; h < CB; ++h) Yc[h * plane + o] = cell[h * TA * pch];
+        if constexpr (BWD) {
+          if (wantg) bw.gbar[o] = (bw.gacc ? bw.gbar[o] : 0.0f) + cell[CB * TA * pch];
+        }
       }
     }
   } else {
     __syncthreads();   // all tile reads done: the image planes become accumulators
-    for (int p = 1; p <= CB; ++p)
-      for (int idx = threadIdx.x; idx < nrow * TB; idx += kWave * Q) {
-        const int ta = 1 + idx / TB, tb = idx - (ta - 1) * TB;
+    constexpr int r0 = BWD ? 0 : 1;   // backward also accumulates the row above
+    for (int p = 1; p <= NO; ++p)
+      for (int idx = threadIdx.x; idx < (nrow + 1 - r0) * TB; idx += kWave * Q) {
+        const int ta = r0 + idx / TB, tb = idx - (ta - r0) * TB;
         smem[p * TA * pch + ta * pch + tb] = 0.0f;
       }
     __syncthreads();
-    // Average over the strips covering each pixel, in a fixed order (q = 0..2r).
+    // Sum over the strips covering each pixel, in a fixed order (q = 0..2r).
 #pragma unroll
     for (int q = 0; q < w; ++q) {
       if (active) {
@@ -1163,11 +1336,20 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
             const int col = ((rho & 1) ? (k + r - q) : (k - r + q)) - colbase;
             float* cell = smem + TA * pch + (wq * R + 1 + rho) * pch + col;
 #pragma unroll
-            for (int h = 0; h < CB; ++h) cell[h * TA * pch] += float(Z[rho * w + q][h]);
+            for (int o = 0; o < NO; ++o) cell[o * TA * pch] += outval(rho * w + q, o);
           }
         }
       }
       __syncthreads();
+    }
+    if constexpr (BWD) {
+      // terms of the previous chunk's last row (odd: element -r+i at k-1-i)
+#pragma unroll
+      for (int i = 0; i < r; ++i) {
+        if (active && wantg)
+          smem[NO * TA * pch + (wq * R) * pch + (k - 1 - i - colbase)] += Gv[i];
+        __syncthreads();
+      }
     }
     const int ncols = b_hi - b_lo;
     for (int idx = threadIdx.x; idx < arows * ncols; idx += kWave * Q) {
@@ -1180,105 +1362,131 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
         tr = idx - bc * arows;
       }
       const int bb = b_lo + bc, a = a_lo + tr;
-      const float inv = 1.0f / float(cover_count(bb, geo, r));
+      const float inv = BWD ? 1.0f : 1.0f / float(cover_count(bb, geo, r));
       const float* cell = smem + TA * pch + (tr + 1) * pch + (bb - colbase);
       const int o = geo.sb == 1 ? a * (int)geo.sa + bb : a + bb * (int)geo.sb;
 #pragma unroll
-      for (int h = 0; h < CB; ++h) Yc[h * (int)geo.plane + o] = cell[h * TA * pch] * inv;
+      for (int h = 0; h < CB; ++h) Yc[h * plane + o] = cell[h * TA * pch] * inv;
+      if constexpr (BWD) {
+        if (wantg) bw.gbar[o] = (bw.gacc ? bw.gbar[o] : 0.0f) + cell[CB * TA * pch];
+      }
+    }
+    if constexpr (BWD) {
+      if (wantg && j0 > 0 && j0 < geo.P)
+        for (int bc = threadIdx.x; bc < ncols; bc += kWave * Q)
+          bw.side[(size_t)j0 * geo.W + b_lo + bc] = smem[NO * TA * pch + (b_lo + bc - colbase)];
     }
   }
 }
 
 // ---------------------------------------------------------------------------
 // Launch of one pass for one (r, channel block, precision, stride class,
-// weight kind, variant).
-template <int r, int CB, int fp64, bool S1, int KIND, int R, int Q>
+// weight kind, variant, mode).
+template <int r, int CB, int fp64, bool S1, int KIND, int R, int Q, int MODE>
 hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const PassGeom& geo,
                        const PassPlan& pl, const WeightParams& wp, const float* lam_dev,
-                       float lam_host, void* iface, hipStream_t stream, int stages) {
+                       float lam_host, void* iface, hipStream_t stream, int stages,
+                       const BwdArgs& bw) {
   using Acc = typename std::conditional<fp64 != 0, double, float>::type;
-  constexpr VariantSet VS = variants_of(r, CB, fp64);
-  using LY = IfaceLayout<r, CB>;
+  constexpr int NR = MODE == kModeBackward ? 2 * CB : CB;
+  constexpr VariantSet VS = variants_for(MODE, r, CB, fp64);
+  using LY = IfaceLayout<r, NR>;
   Acc* sum = reinterpret_cast<Acc*>(iface);
   Acc* us = sum + pl.sum_elems;
   Acc* gb = us + pl.u_elems;
-  const size_t tile = sizeof(float) * (size_t)(CB + 1) * (Q * R + 2) * pl.pitch;
+  const size_t tile = sizeof(float) * (size_t)(NR + 1) * (Q * R + 2) * pl.pitch;
   const size_t stage_out = sizeof(Acc) * (size_t)kWave * Q * LY::F;
   const int gy = (geo.P + Q - 1) / Q;
   if (geo.P > 1 && (stages & kStageReduce)) {
     const int gx = (geo.nK + kWave - 1) / kWave;
-    hipLaunchKernelGGL((k_reduce<r, CB, R, Q, S1, KIND, Acc>), dim3(gx, gy), dim3(kWave * Q),
-                       std::max(tile, stage_out), stream, x, g, geo, wp, lam_dev, lam_host, c0,
-                       pl.pitch, sum);
+    hipLaunchKernelGGL((k_reduce<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(gx, gy), dim3(kWave * Q),
+                       std::max(tile, stage_out), stream, x, bw.ybar, g, geo, wp, lam_dev,
+                       lam_host, c0, pl.pitch, sum);
   }
   if (geo.P > 1 && (stages & kStageInterface)) {
     if (VS.MM > 0 && pl.iface_m > 0 && pl.iface_m <= VS.MM) {
       constexpr int MM = VS.MM > 0 ? VS.MM : 1;
-      hipLaunchKernelGGL((k_interface_pcr<r, CB, MM, Acc>), dim3(geo.nK), dim3(kWave), 0,
+      hipLaunchKernelGGL((k_interface_pcr<r, NR, MM, Acc>), dim3(geo.nK), dim3(kWave), 0,
                          stream, (const Acc*)sum, us, geo.nK, geo.P, pl.iface_m);
     } else {
-      hipLaunchKernelGGL((k_interface_serial<r, CB, Acc>), dim3((geo.nK + kWave - 1) / kWave),
+      hipLaunchKernelGGL((k_interface_serial<r, NR, Acc>), dim3((geo.nK + kWave - 1) / kWave),
                          dim3(kWave), 0, stream, (const Acc*)sum, us, gb, geo.nK, geo.P);
     }
   }
   if (stages & kStageExpand) {
     const int ex = (geo.W + pl.OW - 1) / pl.OW;
-    hipLaunchKernelGGL((k_expand<r, CB, R, Q, S1, KIND, Acc>), dim3(ex, gy), dim3(kWave * Q), tile,
-                       stream, x, g, y, geo, wp, lam_dev, lam_host, c0, (const Acc*)us, pl.OW,
-                       pl.pitch);
+    hipLaunchKernelGGL((k_expand<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(ex, gy), dim3(kWave * Q),
+                       tile, stream, x, g, y, geo, wp, lam_dev, lam_host, c0, (const Acc*)us,
+                       pl.OW, pl.pitch, bw);
   }
   return hipGetLastError();
 }
 
 // Runtime selection of the compiled variant (stride-1 passes) or of the
 // strided kernel (variant 0's R, one chunk per block).
-template <int r, int CB, int fp64, int KIND, int VI>
+template <int r, int CB, int fp64, int KIND, int MODE, int VI>
 hipError_t launch_variant(int vi, const float* x, const float* g, float* y, int c0,
                           const PassGeom& geo, const PassPlan& pl, const WeightParams& wp,
                           const float* lam_dev, float lam_host, void* iface, hipStream_t s,
-                          int st) {
-  constexpr VariantSet VS = variants_of(r, CB, fp64);
+                          int st, const BwdArgs& bw) {
+  constexpr VariantSet VS = variants_for(MODE, r, CB, fp64);
   if constexpr (VI < VS.n) {
     if (vi == VI)
-      return launch_impl<r, CB, fp64, true, KIND, VS.v[VI].R, VS.v[VI].Q>(
-          x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
-    return launch_variant<r, CB, fp64, KIND, VI + 1>(vi, x, g, y, c0, geo, pl, wp, lam_dev,
-                                                     lam_host, iface, s, st);
+      return launch_impl<r, CB, fp64, true, KIND, VS.v[VI].R, VS.v[VI].Q, MODE>(
+          x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st, bw);
+    return launch_variant<r, CB, fp64, KIND, MODE, VI + 1>(vi, x, g, y, c0, geo, pl, wp, lam_dev,
+                                                           lam_host, iface, s, st, bw);
   } else {
     return hipErrorInvalidValue;
   }
 }
 
-template <int r, int CB, int fp64, int KIND>
+template <int r, int CB, int fp64, int KIND, int MODE>
 hipError_t launch_kind(const float* x, const float* g, float* y, int c0, const PassGeom& geo,
                        const PassPlan& pl, const WeightParams& wp, const float* lam_dev,
-                       float lam_host, void* iface, hipStream_t s, int st) {
-  constexpr VariantSet VS = variants_of(r, CB, fp64);
+                       float lam_host, void* iface, hipStream_t s, int st, const BwdArgs& bw) {
+  constexpr VariantSet VS = variants_for(MODE, r, CB, fp64);
   if (geo.stride != 1)
-    return launch_impl<r, CB, fp64, false, KIND, VS.v[0].R, 1>(x, g, y, c0, geo, pl, wp,
-                                                                lam_dev, lam_host, iface, s, st);
-  return launch_variant<r, CB, fp64, KIND, 0>(pl.variant, x, g, y, c0, geo, pl, wp, lam_dev,
-                                              lam_host, iface, s, st);
+    return launch_impl<r, CB, fp64, false, KIND, VS.v[0].R, 1, MODE>(
+        x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st, bw);
+  return launch_variant<r, CB, fp64, KIND, MODE, 0>(pl.variant, x, g, y, c0, geo, pl, wp,
+                                                    lam_dev, lam_host, iface, s, st, bw);
 }
 
-template <int r, int CB, int fp64>
+template <int r, int CB, int fp64, int MODE>
 hipError_t launch_prec(const float* x, const float* g, float* y, int c0, const PassGeom& geo,
                        const PassPlan& pl, const WeightParams& wp, const float* lam_dev,
-                       float lam_host, void* iface, hipStream_t s, int st) {
+                       float lam_host, void* iface, hipStream_t s, int st, const BwdArgs& bw) {
   return wp.kind == 0
-             ? launch_kind<r, CB, fp64, 0>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st)
-             : launch_kind<r, CB, fp64, 1>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
+             ? launch_kind<r, CB, fp64, 0, MODE>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host,
+                                                 iface, s, st, bw)
+             : launch_kind<r, CB, fp64, 1, MODE>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host,
+                                                 iface, s, st, bw);
+}
+
+template <int r, int MODE>
+hipError_t launch_mode(int cb, int fp64, const float* x, const float* g, float* y, int c0,
+                       const PassGeom& geo, const PassPlan& pl, const WeightParams& wp,
+                       const float* lam_dev, float lam_host, void* iface, hipStream_t s, int st,
+                       const BwdArgs& bw) {
+  if (cb == 3)
+    return fp64 ? launch_prec<r, 3, 1, MODE>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st, bw)
+                : launch_prec<r, 3, 0, MODE>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st, bw);
+  return fp64 ? launch_prec<r, 1, 1, MODE>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st, bw)
+              : launch_prec<r, 1, 0, MODE>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st, bw);
 }
 
 template <int r>
 hipError_t launch_r(int cb, int fp64, const float* x, const float* g, float* y, int c0,
                     const PassGeom& geo, const PassPlan& pl, const WeightParams& wp,
-                    const float* lam_dev, float lam_host, void* iface, hipStream_t s, int st) {
-  if (cb == 3)
-    return fp64 ? launch_prec<r, 3, 1>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st)
-                : launch_prec<r, 3, 0>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
-  return fp64 ? launch_prec<r, 1, 1>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st)
-              : launch_prec<r, 1, 0>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st);
+                    const float* lam_dev, float lam_host, void* iface, hipStream_t s, int st,
+                    const BwdArgs* bw) {
+  if (pl.mode == kModeBackward)
+    return launch_mode<r, kModeBackward>(cb, fp64, x, g, y, c0, geo, pl, wp, lam_dev, lam_host,
+                                         iface, s, st, *bw);
+  const BwdArgs none{};
+  return launch_mode<r, kModeForward>(cb, fp64, x, g, y, c0, geo, pl, wp, lam_dev, lam_host,
+                                      iface, s, st, none);
 }
 
 }  // namespace
@@ -1288,9 +1496,10 @@ hipError_t launch_r(int cb, int fp64, const float* x, const float* g, float* y, 
   hipError_t launch_pass_r##RR(int cb, int fp64, const float* x, const float* g, float* y,  \
                                int c0, const PassGeom& geo, const PassPlan& plan,           \
                                const WeightParams& wp, const float* lam_dev,                \
-                               float lam_host, void* iface, hipStream_t stream, int stages) { \
+                               float lam_host, void* iface, hipStream_t stream, int stages, \
+                               const BwdArgs* bw) {                                          \
     return launch_r<RR>(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface,     \
-                        stream, stages);                                                     \
+                        stream, stages, bw);                                                 \
   }
 
 }  // namespace sgwls

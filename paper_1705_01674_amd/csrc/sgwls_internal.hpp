@@ -18,6 +18,7 @@ struct WeightParams {
   float range_c2;              // exp: log2(e) / (2 sigma_r^2), so R = 2^(-dG^2 * range_c2)
   float alpha_r;               // frac: exponent of |G_i - G_j|
   float eps;                   // frac: epsilon
+  float inv_sr2;               // exp: 1 / sigma_r^2 (derivative of the range factor)
 };
 
 // Geometry of one pass.  A pass solves one subsystem per strip centre k; the
@@ -49,6 +50,10 @@ struct VariantSet {
   int MM;   // separators per lane handled by the wave interface solver
 };
 
+// Kernels of a pass: the forward solve, or its adjoint (two right-hand sides
+// per channel: the recomputed pass solution and the adjoint solve).
+constexpr int kModeForward = 0, kModeBackward = 1;
+
 // The expand kernel keeps (r + CB) values per chunk element in registers, so
 // R shrinks as r, the channel block and the precision grow.
 constexpr VariantSet variants_of(int r, int cb, int fp64) {
@@ -70,9 +75,28 @@ constexpr VariantSet variants_of(int r, int cb, int fp64) {
   return VariantSet{1, {{2, 2}}, 0};
 }
 
+// Backward variants: 2*cb right-hand sides per element.
+constexpr VariantSet bwd_variants_of(int r, int cb, int fp64) {
+  if (fp64) {
+    if (r == 1) return cb == 1 ? VariantSet{1, {{8, 4}}, 8} : VariantSet{1, {{4, 4}}, 8};
+    if (r == 2) return VariantSet{1, {{2, 4}}, 0};
+    return VariantSet{1, {{2, 2}}, 0};
+  }
+  if (r == 1)
+    return cb == 1 ? VariantSet{2, {{8, 4}, {4, 4}}, 8} : VariantSet{2, {{4, 4}, {4, 8}}, 8};
+  if (r == 2) return VariantSet{1, {{4, 4}}, 8};
+  return VariantSet{1, {{2, 2}}, 0};
+}
+
+constexpr VariantSet variants_for(int mode, int r, int cb, int fp64) {
+  return mode == kModeBackward ? bwd_variants_of(r, cb, fp64) : variants_of(r, cb, fp64);
+}
+
 // Launch configuration of one (r, channel block, precision, stride, variant).
 struct PassPlan {
-  int variant;      // index into variants_of(r, cb, fp64)
+  int mode;         // kModeForward or kModeBackward
+  int nr;           // right-hand sides per element (cb, or 2*cb backward)
+  int variant;      // index into variants_for(mode, r, cb, fp64)
   int R;            // rows per chunk
   int Q;            // chunks per reduce / expand block (one wave each)
   int P;            // chunks per subsystem
@@ -87,27 +111,52 @@ struct PassPlan {
 
 // Host-side planning (sgwls_plan.cpp).
 int strip_count(int W, int r, int stride);
-PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64, int variant);
+PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64, int variant,
+                   int mode = kModeForward);
 size_t interface_bytes(const PassPlan& pl);
 // Largest interface_bytes over every variant of the case.
-size_t interface_bytes_max(int L, int W, int r, int cb, int stride, int fp64);
+size_t interface_bytes_max(int L, int W, int r, int cb, int stride, int fp64,
+                           int mode = kModeForward);
+// Expand blocks of a plan (one double of the lambda gradient each).
+int expand_blocks(const PassGeom& geo, const PassPlan& pl);
 
 // Stages of one pass (bit mask): reduce, interface solve, expand.
 constexpr int kStageReduce = 1, kStageInterface = 2, kStageExpand = 4, kStageAll = 7;
 
+// Extra operands of a backward pass (all device pointers).
+struct BwdArgs {
+  const float* ybar;   // gradient of the pass output, C planes
+  float* gbar;         // gradient of the guidance (NULL: not wanted)
+  float* side;         // P x W floats: guidance-gradient terms of edges that cross chunk
+                       // boundaries, for the pixels of the chunk above
+  double* lpart;       // one partial lambda gradient per expand block (NULL: not wanted)
+  int gacc;            // 1: add to gbar, 0: overwrite it
+};
+
 // Enqueue the stages in `stages` of one pass for channels [c0, c0+cb) of x
-// into y.  `iface` must hold interface_bytes(plan).  Returns a hipError_t.
+// into y.  `iface` must hold interface_bytes(plan).  For a backward plan, x is
+// the saved pass input, y receives the input gradient and `bw` carries the
+// rest.  Returns a hipError_t.
 hipError_t launch_pass(int r, int cb, int fp64, const float* x, const float* g, float* y,
                        int c0, const PassGeom& geo, const PassPlan& plan,
                        const WeightParams& wp, const float* lam_dev, float lam_host,
-                       void* iface, hipStream_t stream, int stages);
+                       void* iface, hipStream_t stream, int stages,
+                       const BwdArgs* bw = nullptr);
+
+// After the backward expand of a pass: add the side terms into gbar (when
+// non-NULL) and reduce the nparts lambda partials into *glam (when both are
+// non-NULL; lam_acc = 1 adds, 0 overwrites), in a fixed order.
+hipError_t launch_bwd_fixup(const float* side, float* gbar, const PassGeom& geo,
+                            const double* lpart, int nparts, double* glam, int lam_acc,
+                            hipStream_t stream);
 
 // Per-radius entry points (one translation unit each).
 #define SGWLS_DECLARE_LAUNCH(RR)                                                            \
   hipError_t launch_pass_r##RR(int cb, int fp64, const float* x, const float* g, float* y, \
                                int c0, const PassGeom& geo, const PassPlan& plan,          \
                                const WeightParams& wp, const float* lam_dev,               \
-                               float lam_host, void* iface, hipStream_t stream, int stages);
+                               float lam_host, void* iface, hipStream_t stream, int stages, \
+                               const BwdArgs* bw);
 SGWLS_DECLARE_LAUNCH(1)
 SGWLS_DECLARE_LAUNCH(2)
 SGWLS_DECLARE_LAUNCH(3)

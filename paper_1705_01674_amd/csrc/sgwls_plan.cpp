@@ -13,10 +13,12 @@ int strip_count(int W, int r, int stride) {
   return regular + ((span % stride) != 0 ? 1 : 0);
 }
 
-PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64, int variant) {
+PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64, int variant, int mode) {
   PassPlan pl{};
-  const VariantSet vs = variants_of(r, cb, fp64);
+  const VariantSet vs = variants_for(mode, r, cb, fp64);
   if (stride != 1 || variant < 0 || variant >= vs.n) variant = 0;
+  pl.mode = mode;
+  pl.nr = mode == kModeBackward ? 2 * cb : cb;
   pl.variant = variant;
   pl.R = vs.v[variant].R;
   pl.Q = stride == 1 ? vs.v[variant].Q : 1;
@@ -29,10 +31,10 @@ PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64, int varian
   const int m = (n + kWave - 1) / kWave;
   pl.iface_m = (vs.MM > 0 && m <= vs.MM) ? std::max(m, 1) : 0;
   const int T2 = r * (r + 1) / 2;
-  const int F = 2 * T2 + 2 * r * cb + r * r;
+  const int F = 2 * T2 + 2 * r * pl.nr + r * r;
   pl.acc_bytes = fp64 ? 8 : 4;
   pl.sum_elems = (size_t)pl.P * F * pl.nK;
-  pl.u_elems = (size_t)std::max(n, 1) * r * cb * pl.nK;
+  pl.u_elems = (size_t)std::max(n, 1) * r * pl.nr * pl.nK;
   return pl;
 }
 
@@ -42,23 +44,28 @@ size_t interface_bytes(const PassPlan& pl) {
   return (pl.sum_elems + pl.u_elems + g_elems) * (size_t)pl.acc_bytes + 256;
 }
 
-size_t interface_bytes_max(int L, int W, int r, int cb, int stride, int fp64) {
-  const VariantSet vs = variants_of(r, cb, fp64);
+size_t interface_bytes_max(int L, int W, int r, int cb, int stride, int fp64, int mode) {
+  const VariantSet vs = variants_for(mode, r, cb, fp64);
   size_t need = 0;
   for (int v = 0; v < (stride == 1 ? vs.n : 1); ++v)
-    need = std::max(need, interface_bytes(make_plan(L, W, r, cb, stride, fp64, v)));
+    need = std::max(need, interface_bytes(make_plan(L, W, r, cb, stride, fp64, v, mode)));
   return need;
+}
+
+int expand_blocks(const PassGeom& geo, const PassPlan& pl) {
+  return ((geo.W + pl.OW - 1) / pl.OW) * ((geo.P + pl.Q - 1) / pl.Q);
 }
 
 hipError_t launch_pass(int r, int cb, int fp64, const float* x, const float* g, float* y,
                        int c0, const PassGeom& geo, const PassPlan& plan,
                        const WeightParams& wp, const float* lam_dev, float lam_host,
-                       void* iface, hipStream_t stream, int st) {
+                       void* iface, hipStream_t stream, int st, const BwdArgs* bw) {
+  if (plan.mode == kModeBackward && !bw) return hipErrorInvalidValue;
   switch (r) {
-    case 1: return launch_pass_r1(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface, stream, st);
-    case 2: return launch_pass_r2(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface, stream, st);
-    case 3: return launch_pass_r3(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface, stream, st);
-    case 4: return launch_pass_r4(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface, stream, st);
+    case 1: return launch_pass_r1(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface, stream, st, bw);
+    case 2: return launch_pass_r2(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface, stream, st, bw);
+    case 3: return launch_pass_r3(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface, stream, st, bw);
+    case 4: return launch_pass_r4(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface, stream, st, bw);
     default: return hipErrorInvalidValue;
   }
 }

@@ -160,6 +160,137 @@ def sgwls_pass(direction: int, x: torch.Tensor, g: torch.Tensor, p: Params, *,
 
 
 # ---------------------------------------------------------------------------
+# Gradients.
+
+def backward_workspace_bytes(C: int, M: int, N: int, p: Params) -> int:
+    n = nat.lib.sgwls_backward_workspace_bytes(C, M, N, ctypes.byref(p.c()))
+    if n == 0:
+        nat.check(nat.lib.sgwls_validate(C, M, N, ctypes.byref(p.c())), "sgwls_backward_workspace_bytes")
+    return int(n)
+
+
+def _grad_lambda_buffer(grad_lambda: Optional[torch.Tensor], dev):
+    if grad_lambda is None:
+        return None
+    if (not grad_lambda.is_cuda or grad_lambda.dtype != torch.float64 or grad_lambda.numel() != 1
+            or grad_lambda.device != dev):
+        raise TypeError("grad_lambda must be a one-element float64 tensor on the device of f")
+    return grad_lambda
+
+
+def sgwls_pass_backward(direction: int, x: torch.Tensor, g: torch.Tensor, ybar: torch.Tensor,
+                        p: Params, *, lambda_dev: Optional[torch.Tensor] = None,
+                        want_g: bool = True, want_lambda: bool = True):
+    """Adjoint of one pass (column direction 0, row direction 1): returns
+    (xbar, gbar or None, grad_lambda (float64 device tensor) or None)."""
+    C, M, N = _image(x, "x")
+    dev = x.device
+    _guidance(g, M, N, dev)
+    if _image(ybar, "ybar") != (C, M, N):
+        raise ValueError("ybar must match x")
+    lam = _lambda(lambda_dev, dev)
+    xbar = torch.empty_like(x)
+    gbar = torch.empty_like(g) if want_g else None
+    glam = torch.empty(1, dtype=torch.float64, device=dev) if want_lambda else None
+    ws = _workspace(backward_workspace_bytes(C, M, N, p), dev)
+    nat.check(nat.lib.sgwls_pass_backward(int(direction), _ptr(x), _ptr(g), _ptr(ybar), _ptr(xbar),
+                                          _ptr(gbar), _ptr(glam), C, M, N, ctypes.byref(p.c()),
+                                          _ptr(lam), _ptr(ws), ws.numel(), _stream(dev)),
+              "sgwls_pass_backward")
+    return xbar, gbar, glam
+
+
+def sgwls_backward(g: torch.Tensor, saved: torch.Tensor, grad_u: torch.Tensor, p: Params, *,
+                   lambda_dev: Optional[torch.Tensor] = None, want_g: bool = True,
+                   want_lambda: bool = True, grad_f: Optional[torch.Tensor] = None,
+                   workspace: Optional[torch.Tensor] = None):
+    """Adjoint of ``sgwls_filter`` given the pass inputs it saved: returns
+    (grad_f, grad_g or None, grad_lambda (float64 device tensor) or None)."""
+    C, M, N = _image(grad_u, "grad_u")
+    dev = grad_u.device
+    _guidance(g, M, N, dev)
+    if (saved.dtype != torch.float32 or not saved.is_contiguous() or saved.device != dev
+            or saved.numel() != 2 * p.iters * C * M * N):
+        raise ValueError("saved must be a contiguous float32 tensor of 2T*C*M*N elements")
+    lam = _lambda(lambda_dev, dev)
+    if grad_f is None:
+        grad_f = torch.empty_like(grad_u)
+    elif grad_f.shape != grad_u.shape or grad_f.dtype != torch.float32 or not grad_f.is_contiguous():
+        raise ValueError("grad_f must match grad_u")
+    gbar = torch.empty_like(g) if want_g else None
+    glam = torch.empty(1, dtype=torch.float64, device=dev) if want_lambda else None
+    nbytes = backward_workspace_bytes(C, M, N, p)
+    ws = workspace if workspace is not None else _workspace(nbytes, dev)
+    if ws.numel() < nbytes or ws.device != dev:
+        raise ValueError("workspace too small")
+    nat.check(nat.lib.sgwls_backward(_ptr(g), _ptr(saved), _ptr(grad_u), _ptr(grad_f), _ptr(gbar),
+                                     _ptr(glam), C, M, N, ctypes.byref(p.c()), _ptr(lam), _ptr(ws),
+                                     ws.numel(), _stream(dev)),
+              "sgwls_backward")
+    return grad_f, gbar, glam
+
+
+class SGWLSFunction(torch.autograd.Function):
+    """u = SG-WLS(f, g, lambda) with gradients for f, g and lambda.
+
+    f: (C, M, N) or (B, C, M, N) float32; g: (M, N) or (B, M, N) float32;
+    lam: one-element float32 tensor on the device (a learnable scalar).  The
+    forward pass saves every pass input (2T images per image); the backward
+    pass runs the adjoint kernels, which recompute the weights from g."""
+
+    @staticmethod
+    def forward(ctx, f, g, lam, p: Params):
+        batched = f.dim() == 4
+        fb = f.contiguous() if batched else f.contiguous().unsqueeze(0)
+        gb = g.contiguous() if batched else g.contiguous().unsqueeze(0)
+        if fb.dim() != 4 or gb.dim() != 3 or gb.shape[0] != fb.shape[0]:
+            raise ValueError("f must be (C,M,N) or (B,C,M,N) with g (M,N) or (B,M,N)")
+        B, C, M, N = fb.shape
+        lam_dev = lam.detach().reshape(1).to(torch.float32).contiguous()
+        out = torch.empty_like(fb)
+        saved = torch.empty((B, 2 * p.iters, C, M, N), dtype=torch.float32, device=f.device)
+        ws = _workspace(workspace_bytes(C, M, N, p), f.device)
+        for b in range(B):
+            sgwls_filter(fb[b], gb[b], p, lambda_dev=lam_dev, saved=saved[b], out=out[b], workspace=ws)
+        ctx.p = p
+        ctx.batched = batched
+        ctx.lam_shape = lam.shape
+        ctx.save_for_backward(gb, saved, lam_dev)
+        return out if batched else out[0]
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        gb, saved, lam_dev = ctx.saved_tensors
+        p = ctx.p
+        go = grad_out.contiguous() if ctx.batched else grad_out.contiguous().unsqueeze(0)
+        B, C, M, N = go.shape
+        want_f, want_g, want_l = ctx.needs_input_grad[0], ctx.needs_input_grad[1], ctx.needs_input_grad[2]
+        grad_f = torch.empty_like(go)
+        grad_g = torch.empty_like(gb) if want_g else None
+        glam = torch.zeros(B, dtype=torch.float64, device=go.device) if want_l else None
+        ws = _workspace(backward_workspace_bytes(C, M, N, p), go.device)
+        for b in range(B):
+            _, gg, gl = sgwls_backward(gb[b], saved[b], go[b], p, lambda_dev=lam_dev,
+                                       want_g=want_g, want_lambda=want_l, grad_f=grad_f[b],
+                                       workspace=ws)
+            if want_g:
+                grad_g[b].copy_(gg)
+            if want_l:
+                glam[b:b + 1].copy_(gl)
+        gl_out = glam.sum().to(torch.float32).reshape(ctx.lam_shape) if want_l else None
+        if not ctx.batched:
+            grad_f = grad_f[0]
+            grad_g = grad_g[0] if want_g else None
+        return (grad_f if want_f else None), grad_g, gl_out, None
+
+
+def sgwls(f: torch.Tensor, g: torch.Tensor, lam: torch.Tensor, p: Params) -> torch.Tensor:
+    """Differentiable SG-WLS filter (see SGWLSFunction); p.lam is ignored in
+    favour of the tensor lam."""
+    return SGWLSFunction.apply(f, g, lam, p)
+
+
+# ---------------------------------------------------------------------------
 # Kernel variants and autotuning (stride-1 passes).
 
 def variant_count(r: int, channel_block: int, prec: str = "fp32") -> int:
