@@ -13,6 +13,9 @@ Prints ONE JSON line:
              duration (HIP events around launches of that kernel alone), vs
              the 8 TB/s HBM peak
   cpu_baseline  the FP64 oracle on the host cores, same workload
+  fwd_bwd    one forward call that saves the pass inputs plus the backward call
+             (gradients for f, g and lambda) for a fixed output gradient, as
+             MPixel/s and algorithmic bytes / time vs 8 TB/s
 """
 from __future__ import annotations
 
@@ -118,12 +121,40 @@ def main():
     alg = alg_bytes.get(dom)
     achieved = alg / (dom_launch_ms * 1e-3) / 1e9 if alg else None
 
+    # Forward + backward: the forward call saves every pass input, the
+    # backward call consumes them with a fixed output gradient (that of an MSE
+    # loss to a seeded target, computed once outside the timed region).
+    saved = torch.empty((2 * p.iters, C, M, N), dtype=torch.float32, device=dev)
+    ws_b = torch.empty(ops.backward_workspace_bytes(C, M, N, p), dtype=torch.uint8, device=dev)
+    ops.sgwls_filter(f, g, p, saved=saved, out=u, workspace=ws)
+    tgt = torch.from_numpy(synth.image(M, N, C, 200, 0.0, 1000, sinus=True)).to(dev)
+    ubar = (2.0 / u.numel()) * (u - tgt)
+    grad_f = torch.empty_like(f)
+    grad_g = torch.empty_like(g)
+    grad_l = torch.empty(1, dtype=torch.float64, device=dev)
+
+    def step_fb():
+        ops.sgwls_filter(f, g, p, saved=saved, out=u, workspace=ws)
+        ops.sgwls_backward(g, saved, ubar, p, grad_f=grad_f, grad_g=grad_g, grad_lambda=grad_l,
+                           workspace=ws_b)
+
+    for _ in range(args.warmup):
+        step_fb()
+    torch.cuda.synchronize()
+    ms_fb = time_events(torch, step_fb, args.steps)
+    fb_bytes = ((8 * C + 4) + (12 * C + 8)) * M * N * 2 * p.iters
+    step_fb()
+    torch.cuda.synchronize()
+    gpu_grads = (grad_f.cpu().numpy().astype(np.float64), grad_g.cpu().numpy().astype(np.float64),
+                 float(grad_l.item()))
+
     # Accuracy of this very output against the oracle, and the CPU baseline.
     step()
     torch.cuda.synchronize()
     gpu_out = u.cpu().numpy().astype(np.float64)
     cpu = None
     max_rel = None
+    grad_err = None
     if not args.no_cpu_baseline:
         import oracle
         P = oracle.OracleParams(**w.params)
@@ -140,6 +171,11 @@ def main():
                "sample": f"the full workload (one {M}x{N}x{C} filter, T={p.iters}), "
                          f"median of {args.cpu_reps} runs, {tmed:.2f} s each"}
         max_rel = float(np.abs(gpu_out - ref).max() / np.abs(ref).max())
+        _, ref_saved = oracle.filter(f64, g64, P, save=True)
+        rf, rg, rl = oracle.filter_backward(g64, ref_saved, ubar.cpu().numpy().astype(np.float64), P)
+        grad_err = {"grad_f": float(np.abs(gpu_grads[0] - rf).max() / np.abs(rf).max()),
+                    "grad_g": float(np.abs(gpu_grads[1] - rg).max() / np.abs(rg).max()),
+                    "grad_lambda": abs(gpu_grads[2] - rl) / abs(rl)}
 
     line = {
         "metric": "MPixel/s per SG-WLS filter (1080p RGB, r=1, tau=3) fwd",
@@ -168,6 +204,12 @@ def main():
                                   for (d, n), t in stage_ms.items()},
         "filter_alg_GBps": round((8 * C + 4) * px * 2 * p.iters / (ms * 1e-3) / 1e9, 1),
         "max_rel_err_vs_oracle": max_rel,
+        "fwd_bwd": {"metric": "MPixel/s per SG-WLS filter (1080p RGB, r=1, tau=3) fwd+bwd",
+                    "value": round(M * N / (ms_fb * 1e-3) / 1e6, 2), "ms_per_step": round(ms_fb, 5),
+                    "alg_bytes": fb_bytes,
+                    "alg_GBps": round(fb_bytes / (ms_fb * 1e-3) / 1e9, 1),
+                    "hbm_frac": round(fb_bytes / (ms_fb * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "max_rel_err_vs_oracle": grad_err},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -181,7 +181,7 @@ sgwls_status sgwls_autotune(const float* x, const float* g, float* y, int C, int
                             const sgwls_params* p, void* ws, size_t ws_bytes, void* stream,
                             int reps, int* chosen);
 
-/* Persist / restore the tuning table as text, tagged with the library
+/* Persist / restore the tuning table (single-image and batched entries) as text, tagged with the library
  * version and the caller's device architecture name (e.g. "gfx950").  Load
  * rejects (SGWLS_E_ARG, table unchanged) a file with another version or
  * architecture or any malformed line. */
@@ -228,6 +228,21 @@ sgwls_status sgwls_backward(const float* g, const float* saved, const float* gra
                             const float* lambda_dev, void* ws, size_t ws_bytes,
                             void* stream);
 
+/* ---- Batches of uneven images (not in the paper) ----
+ * B images of independent sizes, each with its own parameters p[b] (host
+ * arrays of B entries), are filtered together: every kernel stage of a pass
+ * is ONE persistent launch over the whole batch, whose workgroups take work
+ * units (image, channel, block of strips and chunks) from a global counter,
+ * largest image first.  Requirements (else SGWLS_E_UNSUPPORTED or
+ * SGWLS_E_ARG): every p[b].iters, kind and prec equal; stride 1; r <= 2;
+ * each side at most about 64*8 chunks long (2052 pixels for r = 2 and 4104
+ * for r = 1 with the default variant).  Images with several channels are
+ * filtered channel by channel (the guidance weights are recomputed per
+ * channel).  On a non-default stream that is not being captured, the whole
+ * call (2T passes) is captured once into a hipGraph and replayed by later
+ * calls with identical arguments (same stream, workspace, pointers, shapes
+ * and parameters); otherwise it is enqueued directly.  u may alias f. */
+
 /* One image of a batch: device pointers and its shape. */
 typedef struct {
   const float* f;
@@ -236,15 +251,34 @@ typedef struct {
   int C, M, N;
 } sgwls_image;
 
-/* Workspace bytes for sgwls_filter_batched over B images (0 if invalid). */
+/* Workspace bytes for sgwls_filter_batched over B images (0 if invalid);
+ * enough for every batched variant.  Pointers in imgs may be NULL here. */
 size_t sgwls_batched_workspace_bytes(const sgwls_image* imgs, const sgwls_params* p, int B);
 
-/* Batched SG-WLS over B images of uneven sizes with per-image parameters
- * p[b] (imgs and p are host arrays of B entries; every p[b].iters must be
- * equal).  All images are processed together by one launch per step of a
- * pass.  u may alias f per image. */
+/* Filter B images.  Uses the variant the tuning table holds for this
+ * precision, weight kind and total pixel count (variant 0 if none). */
 sgwls_status sgwls_filter_batched(const sgwls_image* imgs, const sgwls_params* p, int B,
                                   void* ws, size_t ws_bytes, void* stream);
+
+/* Number of compiled batched variants for precision prec (rows per chunk
+ * for r = 1 and r = 2, chunks per workgroup); 0 for an invalid prec. */
+int sgwls_batched_variant_count(int prec);
+
+/* sgwls_filter_batched with an explicit variant (variant < 0: tuned). */
+sgwls_status sgwls_filter_batched_variant(const sgwls_image* imgs, const sgwls_params* p, int B,
+                                          int variant, void* ws, size_t ws_bytes, void* stream);
+
+/* Time every batched variant on this batch (`reps` calls each, eagerly, with
+ * HIP events on `stream`; synchronises it) and store the fastest in the
+ * tuning table; *chosen (nullable) receives it.  Outputs are overwritten. */
+sgwls_status sgwls_autotune_batched(const sgwls_image* imgs, const sgwls_params* p, int B,
+                                    void* ws, size_t ws_bytes, void* stream, int reps,
+                                    int* chosen);
+
+/* Number of cached batched graphs / destroy them all (the cache keeps the 8
+ * most recently used). */
+int sgwls_batched_graph_count(void);
+void sgwls_batched_graph_clear(void);
 
 #ifdef __cplusplus
 }

@@ -20,7 +20,9 @@ EXPORTS = ["sgwls_status_str", "sgwls_version", "sgwls_validate", "sgwls_workspa
            "sgwls_pass_backward", "sgwls_backward_workspace_bytes",
            "sgwls_batched_workspace_bytes", "sgwls_filter_batched", "sgwls_variant_count",
            "sgwls_tune_pin", "sgwls_tune_query", "sgwls_tune_clear", "sgwls_tune_size",
-           "sgwls_autotune", "sgwls_tune_save", "sgwls_tune_load"]
+           "sgwls_autotune", "sgwls_tune_save", "sgwls_tune_load",
+           "sgwls_batched_variant_count", "sgwls_filter_batched_variant",
+           "sgwls_autotune_batched", "sgwls_batched_graph_count", "sgwls_batched_graph_clear"]
 
 
 class SgwlsParams(ctypes.Structure):
@@ -71,6 +73,17 @@ def _load():
     lib.sgwls_batched_workspace_bytes.argtypes = [ctypes.POINTER(SgwlsImage), P, i]
     lib.sgwls_filter_batched.restype = i
     lib.sgwls_filter_batched.argtypes = [ctypes.POINTER(SgwlsImage), P, i, vp, sz, vp]
+    IM = ctypes.POINTER(SgwlsImage)
+    lib.sgwls_batched_variant_count.restype = i
+    lib.sgwls_batched_variant_count.argtypes = [i]
+    lib.sgwls_filter_batched_variant.restype = i
+    lib.sgwls_filter_batched_variant.argtypes = [IM, P, i, i, vp, sz, vp]
+    lib.sgwls_autotune_batched.restype = i
+    lib.sgwls_autotune_batched.argtypes = [IM, P, i, vp, sz, vp, i, ctypes.POINTER(ctypes.c_int)]
+    lib.sgwls_batched_graph_count.restype = i
+    lib.sgwls_batched_graph_count.argtypes = []
+    lib.sgwls_batched_graph_clear.restype = None
+    lib.sgwls_batched_graph_clear.argtypes = []
     lib.sgwls_variant_count.restype = i
     lib.sgwls_variant_count.argtypes = [i, i, i]
     lib.sgwls_tune_pin.restype = i

@@ -10,16 +10,19 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <list>
 #include <map>
 #include <mutex>
+#include <numeric>
 #include <string>
 #include <tuple>
+#include <vector>
 
 using namespace sgwls;
 
 namespace {
 
-constexpr int kVersion = 100;          // 0.1.0
+constexpr int kVersion = 200;          // 0.2.0
 constexpr int kMaxSide = 1 << 16;       // M, N limit (chunk grid dimension)
 constexpr size_t kAlign = 256;
 
@@ -198,6 +201,238 @@ sgwls_status enqueue_pass_backward(int direction, const float* x, const float* g
     c0 += cb;
   }
   return SGWLS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches.  The tuning table stores the batched variant under the key
+// (0, 0, fp64, kind, 2, bucket of the total pixel count).
+constexpr int kBatchDir = 2;
+
+TuneKey batch_tune_key(int fp64, int kind, double pixels) {
+  return TuneKey(0, 0, fp64, kind, kBatchDir, (int)std::lround(2.0 * std::log2(std::max(pixels, 1.0))));
+}
+
+struct BatchPlan {
+  int B = 0, passes = 0, fp64 = 0, kind = 0, variant = 0;
+  std::vector<BatchDesc> tab;      // largest image first
+  std::vector<int> pre;            // [dir][stage][B + 1] unit prefix sums
+  int totals[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  size_t off_tab = 0, off_pre = 0, off_cnt = 0, off_tmp = 0, off_iface = 0, total = 0;
+};
+
+// Validates the batch and lays out its workspace (ws may be NULL: sizes only).
+sgwls_status batch_plan(const sgwls_image* imgs, const sgwls_params* p, int B, int variant,
+                        void* ws, BatchPlan& plan) {
+  if (!imgs || !p || B < 1 || B > (1 << 20)) return SGWLS_E_ARG;
+  const sgwls_params& p0 = p[0];
+  for (int b = 0; b < B; ++b) {
+    const sgwls_image& im = imgs[b];
+    const sgwls_status st = sgwls_validate(im.C, im.M, im.N, &p[b]);
+    if (st != SGWLS_OK) return st;
+    if (p[b].iters != p0.iters || p[b].kind != p0.kind || p[b].prec != p0.prec) return SGWLS_E_ARG;
+    if (p[b].stride != 1 || p[b].r > kBatchMaxR) return SGWLS_E_UNSUPPORTED;
+    if (ws && (!im.f || !im.g || !im.u || (const float*)im.u == im.g)) return SGWLS_E_ARG;
+  }
+  const int fp64 = p0.prec == SGWLS_P_FP64_PIVOT ? 1 : 0;
+  if (variant < 0 || variant >= batch_variant_count(fp64)) return SGWLS_E_ARG;
+  const BatchVariant bv = batch_variant(variant, fp64);
+  plan.B = B;
+  plan.passes = 2 * p0.iters;
+  plan.fp64 = fp64;
+  plan.kind = (int)p0.kind;
+  plan.variant = variant;
+  std::vector<int> order(B);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (long long)imgs[a].C * imgs[a].M * imgs[a].N > (long long)imgs[b].C * imgs[b].M * imgs[b].N;
+  });
+  const size_t acc = fp64 ? 8 : 4;
+  plan.off_tab = 0;
+  plan.off_pre = align_up(sizeof(BatchDesc) * B);
+  plan.off_cnt = plan.off_pre + align_up(sizeof(int) * 6 * (B + 1));
+  plan.off_tmp = plan.off_cnt + align_up(sizeof(int) * 3 * plan.passes);
+  size_t tmp_bytes = 0;
+  for (int b = 0; b < B; ++b) tmp_bytes += image_bytes(imgs[b].C, imgs[b].M, imgs[b].N);
+  plan.off_iface = plan.off_tmp + tmp_bytes;
+  char* base = reinterpret_cast<char*>(ws);
+  plan.tab.assign(B, BatchDesc{});
+  plan.pre.assign(6 * (B + 1), 0);
+  size_t tmp_off = plan.off_tmp, iface_elems = 0;
+  long long units[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  for (int t = 0; t < B; ++t) {
+    const int b = order[t];
+    const sgwls_image& im = imgs[b];
+    const sgwls_params& pb = p[b];
+    BatchDesc& D = plan.tab[t];
+    D.f = im.f;
+    D.g = im.g;
+    D.u = im.u;
+    D.tmp = ws ? reinterpret_cast<float*>(base + tmp_off) : nullptr;
+    tmp_off += image_bytes(im.C, im.M, im.N);
+    D.C = im.C;
+    D.M = im.M;
+    D.N = im.N;
+    D.r = pb.r;
+    D.lam = pb.lambda;
+    D.wp = weight_params(pb);
+    D.OW = kWave - 2 * pb.r;
+    const int R = pb.r == 1 ? bv.R1 : bv.R2;
+    const int T2 = pb.r * (pb.r + 1) / 2;
+    const int F = 2 * T2 + 2 * pb.r + pb.r * pb.r;
+    long long sum_max = 0, us_max = 0;
+    for (int dir = 0; dir < 2; ++dir) {
+      PassGeom& g = D.geo[dir];
+      g.L = dir == 0 ? im.M : im.N;
+      g.W = dir == 0 ? im.N : im.M;
+      g.sa = dir == 0 ? im.N : 1;
+      g.sb = dir == 0 ? 1 : im.N;
+      g.plane = (long long)im.M * im.N;
+      g.nK = strip_count(g.W, pb.r, 1);
+      g.stride = 1;
+      g.R = R;
+      g.P = (g.L + R - 1) / R;
+      const int n = g.P - 1;
+      D.m[dir] = std::max(1, (n + kWave - 1) / kWave);
+      if (n > kWave * kBatchMM) return SGWLS_E_UNSUPPORTED;   // too long for the wave solver
+      D.nbx_red[dir] = (g.nK + kWave - 1) / kWave;
+      D.nbx_exp[dir] = (g.W + D.OW - 1) / D.OW;
+      D.nby[dir] = (g.P + bv.Q - 1) / bv.Q;
+      sum_max = std::max(sum_max, (long long)g.P * F * g.nK);
+      us_max = std::max(us_max, (long long)std::max(n, 1) * pb.r * g.nK);
+      const bool split = g.P > 1;
+      units[dir][0] += split ? (long long)im.C * D.nbx_red[dir] * D.nby[dir] : 0;
+      units[dir][1] += split ? (long long)im.C * g.nK : 0;
+      units[dir][2] += (long long)im.C * D.nbx_exp[dir] * D.nby[dir];
+      for (int st = 0; st < 3; ++st) plan.pre[(dir * 3 + st) * (B + 1) + t + 1] = (int)std::min<long long>(units[dir][st], 0x7fffffff);
+    }
+    D.sum_ch = sum_max;
+    D.us_ch = us_max;
+    D.sum_base = (long long)iface_elems;
+    iface_elems += (size_t)im.C * sum_max;
+    D.us_base = (long long)iface_elems;
+    iface_elems += (size_t)im.C * us_max;
+  }
+  for (int dir = 0; dir < 2; ++dir)
+    for (int st = 0; st < 3; ++st) {
+      if (units[dir][st] > 0x7fffffffLL) return SGWLS_E_SHAPE;
+      plan.totals[dir][st] = (int)units[dir][st];
+    }
+  plan.total = plan.off_iface + align_up(iface_elems * acc);
+  return SGWLS_OK;
+}
+
+// Writes host bytes into device memory with kernels whose arguments carry
+// the data: the copy is ordered on the stream, capturable into a graph and
+// independent of the lifetime of the host buffer.
+hipError_t upload_bytes(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const unsigned int* w = reinterpret_cast<const unsigned int*>(src);
+  const size_t nw = (bytes + 3) / 4;
+  for (size_t o = 0; o < nw; o += WordChunk::kWords) {
+    WordChunk c{};
+    c.n = (unsigned int)std::min<size_t>(WordChunk::kWords, nw - o);
+    std::memcpy(c.w, w + o, std::min<size_t>(bytes - o * 4, (size_t)c.n * 4));
+    hipError_t e = launch_write_words(reinterpret_cast<unsigned int*>(dst) + o, c, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// All launches of one batched filter call.
+sgwls_status batch_enqueue(const BatchPlan& plan, void* ws, hipStream_t s) {
+  char* base = reinterpret_cast<char*>(ws);
+  BatchDesc* tab = reinterpret_cast<BatchDesc*>(base + plan.off_tab);
+  int* pre = reinterpret_cast<int*>(base + plan.off_pre);
+  int* cnt = reinterpret_cast<int*>(base + plan.off_cnt);
+  if (upload_bytes(tab, plan.tab.data(), sizeof(BatchDesc) * plan.B, s) != hipSuccess ||
+      upload_bytes(pre, plan.pre.data(), sizeof(int) * plan.pre.size(), s) != hipSuccess ||
+      launch_zero_ints(cnt, 3 * plan.passes, s) != hipSuccess)
+    return SGWLS_E_HIP;
+  const int B = plan.B;
+  for (int q = 0; q < plan.passes; ++q) {
+    const int dir = q % 2;
+    const int* pr = pre + (dir * 3 + 0) * (B + 1);
+    const int* pi = pre + (dir * 3 + 1) * (B + 1);
+    const int* pe = pre + (dir * 3 + 2) * (B + 1);
+    if (launch_batch_pass(plan.variant, plan.fp64, plan.kind, tab, pr, pi, pe, plan.totals[dir], B,
+                          q, plan.passes, dir, cnt + 3 * q, base + plan.off_iface, s) != hipSuccess)
+      return SGWLS_E_HIP;
+  }
+  return SGWLS_OK;
+}
+
+// Instantiated graphs of batched calls, keyed by stream, workspace and the
+// full plan (tables included), most recent first.
+struct GraphEntry {
+  std::string key;
+  hipGraphExec_t exec;
+};
+constexpr size_t kGraphCacheMax = 8;
+std::list<GraphEntry>& graph_cache() {
+  static std::list<GraphEntry> c;
+  return c;
+}
+std::mutex& graph_mutex() {
+  static std::mutex m;
+  return m;
+}
+
+std::string graph_key(const BatchPlan& plan, void* ws, hipStream_t s) {
+  std::string k;
+  auto put = [&](const void* p, size_t n) { k.append(reinterpret_cast<const char*>(p), n); };
+  put(&s, sizeof(s));
+  put(&ws, sizeof(ws));
+  put(&plan.variant, sizeof(int));
+  put(&plan.fp64, sizeof(int));
+  put(&plan.kind, sizeof(int));
+  put(&plan.passes, sizeof(int));
+  put(plan.tab.data(), sizeof(BatchDesc) * plan.tab.size());
+  put(plan.pre.data(), sizeof(int) * plan.pre.size());
+  return k;
+}
+
+// Runs the call as a graph on a non-default stream that is not capturing
+// (captured once per distinct call, replayed afterwards); eagerly otherwise.
+sgwls_status batch_run(const BatchPlan& plan, void* ws, hipStream_t s) {
+  // Prepare the persistent grid sizes outside any capture (no launch).
+  const int none[3] = {0, 0, 0};
+  if (launch_batch_pass(plan.variant, plan.fp64, plan.kind, nullptr, nullptr, nullptr, nullptr,
+                        none, plan.B, 0, plan.passes, 0, nullptr, nullptr, s) != hipSuccess)
+    return SGWLS_E_HIP;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (s == nullptr || hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    return batch_enqueue(plan, ws, s);
+  const std::string key = graph_key(plan, ws, s);
+  std::lock_guard<std::mutex> lk(graph_mutex());
+  auto& cache = graph_cache();
+  for (auto it = cache.begin(); it != cache.end(); ++it)
+    if (it->key == key) {
+      cache.splice(cache.begin(), cache, it);
+      return hipGraphLaunch(cache.front().exec, s) == hipSuccess ? SGWLS_OK : SGWLS_E_HIP;
+    }
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return SGWLS_E_HIP;
+  const sgwls_status st = batch_enqueue(plan, ws, s);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(s, &graph);
+  if (st != SGWLS_OK || ec != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st != SGWLS_OK ? st : SGWLS_E_HIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess || !exec) return SGWLS_E_HIP;
+  cache.push_front(GraphEntry{key, exec});
+  while (cache.size() > kGraphCacheMax) {
+    (void)hipGraphExecDestroy(cache.back().exec);
+    cache.pop_back();
+  }
+  return hipGraphLaunch(exec, s) == hipSuccess ? SGWLS_OK : SGWLS_E_HIP;
+}
+
+double batch_pixels(const sgwls_image* imgs, int B) {
+  double px = 0.0;
+  for (int b = 0; b < B; ++b) px += (double)imgs[b].C * imgs[b].M * imgs[b].N;
+  return px;
 }
 
 }  // namespace
@@ -430,9 +665,13 @@ sgwls_status sgwls_tune_load(const char* path, const char* arch) {
     int r, cb, fp64, kind, dir, bucket, v;
     const int got = std::fscanf(fp, "%d %d %d %d %d %d %d", &r, &cb, &fp64, &kind, &dir, &bucket, &v);
     if (got == EOF) break;
-    if (got != 7 || r < 1 || r > kMaxR || (cb != 1 && cb != 3) || (fp64 != 0 && fp64 != 1) ||
-        (kind != 0 && kind != 1) || (dir != 0 && dir != 1) || v < 0 ||
-        v >= variants_of(r, cb, fp64).n) {
+    const bool batched = got == 7 && r == 0 && cb == 0 && dir == kBatchDir &&
+                         (fp64 == 0 || fp64 == 1) && (kind == 0 || kind == 1) && v >= 0 &&
+                         v < batch_variant_count(fp64);
+    const bool single = got == 7 && r >= 1 && r <= kMaxR && (cb == 1 || cb == 3) &&
+                        (fp64 == 0 || fp64 == 1) && (kind == 0 || kind == 1) &&
+                        (dir == 0 || dir == 1) && v >= 0 && v < variants_of(r, cb, fp64).n;
+    if (!batched && !single) {
       ok = false;
       break;
     }
@@ -504,14 +743,97 @@ sgwls_status sgwls_backward(const float* g, const float* saved, const float* gra
 }
 
 size_t sgwls_batched_workspace_bytes(const sgwls_image* imgs, const sgwls_params* p, int B) {
-  (void)imgs; (void)p; (void)B;
-  return 0;
+  if (!imgs || !p || B < 1) return 0;
+  const int fp64 = p[0].prec == SGWLS_P_FP64_PIVOT ? 1 : 0;
+  size_t need = 0;
+  for (int v = 0; v < batch_variant_count(fp64); ++v) {
+    BatchPlan plan;
+    if (batch_plan(imgs, p, B, v, nullptr, plan) != SGWLS_OK) return 0;
+    need = std::max(need, plan.total);
+  }
+  return need;
+}
+
+int sgwls_batched_variant_count(int prec) {
+  if (prec != 0 && prec != 1) return 0;
+  return batch_variant_count(prec);
+}
+
+sgwls_status sgwls_filter_batched_variant(const sgwls_image* imgs, const sgwls_params* p, int B,
+                                          int variant, void* ws, size_t ws_bytes, void* stream) {
+  BatchPlan probe;
+  sgwls_status st = batch_plan(imgs, p, B, 0, nullptr, probe);
+  if (st != SGWLS_OK) return st;
+  if (variant < 0) {
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    auto it = tune_table().find(batch_tune_key(probe.fp64, probe.kind, batch_pixels(imgs, B)));
+    variant = it == tune_table().end() ? 0 : it->second;
+  }
+  if (variant >= batch_variant_count(probe.fp64)) return SGWLS_E_ARG;
+  if (!ws || ws_bytes < sgwls_batched_workspace_bytes(imgs, p, B)) return SGWLS_E_WORKSPACE;
+  BatchPlan plan;
+  st = batch_plan(imgs, p, B, variant, ws, plan);
+  if (st != SGWLS_OK) return st;
+  return batch_run(plan, ws, (hipStream_t)stream);
 }
 
 sgwls_status sgwls_filter_batched(const sgwls_image* imgs, const sgwls_params* p, int B,
                                   void* ws, size_t ws_bytes, void* stream) {
-  (void)imgs; (void)p; (void)B; (void)ws; (void)ws_bytes; (void)stream;
-  return SGWLS_E_UNSUPPORTED;
+  return sgwls_filter_batched_variant(imgs, p, B, -1, ws, ws_bytes, stream);
+}
+
+sgwls_status sgwls_autotune_batched(const sgwls_image* imgs, const sgwls_params* p, int B,
+                                    void* ws, size_t ws_bytes, void* stream, int reps,
+                                    int* chosen) {
+  BatchPlan probe;
+  sgwls_status st = batch_plan(imgs, p, B, 0, nullptr, probe);
+  if (st != SGWLS_OK) return st;
+  if (reps < 1) return SGWLS_E_ARG;
+  if (!ws || ws_bytes < sgwls_batched_workspace_bytes(imgs, p, B)) return SGWLS_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return SGWLS_E_HIP;
+  }
+  int best = 0;
+  float best_ms = 0.0f;
+  sgwls_status result = SGWLS_OK;
+  for (int v = 0; v < batch_variant_count(probe.fp64) && result == SGWLS_OK; ++v) {
+    BatchPlan plan;
+    result = batch_plan(imgs, p, B, v, ws, plan);
+    if (result != SGWLS_OK) break;
+    result = batch_enqueue(plan, ws, s);   // warm-up
+    if (result != SGWLS_OK || hipEventRecord(e0, s) != hipSuccess) { result = SGWLS_E_HIP; break; }
+    for (int i = 0; i < reps && result == SGWLS_OK; ++i) result = batch_enqueue(plan, ws, s);
+    float ms = 0.0f;
+    if (result != SGWLS_OK || hipEventRecord(e1, s) != hipSuccess ||
+        hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      if (result == SGWLS_OK) result = SGWLS_E_HIP;
+      break;
+    }
+    if (v == 0 || ms < best_ms) { best = v; best_ms = ms; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (result != SGWLS_OK) return result;
+  {
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    tune_table()[batch_tune_key(probe.fp64, probe.kind, batch_pixels(imgs, B))] = best;
+  }
+  if (chosen) *chosen = best;
+  return SGWLS_OK;
+}
+
+int sgwls_batched_graph_count(void) {
+  std::lock_guard<std::mutex> lk(graph_mutex());
+  return (int)graph_cache().size();
+}
+
+void sgwls_batched_graph_clear(void) {
+  std::lock_guard<std::mutex> lk(graph_mutex());
+  for (auto& e : graph_cache()) (void)hipGraphExecDestroy(e.exec);
+  graph_cache().clear();
 }
 
 }  // extern "C"

@@ -1,4 +1,5 @@
-// Radius-independent kernels: the fix-up step of a backward pass.
+// Radius-independent kernels: the fix-up step of a backward pass and small
+// stream-ordered writes of host data.
 #include "sgwls_internal.hpp"
 
 namespace sgwls {
@@ -39,7 +40,17 @@ __global__ __launch_bounds__(kFixThreads) void k_bwd_fixup(const float* __restri
   if (threadIdx.x == 0) *glam = lam_acc ? *glam + red[0] : red[0];
 }
 
+__global__ __launch_bounds__(256) void k_write_words(unsigned int* __restrict__ dst, WordChunk c) {
+  for (unsigned int i = threadIdx.x; i < c.n; i += blockDim.x) dst[i] = c.w[i];
+}
+
 }  // namespace
+
+hipError_t launch_write_words(unsigned int* dst, const WordChunk& c, hipStream_t stream) {
+  if (c.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_write_words, dim3(1), dim3(256), 0, stream, dst, c);
+  return hipGetLastError();
+}
 
 hipError_t launch_bwd_fixup(const float* side, float* gbar, const PassGeom& geo,
                             const double* lpart, int nparts, double* glam, int lam_acc,

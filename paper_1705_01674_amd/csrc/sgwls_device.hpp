@@ -505,21 +505,22 @@ DEV float domega(float w, float dg, const WeightParams& wp) {
 // Forward: the right-hand sides are the CB channels of X.  Backward: also the
 // CB channels of the output gradient X2 divided by the cover counts, so the
 // pass solution and the adjoint solve share one elimination (NR = 2 CB).
+// Block (bx, by) of the reduce grid: strips [64 bx, 64 bx + 64), chunks
+// [Q by, Q by + Q).  smem: the block's dynamic LDS.
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE>
-__global__ __launch_bounds__(kWave* Q) void k_reduce(
-    const float* __restrict__ X, const float* __restrict__ X2, const float* __restrict__ G,
-    PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
-    int pitch, Acc* __restrict__ sum) {
+DEV void reduce_block(const float* __restrict__ X, const float* __restrict__ X2,
+                      const float* __restrict__ G, const PassGeom& geo, const WeightParams& wp,
+                      float lam, int c0, int pitch, Acc* __restrict__ sum, int bx, int by,
+                      float* smem) {
   constexpr int NR = MODE == kModeBackward ? 2 * CB : CB;
   using CV = ChunkView<r, R, S1>;
   using LY = IfaceLayout<r, NR>;
   constexpr int E = CV::E;
   constexpr int TA = Q * R + 2;
-  extern __shared__ float smem[];
   const int lane = threadIdx.x % kWave;
   const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
-  const int ki_lo = blockIdx.x * kWave;
-  const int j0 = blockIdx.y * Q, j = j0 + wq;
+  const int ki_lo = bx * kWave;
+  const int j0 = by * Q, j = j0 + wq;
   const int a_lo = j0 * R;
   const int colbase = centre_of(ki_lo, geo, r) - r;
   const int TB = S1 ? kWave + 2 * r : tile_width<r>(geo.stride);
@@ -539,7 +540,6 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce(
   Acc Rw[r + 1][NR];     // window right-hand sides
   Acc TT[r][r], RT[r][NR];
   if (active) {
-    const float lam = load_lambda(lam_dev, lam_host);
     float lamS[r + 1];
 #pragma unroll
     for (int d = 0; d <= r; ++d) lamS[d] = lam * wp.spatial[d];
@@ -671,6 +671,16 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce(
   }
 }
 
+template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE>
+__global__ __launch_bounds__(kWave* Q) void k_reduce(
+    const float* __restrict__ X, const float* __restrict__ X2, const float* __restrict__ G,
+    PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
+    int pitch, Acc* __restrict__ sum) {
+  extern __shared__ float smem[];
+  reduce_block<r, CB, R, Q, S1, KIND, Acc, MODE>(X, X2, G, geo, wp, load_lambda(lam_dev, lam_host),
+                                                 c0, pitch, sum, blockIdx.x, blockIdx.y, smem);
+}
+
 // ---------------------------------------------------------------------------
 // Separator system of one strip: Sigma_jj = W_j - TT_{j+1},
 // Sigma_{j,j+1}[a][c] = TB_{j+1}[c][a], rhs_j = Rf_j - RT_{j+1}, j = 0..P-2.
@@ -710,11 +720,9 @@ struct SepReader {
 // [l*m, min(l*m + m, P-1)); MM is the compiled maximum of m.
 // U receives the separator solutions strip-major: U[(ki*(P-1) + j)*r*CB + a*CB + h].
 template <int r, int CB, int MM, typename Acc>
-__global__ __launch_bounds__(kWave) void k_interface_pcr(const Acc* __restrict__ sum,
-                                                         Acc* __restrict__ U, int nK, int P,
-                                                         int m) {
+DEV void iface_pcr_strip(const Acc* __restrict__ sum, Acc* __restrict__ U, int P, int m, int ki) {
   using LY = IfaceLayout<r, CB>;
-  const int ki = blockIdx.x, lane = threadIdx.x;
+  const int lane = threadIdx.x % kWave;
   const int n = P - 1;
   const int s = lane * m, e = min(s + m, n);
   const bool active = s < n;
@@ -924,6 +932,13 @@ __global__ __launch_bounds__(kWave) void k_interface_pcr(const Acc* __restrict__
   }
 }
 
+template <int r, int CB, int MM, typename Acc>
+__global__ __launch_bounds__(kWave) void k_interface_pcr(const Acc* __restrict__ sum,
+                                                         Acc* __restrict__ U, int nK, int P,
+                                                         int m) {
+  iface_pcr_strip<r, CB, MM, Acc>(sum, U, P, m, blockIdx.x);
+}
+
 // k_interface_serial: one lane per strip, block Cholesky over all separators
 // (for runs too long for the wave solver).  Uses U as scratch for h_j and
 // gb for the G_j blocks.
@@ -1015,23 +1030,22 @@ __global__ __launch_bounds__(kWave) void k_interface_serial(const Acc* __restric
 // the block owns (a strip is solved by the two blocks whose columns it
 // touches, and owned by the first).
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE>
-__global__ __launch_bounds__(kWave* Q) void k_expand(
-    const float* __restrict__ X, const float* __restrict__ G, float* __restrict__ Y,
-    PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
-    const Acc* __restrict__ Us, int OW, int pitch, BwdArgs bw) {
+DEV void expand_block(const float* __restrict__ X, const float* __restrict__ G,
+                      float* __restrict__ Y, const PassGeom& geo, const WeightParams& wp,
+                      float lam_in, int c0, const Acc* __restrict__ Us, int OW, int pitch,
+                      const BwdArgs& bw, int bx, int by, int nbx, float* smem) {
   constexpr bool BWD = MODE == kModeBackward;
   constexpr int NR = BWD ? 2 * CB : CB;   // right-hand sides
   constexpr int NO = BWD ? CB + 1 : CB;   // output planes (backward: + guidance gradient)
   using CV = ChunkView<r, R, S1>;
   constexpr int E = CV::E, w = CV::w;
   constexpr int TA = Q * R + 2;
-  extern __shared__ float smem[];
   const int lane = threadIdx.x % kWave;
   const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
-  const int b_lo = blockIdx.x * OW, b_hi = min(b_lo + OW, geo.W);
-  const int ki_lo = expand_first_strip(blockIdx.x, OW, geo, r);
+  const int b_lo = bx * OW, b_hi = min(b_lo + OW, geo.W);
+  const int ki_lo = expand_first_strip(bx, OW, geo, r);
   const int colbase = centre_of(ki_lo, geo, r) - r;
-  const int j0 = blockIdx.y * Q, j = j0 + wq;
+  const int j0 = by * Q, j = j0 + wq;
   const int a_lo = j0 * R;
   const int TB = S1 ? kWave + 2 * r : tile_width<r>(geo.stride);
   const int pch = S1 ? CV::PITCH1 : pitch;
@@ -1053,9 +1067,8 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
   Acc uT[r][NR], uB[r][NR];
   float gv[E + 2 * r];
   float om[E + r][r];
-  float lam = 0.0f;
+  const float lam = lam_in;
   if (active) {
-    lam = load_lambda(lam_dev, lam_host);
     CV cv;
     cv.base = smem + (wq * R + 1) * pch + (k - colbase);
     cv.pitch = pch;
@@ -1197,8 +1210,7 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
   if constexpr (BWD) {
 #pragma unroll
     for (int m = 0; m < E + r; ++m) Gv[m] = 0.0f;
-    const int ki_next = blockIdx.x + 1 < gridDim.x
-                            ? expand_first_strip(blockIdx.x + 1, OW, geo, r) : geo.nK;
+    const int ki_next = bx + 1 < nbx ? expand_first_strip(bx + 1, OW, geo, r) : geo.nK;
     const bool owns = ki < ki_next;
     if (active && want_edges) {
 #pragma unroll
@@ -1232,7 +1244,7 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
       if (threadIdx.x == 0) {
         double s = 0.0;
         for (int i = 0; i < Q; ++i) s += lred[i];
-        bw.lpart[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+        bw.lpart[(size_t)by * nbx + bx] = s;
       }
     }
   }
@@ -1377,6 +1389,17 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
           bw.side[(size_t)j0 * geo.W + b_lo + bc] = smem[NO * TA * pch + (b_lo + bc - colbase)];
     }
   }
+}
+
+template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE>
+__global__ __launch_bounds__(kWave* Q) void k_expand(
+    const float* __restrict__ X, const float* __restrict__ G, float* __restrict__ Y,
+    PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
+    const Acc* __restrict__ Us, int OW, int pitch, BwdArgs bw) {
+  extern __shared__ float smem[];
+  expand_block<r, CB, R, Q, S1, KIND, Acc, MODE>(X, G, Y, geo, wp, load_lambda(lam_dev, lam_host),
+                                                 c0, Us, OW, pitch, bw, blockIdx.x, blockIdx.y,
+                                                 gridDim.x, smem);
 }
 
 // ---------------------------------------------------------------------------

@@ -150,6 +150,66 @@ hipError_t launch_bwd_fixup(const float* side, float* gbar, const PassGeom& geo,
                             const double* lpart, int nparts, double* glam, int lam_acc,
                             hipStream_t stream);
 
+// ---------------------------------------------------------------------------
+// Batches of uneven images (one channel per work unit, stride 1, r <= 2).
+// Each stage of a pass is one persistent launch over the whole batch: its
+// workgroups take units (image, channel, block) from a global counter, so
+// small and large images share the GPU.
+
+constexpr int kBatchMaxR = 2;
+constexpr int kBatchMM = 8;       // separators per lane of the batched wave solver
+constexpr int kBatchVariants = 3;
+
+// Rows per chunk for r = 1 and r = 2 and chunks per block (all variants of
+// one precision share the block shape only within a variant).
+struct BatchVariant {
+  int R1, R2, Q;
+};
+constexpr BatchVariant batch_variant(int v, int fp64) {
+  if (fp64) return BatchVariant{8, 4, 4};
+  return v == 1 ? BatchVariant{8, 4, 4} : v == 2 ? BatchVariant{16, 6, 2} : BatchVariant{16, 6, 4};
+}
+constexpr int batch_variant_count(int fp64) { return fp64 ? 1 : kBatchVariants; }
+
+// Device table entry of one image.
+struct BatchDesc {
+  const float* f;      // input, C x M x N
+  const float* g;      // guidance, M x N
+  float* u;            // output
+  float* tmp;          // ping-pong image (workspace)
+  int C, M, N, r;
+  float lam;
+  int pad0;
+  WeightParams wp;
+  PassGeom geo[2];     // column and row pass
+  int OW;              // output columns per expand block
+  int m[2];            // separator blocks per lane of the interface solver
+  int nbx_red[2], nbx_exp[2], nby[2];
+  long long sum_base, us_base;   // interface buffers (elements of the accumulation type)
+  long long sum_ch, us_ch;       // per-channel strides of those buffers
+};
+
+// Stages of one batched pass; prefix = the (B+1) unit prefix sums of the
+// stage's direction, counters = 3 ints (one per stage), zeroed beforehand.
+// With all totals 0 it launches nothing and only prepares the persistent
+// grid sizes of the variant (a device query, not a stream operation).
+hipError_t launch_batch_pass(int variant, int fp64, int kind, const BatchDesc* tab,
+                             const int* prefix_reduce, const int* prefix_iface,
+                             const int* prefix_expand, const int totals[3], int B, int q,
+                             int passes, int dir, int* counters, void* iface,
+                             hipStream_t stream);
+// Zero n ints with a kernel (graph-capturable).
+hipError_t launch_zero_ints(int* p, int n, hipStream_t stream);
+
+// Up to kWords 32-bit words carried by value as kernel arguments.
+struct WordChunk {
+  static constexpr unsigned int kWords = 896;   // kernel arguments stay below 4 KiB
+  unsigned int n;
+  unsigned int w[kWords];
+};
+// dst[0..c.n) = c.w[0..c.n), ordered on the stream.
+hipError_t launch_write_words(unsigned int* dst, const WordChunk& c, hipStream_t stream);
+
 // Per-radius entry points (one translation unit each).
 #define SGWLS_DECLARE_LAUNCH(RR)                                                            \
   hipError_t launch_pass_r##RR(int cb, int fp64, const float* x, const float* g, float* y, \

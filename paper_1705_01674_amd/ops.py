@@ -203,6 +203,8 @@ def sgwls_pass_backward(direction: int, x: torch.Tensor, g: torch.Tensor, ybar: 
 def sgwls_backward(g: torch.Tensor, saved: torch.Tensor, grad_u: torch.Tensor, p: Params, *,
                    lambda_dev: Optional[torch.Tensor] = None, want_g: bool = True,
                    want_lambda: bool = True, grad_f: Optional[torch.Tensor] = None,
+                   grad_g: Optional[torch.Tensor] = None,
+                   grad_lambda: Optional[torch.Tensor] = None,
                    workspace: Optional[torch.Tensor] = None):
     """Adjoint of ``sgwls_filter`` given the pass inputs it saved: returns
     (grad_f, grad_g or None, grad_lambda (float64 device tensor) or None)."""
@@ -217,8 +219,17 @@ def sgwls_backward(g: torch.Tensor, saved: torch.Tensor, grad_u: torch.Tensor, p
         grad_f = torch.empty_like(grad_u)
     elif grad_f.shape != grad_u.shape or grad_f.dtype != torch.float32 or not grad_f.is_contiguous():
         raise ValueError("grad_f must match grad_u")
-    gbar = torch.empty_like(g) if want_g else None
-    glam = torch.empty(1, dtype=torch.float64, device=dev) if want_lambda else None
+    if want_g:
+        gbar = torch.empty_like(g) if grad_g is None else grad_g
+        if gbar.shape != g.shape or gbar.dtype != torch.float32 or not gbar.is_contiguous():
+            raise ValueError("grad_g must match g")
+    else:
+        gbar = None
+    if want_lambda:
+        glam = (torch.empty(1, dtype=torch.float64, device=dev) if grad_lambda is None
+                else _grad_lambda_buffer(grad_lambda, dev))
+    else:
+        glam = None
     nbytes = backward_workspace_bytes(C, M, N, p)
     ws = workspace if workspace is not None else _workspace(nbytes, dev)
     if ws.numel() < nbytes or ws.device != dev:
@@ -288,6 +299,85 @@ def sgwls(f: torch.Tensor, g: torch.Tensor, lam: torch.Tensor, p: Params) -> tor
     """Differentiable SG-WLS filter (see SGWLSFunction); p.lam is ignored in
     favour of the tensor lam."""
     return SGWLSFunction.apply(f, g, lam, p)
+
+
+# ---------------------------------------------------------------------------
+# Batches of uneven images.
+
+def _batch_args(fs, gs, ps, outs):
+    B = len(fs)
+    if B < 1 or len(gs) != B or len(ps) != B or (outs is not None and len(outs) != B):
+        raise ValueError("fs, gs, ps (and outs) must be non-empty lists of equal length")
+    imgs = (nat.SgwlsImage * B)()
+    cps = (nat.SgwlsParams * B)()
+    dev = fs[0].device
+    res = []
+    for b in range(B):
+        C, M, N = _image(fs[b], f"fs[{b}]")
+        if fs[b].device != dev:
+            raise ValueError("all images must be on one device")
+        _guidance(gs[b], M, N, dev)
+        u = torch.empty_like(fs[b]) if outs is None else outs[b]
+        if u.shape != fs[b].shape or u.dtype != torch.float32 or not u.is_contiguous() or u.device != dev:
+            raise ValueError(f"outs[{b}] must match fs[{b}]")
+        imgs[b] = nat.SgwlsImage(fs[b].data_ptr(), gs[b].data_ptr(), u.data_ptr(), C, M, N)
+        cps[b] = ps[b].c()
+        res.append(u)
+    return imgs, cps, B, dev, res
+
+
+def batched_workspace_bytes(fs, gs, ps) -> int:
+    imgs, cps, B, _, _ = _batch_args(fs, gs, ps, list(fs))
+    n = nat.lib.sgwls_batched_workspace_bytes(imgs, cps, B)
+    if n == 0:
+        raise nat.SgwlsError(1, "sgwls_batched_workspace_bytes: invalid batch")
+    return int(n)
+
+
+def sgwls_filter_batched(fs, gs, ps, *, outs=None, variant: Optional[int] = None,
+                         workspace: Optional[torch.Tensor] = None, stream=None):
+    """Filter a list of images (each (C, M, N) or (M, N) float32) with their
+    guidance images and per-image Params in one batched call.  On a
+    non-default stream the call is captured into a hipGraph once and replayed
+    by identical later calls.  Returns the list of outputs."""
+    imgs, cps, B, dev, outs = _batch_args(fs, gs, ps, outs)
+    nbytes = nat.lib.sgwls_batched_workspace_bytes(imgs, cps, B)
+    if nbytes == 0:
+        nat.check(nat.lib.sgwls_filter_batched_variant(imgs, cps, B, -1, None, 0, None),
+                  "sgwls_filter_batched")
+    ws = workspace if workspace is not None else _workspace(nbytes, dev)
+    if ws.numel() < nbytes or ws.device != dev:
+        raise ValueError("workspace too small")
+    st = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream(dev)
+    nat.check(nat.lib.sgwls_filter_batched_variant(imgs, cps, B, -1 if variant is None else int(variant),
+                                                   _ptr(ws), ws.numel(), st),
+              "sgwls_filter_batched")
+    return outs
+
+
+def batched_variant_count(prec: str = "fp32") -> int:
+    return int(nat.lib.sgwls_batched_variant_count(_PREC[prec]))
+
+
+def autotune_batched(fs, gs, ps, reps: int = 3, workspace: Optional[torch.Tensor] = None) -> int:
+    """Time every batched variant on this batch and keep the fastest for its
+    precision, weight kind and total size; returns the chosen variant."""
+    imgs, cps, B, dev, _ = _batch_args(fs, gs, ps, None)
+    nbytes = batched_workspace_bytes(fs, gs, ps)
+    ws = workspace if workspace is not None else _workspace(nbytes, dev)
+    chosen = ctypes.c_int(-1)
+    nat.check(nat.lib.sgwls_autotune_batched(imgs, cps, B, _ptr(ws), ws.numel(), _stream(dev),
+                                             int(reps), ctypes.byref(chosen)),
+              "sgwls_autotune_batched")
+    return int(chosen.value)
+
+
+def batched_graph_count() -> int:
+    return int(nat.lib.sgwls_batched_graph_count())
+
+
+def batched_graph_clear() -> None:
+    nat.lib.sgwls_batched_graph_clear()
 
 
 # ---------------------------------------------------------------------------

@@ -130,7 +130,9 @@ def test_tune_table_pin_query_save_load(nat, tmp_path):
     assert lib.sgwls_tune_load(str(bad).encode(), b"gfx950") == 1
     assert lib.sgwls_tune_size() == 0
     stale = tmp_path / "stale.txt"
-    stale.write_text(lines[0].replace("sgwls-tune 100", "sgwls-tune 1") + "\n")
+    ver = lib.sgwls_version()
+    assert lines[0].startswith(f"sgwls-tune {ver} ")
+    stale.write_text(lines[0].replace(f"sgwls-tune {ver}", "sgwls-tune 1") + "\n")
     assert lib.sgwls_tune_load(str(stale).encode(), b"gfx950") == 1
     assert lib.sgwls_tune_load(str(tmp_path / "missing.txt").encode(), b"gfx950") == 1
     lib.sgwls_tune_clear()
@@ -145,3 +147,67 @@ def test_autotune_error_paths_return_before_any_launch(nat):
     assert lib.sgwls_autotune(f, g, f, 3, 64, 64, p, ws, 1 << 30, None, 5, chosen) == 1
     assert lib.sgwls_autotune(f, g, u, 3, 64, 64, p, ws, 1 << 30, None, 0, chosen) == 1
     assert lib.sgwls_autotune(f, g, u, 3, 64, 64, p, ws, 16, None, 5, chosen) == 3
+
+
+def batch(nat, shapes, **kw):
+    B = len(shapes)
+    imgs = (nat.SgwlsImage * B)()
+    ps = (nat.SgwlsParams * B)()
+    for b, sh in enumerate(shapes):
+        C, M, N = sh[:3]
+        extra = sh[3] if len(sh) > 3 else {}
+        imgs[b] = nat.SgwlsImage(None, None, None, C, M, N)
+        ps[b] = P(nat, **{**kw, **extra})
+    return imgs, ps, B
+
+
+def test_batched_workspace_and_validation(nat):
+    lib = nat.lib
+    imgs, ps, B = batch(nat, [(1, 300, 500), (1, 2048, 256, {"r": 2, "lam": 16.0}), (3, 64, 64)])
+    n = lib.sgwls_batched_workspace_bytes(imgs, ps, B)
+    px = 300 * 500 + 2048 * 256 + 3 * 64 * 64
+    assert n >= 4 * px                                   # at least the ping-pong images
+    assert lib.sgwls_batched_workspace_bytes(imgs, ps, 0) == 0
+    for bad in ({"iters": 2}, {"stride": 2}, {"r": 3}):
+        imgs, ps, B = batch(nat, [(1, 300, 500), (1, 200, 200, bad)])
+        assert lib.sgwls_batched_workspace_bytes(imgs, ps, B) == 0
+    # a side too long for the wave interface solver of the batched kernels
+    imgs, ps, B = batch(nat, [(1, 8000, 64, {"r": 2})])
+    assert lib.sgwls_batched_workspace_bytes(imgs, ps, B) == 0
+    assert lib.sgwls_batched_variant_count(0) == 3
+    assert lib.sgwls_batched_variant_count(1) == 1
+    assert lib.sgwls_batched_variant_count(7) == 0
+
+
+def test_batched_error_paths_return_before_any_launch(nat):
+    lib = nat.lib
+    ws = ctypes.c_void_p(0x4000)
+    imgs, ps, B = batch(nat, [(1, 300, 500), (1, 200, 200, {"iters": 2})])
+    assert lib.sgwls_filter_batched(imgs, ps, B, ws, 1 << 30, None) == 1      # mixed T
+    imgs, ps, B = batch(nat, [(1, 300, 500), (1, 200, 200, {"stride": 3})])
+    assert lib.sgwls_filter_batched(imgs, ps, B, ws, 1 << 30, None) == 4      # unsupported
+    imgs, ps, B = batch(nat, [(1, 300, 500)])
+    assert lib.sgwls_filter_batched(imgs, ps, B, ws, 1 << 30, None) == 1      # NULL image pointers
+    fake = (nat.SgwlsImage * 1)(nat.SgwlsImage(0x1000, 0x2000, 0x3000, 1, 300, 500))
+    assert lib.sgwls_filter_batched(fake, ps, 1, ws, 16, None) == 3           # workspace
+    assert lib.sgwls_filter_batched_variant(fake, ps, 1, 5, ws, 1 << 30, None) == 1
+    chosen = ctypes.c_int(-7)
+    assert lib.sgwls_autotune_batched(fake, ps, 1, ws, 1 << 30, None, 0, ctypes.byref(chosen)) == 1
+    assert chosen.value == -7
+    assert lib.sgwls_batched_graph_count() == 0
+    lib.sgwls_batched_graph_clear()
+
+
+def test_tune_file_accepts_batched_entries(nat, tmp_path):
+    lib = nat.lib
+    lib.sgwls_tune_clear()
+    ver = lib.sgwls_version()
+    good = tmp_path / "b.txt"
+    good.write_text(f"sgwls-tune {ver} gfx950\n0 0 0 0 2 41 2\n1 3 0 0 1 41 1\n")
+    assert lib.sgwls_tune_load(str(good).encode(), b"gfx950") == 0
+    assert lib.sgwls_tune_size() == 2
+    lib.sgwls_tune_clear()
+    bad = tmp_path / "bb.txt"
+    bad.write_text(f"sgwls-tune {ver} gfx950\n0 0 1 0 2 41 1\n")           # fp64 has 1 variant
+    assert lib.sgwls_tune_load(str(bad).encode(), b"gfx950") == 1
+    assert lib.sgwls_tune_size() == 0

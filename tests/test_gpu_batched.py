@@ -1,0 +1,168 @@
+"""GPU parity of the batched (uneven images, persistent launches, hipGraph)
+path against the FP64 CPU oracle, image by image.
+
+Error measure: normwise relative per image, max|gpu - oracle| / max|oracle|.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_1705_01674_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ops():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1705_01674_amd import ops as _ops
+    return _ops
+
+
+def rel(gpu, ref):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    return float(np.abs(gpu - ref).max() / np.abs(ref).max())
+
+
+def small_batch(seed=1, kinds=("exp",), C_choices=(1,)):
+    """Uneven images covering one chunk only, several chunks, several expand
+    blocks, both radii and ragged sizes."""
+    rng = np.random.default_rng(seed)
+    shapes = [(40, 200), (131, 77), (7, 300), (260, 90), (65, 65), (5, 5), (300, 140), (96, 513)]
+    out = []
+    for i, (M, N) in enumerate(shapes):
+        C = int(rng.choice(C_choices))
+        r = 1 + (i % 2)
+        if min(M, N) < 2 * r + 1:
+            r = 1
+        lam = float(2.0 ** rng.uniform(-1, 5))
+        f = rng.uniform(0, 1, (C, M, N)).astype(np.float32)
+        g = (f.mean(axis=0) + 0.02 * rng.standard_normal((M, N))).astype(np.float32)
+        pd = dict(lam=lam, r=r, iters=2, stride=1, kind=kinds[i % len(kinds)], sigma_s=float(r),
+                  sigma_r=0.15, alpha_s=1.2, alpha_r=1.2, eps=1e-4)
+        out.append((f, g, pd))
+    return out
+
+
+def run_batch(ops, items, prec="fp32", stream=None, variant=None, outs=None):
+    fs = [torch.from_numpy(f).cuda() for f, _, _ in items]
+    gs = [torch.from_numpy(g).cuda() for _, g, _ in items]
+    ps = [ops.Params(**pd, prec=prec) for _, _, pd in items]
+    us = ops.sgwls_filter_batched(fs, gs, ps, stream=stream, variant=variant, outs=outs)
+    torch.cuda.synchronize()
+    return [u.cpu().numpy() for u in us]
+
+
+def oracle_outs(items):
+    return [oracle.filter(f.astype(np.float64), g.astype(np.float64), oracle.OracleParams(**pd))
+            for f, g, pd in items]
+
+
+def check_all(name, outs, refs, tol=TOL):
+    errs = [rel(o, r) for o, r in zip(outs, refs)]
+    print(f"[batched] {name}: max over images {max(errs):.3e}", flush=True)
+    assert max(errs) <= tol, (name, errs)
+
+
+def test_small_uneven_batch_eager(ops):
+    items = small_batch()
+    check_all("eager", run_batch(ops, items), oracle_outs(items))
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_every_batched_variant(ops, variant):
+    items = small_batch(seed=2)
+    check_all(f"variant {variant}", run_batch(ops, items, variant=variant), oracle_outs(items))
+
+
+def test_multichannel_kinds_and_fp64(ops):
+    items = small_batch(seed=3, C_choices=(1, 3))
+    check_all("multichannel", run_batch(ops, items), oracle_outs(items))
+    items = small_batch(seed=4, kinds=("frac",))
+    # omega^frac in float32 loses digits to cancellation: FP64 pivots keep 1e-5
+    check_all("frac fp64_pivot", run_batch(ops, items, prec="fp64_pivot"), oracle_outs(items))
+    items = small_batch(seed=5)
+    check_all("exp fp64_pivot", run_batch(ops, items, prec="fp64_pivot"), oracle_outs(items))
+
+
+def test_graph_capture_and_replays(ops):
+    """On a side stream the call is captured once and replayed; every replay
+    (with other GPU work in between) must equal the eager result bit for bit."""
+    items = small_batch(seed=6)
+    refs = oracle_outs(items)
+    eager = run_batch(ops, items)
+    check_all("eager before graph", eager, refs)
+    ops.batched_graph_clear()
+    side = torch.cuda.Stream()
+    fs = [torch.from_numpy(f).cuda() for f, _, _ in items]
+    gs = [torch.from_numpy(g).cuda() for _, g, _ in items]
+    ps = [ops.Params(**pd) for _, _, pd in items]
+    outs = [torch.empty_like(f) for f in fs]
+    ws = torch.empty(ops.batched_workspace_bytes(fs, gs, ps), dtype=torch.uint8, device="cuda")
+    for rep in range(4):
+        for o in outs:
+            o.fill_(-1.0)                                  # eager work between replays
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            ops.sgwls_filter_batched(fs, gs, ps, outs=outs, workspace=ws, stream=side)
+        side.synchronize()
+        got = [o.cpu().numpy() for o in outs]
+        for a, b in zip(got, eager):
+            assert np.array_equal(a, b), f"replay {rep} differs from the eager result"
+        _ = torch.randn(1000, device="cuda").sum().item()   # unrelated eager work
+    assert ops.batched_graph_count() == 1
+    ops.batched_graph_clear()
+    assert ops.batched_graph_count() == 0
+
+
+def test_in_place_batch(ops):
+    items = small_batch(seed=7)
+    refs = oracle_outs(items)
+    fs = [torch.from_numpy(f).cuda() for f, _, _ in items]
+    gs = [torch.from_numpy(g).cuda() for _, g, _ in items]
+    ps = [ops.Params(**pd) for _, _, pd in items]
+    ops.sgwls_filter_batched(fs, gs, ps, outs=fs)
+    torch.cuda.synchronize()
+    check_all("in place", [f.cpu().numpy() for f in fs], refs)
+
+
+def test_uneven_64_image_batch(ops):
+    """The 64-image workload (sides 256..2048, r in {1, 2}, lambda in
+    [0.5, 32], T = 3): every image on the GPU in one batched call, then the
+    smallest, the largest and four more images against the oracle."""
+    ws_ = synth.batch_uneven()
+    fs = [torch.from_numpy(w.f).cuda() for w in ws_]
+    gs = [torch.from_numpy(w.g).cuda() for w in ws_]
+    ps = [ops.Params(**w.params) for w in ws_]
+    print(f"[batched] 64 images, {sum(w.f.size for w in ws_) / 1e6:.1f} MPixel", flush=True)
+    us = ops.sgwls_filter_batched(fs, gs, ps)
+    torch.cuda.synchronize()
+    sizes = [w.f.size for w in ws_]
+    pick = {int(np.argmin(sizes)), int(np.argmax(sizes)), 3, 17, 40, 63}
+    errs = {}
+    for b in sorted(pick):
+        w = ws_[b]
+        ref = oracle.filter(w.f.astype(np.float64), w.g.astype(np.float64),
+                            oracle.OracleParams(**w.params))
+        errs[b] = rel(us[b].cpu().numpy(), ref)
+        print(f"[batched] image {b} {w.f.shape} r={w.params['r']} lam={w.params['lam']:.2f}: "
+              f"{errs[b]:.3e}", flush=True)
+    assert max(errs.values()) <= TOL, errs
+
+
+def test_autotune_batched(ops):
+    items = small_batch(seed=8)
+    fs = [torch.from_numpy(f).cuda() for f, _, _ in items]
+    gs = [torch.from_numpy(g).cuda() for _, g, _ in items]
+    ps = [ops.Params(**pd) for _, _, pd in items]
+    try:
+        v = ops.autotune_batched(fs, gs, ps, reps=2)
+        assert 0 <= v < ops.batched_variant_count()
+        check_all("autotuned", run_batch(ops, items), oracle_outs(items))
+    finally:
+        ops.tune_clear()
