@@ -16,6 +16,10 @@ Prints ONE JSON line:
   fwd_bwd    one forward call that saves the pass inputs plus the backward call
              (gradients for f, g and lambda) for a fixed output gradient, as
              MPixel/s and algorithmic bytes / time vs 8 TB/s
+  fp64_pivot the same forward call with float64 pivots and recurrences
+  batched    64 grey images with sides in [256, 2048], r in {1, 2}, lambda in
+             [0.5, 32], T = 3, in one batched call (hipGraph replay on a side
+             stream, autotuned variant), against a loop of single-image calls
 """
 from __future__ import annotations
 
@@ -39,6 +43,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--stride", type=int, default=1)
+    ap.add_argument("--no-batched", action="store_true")
     return ap.parse_args()
 
 
@@ -53,6 +58,53 @@ def time_events(torch, fn, reps):
     stop.record()
     torch.cuda.synchronize()
     return start.elapsed_time(stop) / reps
+
+
+def bench_batched(torch, ops, synth, args):
+    """The 64-image uneven batch: one batched call (graph replay on a side
+    stream) against a loop of single-image filter calls on the same images."""
+    ws_ = synth.batch_uneven()
+    fs = [torch.from_numpy(w.f).cuda() for w in ws_]
+    gs = [torch.from_numpy(w.g).cuda() for w in ws_]
+    ps = [ops.Params(**w.params) for w in ws_]
+    outs = [torch.empty_like(x) for x in fs]
+    px = sum(w.f.shape[-2] * w.f.shape[-1] for w in ws_)
+    ws = torch.empty(ops.batched_workspace_bytes(fs, gs, ps), dtype=torch.uint8, device="cuda")
+    variant = ops.autotune_batched(fs, gs, ps, reps=2, workspace=ws)
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+
+    def step():
+        ops.sgwls_filter_batched(fs, gs, ps, outs=outs, workspace=ws, stream=side)
+
+    with torch.cuda.stream(side):
+        for _ in range(2):
+            step()
+        side.synchronize()
+        reps = max(3, args.steps // 10)
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(side)
+        for _ in range(reps):
+            step()
+        stop.record(side)
+        side.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    wss = [torch.empty(ops.workspace_bytes(1, x.shape[-2], x.shape[-1], p), dtype=torch.uint8,
+                       device="cuda") for x, p in zip(fs, ps)]
+
+    def loop():
+        for x, gg, p, o, w in zip(fs, gs, ps, outs, wss):
+            ops.sgwls_filter(x, gg, p, out=o, workspace=w)
+
+    loop()
+    ms_loop = time_events(torch, loop, max(3, args.steps // 10))
+    alg = 12 * px * 2 * ps[0].iters            # grey: (8C + 4) bytes per pixel and pass
+    return {"workload": "64 grey images, sides U[256, 2048], r in {1, 2}, lambda 2^U[-1, 5], T=3",
+            "MPixel": round(px / 1e6, 2), "variant": variant,
+            "value": round(px / (ms * 1e-3) / 1e6, 2), "unit": "MPixel/s", "ms_per_step": round(ms, 4),
+            "alg_GBps": round(alg / (ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "per_image_loop_ms": round(ms_loop, 4), "speedup_vs_loop": round(ms_loop / ms, 3)}
 
 
 def main():
@@ -148,12 +200,27 @@ def main():
     gpu_grads = (grad_f.cpu().numpy().astype(np.float64), grad_g.cpu().numpy().astype(np.float64),
                  float(grad_l.item()))
 
+    # Float64 pivots and recurrences on the same workload.
+    p64 = p.with_(prec="fp64_pivot")
+    ws64 = torch.empty(ops.workspace_bytes(C, M, N, p64), dtype=torch.uint8, device=dev)
+    u64 = torch.empty_like(f)
+
+    def step64():
+        ops.sgwls_filter(f, g, p64, out=u64, workspace=ws64)
+
+    for _ in range(args.warmup):
+        step64()
+    ms64 = time_events(torch, step64, max(5, args.steps // 2))
+
+    batched = None if args.no_batched else bench_batched(torch, ops, synth, args)
+
     # Accuracy of this very output against the oracle, and the CPU baseline.
     step()
     torch.cuda.synchronize()
     gpu_out = u.cpu().numpy().astype(np.float64)
     cpu = None
     max_rel = None
+    max_rel64 = None
     grad_err = None
     if not args.no_cpu_baseline:
         import oracle
@@ -171,6 +238,7 @@ def main():
                "sample": f"the full workload (one {M}x{N}x{C} filter, T={p.iters}), "
                          f"median of {args.cpu_reps} runs, {tmed:.2f} s each"}
         max_rel = float(np.abs(gpu_out - ref).max() / np.abs(ref).max())
+        max_rel64 = float(np.abs(u64.cpu().numpy().astype(np.float64) - ref).max() / np.abs(ref).max())
         _, ref_saved = oracle.filter(f64, g64, P, save=True)
         rf, rg, rl = oracle.filter_backward(g64, ref_saved, ubar.cpu().numpy().astype(np.float64), P)
         grad_err = {"grad_f": float(np.abs(gpu_grads[0] - rf).max() / np.abs(rf).max()),
@@ -210,6 +278,9 @@ def main():
                     "alg_GBps": round(fb_bytes / (ms_fb * 1e-3) / 1e9, 1),
                     "hbm_frac": round(fb_bytes / (ms_fb * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                     "max_rel_err_vs_oracle": grad_err},
+        "fp64_pivot": {"ms_per_step": round(ms64, 5), "value": round(M * N / (ms64 * 1e-3) / 1e6, 2),
+                       "max_rel_err_vs_oracle": max_rel64},
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
