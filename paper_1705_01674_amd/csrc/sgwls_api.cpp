@@ -22,7 +22,7 @@ using namespace sgwls;
 
 namespace {
 
-constexpr int kVersion = 200;          // 0.2.0
+constexpr int kVersion = 201;          // 0.2.1
 constexpr int kMaxSide = 1 << 16;       // M, N limit (chunk grid dimension)
 constexpr size_t kAlign = 256;
 

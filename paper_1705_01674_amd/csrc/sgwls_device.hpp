@@ -414,14 +414,57 @@ struct ChunkView {
   DEV float f(int m, int c) const { return base[(c + 1) * plane + off(m)]; }
 };
 
+// The chunk of one lane read straight from global memory (column pass at
+// stride 1, where the 64 lanes of a wave are 64 adjacent columns, so every
+// element load is one coalesced row segment): no LDS tile and no workgroup
+// barrier, so the waves of a SIMD drift apart and overlap their loads with
+// each other's arithmetic.  Buffer descriptors cover exactly the image rows
+// the chunk touches (its rows and one row on each side), so offsets are
+// 32-bit and rows outside the image read 0; the guidance of those rows is
+// replaced by the sentinel.
+template <int r, int R, int NP>
+struct GlobalChunk {
+  static constexpr int w = 2 * r + 1;
+  static constexpr int E = R * w;
+  __amdgpu_buffer_rsrc_t rg, rf[NP];
+  int lane_off;   // byte offset of (row a0, column k - r) from the descriptor base
+  int row_bytes, a0, L;
+  template <int NX>
+  DEV void init(const float* G, const PlaneSrc<NX>& src, const PassGeom& geo, int a0_, int k) {
+    a0 = a0_;
+    L = geo.L;
+    const int n = (int)geo.sa;
+    const int lo = max(a0 - 1, 0), hi = min(a0 + R + 1, L);
+    const int base = lo * n, bytes = (hi - lo) * n * 4;
+    rg = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(G + base), (short)0, bytes, 0x00020000);
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+      rf[p] = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(src.at(p) + base), (short)0, bytes,
+                                                0x00020000);
+    row_bytes = n * 4;
+    lane_off = ((a0 - lo) * n + k - r) * 4;
+  }
+  DEV int off(int m) const { return lane_off + row_of<r>(m) * row_bytes + (col_of<r>(m) + r) * 4; }
+  DEV bool ok(int m) const {
+    const int a = a0 + row_of<r>(m);
+    return a >= 0 && a < L;
+  }
+  DEV float g(int m) const {
+    const float v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, off(m), 0, 0));
+    return ok(m) ? v : kSentinel;
+  }
+  DEV float f(int m, int c) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rf[c], off(m), 0, 0));
+  }
+};
+
 // lambda * w(m, m+d) for local m in [-r, E) and d = 1..r, at lw[m + r][d - 1].
 // Ends outside the subsystem read the sentinel guidance, so their edges
 // weigh 0 and the padding elements are decoupled from the subsystem.
-template <int r, int R, bool S1, int KIND>
-DEV void chunk_weights(const ChunkView<r, R, S1>& cv, const WeightParams& wp,
-                       const float (&lamS)[r + 1],
-                       float (&lw)[ChunkView<r, R, S1>::E + r][r]) {
-  constexpr int E = ChunkView<r, R, S1>::E;
+template <int r, int KIND, class V>
+DEV void chunk_weights(const V& cv, const WeightParams& wp, const float (&lamS)[r + 1],
+                       float (&lw)[V::E + r][r]) {
+  constexpr int E = V::E;
   float gv[E + 2 * r];
 #pragma unroll
   for (int m = -r; m < E + r; ++m) gv[m + r] = cv.g(m);
@@ -474,11 +517,10 @@ DEV int expand_first_strip(int bx, int OW, const PassGeom& geo, int r) {
 
 // Guidance of the chunk elements m in [-r, E + r) (gv[m + r]) and the weights
 // omega(m, m+d) of Eq. (2) without lambda (om[m + r][d - 1], m in [-r, E)).
-template <int r, int R, bool S1, int KIND>
-DEV void chunk_omega(const ChunkView<r, R, S1>& cv, const WeightParams& wp,
-                     float (&gv)[ChunkView<r, R, S1>::E + 2 * r],
-                     float (&om)[ChunkView<r, R, S1>::E + r][r]) {
-  constexpr int E = ChunkView<r, R, S1>::E;
+template <int r, int KIND, class V>
+DEV void chunk_omega(const V& cv, const WeightParams& wp, float (&gv)[V::E + 2 * r],
+                     float (&om)[V::E + r][r]) {
+  constexpr int E = V::E;
 #pragma unroll
   for (int m = -r; m < E + r; ++m) gv[m + r] = cv.g(m);
 #pragma unroll
@@ -505,6 +547,12 @@ DEV float domega(float w, float dg, const WeightParams& wp) {
 // Forward: the right-hand sides are the CB channels of X.  Backward: also the
 // CB channels of the output gradient X2 divided by the cover counts, so the
 // pass solution and the adjoint solve share one elimination (NR = 2 CB).
+template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE,
+          bool DIRECT = false>
+DEV void reduce_tile(const PassGeom& geo, const WeightParams& wp, float lam, int pch,
+                     Acc* __restrict__ sum, int bx, int by, float* smem,
+                     const float* G = nullptr, const PlaneSrc<CB>* src = nullptr);
+
 // Block (bx, by) of the reduce grid: strips [64 bx, 64 bx + 64), chunks
 // [Q by, Q by + Q).  smem: the block's dynamic LDS.
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE>
@@ -531,7 +579,25 @@ DEV void reduce_block(const float* __restrict__ X, const float* __restrict__ X2,
   else
     load_tile<NR, CB, TA, kWave * Q, 8>(smem, G, src, geo, a_lo, colbase, TB, pch, threadIdx.x);
   __syncthreads();
+  reduce_tile<r, CB, R, Q, S1, KIND, Acc, MODE>(geo, wp, lam, pch, sum, bx, by, smem);
+}
 
+// The elimination of a block whose tile is in LDS (see reduce_block), or, with
+// DIRECT, whose chunks are read from global memory (stride-1 column pass).
+template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE, bool DIRECT>
+DEV void reduce_tile(const PassGeom& geo, const WeightParams& wp, float lam, int pch,
+                     Acc* __restrict__ sum, int bx, int by, float* smem, const float* G,
+                     const PlaneSrc<CB>* src) {
+  constexpr int NR = MODE == kModeBackward ? 2 * CB : CB;
+  using CV = ChunkView<r, R, S1>;
+  using LY = IfaceLayout<r, NR>;
+  constexpr int E = CV::E;
+  constexpr int TA = Q * R + 2;
+  const int lane = threadIdx.x % kWave;
+  const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
+  const int ki_lo = bx * kWave;
+  const int j0 = by * Q, j = j0 + wq;
+  const int colbase = centre_of(ki_lo, geo, r) - r;
   const int ki = ki_lo + lane;
   const bool active = ki < geo.nK && j < geo.P;
   const bool hasT = j > 0, hasB = j + 1 < geo.P;
@@ -544,19 +610,33 @@ DEV void reduce_block(const float* __restrict__ X, const float* __restrict__ X2,
 #pragma unroll
     for (int d = 0; d <= r; ++d) lamS[d] = lam * wp.spatial[d];
     const int k = centre_of(ki, geo, r);
-    CV cv;
-    cv.base = smem + (wq * R + 1) * pch + (k - colbase);
-    cv.pitch = pch;
-    cv.plane = TA * pch;
-    cv.a0 = j * R;
-    cv.L = geo.L;
+    typename std::conditional<DIRECT, GlobalChunk<r, R, NR>, CV>::type cv;
+    if constexpr (DIRECT) {
+      cv.init(G, *src, geo, j * R, k);
+    } else {
+      cv.base = smem + (wq * R + 1) * pch + (k - colbase);
+      cv.pitch = pch;
+      cv.plane = TA * pch;
+      cv.a0 = j * R;
+      cv.L = geo.L;
+    }
+    // Direct reads: every chunk value is requested before the elimination
+    // starts, so the loads are in flight together instead of inside the chain.
+    float fpre[DIRECT ? E : 1][NR];
+    if constexpr (DIRECT) {
+#pragma unroll
+      for (int m = 0; m < E; ++m)
+#pragma unroll
+        for (int c = 0; c < NR; ++c) fpre[m][c] = cv.f(m, c);
+    }
     float lw[E + r][r];
-    chunk_weights<r, R, S1, KIND>(cv, wp, lamS, lw);
+    chunk_weights<r, KIND>(cv, wp, lamS, lw);
     float ic[2 * r + 1];
     if constexpr (MODE == kModeBackward) inv_counts<r, S1>(k, geo, ic);
     auto fval = [&](int m, int c) -> Acc {   // 0 outside the subsystem
-      if (MODE == kModeBackward && c >= CB) return Acc(cv.f(m, c) * ic[col_of<r>(m) + r]);
-      return Acc(cv.f(m, c));
+      const float v = DIRECT ? fpre[DIRECT ? m : 0][c] : cv.f(m, c);
+      if (MODE == kModeBackward && c >= CB) return Acc(v * ic[col_of<r>(m) + r]);
+      return Acc(v);
     };
 #pragma unroll
     for (int a = 0; a < r; ++a) {
@@ -1029,6 +1109,13 @@ __global__ __launch_bounds__(kWave) void k_interface_serial(const Acc* __restric
 // kernel); lambda partials go to bw.lpart, one per block, from the strips
 // the block owns (a strip is solved by the two blocks whose columns it
 // touches, and owned by the first).
+template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE,
+          bool DIRECT = false>
+DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const PassGeom& geo,
+                     const WeightParams& wp, float lam_in, int c0, const Acc* __restrict__ Us,
+                     int OW, int pch, const BwdArgs& bw, int bx, int by, int nbx, float* smem,
+                     const PlaneSrc<CB>* src = nullptr);
+
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE>
 DEV void expand_block(const float* __restrict__ X, const float* __restrict__ G,
                       float* __restrict__ Y, const PassGeom& geo, const WeightParams& wp,
@@ -1055,7 +1142,31 @@ DEV void expand_block(const float* __restrict__ X, const float* __restrict__ G,
   else
     load_tile<NR, CB, TA, kWave * Q, 8>(smem, G, src, geo, a_lo, colbase, TB, pch, threadIdx.x);
   __syncthreads();
+  expand_tile<r, CB, R, Q, S1, KIND, Acc, MODE>(G, Y, geo, wp, lam_in, c0, Us, OW, pch, bw, bx,
+                                                by, nbx, smem);
+}
 
+// The solve and output of a block whose tile is in LDS (see expand_block), or,
+// with DIRECT, whose chunks are read from global memory (stride-1 column pass).
+template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE, bool DIRECT>
+DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const PassGeom& geo,
+                     const WeightParams& wp, float lam_in, int c0, const Acc* __restrict__ Us,
+                     int OW, int pch, const BwdArgs& bw, int bx, int by, int nbx, float* smem,
+                     const PlaneSrc<CB>* src) {
+  constexpr bool BWD = MODE == kModeBackward;
+  constexpr int NR = BWD ? 2 * CB : CB;   // right-hand sides
+  constexpr int NO = BWD ? CB + 1 : CB;   // output planes (backward: + guidance gradient)
+  using CV = ChunkView<r, R, S1>;
+  constexpr int E = CV::E, w = CV::w;
+  constexpr int TA = Q * R + 2;
+  const int lane = threadIdx.x % kWave;
+  const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
+  const int b_lo = bx * OW, b_hi = min(b_lo + OW, geo.W);
+  const int ki_lo = expand_first_strip(bx, OW, geo, r);
+  const int colbase = centre_of(ki_lo, geo, r) - r;
+  const int j0 = by * Q, j = j0 + wq;
+  const int a_lo = j0 * R;
+  const int TB = S1 ? kWave + 2 * r : tile_width<r>(geo.stride);
   const int ki = ki_lo + lane;
   const bool active = ki < geo.nK && j < geo.P;
   const bool hasT = j > 0, hasB = j + 1 < geo.P;
@@ -1064,36 +1175,16 @@ DEV void expand_block(const float* __restrict__ X, const float* __restrict__ G,
   const bool want_edges = BWD && (bw.gbar != nullptr || bw.lpart != nullptr);
 
   Acc Z[E][NR];     // z = D^{-1} L^{-1} f, overwritten by the solution u
+  Acc Lf[E][r];     // Lf[m][a-1] = L(m+a, m)
   Acc uT[r][NR], uB[r][NR];
   float gv[E + 2 * r];
   float om[E + r][r];
   const float lam = lam_in;
+  // Forward direct column pass: each output row is stored as soon as its
+  // back substitution is done, so the stores drain during the rest of it.
+  constexpr bool ROWWISE = DIRECT && !BWD;
   if (active) {
-    CV cv;
-    cv.base = smem + (wq * R + 1) * pch + (k - colbase);
-    cv.pitch = pch;
-    cv.plane = TA * pch;
-    cv.a0 = j * R;
-    cv.L = geo.L;
-    float lw[E + r][r];
-    if constexpr (BWD) {
-      chunk_omega<r, R, S1, KIND>(cv, wp, gv, om);
-#pragma unroll
-      for (int m = 0; m < E + r; ++m)
-#pragma unroll
-        for (int d = 0; d < r; ++d) lw[m][d] = lam * om[m][d];
-    } else {
-      float lamS[r + 1];
-#pragma unroll
-      for (int d = 0; d <= r; ++d) lamS[d] = lam * wp.spatial[d];
-      chunk_weights<r, R, S1, KIND>(cv, wp, lamS, lw);
-    }
-    float ic[2 * r + 1];
-    if constexpr (BWD) inv_counts<r, S1>(k, geo, ic);
-    auto fval = [&](int m, int c) -> Acc {   // 0 outside the subsystem
-      if (BWD && c >= CB) return Acc(cv.f(m, c) * ic[col_of<r>(m) + r]);
-      return Acc(cv.f(m, c));
-    };
+    // Separator values first: their loads are the head of the dependency chain.
     const int n_sep = geo.P - 1;
     const Acc* us = Us + (size_t)ki * n_sep * r * NR;
 #pragma unroll
@@ -1103,7 +1194,43 @@ DEV void expand_block(const float* __restrict__ X, const float* __restrict__ G,
         uT[a][h] = hasT ? us[(size_t)(j - 1) * r * NR + a * NR + h] : Acc(0);
         uB[a][h] = hasB ? us[(size_t)j * r * NR + a * NR + h] : Acc(0);
       }
-    Acc Lf[E][r];   // Lf[m][a-1] = L(m+a, m)
+    typename std::conditional<DIRECT, GlobalChunk<r, R, NR>, CV>::type cv;
+    if constexpr (DIRECT) {
+      cv.init(G, *src, geo, j * R, k);
+    } else {
+      cv.base = smem + (wq * R + 1) * pch + (k - colbase);
+      cv.pitch = pch;
+      cv.plane = TA * pch;
+      cv.a0 = j * R;
+      cv.L = geo.L;
+    }
+    float fpre[DIRECT ? E : 1][NR];   // see reduce_tile
+    if constexpr (DIRECT) {
+#pragma unroll
+      for (int m = 0; m < E; ++m)
+#pragma unroll
+        for (int c = 0; c < NR; ++c) fpre[m][c] = cv.f(m, c);
+    }
+    float lw[E + r][r];
+    if constexpr (BWD) {
+      chunk_omega<r, KIND>(cv, wp, gv, om);
+#pragma unroll
+      for (int m = 0; m < E + r; ++m)
+#pragma unroll
+        for (int d = 0; d < r; ++d) lw[m][d] = lam * om[m][d];
+    } else {
+      float lamS[r + 1];
+#pragma unroll
+      for (int d = 0; d <= r; ++d) lamS[d] = lam * wp.spatial[d];
+      chunk_weights<r, KIND>(cv, wp, lamS, lw);
+    }
+    float ic[2 * r + 1];
+    if constexpr (BWD) inv_counts<r, S1>(k, geo, ic);
+    auto fval = [&](int m, int c) -> Acc {   // 0 outside the subsystem
+      const float v = DIRECT ? fpre[DIRECT ? m : 0][c] : cv.f(m, c);
+      if (BWD && c >= CB) return Acc(v * ic[col_of<r>(m) + r]);
+      return Acc(v);
+    };
     Acc W[r + 1][r + 1];
     Acc Rw[r + 1][NR];
 #pragma unroll
@@ -1186,7 +1313,7 @@ DEV void expand_block(const float* __restrict__ X, const float* __restrict__ G,
     // back substitution u_m = z_m - sum_a L(m+a, m) u_{m+a}
 #pragma unroll
     for (int m = E - 1; m >= 0; --m) {
-      if (m < E - r || !hasB) {
+      if (!ROWWISE && (m < E - r || !hasB)) {
 #pragma unroll
         for (int h = 0; h < NR; ++h) {
           Acc v = Z[m][h];
@@ -1271,6 +1398,41 @@ DEV void expand_block(const float* __restrict__ X, const float* __restrict__ G,
     if constexpr (!BWD) {
       const int cnt = min(geo.W - 1 - r, b + r) - max(r, b - r) + 1;
       inv = __builtin_amdgcn_rcpf(float(max(cnt, 1)));
+    }
+    if constexpr (ROWWISE) {
+#pragma unroll
+      for (int rho = R - 1; rho >= 0; --rho) {
+        if (active) {
+#pragma unroll
+          for (int m = rho * w + w - 1; m >= rho * w; --m) {
+            if (m < E - r || !hasB) {
+#pragma unroll
+              for (int h = 0; h < NR; ++h) {
+                Acc v = Z[m][h];
+#pragma unroll
+                for (int a = 1; a <= r; ++a)
+                  if (m + a < E) v -= Lf[m][a - 1] * Z[m + a][h];
+                Z[m][h] = v;
+              }
+            }
+          }
+        }
+        float orow[NO];
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+          float acc = outval(rho * w + ((rho & 1) ? 0 : 2 * r), o);
+#pragma unroll
+          for (int t = 2 * r - 1; t >= 0; --t)
+            acc = outval(rho * w + ((rho & 1) ? 2 * r - t : t), o) + lane_shr1(acc);
+          orow[o] = acc * inv;
+        }
+        if (own && rho < rows) {
+          const int o = (j * R + rho) * (int)geo.sa + b;
+#pragma unroll
+          for (int h = 0; h < CB; ++h) Yc[h * plane + o] = orow[h];
+        }
+      }
+      return;
     }
     float out[R][NO];
 #pragma unroll
@@ -1391,6 +1553,30 @@ DEV void expand_block(const float* __restrict__ X, const float* __restrict__ G,
   }
 }
 
+// Stride-1 column-pass kernels without an LDS tile (GlobalChunk views).
+template <int r, int CB, int R, int Q, int KIND, typename Acc, int MODE>
+__global__ __launch_bounds__(kWave* Q) void k_reduce_d(
+    const float* __restrict__ X, const float* __restrict__ X2, const float* __restrict__ G,
+    PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
+    Acc* __restrict__ sum) {
+  extern __shared__ float smem[];
+  const PlaneSrc<CB> src{X, X2, c0, (int)geo.plane};
+  reduce_tile<r, CB, R, Q, true, KIND, Acc, MODE, true>(
+      geo, wp, load_lambda(lam_dev, lam_host), 0, sum, blockIdx.x, blockIdx.y, smem, G, &src);
+}
+
+template <int r, int CB, int R, int Q, int KIND, typename Acc, int MODE>
+__global__ __launch_bounds__(kWave* Q) void k_expand_d(
+    const float* __restrict__ X, const float* __restrict__ G, float* __restrict__ Y,
+    PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
+    const Acc* __restrict__ Us, int OW, BwdArgs bw) {
+  extern __shared__ float smem[];
+  const PlaneSrc<CB> src{X, bw.ybar, c0, (int)geo.plane};
+  expand_tile<r, CB, R, Q, true, KIND, Acc, MODE, true>(G, Y, geo, wp, load_lambda(lam_dev, lam_host),
+                                                        c0, Us, OW, 0, bw, blockIdx.x, blockIdx.y,
+                                                        gridDim.x, smem, &src);
+}
+
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE>
 __global__ __launch_bounds__(kWave* Q) void k_expand(
     const float* __restrict__ X, const float* __restrict__ G, float* __restrict__ Y,
@@ -1405,7 +1591,7 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
 // ---------------------------------------------------------------------------
 // Launch of one pass for one (r, channel block, precision, stride class,
 // weight kind, variant, mode).
-template <int r, int CB, int fp64, bool S1, int KIND, int R, int Q, int MODE>
+template <int r, int CB, int fp64, bool S1, int KIND, int R, int Q, int MODE, int D = 0>
 hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const PassGeom& geo,
                        const PassPlan& pl, const WeightParams& wp, const float* lam_dev,
                        float lam_host, void* iface, hipStream_t stream, int stages,
@@ -1422,9 +1608,13 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
   const int gy = (geo.P + Q - 1) / Q;
   if (geo.P > 1 && (stages & kStageReduce)) {
     const int gx = (geo.nK + kWave - 1) / kWave;
-    hipLaunchKernelGGL((k_reduce<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(gx, gy), dim3(kWave * Q),
-                       std::max(tile, stage_out), stream, x, bw.ybar, g, geo, wp, lam_dev,
-                       lam_host, c0, pl.pitch, sum);
+    if (S1 && D && geo.sb == 1)
+      hipLaunchKernelGGL((k_reduce_d<r, CB, R, Q, KIND, Acc, MODE>), dim3(gx, gy), dim3(kWave * Q),
+                         stage_out, stream, x, bw.ybar, g, geo, wp, lam_dev, lam_host, c0, sum);
+    else
+      hipLaunchKernelGGL((k_reduce<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(gx, gy),
+                         dim3(kWave * Q), std::max(tile, stage_out), stream, x, bw.ybar, g, geo,
+                         wp, lam_dev, lam_host, c0, pl.pitch, sum);
   }
   if (geo.P > 1 && (stages & kStageInterface)) {
     if (VS.MM > 0 && pl.iface_m > 0 && pl.iface_m <= VS.MM) {
@@ -1438,9 +1628,14 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
   }
   if (stages & kStageExpand) {
     const int ex = (geo.W + pl.OW - 1) / pl.OW;
-    hipLaunchKernelGGL((k_expand<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(ex, gy), dim3(kWave * Q),
-                       tile, stream, x, g, y, geo, wp, lam_dev, lam_host, c0, (const Acc*)us,
-                       pl.OW, pl.pitch, bw);
+    if (S1 && D && geo.sb == 1)
+      hipLaunchKernelGGL((k_expand_d<r, CB, R, Q, KIND, Acc, MODE>), dim3(ex, gy), dim3(kWave * Q),
+                         0, stream, x, g, y, geo, wp, lam_dev, lam_host, c0, (const Acc*)us, pl.OW,
+                         bw);
+    else
+      hipLaunchKernelGGL((k_expand<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(ex, gy),
+                         dim3(kWave * Q), tile, stream, x, g, y, geo, wp, lam_dev, lam_host, c0,
+                         (const Acc*)us, pl.OW, pl.pitch, bw);
   }
   return hipGetLastError();
 }
@@ -1455,7 +1650,7 @@ hipError_t launch_variant(int vi, const float* x, const float* g, float* y, int 
   constexpr VariantSet VS = variants_for(MODE, r, CB, fp64);
   if constexpr (VI < VS.n) {
     if (vi == VI)
-      return launch_impl<r, CB, fp64, true, KIND, VS.v[VI].R, VS.v[VI].Q, MODE>(
+      return launch_impl<r, CB, fp64, true, KIND, VS.v[VI].R, VS.v[VI].Q, MODE, VS.v[VI].D>(
           x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st, bw);
     return launch_variant<r, CB, fp64, KIND, MODE, VI + 1>(vi, x, g, y, c0, geo, pl, wp, lam_dev,
                                                            lam_host, iface, s, st, bw);

@@ -42,8 +42,9 @@ struct PassGeom {
 // variant 0's R with Q = 1 (their tiles are wider).
 struct Variant {
   int R, Q;
+  int D;    // 1: the column pass reads chunks straight from global memory (no LDS tile)
 };
-constexpr int kMaxVariants = 8;
+constexpr int kMaxVariants = 12;
 struct VariantSet {
   int n;
   Variant v[kMaxVariants];
@@ -58,7 +59,7 @@ constexpr int kModeForward = 0, kModeBackward = 1;
 // R shrinks as r, the channel block and the precision grow.
 constexpr VariantSet variants_of(int r, int cb, int fp64) {
   if (fp64) {
-    if (r == 1) return cb == 1 ? VariantSet{2, {{8, 4}, {4, 4}}, 8} : VariantSet{2, {{4, 4}, {4, 2}}, 8};
+    if (r == 1) return cb == 1 ? VariantSet{2, {{8, 4, 1}, {4, 4}}, 8} : VariantSet{2, {{4, 4, 1}, {4, 2}}, 8};
     if (r == 2) return cb == 1 ? VariantSet{1, {{4, 4}}, 4} : VariantSet{1, {{2, 4}}, 4};
     return VariantSet{1, {{2, 2}}, 0};
   }
@@ -66,11 +67,14 @@ constexpr VariantSet variants_of(int r, int cb, int fp64) {
   // Q*R + 2 close to (and not above) 64 uses the lanes best.  Every tile
   // stays within 64 KB of LDS.
   if (r == 1)
-    return cb == 1 ? VariantSet{6, {{16, 4}, {16, 3}, {8, 7}, {12, 5}, {8, 4}, {16, 2}}, 8}
-                   : VariantSet{8, {{8, 4}, {8, 7}, {6, 9}, {4, 14}, {10, 5}, {8, 2}, {6, 4}, {4, 4}}, 8};
+    return cb == 1
+               ? VariantSet{9, {{16, 4, 1}, {16, 3, 0}, {8, 7, 0}, {12, 5, 0}, {8, 4, 1},
+                                {16, 4, 0}, {16, 2, 1}, {12, 4, 1}, {8, 4, 0}}, 8}
+               : VariantSet{8, {{8, 4, 1}, {8, 7, 0}, {6, 9, 0}, {10, 5, 0}, {8, 2, 1},
+                                {6, 4, 1}, {10, 4, 1}, {8, 4, 0}}, 8};
   if (r == 2)
-    return cb == 1 ? VariantSet{4, {{6, 4}, {6, 9}, {4, 14}, {4, 4}}, 8}
-                   : VariantSet{4, {{4, 4}, {4, 14}, {4, 8}, {4, 2}}, 8};
+    return cb == 1 ? VariantSet{5, {{6, 4, 1}, {6, 9}, {4, 14}, {4, 4}, {6, 4}}, 8}
+                   : VariantSet{5, {{4, 4, 1}, {4, 14}, {4, 8}, {4, 2}, {4, 4}}, 8};
   if (r == 3) return cb == 1 ? VariantSet{1, {{4, 2}}, 0} : VariantSet{1, {{2, 2}}, 0};
   return VariantSet{1, {{2, 2}}, 0};
 }
@@ -78,13 +82,14 @@ constexpr VariantSet variants_of(int r, int cb, int fp64) {
 // Backward variants: 2*cb right-hand sides per element.
 constexpr VariantSet bwd_variants_of(int r, int cb, int fp64) {
   if (fp64) {
-    if (r == 1) return cb == 1 ? VariantSet{1, {{8, 4}}, 8} : VariantSet{1, {{4, 4}}, 8};
+    if (r == 1) return cb == 1 ? VariantSet{1, {{8, 4, 1}}, 8} : VariantSet{1, {{4, 4, 1}}, 8};
     if (r == 2) return VariantSet{1, {{2, 4}}, 0};
     return VariantSet{1, {{2, 2}}, 0};
   }
   if (r == 1)
-    return cb == 1 ? VariantSet{2, {{8, 4}, {4, 4}}, 8} : VariantSet{2, {{4, 4}, {4, 8}}, 8};
-  if (r == 2) return VariantSet{1, {{4, 4}}, 8};
+    return cb == 1 ? VariantSet{3, {{8, 4, 1}, {8, 4}, {4, 4}}, 8}
+                   : VariantSet{3, {{4, 4, 1}, {4, 4}, {4, 8}}, 8};
+  if (r == 2) return VariantSet{2, {{4, 4, 1}, {4, 4}}, 8};
   return VariantSet{1, {{2, 2}}, 0};
 }
 
