@@ -143,22 +143,35 @@ def main():
     ms = time_events(torch, step, args.steps)
     mpix = M * N / (ms * 1e-3) / 1e6
 
-    # Per-kernel timing: each stage of each pass direction launched alone on
-    # the current stream, between HIP events.
+    # Per-kernel timing: each stage of each pass launched alone on the current
+    # stream, between HIP events, exactly as the filter launches it.  When the
+    # filter runs every pass as a column pass (of the image, then of its
+    # transpose, storing transposed), so does this timing.
     cp = p.c()
     stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
     y = torch.empty_like(f)
+
+    def stages_call(mask, direction, xx, gg, yy, MM, NN):
+        return nat.lib.sgwls_pass_stages(mask, direction, ctypes.c_void_p(xx.data_ptr()),
+                                         ctypes.c_void_p(gg.data_ptr()), ctypes.c_void_p(yy.data_ptr()),
+                                         C, MM, NN, ctypes.byref(cp), None,
+                                         ctypes.c_void_p(ws.data_ptr()), ws.numel(), stream)
+
+    transposed = stages_call(7 | 8, 0, f, g, y, M, N) == 0
+    if transposed:
+        fT = f.transpose(1, 2).contiguous()
+        gT = g.t().contiguous()
+        frames = [(0, f, g, M, N, 8), (0, fT, gT, N, M, 8)]
+    else:
+        frames = [(0, f, g, M, N, 0), (1, f, g, M, N, 0)]
     stage_names = {1: "k_reduce", 2: "k_interface", 4: "k_expand"}
     per_filter_ms = {}
     stage_ms = {}
-    for direction in (0, 1):
+    for direction, (dflag, xx, gg, MM, NN, extra) in enumerate(frames):
+        yy = torch.empty_like(xx)
+
         def run(mask):
-            nat.check(nat.lib.sgwls_pass_stages(mask, direction, ctypes.c_void_p(f.data_ptr()),
-                                                ctypes.c_void_p(g.data_ptr()),
-                                                ctypes.c_void_p(y.data_ptr()), C, M, N,
-                                                ctypes.byref(cp), None,
-                                                ctypes.c_void_p(ws.data_ptr()), ws.numel(),
-                                                stream), "sgwls_pass_stages")
+            nat.check(stages_call(mask | extra, dflag, xx, gg, yy, MM, NN), "sgwls_pass_stages")
         run(7)
         for mask, name in stage_names.items():
             for _ in range(3):
@@ -270,6 +283,7 @@ def main():
                      "traffic": None},
         "kernels_ms_per_launch": {f"{'col' if d == 0 else 'row'}:{n}": round(t, 5)
                                   for (d, n), t in stage_ms.items()},
+        "row_pass_as_transposed_column_pass": transposed,
         "filter_alg_GBps": round((8 * C + 4) * px * 2 * p.iters / (ms * 1e-3) / 1e9, 1),
         "max_rel_err_vs_oracle": max_rel,
         "fwd_bwd": {"metric": "MPixel/s per SG-WLS filter (1080p RGB, r=1, tau=3) fwd+bwd",

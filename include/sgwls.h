@@ -125,7 +125,12 @@ sgwls_status sgwls_pass(int direction, const float* x, const float* g, float* y,
  * the pixels covered by several subsystems are averaged into y).  `stages`
  * is a bit mask (1..7); stage 2 reads what stage 1 left in ws and stage 4
  * what stage 2 left there, so calling masks 1, 2 and 4 in order on the same
- * ws and stream computes exactly sgwls_pass.  Other arguments as sgwls_pass. */
+ * ws and stream computes exactly sgwls_pass.  Adding 8 to the mask (direction 0,
+ * stride 1, only when the tuned column-pass variants read chunks directly)
+ * stores the output transposed: y becomes C planes of N x M, pixel (i, j) of
+ * the pass output at y[c*M*N + j*M + i].  sgwls_filter uses this form
+ * internally when it saves nothing: every pass is then a column pass, of the
+ * image or of its transpose.  Other arguments as sgwls_pass. */
 sgwls_status sgwls_pass_stages(int stages, int direction, const float* x, const float* g,
                                float* y, int C, int M, int N, const sgwls_params* p,
                                const float* lambda_dev, void* ws, size_t ws_bytes,

@@ -123,12 +123,15 @@ sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* 
                           hipStream_t stream, int stages = kStageAll, int variant = -1) {
   const int L = direction == 0 ? M : N, W = direction == 0 ? N : M;
   const WeightParams wp = weight_params(p);
+  const int out_t = (stages & kStageTransposeOut) ? 1 : 0;
   for (int c0 = 0; c0 < C;) {
     const int cb = channel_block(C - c0);
     const int v = variant >= 0 ? variant
                                : tuned_variant(p.r, cb, p.prec, (int)p.kind, direction, L, W);
     const PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, v);
-    const PassGeom geo = pass_geom(direction, M, N, pl, p.stride);
+    PassGeom geo = pass_geom(direction, M, N, pl, p.stride);
+    geo.out_t = out_t;
+    stages &= kStageAll;
     hipError_t e = launch_pass(p.r, cb, p.prec, x, g, y, c0, geo, pl, wp, lam_dev, p.lambda,
                                iface, stream, stages);
     if (e != hipSuccess) return SGWLS_E_HIP;
@@ -435,6 +438,25 @@ double batch_pixels(const sgwls_image* imgs, int B) {
   return px;
 }
 
+// The forward filter can run every pass as a direct-read column pass when
+// the tuned variants of the column direction are direct ones (for both frame
+// shapes): pass 2t reads the image and writes its transpose, pass 2t+1 reads
+// that (a column pass of the transposed image is the row pass of Sec. 2.3)
+// and writes the image layout again.
+bool transposed_frames_ok(int C, int M, int N, const sgwls_params& p) {
+  if (p.stride != 1) return false;
+  for (int c0 = 0; c0 < C;) {
+    const int cb = channel_block(C - c0);
+    for (int f = 0; f < 2; ++f) {
+      const int L = f == 0 ? M : N, W = f == 0 ? N : M;
+      const int v = tuned_variant(p.r, cb, p.prec, (int)p.kind, 0, L, W);
+      if (!variants_of(p.r, cb, p.prec).v[v].D) return false;
+    }
+    c0 += cb;
+  }
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -477,7 +499,7 @@ sgwls_status sgwls_validate(int C, int M, int N, const sgwls_params* p) {
 
 size_t sgwls_workspace_bytes(int C, int M, int N, const sgwls_params* p) {
   if (sgwls_validate(C, M, N, p) != SGWLS_OK) return 0;
-  return image_bytes(C, M, N) + iface_bytes_all(C, M, N, *p);
+  return image_bytes(C, M, N) + image_bytes(1, M, N) + iface_bytes_all(C, M, N, *p);
 }
 
 sgwls_status sgwls_pass_stages(int stages, int direction, const float* x, const float* g,
@@ -487,7 +509,10 @@ sgwls_status sgwls_pass_stages(int stages, int direction, const float* x, const 
   sgwls_status st = sgwls_validate(C, M, N, p);
   if (st != SGWLS_OK) return st;
   if (direction != 0 && direction != 1) return SGWLS_E_ARG;
-  if (stages < 1 || stages > kStageAll) return SGWLS_E_ARG;
+  if ((stages & kStageAll) == 0 || stages > (kStageAll | kStageTransposeOut)) return SGWLS_E_ARG;
+  if ((stages & kStageTransposeOut) &&
+      (direction != 0 || p->stride != 1 || !transposed_frames_ok(C, M, N, *p)))
+    return SGWLS_E_UNSUPPORTED;
   if (!x || !g || !y || y == x || (const float*)y == g) return SGWLS_E_ARG;
   const size_t need = pass_iface_bytes(direction, C, M, N, *p);
   if (!ws || ws_bytes < need) return SGWLS_E_WORKSPACE;
@@ -508,14 +533,29 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u, int C, int M
   sgwls_status st = sgwls_validate(C, M, N, p);
   if (st != SGWLS_OK) return st;
   if (!f || !g || !u || (const float*)u == g) return SGWLS_E_ARG;
-  const size_t img = image_bytes(C, M, N);
-  const size_t need = img + iface_bytes_all(C, M, N, *p);
+  const size_t img = image_bytes(C, M, N), gimg = image_bytes(1, M, N);
+  const size_t need = img + gimg + iface_bytes_all(C, M, N, *p);
   if (!ws || ws_bytes < need) return SGWLS_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   float* tmp = reinterpret_cast<float*>(ws);
-  void* iface = reinterpret_cast<char*>(ws) + img;
+  float* gT = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + img);
+  void* iface = reinterpret_cast<char*>(ws) + img + gimg;
   const size_t plane = (size_t)C * M * N;
   const int passes = 2 * p->iters;
+  if (!saved && transposed_frames_ok(C, M, N, *p)) {
+    // Pass 2t: image (M x N) -> tmp, transposed (N x M); pass 2t+1: tmp -> u.
+    if (launch_transpose(g, gT, M, N, s) != hipSuccess) return SGWLS_E_HIP;
+    const float* x = f;
+    for (int q = 0; q < passes; ++q) {
+      const bool even = q % 2 == 0;
+      float* y = even ? tmp : u;
+      st = enqueue_pass(0, x, even ? g : gT, y, C, even ? M : N, even ? N : M, *p, lambda_dev,
+                        iface, s, kStageAll | kStageTransposeOut);
+      if (st != SGWLS_OK) return st;
+      x = y;
+    }
+    return SGWLS_OK;
+  }
   // Pass q reads x_q and writes x_{q+1}; x_0 = f and x_{2T} = u.  With saved,
   // x_q lives in saved[q] (q < 2T); otherwise passes ping-pong between tmp
   // and u so that the last one lands in u.

@@ -44,7 +44,30 @@ __global__ __launch_bounds__(256) void k_write_words(unsigned int* __restrict__ 
   for (unsigned int i = threadIdx.x; i < c.n; i += blockDim.x) dst[i] = c.w[i];
 }
 
+// 32 x 32 tiles through LDS (padded row), coalesced reads and writes.
+__global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ src,
+                                                   float* __restrict__ dst, int rows, int cols) {
+  __shared__ float t[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+  for (int i = ty; i < 32; i += 8) {
+    const int rr = r0 + i, cc = c0 + tx;
+    if (rr < rows && cc < cols) t[i][tx] = src[(size_t)rr * cols + cc];
+  }
+  __syncthreads();
+  for (int i = ty; i < 32; i += 8) {
+    const int cc = c0 + i, rr = r0 + tx;
+    if (rr < rows && cc < cols) dst[(size_t)cc * rows + rr] = t[tx][i];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_transpose(const float* src, float* dst, int rows, int cols, hipStream_t stream) {
+  hipLaunchKernelGGL(k_transpose, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(256), 0, stream,
+                     src, dst, rows, cols);
+  return hipGetLastError();
+}
 
 hipError_t launch_write_words(unsigned int* dst, const WordChunk& c, hipStream_t stream) {
   if (c.n == 0) return hipSuccess;

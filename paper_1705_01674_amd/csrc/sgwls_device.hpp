@@ -1426,10 +1426,27 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
             acc = outval(rho * w + ((rho & 1) ? 2 * r - t : t), o) + lane_shr1(acc);
           orow[o] = acc * inv;
         }
-        if (own && rho < rows) {
+        if (geo.out_t) {           // stage the row for the transposed store below
+#pragma unroll
+          for (int h = 0; h < CB; ++h) smem[(h * Q * R + wq * R + rho) * (kWave + 1) + lane] = orow[h];
+        } else if (own && rho < rows) {
           const int o = (j * R + rho) * (int)geo.sa + b;
 #pragma unroll
           for (int h = 0; h < CB; ++h) Yc[h * plane + o] = orow[h];
+        }
+      }
+      if (geo.out_t) {
+        // Transposed output: column b of the block's rows is contiguous, so
+        // consecutive threads take consecutive rows of one column.
+        __syncthreads();
+        const int ncols = b_hi - b_lo;
+        for (int idx = threadIdx.x; idx < arows * ncols; idx += kWave * Q) {
+          const int bc = idx / arows, tr = idx - bc * arows;
+          const int bb = b_lo + bc;
+          const float* cell = smem + tr * (kWave + 1) + (bb - colbase);
+#pragma unroll
+          for (int h = 0; h < CB; ++h)
+            Yc[h * plane + bb * geo.L + a_lo + tr] = cell[h * Q * R * (kWave + 1)];
         }
       }
       return;
@@ -1600,6 +1617,7 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
   constexpr int NR = MODE == kModeBackward ? 2 * CB : CB;
   constexpr VariantSet VS = variants_for(MODE, r, CB, fp64);
   using LY = IfaceLayout<r, NR>;
+  if (MODE == kModeBackward && geo.out_t) return hipErrorInvalidValue;
   Acc* sum = reinterpret_cast<Acc*>(iface);
   Acc* us = sum + pl.sum_elems;
   Acc* gb = us + pl.u_elems;
@@ -1630,8 +1648,10 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
     const int ex = (geo.W + pl.OW - 1) / pl.OW;
     if (S1 && D && geo.sb == 1)
       hipLaunchKernelGGL((k_expand_d<r, CB, R, Q, KIND, Acc, MODE>), dim3(ex, gy), dim3(kWave * Q),
-                         0, stream, x, g, y, geo, wp, lam_dev, lam_host, c0, (const Acc*)us, pl.OW,
-                         bw);
+                         geo.out_t ? sizeof(float) * CB * Q * R * (kWave + 1) : 0, stream, x, g, y,
+                         geo, wp, lam_dev, lam_host, c0, (const Acc*)us, pl.OW, bw);
+    else if (geo.out_t)
+      return hipErrorInvalidValue;   // transposed output needs the direct forward kernels
     else
       hipLaunchKernelGGL((k_expand<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(ex, gy),
                          dim3(kWave * Q), tile, stream, x, g, y, geo, wp, lam_dev, lam_host, c0,

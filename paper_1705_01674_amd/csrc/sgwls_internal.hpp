@@ -35,6 +35,8 @@ struct PassGeom {
   int stride;       // sliding step tau between centres
   int R;            // rows per chunk (the partition of every subsystem)
   int P;            // chunks per subsystem = ceil(L / R)
+  int out_t;        // 1: the output is stored transposed, pixel (a, b) at b*L + a
+                    // (stride-1 column passes with direct reads only)
 };
 
 // Kernel variants: rows per chunk R (even) and chunks per block Q.  Stride-1
@@ -127,6 +129,8 @@ int expand_blocks(const PassGeom& geo, const PassPlan& pl);
 
 // Stages of one pass (bit mask): reduce, interface solve, expand.
 constexpr int kStageReduce = 1, kStageInterface = 2, kStageExpand = 4, kStageAll = 7;
+// With the stage mask: store the pass output transposed (see PassGeom::out_t).
+constexpr int kStageTransposeOut = 8;
 
 // Extra operands of a backward pass (all device pointers).
 struct BwdArgs {
@@ -203,6 +207,9 @@ hipError_t launch_batch_pass(int variant, int fp64, int kind, const BatchDesc* t
                              const int* prefix_expand, const int totals[3], int B, int q,
                              int passes, int dir, int* counters, void* iface,
                              hipStream_t stream);
+// dst (cols x rows) = transpose of src (rows x cols), one plane.
+hipError_t launch_transpose(const float* src, float* dst, int rows, int cols, hipStream_t stream);
+
 // Zero n ints with a kernel (graph-capturable).
 hipError_t launch_zero_ints(int* p, int n, hipStream_t stream);
 
