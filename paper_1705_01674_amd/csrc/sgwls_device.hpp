@@ -84,9 +84,15 @@ DEV constexpr int col_of(int m) {  // offset from the centre column k
                             : ((m - row_of<r>(m) * (2 * r + 1)) - r);
 }
 
-// Small dense helpers on r x r blocks.
+// Small dense helpers on r x r blocks.  chol leaves a factor that chol_solve
+// applies: the Cholesky factor for n > 1; for n = 1 the reciprocal of the
+// scalar itself (one rcp instead of a square root and two divisions).
 template <int n, typename Acc>
 DEV void chol(Acc (&A)[n][n]) {
+  if constexpr (n == 1) {
+    A[0][0] = recip(A[0][0]);
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < n; ++j) {
     Acc d = A[j][j];
@@ -107,6 +113,11 @@ DEV void chol(Acc (&A)[n][n]) {
 
 template <int n, int m, typename Acc>
 DEV void chol_solve(const Acc (&Lc)[n][n], Acc (&B)[n][m]) {
+  if constexpr (n == 1) {
+#pragma unroll
+    for (int c = 0; c < m; ++c) B[0][c] *= Lc[0][0];
+    return;
+  }
 #pragma unroll
   for (int c = 0; c < m; ++c) {
 #pragma unroll
@@ -129,6 +140,10 @@ DEV void chol_solve(const Acc (&Lc)[n][n], Acc (&B)[n][m]) {
 // Inverse of a small SPD matrix through its Cholesky factor.
 template <int n, typename Acc>
 DEV void spd_inverse(const Acc (&A)[n][n], Acc (&Ai)[n][n]) {
+  if constexpr (n == 1) {
+    Ai[0][0] = recip(A[0][0]);
+    return;
+  }
   Acc Lc[n][n];
 #pragma unroll
   for (int i = 0; i < n; ++i)
@@ -1626,10 +1641,16 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
   const int gy = (geo.P + Q - 1) / Q;
   if (geo.P > 1 && (stages & kStageReduce)) {
     const int gx = (geo.nK + kWave - 1) / kWave;
-    if (S1 && D && geo.sb == 1)
-      hipLaunchKernelGGL((k_reduce_d<r, CB, R, Q, KIND, Acc, MODE>), dim3(gx, gy), dim3(kWave * Q),
-                         stage_out, stream, x, bw.ybar, g, geo, wp, lam_dev, lam_host, c0, sum);
-    else
+    bool direct = false;
+    if constexpr (S1 && D) {
+      if (geo.sb == 1) {
+        direct = true;
+        hipLaunchKernelGGL((k_reduce_d<r, CB, R, Q, KIND, Acc, MODE>), dim3(gx, gy),
+                           dim3(kWave * Q), stage_out, stream, x, bw.ybar, g, geo, wp, lam_dev,
+                           lam_host, c0, sum);
+      }
+    }
+    if (!direct)
       hipLaunchKernelGGL((k_reduce<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(gx, gy),
                          dim3(kWave * Q), std::max(tile, stage_out), stream, x, bw.ybar, g, geo,
                          wp, lam_dev, lam_host, c0, pl.pitch, sum);
@@ -1646,16 +1667,22 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
   }
   if (stages & kStageExpand) {
     const int ex = (geo.W + pl.OW - 1) / pl.OW;
-    if (S1 && D && geo.sb == 1)
-      hipLaunchKernelGGL((k_expand_d<r, CB, R, Q, KIND, Acc, MODE>), dim3(ex, gy), dim3(kWave * Q),
-                         geo.out_t ? sizeof(float) * CB * Q * R * (kWave + 1) : 0, stream, x, g, y,
-                         geo, wp, lam_dev, lam_host, c0, (const Acc*)us, pl.OW, bw);
-    else if (geo.out_t)
-      return hipErrorInvalidValue;   // transposed output needs the direct forward kernels
-    else
+    bool direct = false;
+    if constexpr (S1 && D) {
+      if (geo.sb == 1) {
+        direct = true;
+        hipLaunchKernelGGL((k_expand_d<r, CB, R, Q, KIND, Acc, MODE>), dim3(ex, gy),
+                           dim3(kWave * Q),
+                           geo.out_t ? sizeof(float) * CB * Q * R * (kWave + 1) : 0, stream, x, g,
+                           y, geo, wp, lam_dev, lam_host, c0, (const Acc*)us, pl.OW, bw);
+      }
+    }
+    if (!direct) {
+      if (geo.out_t) return hipErrorInvalidValue;   // needs the direct forward kernels
       hipLaunchKernelGGL((k_expand<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(ex, gy),
                          dim3(kWave * Q), tile, stream, x, g, y, geo, wp, lam_dev, lam_host, c0,
                          (const Acc*)us, pl.OW, pl.pitch, bw);
+    }
   }
   return hipGetLastError();
 }

@@ -75,8 +75,8 @@ constexpr VariantSet variants_of(int r, int cb, int fp64) {
                : VariantSet{8, {{8, 4, 1}, {8, 7, 0}, {6, 9, 0}, {10, 5, 0}, {8, 2, 1},
                                 {6, 4, 1}, {10, 4, 1}, {8, 4, 0}}, 8};
   if (r == 2)
-    return cb == 1 ? VariantSet{5, {{6, 4, 1}, {6, 9}, {4, 14}, {4, 4}, {6, 4}}, 8}
-                   : VariantSet{5, {{4, 4, 1}, {4, 14}, {4, 8}, {4, 2}, {4, 4}}, 8};
+    return cb == 1 ? VariantSet{5, {{6, 4, 1}, {6, 9}, {4, 8, 1}, {4, 4}, {6, 4}}, 8}
+                   : VariantSet{5, {{4, 4, 1}, {4, 8}, {4, 8, 1}, {4, 2}, {4, 4}}, 8};
   if (r == 3) return cb == 1 ? VariantSet{1, {{4, 2}}, 0} : VariantSet{1, {{2, 2}}, 0};
   return VariantSet{1, {{2, 2}}, 0};
 }
