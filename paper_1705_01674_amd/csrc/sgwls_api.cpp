@@ -126,8 +126,9 @@ sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* 
   const int out_t = (stages & kStageTransposeOut) ? 1 : 0;
   for (int c0 = 0; c0 < C;) {
     const int cb = channel_block(C - c0);
-    const int v = variant >= 0 ? variant
-                               : tuned_variant(p.r, cb, p.prec, (int)p.kind, direction, L, W);
+    int v = variant >= 0 ? variant
+                         : tuned_variant(p.r, cb, p.prec, (int)p.kind, direction, L, W);
+    if (out_t && !variants_of(p.r, cb, p.prec).v[v].D) v = 0;   // variant 0 reads directly
     const PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, v);
     PassGeom geo = pass_geom(direction, M, N, pl, p.stride);
     geo.out_t = out_t;
@@ -145,6 +146,7 @@ sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* 
 // chunk-boundary edges (P x W floats) and the per-block lambda partials.
 struct BwdLayout {
   size_t img_off, iface_off, side_off, lpart_off, total;
+  size_t gt_off, gtacc_off, yt_off;   // transposed-frame buffers (frames only)
 };
 
 BwdLayout bwd_layout(int C, int M, int N, const sgwls_params& p) {
@@ -169,7 +171,10 @@ BwdLayout bwd_layout(int C, int M, int N, const sgwls_params& p) {
   l.iface_off = image_bytes(C, M, N);
   l.side_off = l.iface_off + align_up(iface);
   l.lpart_off = l.side_off + align_up(side * sizeof(float));
-  l.total = l.lpart_off + align_up(blocks * sizeof(double));
+  l.gt_off = l.lpart_off + align_up(blocks * sizeof(double));
+  l.gtacc_off = l.gt_off + image_bytes(1, M, N);
+  l.yt_off = l.gtacc_off + image_bytes(1, M, N);
+  l.total = l.yt_off + image_bytes(C, M, N);
   return l;
 }
 
@@ -180,7 +185,8 @@ sgwls_status enqueue_pass_backward(int direction, const float* x, const float* g
                                    const float* ybar, float* xbar, float* gbar,
                                    double* grad_lambda, int C, int M, int N,
                                    const sgwls_params& p, const float* lam_dev, void* ws,
-                                   const BwdLayout& lay, hipStream_t stream, bool& first) {
+                                   const BwdLayout& lay, hipStream_t stream, bool& first,
+                                   bool* gfirst = nullptr, int out_t = 0) {
   const int L = direction == 0 ? M : N, W = direction == 0 ? N : M;
   const WeightParams wp = weight_params(p);
   char* base = reinterpret_cast<char*>(ws);
@@ -192,8 +198,10 @@ sgwls_status enqueue_pass_backward(int direction, const float* x, const float* g
   for (int c0 = 0; c0 < C;) {
     const int cb = channel_block(C - c0);
     const PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, 0, kModeBackward);
-    const PassGeom geo = pass_geom(direction, M, N, pl, p.stride);
-    bw.gacc = first ? 0 : 1;
+    PassGeom geo = pass_geom(direction, M, N, pl, p.stride);
+    geo.out_t = out_t;
+    bool& gf = gfirst ? *gfirst : first;   // first write of this guidance-gradient buffer
+    bw.gacc = gf ? 0 : 1;
     hipError_t e = launch_pass(p.r, cb, p.prec, x, g, xbar, c0, geo, pl, wp, lam_dev, p.lambda,
                                base + lay.iface_off, stream, kStageAll, &bw);
     if (e != hipSuccess) return SGWLS_E_HIP;
@@ -201,6 +209,7 @@ sgwls_status enqueue_pass_backward(int direction, const float* x, const float* g
                          first ? 0 : 1, stream);
     if (e != hipSuccess) return SGWLS_E_HIP;
     first = false;
+    gf = false;
     c0 += cb;
   }
   return SGWLS_OK;
@@ -438,25 +447,6 @@ double batch_pixels(const sgwls_image* imgs, int B) {
   return px;
 }
 
-// The forward filter can run every pass as a direct-read column pass when
-// the tuned variants of the column direction are direct ones (for both frame
-// shapes): pass 2t reads the image and writes its transpose, pass 2t+1 reads
-// that (a column pass of the transposed image is the row pass of Sec. 2.3)
-// and writes the image layout again.
-bool transposed_frames_ok(int C, int M, int N, const sgwls_params& p) {
-  if (p.stride != 1) return false;
-  for (int c0 = 0; c0 < C;) {
-    const int cb = channel_block(C - c0);
-    for (int f = 0; f < 2; ++f) {
-      const int L = f == 0 ? M : N, W = f == 0 ? N : M;
-      const int v = tuned_variant(p.r, cb, p.prec, (int)p.kind, 0, L, W);
-      if (!variants_of(p.r, cb, p.prec).v[v].D) return false;
-    }
-    c0 += cb;
-  }
-  return true;
-}
-
 }  // namespace
 
 extern "C" {
@@ -511,7 +501,7 @@ sgwls_status sgwls_pass_stages(int stages, int direction, const float* x, const 
   if (direction != 0 && direction != 1) return SGWLS_E_ARG;
   if ((stages & kStageAll) == 0 || stages > (kStageAll | kStageTransposeOut)) return SGWLS_E_ARG;
   if ((stages & kStageTransposeOut) &&
-      (direction != 0 || p->stride != 1 || !transposed_frames_ok(C, M, N, *p)))
+      (direction != 0 || p->stride != 1 || !frames_supported(C, p->r, p->stride, p->prec)))
     return SGWLS_E_UNSUPPORTED;
   if (!x || !g || !y || y == x || (const float*)y == g) return SGWLS_E_ARG;
   const size_t need = pass_iface_bytes(direction, C, M, N, *p);
@@ -542,13 +532,20 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u, int C, int M
   void* iface = reinterpret_cast<char*>(ws) + img + gimg;
   const size_t plane = (size_t)C * M * N;
   const int passes = 2 * p->iters;
-  if (!saved && transposed_frames_ok(C, M, N, *p)) {
-    // Pass 2t: image (M x N) -> tmp, transposed (N x M); pass 2t+1: tmp -> u.
+  if (frames_supported(C, p->r, p->stride, p->prec)) {
+    // Every pass is a column pass that stores its output transposed: pass 2t
+    // reads the image (M x N), pass 2t+1 its transpose (N x M) -- the row pass
+    // -- and writes the image layout again.  Without saved, pass 2t writes tmp
+    // and pass 2t+1 writes u; with saved, pass q writes saved[q+1] (so odd
+    // entries hold transposed images) and the last pass writes u.
     if (launch_transpose(g, gT, M, N, s) != hipSuccess) return SGWLS_E_HIP;
-    const float* x = f;
+    if (saved && hipMemcpyAsync(saved, f, sizeof(float) * plane, hipMemcpyDeviceToDevice, s) !=
+                     hipSuccess)
+      return SGWLS_E_HIP;
+    const float* x = saved ? saved : f;
     for (int q = 0; q < passes; ++q) {
       const bool even = q % 2 == 0;
-      float* y = even ? tmp : u;
+      float* y = q == passes - 1 ? u : saved ? saved + (size_t)(q + 1) * plane : even ? tmp : u;
       st = enqueue_pass(0, x, even ? g : gT, y, C, even ? M : N, even ? N : M, *p, lambda_dev,
                         iface, s, kStageAll | kStageTransposeOut);
       if (st != SGWLS_OK) return st;
@@ -770,8 +767,37 @@ sgwls_status sgwls_backward(const float* g, const float* saved, const float* gra
   // Passes in reverse order.  Pass q reads the gradient of its output (grad_u
   // for the last pass) and writes that of its input: into grad_f for even q,
   // tmp for odd q, so pass 0 ends in grad_f and grad_u may alias grad_f.
-  const float* ybar = grad_u;
   bool first = true;
+  if (frames_supported(C, p->r, p->stride, p->prec)) {
+    // The saved inputs of odd (row) passes are transposed (see sgwls_filter).
+    // Pass q runs as a column pass in its frame (q odd: the transposed image
+    // with the transposed guidance) and stores the input gradient transposed,
+    // i.e. in the frame of pass q-1; pass 0 stores it as the image.  The
+    // guidance gradient of odd passes accumulates transposed and is added to
+    // grad_g at the end.
+    char* base = reinterpret_cast<char*>(ws);
+    float* gT = reinterpret_cast<float*>(base + lay.gt_off);
+    float* gTacc = reinterpret_cast<float*>(base + lay.gtacc_off);
+    float* yT = reinterpret_cast<float*>(base + lay.yt_off);
+    if (launch_transpose(g, gT, M, N, s) != hipSuccess ||
+        launch_transpose(grad_u, yT, M, N, s, C) != hipSuccess)
+      return SGWLS_E_HIP;
+    const float* ybar = yT;
+    bool gfirst[2] = {true, true};
+    for (int q = passes - 1; q >= 0; --q) {
+      const bool odd = q % 2 == 1;
+      float* xbar = (q % 2 == 0) ? grad_f : tmp;
+      st = enqueue_pass_backward(0, saved + (size_t)q * plane, odd ? gT : g, ybar, xbar,
+                                 grad_g ? (odd ? gTacc : grad_g) : nullptr, grad_lambda, C,
+                                 odd ? N : M, odd ? M : N, *p, lambda_dev, ws, lay, s, first,
+                                 &gfirst[odd ? 1 : 0], q > 0 ? 1 : 0);
+      if (st != SGWLS_OK) return st;
+      ybar = xbar;
+    }
+    if (grad_g && launch_transpose(gTacc, grad_g, N, M, s, 1, 1) != hipSuccess) return SGWLS_E_HIP;
+    return SGWLS_OK;
+  }
+  const float* ybar = grad_u;
   for (int q = passes - 1; q >= 0; --q) {
     float* xbar = (q % 2 == 0) ? grad_f : tmp;
     st = enqueue_pass_backward(q % 2, saved + (size_t)q * plane, g, ybar, xbar, grad_g,

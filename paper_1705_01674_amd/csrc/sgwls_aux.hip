@@ -46,8 +46,12 @@ __global__ __launch_bounds__(256) void k_write_words(unsigned int* __restrict__ 
 
 // 32 x 32 tiles through LDS (padded row), coalesced reads and writes.
 __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ src,
-                                                   float* __restrict__ dst, int rows, int cols) {
+                                                   float* __restrict__ dst, int rows, int cols,
+                                                   int accumulate) {
   __shared__ float t[32][33];
+  const size_t plane = (size_t)rows * cols;
+  src += blockIdx.z * plane;
+  dst += blockIdx.z * plane;
   const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
   const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
   for (int i = ty; i < 32; i += 8) {
@@ -57,15 +61,19 @@ __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ src
   __syncthreads();
   for (int i = ty; i < 32; i += 8) {
     const int cc = c0 + i, rr = r0 + tx;
-    if (rr < rows && cc < cols) dst[(size_t)cc * rows + rr] = t[tx][i];
+    if (rr < rows && cc < cols) {
+      float* d = dst + (size_t)cc * rows + rr;
+      *d = accumulate ? *d + t[tx][i] : t[tx][i];
+    }
   }
 }
 
 }  // namespace
 
-hipError_t launch_transpose(const float* src, float* dst, int rows, int cols, hipStream_t stream) {
-  hipLaunchKernelGGL(k_transpose, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(256), 0, stream,
-                     src, dst, rows, cols);
+hipError_t launch_transpose(const float* src, float* dst, int rows, int cols, hipStream_t stream,
+                            int planes, int accumulate) {
+  hipLaunchKernelGGL(k_transpose, dim3((cols + 31) / 32, (rows + 31) / 32, planes), dim3(256), 0,
+                     stream, src, dst, rows, cols, accumulate);
   return hipGetLastError();
 }
 

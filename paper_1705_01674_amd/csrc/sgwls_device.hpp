@@ -1494,12 +1494,30 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
         for (int rho = 0; rho < R; ++rho)
           if (rho < rows) {
             const int o = (j * R + rho) * (int)geo.sa + b;
+            if (geo.out_t) {   // staged for the transposed store below
 #pragma unroll
-            for (int h = 0; h < CB; ++h) Yc[h * plane + o] = out[rho][h];
-            if constexpr (BWD) {
+              for (int h = 0; h < CB; ++h)
+                smem[(h * Q * R + wq * R + rho) * (kWave + 1) + lane] = out[rho][h];
+            } else {
+#pragma unroll
+              for (int h = 0; h < CB; ++h) Yc[h * plane + o] = out[rho][h];
+            }
+            if constexpr (BWD) {   // the guidance gradient stays in the frame of the pass
               if (wantg) bw.gbar[o] = (bw.gacc ? bw.gbar[o] : 0.0f) + out[rho][CB];
             }
           }
+      }
+      if (geo.out_t) {
+        __syncthreads();
+        const int ncols = b_hi - b_lo;
+        for (int idx = threadIdx.x; idx < arows * ncols; idx += kWave * Q) {
+          const int bc = idx / arows, tr = idx - bc * arows;
+          const int bb = b_lo + bc;
+          const float* cell = smem + tr * (kWave + 1) + (bb - colbase);
+#pragma unroll
+          for (int h = 0; h < CB; ++h)
+            Yc[h * plane + bb * geo.L + a_lo + tr] = cell[h * Q * R * (kWave + 1)];
+        }
       }
     } else {             // row pass: transpose through the (consumed) image planes
       if (own) {
@@ -1632,7 +1650,6 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
   constexpr int NR = MODE == kModeBackward ? 2 * CB : CB;
   constexpr VariantSet VS = variants_for(MODE, r, CB, fp64);
   using LY = IfaceLayout<r, NR>;
-  if (MODE == kModeBackward && geo.out_t) return hipErrorInvalidValue;
   Acc* sum = reinterpret_cast<Acc*>(iface);
   Acc* us = sum + pl.sum_elems;
   Acc* gb = us + pl.u_elems;

@@ -127,6 +127,11 @@ size_t interface_bytes_max(int L, int W, int r, int cb, int stride, int fp64,
 // Expand blocks of a plan (one double of the lambda gradient each).
 int expand_blocks(const PassGeom& geo, const PassPlan& pl);
 
+// Whether every channel block of a stride-1 request has direct-read variant 0
+// forward and backward, so that passes can run as column passes of the image
+// and of its transpose (the layout of saved pass inputs depends on this).
+bool frames_supported(int C, int r, int stride, int fp64);
+
 // Stages of one pass (bit mask): reduce, interface solve, expand.
 constexpr int kStageReduce = 1, kStageInterface = 2, kStageExpand = 4, kStageAll = 7;
 // With the stage mask: store the pass output transposed (see PassGeom::out_t).
@@ -207,8 +212,10 @@ hipError_t launch_batch_pass(int variant, int fp64, int kind, const BatchDesc* t
                              const int* prefix_expand, const int totals[3], int B, int q,
                              int passes, int dir, int* counters, void* iface,
                              hipStream_t stream);
-// dst (cols x rows) = transpose of src (rows x cols), one plane.
-hipError_t launch_transpose(const float* src, float* dst, int rows, int cols, hipStream_t stream);
+// dst (cols x rows) = transpose of src (rows x cols), `planes` planes; with
+// accumulate, dst += the transpose.
+hipError_t launch_transpose(const float* src, float* dst, int rows, int cols, hipStream_t stream,
+                            int planes = 1, int accumulate = 0);
 
 // Zero n ints with a kernel (graph-capturable).
 hipError_t launch_zero_ints(int* p, int n, hipStream_t stream);

@@ -52,6 +52,17 @@ size_t interface_bytes_max(int L, int W, int r, int cb, int stride, int fp64, in
   return need;
 }
 
+bool frames_supported(int C, int r, int stride, int fp64) {
+  if (stride != 1 || r < 1 || r > kMaxR) return false;
+  const int cbs[2] = {3, 1};
+  for (int cb : cbs) {
+    if (cb == 3 && C < 3) continue;
+    if (cb == 1 && C % 3 == 0) continue;
+    if (!variants_of(r, cb, fp64).v[0].D || !bwd_variants_of(r, cb, fp64).v[0].D) return false;
+  }
+  return true;
+}
+
 int expand_blocks(const PassGeom& geo, const PassPlan& pl) {
   return ((geo.W + pl.OW - 1) / pl.OW) * ((geo.P + pl.Q - 1) / pl.Q);
 }
