@@ -638,15 +638,27 @@ sgwls_status sgwls_autotune(const float* x, const float* g, float* y, int C, int
         c += b;
       }
       if (c0 < 0) continue;
-      const int nv = variants_of(p->r, cb, p->prec).n;
+      const VariantSet vs = variants_of(p->r, cb, p->prec);
+      // With transposed frames the filter runs every pass as a direct column
+      // pass storing transposed, over the M x N and the N x M frame, both
+      // under the column-direction key: time exactly that.
+      const bool frames = dir == 0 && frames_supported(C, p->r, p->stride, p->prec);
       int best = 0;
       float best_ms = 0.0f;
-      for (int v = 0; v < nv && result == SGWLS_OK; ++v) {
-        const PassPlan pl = make_plan(L, W, p->r, cb, p->stride, p->prec, v);
-        const PassGeom geo = pass_geom(dir, M, N, pl, p->stride);
+      for (int v = 0; v < vs.n && result == SGWLS_OK; ++v) {
+        if (frames && !vs.v[v].D) continue;
         auto run = [&]() {
-          return launch_pass(p->r, cb, p->prec, x, g, y, c0, geo, pl, wp, nullptr, p->lambda,
-                             ws, s, kStageAll);
+          for (int f = 0; f < (frames ? 2 : 1); ++f) {
+            const int Mf = f == 0 ? M : N, Nf = f == 0 ? N : M;
+            const int Lf = dir == 0 ? Mf : Nf, Wf = dir == 0 ? Nf : Mf;
+            const PassPlan pl = make_plan(Lf, Wf, p->r, cb, p->stride, p->prec, v);
+            PassGeom geo = pass_geom(dir, Mf, Nf, pl, p->stride);
+            geo.out_t = frames ? 1 : 0;
+            const hipError_t e = launch_pass(p->r, cb, p->prec, x, g, y, c0, geo, pl, wp, nullptr,
+                                             p->lambda, ws, s, kStageAll);
+            if (e != hipSuccess) return e;
+          }
+          return hipSuccess;
         };
         if (run() != hipSuccess || hipEventRecord(e0, s) != hipSuccess) { result = SGWLS_E_HIP; break; }
         for (int i = 0; i < reps; ++i)
@@ -657,7 +669,7 @@ sgwls_status sgwls_autotune(const float* x, const float* g, float* y, int C, int
           result = SGWLS_E_HIP;
           break;
         }
-        if (v == 0 || ms < best_ms) { best = v; best_ms = ms; }
+        if (best_ms == 0.0f || ms < best_ms) { best = v; best_ms = ms; }
       }
       if (result != SGWLS_OK) break;
       {

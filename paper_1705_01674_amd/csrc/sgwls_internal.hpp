@@ -72,8 +72,8 @@ constexpr VariantSet variants_of(int r, int cb, int fp64) {
     return cb == 1
                ? VariantSet{9, {{16, 4, 1}, {16, 3, 0}, {8, 7, 0}, {12, 5, 0}, {8, 4, 1},
                                 {16, 4, 0}, {16, 2, 1}, {12, 4, 1}, {8, 4, 0}}, 8}
-               : VariantSet{8, {{8, 4, 1}, {8, 7, 0}, {6, 9, 0}, {10, 5, 0}, {8, 2, 1},
-                                {6, 4, 1}, {10, 4, 1}, {8, 4, 0}}, 8};
+               : VariantSet{10, {{8, 4, 1}, {8, 7, 0}, {6, 9, 0}, {10, 5, 0}, {8, 2, 1},
+                                 {6, 4, 1}, {10, 4, 1}, {8, 4, 0}, {8, 8, 1}, {4, 8, 1}}, 8};
   if (r == 2)
     return cb == 1 ? VariantSet{5, {{6, 4, 1}, {6, 9}, {4, 8, 1}, {4, 4}, {6, 4}}, 8}
                    : VariantSet{5, {{4, 4, 1}, {4, 8}, {4, 8, 1}, {4, 2}, {4, 4}}, 8};
@@ -90,7 +90,7 @@ constexpr VariantSet bwd_variants_of(int r, int cb, int fp64) {
   }
   if (r == 1)
     return cb == 1 ? VariantSet{3, {{8, 4, 1}, {8, 4}, {4, 4}}, 8}
-                   : VariantSet{3, {{4, 4, 1}, {4, 4}, {4, 8}}, 8};
+                   : VariantSet{3, {{6, 4, 1}, {4, 4, 1}, {4, 4}}, 8};
   if (r == 2) return VariantSet{2, {{4, 4, 1}, {4, 4}}, 8};
   return VariantSet{1, {{2, 2}}, 0};
 }
