@@ -239,9 +239,9 @@ sgwls_status sgwls_backward(const float* g, const float* saved, const float* gra
 /* ---- Batches of uneven images (not in the paper) ----
  * B images of independent sizes, each with its own parameters p[b] (host
  * arrays of B entries), are filtered together: every kernel stage of a pass
- * is ONE persistent launch over the whole batch, whose workgroups take work
- * units (image, channel, block of strips and chunks) from a global counter,
- * largest image first.  Requirements (else SGWLS_E_UNSUPPORTED or
+ * is one persistent launch per radius over all images of that radius, whose
+ * workgroups stride over the work units (image, channel, block of strips and
+ * chunks), largest image first.  Requirements (else SGWLS_E_UNSUPPORTED or
  * SGWLS_E_ARG): every p[b].iters, kind and prec equal; stride 1; r <= 2;
  * each side at most about 64*8 chunks long (2052 pixels for r = 2 and 4104
  * for r = 1 with the default variant).  Images with several channels are

@@ -226,10 +226,16 @@ TuneKey batch_tune_key(int fp64, int kind, double pixels) {
 
 struct BatchPlan {
   int B = 0, passes = 0, fp64 = 0, kind = 0, variant = 0;
-  std::vector<BatchDesc> tab;      // largest image first
-  std::vector<int> pre;            // [dir][stage][B + 1] unit prefix sums
-  int totals[2][3] = {{0, 0, 0}, {0, 0, 0}};
-  size_t off_tab = 0, off_pre = 0, off_cnt = 0, off_tmp = 0, off_iface = 0, total = 0;
+  std::vector<BatchDesc> tab;      // by radius, then largest image first
+  int first[kBatchMaxR + 1] = {};  // images of radius r: tab[first[r-1], first[r])
+  std::vector<int> pre;            // [radius][dir][stage][B + 1] unit prefix sums over
+                                   // the images of that radius, then the [B + 1]
+                                   // tile prefix sums of the guidance transposes
+  int totals[kBatchMaxR][2][3] = {};
+  int tiles_t = 0;                 // 32 x 32 tiles of all guidance transposes
+  size_t pre_at(int r, int dir, int st) const { return (size_t)(((r - 1) * 2 + dir) * 3 + st) * (B + 1); }
+  size_t pre_tiles() const { return (size_t)kBatchMaxR * 6 * (B + 1); }
+  size_t off_tab = 0, off_pre = 0, off_tmp = 0, off_gt = 0, off_iface = 0, total = 0;
 };
 
 // Validates the batch and lays out its workspace (ws may be NULL: sizes only).
@@ -256,21 +262,28 @@ sgwls_status batch_plan(const sgwls_image* imgs, const sgwls_params* p, int B, i
   std::vector<int> order(B);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (p[a].r != p[b].r) return p[a].r < p[b].r;
     return (long long)imgs[a].C * imgs[a].M * imgs[a].N > (long long)imgs[b].C * imgs[b].M * imgs[b].N;
   });
+  for (int r = 0; r <= kBatchMaxR; ++r) plan.first[r] = 0;
+  for (int b = 0; b < B; ++b)
+    for (int r = p[b].r; r <= kBatchMaxR; ++r) ++plan.first[r];
   const size_t acc = fp64 ? 8 : 4;
   plan.off_tab = 0;
   plan.off_pre = align_up(sizeof(BatchDesc) * B);
-  plan.off_cnt = plan.off_pre + align_up(sizeof(int) * 6 * (B + 1));
-  plan.off_tmp = plan.off_cnt + align_up(sizeof(int) * 3 * plan.passes);
-  size_t tmp_bytes = 0;
-  for (int b = 0; b < B; ++b) tmp_bytes += image_bytes(imgs[b].C, imgs[b].M, imgs[b].N);
-  plan.off_iface = plan.off_tmp + tmp_bytes;
+  plan.off_tmp = plan.off_pre + align_up(sizeof(int) * (kBatchMaxR * 6 + 1) * (B + 1));
+  size_t tmp_bytes = 0, gt_bytes = 0;
+  for (int b = 0; b < B; ++b) {
+    tmp_bytes += image_bytes(imgs[b].C, imgs[b].M, imgs[b].N);
+    gt_bytes += image_bytes(1, imgs[b].M, imgs[b].N);
+  }
+  plan.off_gt = plan.off_tmp + tmp_bytes;
+  plan.off_iface = plan.off_gt + gt_bytes;
   char* base = reinterpret_cast<char*>(ws);
   plan.tab.assign(B, BatchDesc{});
-  plan.pre.assign(6 * (B + 1), 0);
-  size_t tmp_off = plan.off_tmp, iface_elems = 0;
-  long long units[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  plan.pre.assign((kBatchMaxR * 6 + 1) * (B + 1), 0);
+  size_t tmp_off = plan.off_tmp, gt_off = plan.off_gt, iface_elems = 0;
+  long long units[kBatchMaxR][2][3] = {}, tiles = 0;
   for (int t = 0; t < B; ++t) {
     const int b = order[t];
     const sgwls_image& im = imgs[b];
@@ -281,6 +294,10 @@ sgwls_status batch_plan(const sgwls_image* imgs, const sgwls_params* p, int B, i
     D.u = im.u;
     D.tmp = ws ? reinterpret_cast<float*>(base + tmp_off) : nullptr;
     tmp_off += image_bytes(im.C, im.M, im.N);
+    D.gT = ws ? reinterpret_cast<float*>(base + gt_off) : nullptr;
+    gt_off += image_bytes(1, im.M, im.N);
+    tiles += (long long)((im.M + 31) / 32) * ((im.N + 31) / 32);
+    plan.pre[plan.pre_tiles() + t + 1] = (int)std::min<long long>(tiles, 0x7fffffff);
     D.C = im.C;
     D.M = im.M;
     D.N = im.N;
@@ -293,11 +310,14 @@ sgwls_status batch_plan(const sgwls_image* imgs, const sgwls_params* p, int B, i
     const int F = 2 * T2 + 2 * pb.r + pb.r * pb.r;
     long long sum_max = 0, us_max = 0;
     for (int dir = 0; dir < 2; ++dir) {
+      // Both passes are column passes storing transposed: the row pass runs
+      // on the transposed image (N x M) that the column pass leaves.
       PassGeom& g = D.geo[dir];
       g.L = dir == 0 ? im.M : im.N;
       g.W = dir == 0 ? im.N : im.M;
-      g.sa = dir == 0 ? im.N : 1;
-      g.sb = dir == 0 ? 1 : im.N;
+      g.sa = g.W;
+      g.sb = 1;
+      g.out_t = 1;
       g.plane = (long long)im.M * im.N;
       g.nK = strip_count(g.W, pb.r, 1);
       g.stride = 1;
@@ -311,11 +331,15 @@ sgwls_status batch_plan(const sgwls_image* imgs, const sgwls_params* p, int B, i
       D.nby[dir] = (g.P + bv.Q - 1) / bv.Q;
       sum_max = std::max(sum_max, (long long)g.P * F * g.nK);
       us_max = std::max(us_max, (long long)std::max(n, 1) * pb.r * g.nK);
+      // Prefix sums of the radius' sub-table: entry t - first + 1.
       const bool split = g.P > 1;
-      units[dir][0] += split ? (long long)im.C * D.nbx_red[dir] * D.nby[dir] : 0;
-      units[dir][1] += split ? (long long)im.C * g.nK : 0;
-      units[dir][2] += (long long)im.C * D.nbx_exp[dir] * D.nby[dir];
-      for (int st = 0; st < 3; ++st) plan.pre[(dir * 3 + st) * (B + 1) + t + 1] = (int)std::min<long long>(units[dir][st], 0x7fffffff);
+      long long* un = units[pb.r - 1][dir];
+      un[0] += split ? (long long)im.C * D.nbx_red[dir] * D.nby[dir] : 0;
+      un[1] += split ? (long long)im.C * g.nK : 0;
+      un[2] += (long long)im.C * D.nbx_exp[dir] * D.nby[dir];
+      const int tl = t - plan.first[pb.r - 1];
+      for (int st = 0; st < 3; ++st)
+        plan.pre[plan.pre_at(pb.r, dir, st) + tl + 1] = (int)std::min<long long>(un[st], 0x7fffffff);
     }
     D.sum_ch = sum_max;
     D.us_ch = us_max;
@@ -324,11 +348,14 @@ sgwls_status batch_plan(const sgwls_image* imgs, const sgwls_params* p, int B, i
     D.us_base = (long long)iface_elems;
     iface_elems += (size_t)im.C * us_max;
   }
-  for (int dir = 0; dir < 2; ++dir)
-    for (int st = 0; st < 3; ++st) {
-      if (units[dir][st] > 0x7fffffffLL) return SGWLS_E_SHAPE;
-      plan.totals[dir][st] = (int)units[dir][st];
-    }
+  for (int r = 0; r < kBatchMaxR; ++r)
+    for (int dir = 0; dir < 2; ++dir)
+      for (int st = 0; st < 3; ++st) {
+        if (units[r][dir][st] > 0x7fffffffLL) return SGWLS_E_SHAPE;
+        plan.totals[r][dir][st] = (int)units[r][dir][st];
+      }
+  if (tiles > 0x7fffffffLL) return SGWLS_E_SHAPE;
+  plan.tiles_t = (int)tiles;
   plan.total = plan.off_iface + align_up(iface_elems * acc);
   return SGWLS_OK;
 }
@@ -354,20 +381,22 @@ sgwls_status batch_enqueue(const BatchPlan& plan, void* ws, hipStream_t s) {
   char* base = reinterpret_cast<char*>(ws);
   BatchDesc* tab = reinterpret_cast<BatchDesc*>(base + plan.off_tab);
   int* pre = reinterpret_cast<int*>(base + plan.off_pre);
-  int* cnt = reinterpret_cast<int*>(base + plan.off_cnt);
   if (upload_bytes(tab, plan.tab.data(), sizeof(BatchDesc) * plan.B, s) != hipSuccess ||
-      upload_bytes(pre, plan.pre.data(), sizeof(int) * plan.pre.size(), s) != hipSuccess ||
-      launch_zero_ints(cnt, 3 * plan.passes, s) != hipSuccess)
+      upload_bytes(pre, plan.pre.data(), sizeof(int) * plan.pre.size(), s) != hipSuccess)
     return SGWLS_E_HIP;
-  const int B = plan.B;
+  if (launch_batch_transpose(tab, pre + plan.pre_tiles(), plan.B, plan.tiles_t, s) != hipSuccess)
+    return SGWLS_E_HIP;
   for (int q = 0; q < plan.passes; ++q) {
     const int dir = q % 2;
-    const int* pr = pre + (dir * 3 + 0) * (B + 1);
-    const int* pi = pre + (dir * 3 + 1) * (B + 1);
-    const int* pe = pre + (dir * 3 + 2) * (B + 1);
-    if (launch_batch_pass(plan.variant, plan.fp64, plan.kind, tab, pr, pi, pe, plan.totals[dir], B,
-                          q, plan.passes, dir, cnt + 3 * q, base + plan.off_iface, s) != hipSuccess)
-      return SGWLS_E_HIP;
+    for (int r = 1; r <= kBatchMaxR; ++r) {
+      const int b0 = plan.first[r - 1], nb = plan.first[r] - b0;
+      if (nb == 0) continue;
+      if (launch_batch_pass(plan.variant, plan.fp64, plan.kind, r, tab + b0,
+                            pre + plan.pre_at(r, dir, 0), pre + plan.pre_at(r, dir, 1),
+                            pre + plan.pre_at(r, dir, 2), plan.totals[r - 1][dir], nb, q, dir,
+                            base + plan.off_iface, s) != hipSuccess)
+        return SGWLS_E_HIP;
+    }
   }
   return SGWLS_OK;
 }
@@ -407,9 +436,11 @@ std::string graph_key(const BatchPlan& plan, void* ws, hipStream_t s) {
 sgwls_status batch_run(const BatchPlan& plan, void* ws, hipStream_t s) {
   // Prepare the persistent grid sizes outside any capture (no launch).
   const int none[3] = {0, 0, 0};
-  if (launch_batch_pass(plan.variant, plan.fp64, plan.kind, nullptr, nullptr, nullptr, nullptr,
-                        none, plan.B, 0, plan.passes, 0, nullptr, nullptr, s) != hipSuccess)
-    return SGWLS_E_HIP;
+  for (int r = 1; r <= kBatchMaxR; ++r)
+    if (plan.first[r] > plan.first[r - 1] &&
+        launch_batch_pass(plan.variant, plan.fp64, plan.kind, r, nullptr, nullptr, nullptr, nullptr,
+                          none, 0, 0, 0, nullptr, s) != hipSuccess)
+      return SGWLS_E_HIP;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (s == nullptr || hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
     return batch_enqueue(plan, ws, s);

@@ -1,9 +1,12 @@
-// Persistent kernels for batches of uneven images.  Each workgroup loops:
-// take the next unit from the stage's counter, locate its image by binary
-// search over the unit prefix sums, run the same block code as the
-// single-image kernels for that image's geometry, radius and lambda.  Units
-// are ordered largest image first (the host sorts the table), so the tail of
-// a launch is made of small blocks.
+// Persistent kernels for batches of uneven images (every pass a direct-read
+// column pass storing transposed, as for single images).  Each workgroup
+// strides over the units of its stage (unit blockIdx.x, then + gridDim.x, ...),
+// locates each unit's image over the unit prefix sums and runs the same block
+// code as the single-image kernels for that image's geometry and lambda.
+// Units are ordered largest image first (the host sorts the table), so the
+// tail of a launch is made of small blocks.  A static stride replaces a shared
+// work counter: atomics on one address serialise at the L2 and cost more than
+// the balance they buy across units of near-equal size.
 #include "sgwls_device.hpp"
 
 namespace sgwls {
@@ -21,183 +24,208 @@ DEV int unit_image(const int* __restrict__ pre, int B, int u) {
   return lo;
 }
 
-// Input and output of pass q (x_0 = f, x_passes = u; the others alternate
-// between tmp and u so that the last pass lands in u).
-DEV const float* pass_in(const BatchDesc& D, int q, int passes) {
+// Image of unit u, remembered with its unit range [lo, hi): consecutive
+// units of a workgroup mostly fall in one image (units are handed out in
+// increasing order), which then costs no search.
+struct Cursor {
+  int i = 0, lo = 0, hi = 0;
+  DEV int locate(const int* __restrict__ pre, int B, int u) {
+    if (u < lo || u >= hi) {
+      i = unit_image(pre, B, u);
+      lo = pre[i];
+      hi = pre[i + 1];
+    }
+    return i;
+  }
+};
+
+// Every pass is a column pass storing its output transposed: pass 2t reads
+// the image (f, then u) and writes tmp (N x M); pass 2t+1 reads tmp -- the
+// row pass, on the transposed image -- and writes u.
+DEV const float* pass_in(const BatchDesc& D, int q) {
   if (q == 0) return D.f;
-  return ((passes - (q - 1)) % 2 == 0) ? D.tmp : D.u;
+  return (q % 2) ? D.tmp : D.u;
 }
-DEV float* pass_out(const BatchDesc& D, int q, int passes) {
-  if (q == passes - 1) return D.u;
-  return ((passes - q) % 2 == 0) ? D.tmp : D.u;
-}
+DEV float* pass_out(const BatchDesc& D, int q) { return (q % 2) ? D.u : D.tmp; }
 
-// Next unit of the workgroup (all threads receive the same value).
-DEV int next_unit(int* counter, int* slot) {
-  __syncthreads();   // the previous unit is finished with the LDS and the slot
-  if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
-  __syncthreads();
-  return __builtin_amdgcn_readfirstlane(*slot);
-}
-
-template <int KIND, typename Acc, int R1, int R2, int Q>
+// The kernels of one radius: a batch runs one launch per stage and radius
+// over the images of that radius, so each kernel holds the registers of its
+// own radius only.
+template <int r, int KIND, typename Acc, int R, int Q>
 __global__ __launch_bounds__(kWave* Q) void k_batch_reduce(const BatchDesc* __restrict__ tab,
                                                            const int* __restrict__ pre, int B,
-                                                           int q, int passes, int dir,
-                                                           int* counter, Acc* __restrict__ iface) {
+                                                           int q, int dir,
+                                                           Acc* __restrict__ iface) {
   extern __shared__ float smem[];
-  __shared__ int slot;
   const int total = pre[B];
-  for (;;) {
-    const int u = next_unit(counter, &slot);
-    if (u >= total) break;
-    const int i = unit_image(pre, B, u);
+  Cursor cur;
+  for (int u = blockIdx.x; u < total; u += gridDim.x) {
+    __syncthreads();   // the previous unit is finished with the LDS
+    const int i = cur.locate(pre, B, u);
     const BatchDesc& D = tab[i];
-    int local = u - pre[i];
+    int local = u - cur.lo;
     const int nbx = D.nbx_red[dir], per_c = nbx * D.nby[dir];
     const int c = local / per_c;
     local -= c * per_c;
     const int by = local / nbx, bx = local - by * nbx;
-    const float* x = pass_in(D, q, passes);
+    const PassGeom& geo = D.geo[dir];
+    const PlaneSrc<1> src{pass_in(D, q), nullptr, c, (int)geo.plane};
+    const float* gf = dir ? D.gT : D.g;
     Acc* sum = iface + D.sum_base + c * D.sum_ch;
-    if (D.r == 1)
-      reduce_block<1, 1, R1, Q, true, KIND, Acc, kModeForward>(x, nullptr, D.g, D.geo[dir], D.wp,
-                                                               D.lam, c, 0, sum, bx, by, smem);
-    else
-      reduce_block<2, 1, R2, Q, true, KIND, Acc, kModeForward>(x, nullptr, D.g, D.geo[dir], D.wp,
-                                                               D.lam, c, 0, sum, bx, by, smem);
+    reduce_tile<r, 1, R, Q, true, KIND, Acc, kModeForward, true>(geo, D.wp, D.lam, 0, sum, bx, by,
+                                                                 smem, gf, &src);
   }
 }
 
-// One wave per workgroup; each wave solves the separator system of one
-// (image, channel, strip) unit at a time.
-template <typename Acc>
-__global__ __launch_bounds__(kWave) void k_batch_iface(const BatchDesc* __restrict__ tab,
-                                                       const int* __restrict__ pre, int B,
-                                                       int dir, int* counter,
-                                                       Acc* __restrict__ iface) {
-  __shared__ int slot;
+// kIfaceWaves independent waves per workgroup, each solving the separator
+// systems of its own (image, channel, strip) units (the solver is
+// wave-local: no workgroup barrier).
+constexpr int kIfaceWaves = 4;
+
+template <int r, typename Acc>
+__global__ __launch_bounds__(kWave* kIfaceWaves) void k_batch_iface(
+    const BatchDesc* __restrict__ tab, const int* __restrict__ pre, int B, int dir,
+    Acc* __restrict__ iface) {
   const int total = pre[B];
-  for (;;) {
-    const int u = next_unit(counter, &slot);
-    if (u >= total) break;
-    const int i = unit_image(pre, B, u);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  Cursor cur;
+  for (int u = blockIdx.x * kIfaceWaves + wave; u < total; u += gridDim.x * kIfaceWaves) {
+    const int i = cur.locate(pre, B, u);
     const BatchDesc& D = tab[i];
-    const int local = u - pre[i];
+    const int local = u - cur.lo;
     const int nK = D.geo[dir].nK;
     const int c = local / nK, ki = local - c * nK;
     const Acc* sum = iface + D.sum_base + c * D.sum_ch;
     Acc* us = iface + D.us_base + c * D.us_ch;
-    if (D.r == 1)
-      iface_pcr_strip<1, 1, kBatchMM, Acc>(sum, us, D.geo[dir].P, D.m[dir], ki);
-    else
-      iface_pcr_strip<2, 1, kBatchMM, Acc>(sum, us, D.geo[dir].P, D.m[dir], ki);
+    iface_pcr_strip<r, 1, kBatchMM, Acc>(sum, us, D.geo[dir].P, D.m[dir], ki);
   }
 }
 
-template <int KIND, typename Acc, int R1, int R2, int Q>
+template <int r, int KIND, typename Acc, int R, int Q>
 __global__ __launch_bounds__(kWave* Q) void k_batch_expand(const BatchDesc* __restrict__ tab,
                                                            const int* __restrict__ pre, int B,
-                                                           int q, int passes, int dir,
-                                                           int* counter,
+                                                           int q, int dir,
                                                            const Acc* __restrict__ iface) {
   extern __shared__ float smem[];
-  __shared__ int slot;
   const int total = pre[B];
   const BwdArgs none{};
-  for (;;) {
-    const int u = next_unit(counter, &slot);
-    if (u >= total) break;
-    const int i = unit_image(pre, B, u);
+  Cursor cur;
+  for (int u = blockIdx.x; u < total; u += gridDim.x) {
+    __syncthreads();   // the previous unit is finished with the LDS
+    const int i = cur.locate(pre, B, u);
     const BatchDesc& D = tab[i];
-    int local = u - pre[i];
+    int local = u - cur.lo;
     const int nbx = D.nbx_exp[dir], per_c = nbx * D.nby[dir];
     const int c = local / per_c;
     local -= c * per_c;
     const int by = local / nbx, bx = local - by * nbx;
-    const float* x = pass_in(D, q, passes);
-    float* y = pass_out(D, q, passes);
+    const PassGeom& geo = D.geo[dir];
+    const PlaneSrc<1> src{pass_in(D, q), nullptr, c, (int)geo.plane};
+    const float* gf = dir ? D.gT : D.g;
+    float* y = pass_out(D, q);
     const Acc* us = iface + D.us_base + c * D.us_ch;
-    if (D.r == 1)
-      expand_block<1, 1, R1, Q, true, KIND, Acc, kModeForward>(x, D.g, y, D.geo[dir], D.wp, D.lam,
-                                                               c, us, D.OW, 0, none, bx, by, nbx,
-                                                               smem);
-    else
-      expand_block<2, 1, R2, Q, true, KIND, Acc, kModeForward>(x, D.g, y, D.geo[dir], D.wp, D.lam,
-                                                               c, us, D.OW, 0, none, bx, by, nbx,
-                                                               smem);
+    expand_tile<r, 1, R, Q, true, KIND, Acc, kModeForward, true>(gf, y, geo, D.wp, D.lam, c, us,
+                                                                 D.OW, 0, none, bx, by, nbx, smem,
+                                                                 &src);
   }
 }
 
-__global__ void k_zero_ints(int* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
+// LDS of one batched reduce / expand block (direct reads: the reduce output
+// staging and the transposed-store staging).
+template <typename Acc, int r, int R, int Q>
+constexpr size_t batch_lds() {
+  const size_t out = sizeof(float) * Q * R * (kWave + 1);
+  const size_t F = r * (r + 1) + 2 * r + r * r;
+  const size_t stage = sizeof(Acc) * kWave * Q * F;
+  return out > stage ? out : stage;
 }
 
-// LDS of one batched reduce / expand block: the larger radius decides.
-template <typename Acc, int R1, int R2, int Q>
-size_t batch_lds() {
-  size_t need = 0;
-  const int R[2] = {R1, R2};
-  for (int r = 1; r <= kBatchMaxR; ++r) {
-    const size_t pitch = kWave + 2 * r + 1;
-    const size_t tile = sizeof(float) * 2 * (Q * R[r - 1] + 2) * pitch;
-    const size_t F = r * (r + 1) + 2 * r + r * r;
-    const size_t stage = sizeof(Acc) * kWave * Q * F;
-    need = std::max(need, std::max(tile, stage));
+// Guidance transposes of a batch: one 32 x 32 tile per workgroup.
+__global__ __launch_bounds__(256) void k_batch_transpose(const BatchDesc* __restrict__ tab,
+                                                         const int* __restrict__ pre, int B) {
+  __shared__ float t[32][33];
+  const int u = blockIdx.x;
+  const int i = unit_image(pre, B, u);
+  const BatchDesc& D = tab[i];
+  const int rows = D.M, cols = D.N;
+  const int tiles_x = (cols + 31) / 32;
+  const int local = u - pre[i];
+  const int c0 = (local % tiles_x) * 32, r0 = (local / tiles_x) * 32;
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+  for (int k = ty; k < 32; k += 8) {
+    const int rr = r0 + k, cc = c0 + tx;
+    if (rr < rows && cc < cols) t[k][tx] = D.g[(size_t)rr * cols + cc];
   }
-  return need;
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int cc = c0 + k, rr = r0 + tx;
+    if (rr < rows && cc < cols) D.gT[(size_t)cc * rows + rr] = t[tx][k];
+  }
 }
 
-// Resident workgroups of a kernel over the whole device (the persistent grid).
+// Resident workgroups of a kernel over the whole device (the persistent
+// grid), from its register and LDS footprint: 512 VGPRs per lane and at
+// most 8 waves per SIMD, 4 SIMDs and 160 KiB of LDS per compute unit.
+// Workgroups beyond what fits only start late and find the queue drained.
 template <typename K>
 int persistent_grid(K kernel, int block, size_t lds) {
-  int dev = 0, cus = 0, per_cu = 0;
+  int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) != hipSuccess)
-    return 0;
-  return std::max(1, per_cu) * std::max(1, cus);
+  hipFuncAttributes fa{};
+  if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kernel)) != hipSuccess) return 0;
+  const int vgprs = std::max(8, (fa.numRegs + 7) / 8 * 8);
+  const int waves_simd = std::min(8, 512 / vgprs);
+  const int waves_wg = (block + kWave - 1) / kWave;
+  int per_cu = std::max(1, waves_simd * 4 / waves_wg);
+  const size_t lds_wg = lds + fa.sharedSizeBytes;
+  if (lds_wg > 0) per_cu = std::min<long long>(per_cu, std::max<size_t>(1, (160u << 10) / lds_wg));
+  return per_cu * std::max(1, cus);
 }
 
-template <int KIND, typename Acc, int R1, int R2, int Q>
+template <int r, int KIND, typename Acc, int R, int Q>
 hipError_t batch_pass_impl(const BatchDesc* tab, const int* pre_r, const int* pre_i,
-                           const int* pre_e, const int totals[3], int B, int q, int passes,
-                           int dir, int* counters, void* iface, hipStream_t s) {
+                           const int* pre_e, const int totals[3], int B, int q, int dir,
+                           void* iface, hipStream_t s) {
   Acc* buf = reinterpret_cast<Acc*>(iface);
-  const size_t lds = batch_lds<Acc, R1, R2, Q>();
-  static const int g_red = persistent_grid(k_batch_reduce<KIND, Acc, R1, R2, Q>, kWave * Q, lds);
-  static const int g_if = persistent_grid(k_batch_iface<Acc>, kWave, 0);
-  static const int g_exp = persistent_grid(k_batch_expand<KIND, Acc, R1, R2, Q>, kWave * Q, lds);
+  constexpr size_t lds = batch_lds<Acc, r, R, Q>();
+  static const int g_red = persistent_grid(k_batch_reduce<r, KIND, Acc, R, Q>, kWave * Q, lds);
+  static const int g_if = persistent_grid(k_batch_iface<r, Acc>, kWave * kIfaceWaves, 0);
+  static const int g_exp = persistent_grid(k_batch_expand<r, KIND, Acc, R, Q>, kWave * Q, lds);
   if (g_red <= 0 || g_if <= 0 || g_exp <= 0) return hipErrorInvalidConfiguration;
   if (totals[0] + totals[1] + totals[2] == 0) return hipSuccess;
   if (totals[0] > 0)
-    hipLaunchKernelGGL((k_batch_reduce<KIND, Acc, R1, R2, Q>), dim3(std::min(g_red, totals[0])),
-                       dim3(kWave * Q), lds, s, tab, pre_r, B, q, passes, dir, counters + 0, buf);
+    hipLaunchKernelGGL((k_batch_reduce<r, KIND, Acc, R, Q>), dim3(std::min(g_red, totals[0])),
+                       dim3(kWave * Q), lds, s, tab, pre_r, B, q, dir, buf);
   if (totals[1] > 0)
-    hipLaunchKernelGGL((k_batch_iface<Acc>), dim3(std::min(g_if, totals[1])), dim3(kWave), 0, s,
-                       tab, pre_i, B, dir, counters + 1, buf);
+    hipLaunchKernelGGL((k_batch_iface<r, Acc>),
+                       dim3(std::min(g_if, (totals[1] + kIfaceWaves - 1) / kIfaceWaves)),
+                       dim3(kWave * kIfaceWaves), 0, s, tab, pre_i, B, dir, buf);
   if (totals[2] > 0)
-    hipLaunchKernelGGL((k_batch_expand<KIND, Acc, R1, R2, Q>), dim3(std::min(g_exp, totals[2])),
-                       dim3(kWave * Q), lds, s, tab, pre_e, B, q, passes, dir, counters + 2,
-                       (const Acc*)buf);
+    hipLaunchKernelGGL((k_batch_expand<r, KIND, Acc, R, Q>), dim3(std::min(g_exp, totals[2])),
+                       dim3(kWave * Q), lds, s, tab, pre_e, B, q, dir, (const Acc*)buf);
   return hipGetLastError();
 }
 
 template <int KIND, int fp64, int V>
-hipError_t batch_variant_impl(int v, const BatchDesc* tab, const int* pre_r, const int* pre_i,
-                              const int* pre_e, const int totals[3], int B, int q, int passes,
-                              int dir, int* counters, void* iface, hipStream_t s) {
+hipError_t batch_variant_impl(int v, int r, const BatchDesc* tab, const int* pre_r,
+                              const int* pre_i, const int* pre_e, const int totals[3], int B,
+                              int q, int dir, void* iface, hipStream_t s) {
   if constexpr (V < batch_variant_count(fp64)) {
     if (v == V) {
       constexpr BatchVariant bv = batch_variant(V, fp64);
       using Acc = typename std::conditional<fp64 != 0, double, float>::type;
-      return batch_pass_impl<KIND, Acc, bv.R1, bv.R2, bv.Q>(tab, pre_r, pre_i, pre_e, totals, B,
-                                                            q, passes, dir, counters, iface, s);
+      if (r == 1)
+        return batch_pass_impl<1, KIND, Acc, bv.R1, bv.Q>(tab, pre_r, pre_i, pre_e, totals, B, q,
+                                                          dir, iface, s);
+      if (r == 2)
+        return batch_pass_impl<2, KIND, Acc, bv.R2, bv.Q>(tab, pre_r, pre_i, pre_e, totals, B, q,
+                                                          dir, iface, s);
+      return hipErrorInvalidValue;
     }
-    return batch_variant_impl<KIND, fp64, V + 1>(v, tab, pre_r, pre_i, pre_e, totals, B, q,
-                                                 passes, dir, counters, iface, s);
+    return batch_variant_impl<KIND, fp64, V + 1>(v, r, tab, pre_r, pre_i, pre_e, totals, B, q,
+                                                 dir, iface, s);
   } else {
     return hipErrorInvalidValue;
   }
@@ -205,24 +233,25 @@ hipError_t batch_variant_impl(int v, const BatchDesc* tab, const int* pre_r, con
 
 }  // namespace
 
-hipError_t launch_batch_pass(int variant, int fp64, int kind, const BatchDesc* tab,
+hipError_t launch_batch_pass(int variant, int fp64, int kind, int r, const BatchDesc* tab,
                              const int* pre_r, const int* pre_i, const int* pre_e,
-                             const int totals[3], int B, int q, int passes, int dir,
-                             int* counters, void* iface, hipStream_t s) {
+                             const int totals[3], int B, int q, int dir, void* iface,
+                             hipStream_t s) {
   if (kind == 0)
-    return fp64 ? batch_variant_impl<0, 1, 0>(variant, tab, pre_r, pre_i, pre_e, totals, B, q,
-                                              passes, dir, counters, iface, s)
-                : batch_variant_impl<0, 0, 0>(variant, tab, pre_r, pre_i, pre_e, totals, B, q,
-                                              passes, dir, counters, iface, s);
-  return fp64 ? batch_variant_impl<1, 1, 0>(variant, tab, pre_r, pre_i, pre_e, totals, B, q,
-                                            passes, dir, counters, iface, s)
-              : batch_variant_impl<1, 0, 0>(variant, tab, pre_r, pre_i, pre_e, totals, B, q,
-                                            passes, dir, counters, iface, s);
+    return fp64 ? batch_variant_impl<0, 1, 0>(variant, r, tab, pre_r, pre_i, pre_e, totals, B, q,
+                                              dir, iface, s)
+                : batch_variant_impl<0, 0, 0>(variant, r, tab, pre_r, pre_i, pre_e, totals, B, q,
+                                              dir, iface, s);
+  return fp64 ? batch_variant_impl<1, 1, 0>(variant, r, tab, pre_r, pre_i, pre_e, totals, B, q,
+                                            dir, iface, s)
+              : batch_variant_impl<1, 0, 0>(variant, r, tab, pre_r, pre_i, pre_e, totals, B, q,
+                                            dir, iface, s);
 }
 
-hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_ints, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+hipError_t launch_batch_transpose(const BatchDesc* tab, const int* pre_t, int B, int tiles,
+                                  hipStream_t s) {
+  if (tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_transpose, dim3(tiles), dim3(256), 0, s, tab, pre_t, B);
   return hipGetLastError();
 }
 

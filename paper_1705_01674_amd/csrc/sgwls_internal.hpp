@@ -166,9 +166,9 @@ hipError_t launch_bwd_fixup(const float* side, float* gbar, const PassGeom& geo,
 
 // ---------------------------------------------------------------------------
 // Batches of uneven images (one channel per work unit, stride 1, r <= 2).
-// Each stage of a pass is one persistent launch over the whole batch: its
-// workgroups take units (image, channel, block) from a global counter, so
-// small and large images share the GPU.
+// Each stage of a pass is one persistent launch per radius over all images
+// of that radius: its workgroups stride over the units (image, channel,
+// block), so small and large images share the GPU.
 
 constexpr int kBatchMaxR = 2;
 constexpr int kBatchMM = 8;       // separators per lane of the batched wave solver
@@ -190,12 +190,13 @@ struct BatchDesc {
   const float* f;      // input, C x M x N
   const float* g;      // guidance, M x N
   float* u;            // output
-  float* tmp;          // ping-pong image (workspace)
+  float* tmp;          // ping-pong image, transposed frame (workspace)
+  float* gT;           // transposed guidance, N x M (workspace)
   int C, M, N, r;
   float lam;
   int pad0;
   WeightParams wp;
-  PassGeom geo[2];     // column and row pass
+  PassGeom geo[2];     // column pass of the image (M x N) and of its transpose (N x M)
   int OW;              // output columns per expand block
   int m[2];            // separator blocks per lane of the interface solver
   int nbx_red[2], nbx_exp[2], nby[2];
@@ -203,22 +204,24 @@ struct BatchDesc {
   long long sum_ch, us_ch;       // per-channel strides of those buffers
 };
 
-// Stages of one batched pass; prefix = the (B+1) unit prefix sums of the
-// stage's direction, counters = 3 ints (one per stage), zeroed beforehand.
+// Stages of one batched pass over the images of radius r (tab: their
+// table entries, B of them); prefix = the (B+1) unit prefix sums of the
+// stage's direction.
 // With all totals 0 it launches nothing and only prepares the persistent
 // grid sizes of the variant (a device query, not a stream operation).
-hipError_t launch_batch_pass(int variant, int fp64, int kind, const BatchDesc* tab,
+hipError_t launch_batch_pass(int variant, int fp64, int kind, int r, const BatchDesc* tab,
                              const int* prefix_reduce, const int* prefix_iface,
                              const int* prefix_expand, const int totals[3], int B, int q,
-                             int passes, int dir, int* counters, void* iface,
-                             hipStream_t stream);
+                             int dir, void* iface, hipStream_t stream);
 // dst (cols x rows) = transpose of src (rows x cols), `planes` planes; with
 // accumulate, dst += the transpose.
 hipError_t launch_transpose(const float* src, float* dst, int rows, int cols, hipStream_t stream,
                             int planes = 1, int accumulate = 0);
 
-// Zero n ints with a kernel (graph-capturable).
-hipError_t launch_zero_ints(int* p, int n, hipStream_t stream);
+// Transposed guidance of every image of a batch (pre_t: tile prefix sums).
+hipError_t launch_batch_transpose(const BatchDesc* tab, const int* pre_t, int B, int tiles,
+                                  hipStream_t stream);
+
 
 // Up to kWords 32-bit words carried by value as kernel arguments.
 struct WordChunk {
