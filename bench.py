@@ -44,7 +44,26 @@ def parse():
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--stride", type=int, default=1)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--counters", action="store_true",
+                    help="for rocprofv3 --pmc runs: the tuned forward steps only, then three "
+                         "copies of 64 MiB (the counter calibration), one short JSON line")
     return ap.parse_args()
+
+
+def counter_run(torch, step, args, ms_note):
+    """Forward steps followed by a plain device copy of known size: a counter
+    pass divides each kernel's FETCH_SIZE / WRITE_SIZE by what the copy's
+    dispatches read for their 64 MiB, which gives HBM bytes."""
+    for _ in range(args.warmup + args.steps):
+        step()
+    torch.cuda.synchronize()
+    src = torch.ones(64 * 1024 * 1024 // 4, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)          # 64 MiB read + 64 MiB written per copy
+    torch.cuda.synchronize()
+    print(json.dumps({"counters_run": True, "filter_calls": args.warmup + args.steps,
+                      "calibration_copy_bytes": 64 * 1024 * 1024, **ms_note}), flush=True)
 
 
 def time_events(torch, fn, reps):
@@ -136,6 +155,11 @@ def main():
 
     def step():
         ops.sgwls_filter(f, g, p, out=u, workspace=ws)
+
+    if args.counters:
+        counter_run(torch, step, args, {"variants": {f"{'col' if d == 0 else 'row'}_c{cb}": v
+                                                     for (d, cb), v in sorted(tuned.items())}})
+        return
 
     for _ in range(args.warmup):
         step()

@@ -1603,6 +1603,22 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
   }
 }
 
+// Logical block (bx, by) of this workgroup such that each XCD runs one
+// contiguous range of the row-major block order.  The dispatcher deals
+// workgroups to the 8 XCDs round-robin by linear id; neighbouring blocks
+// overlap in their halo columns and rows, and the overlap is an L2 hit only
+// when both run on one XCD (each XCD has its own L2).
+constexpr int kXcds = 8;
+DEV void xcd_block(int& bx, int& by) {
+  const int nx = gridDim.x, nb = nx * gridDim.y;
+  const int lin = blockIdx.y * nx + blockIdx.x;
+  const int x = lin % kXcds, idx = lin / kXcds;
+  const int q = nb / kXcds, rem = nb % kXcds;
+  const int logical = x * q + min(x, rem) + idx;
+  by = logical / nx;
+  bx = logical - by * nx;
+}
+
 // Stride-1 column-pass kernels without an LDS tile (GlobalChunk views).
 template <int r, int CB, int R, int Q, int KIND, typename Acc, int MODE>
 __global__ __launch_bounds__(kWave* Q) void k_reduce_d(
@@ -1611,8 +1627,10 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce_d(
     Acc* __restrict__ sum) {
   extern __shared__ float smem[];
   const PlaneSrc<CB> src{X, X2, c0, (int)geo.plane};
+  int bx, by;
+  xcd_block(bx, by);
   reduce_tile<r, CB, R, Q, true, KIND, Acc, MODE, true>(
-      geo, wp, load_lambda(lam_dev, lam_host), 0, sum, blockIdx.x, blockIdx.y, smem, G, &src);
+      geo, wp, load_lambda(lam_dev, lam_host), 0, sum, bx, by, smem, G, &src);
 }
 
 template <int r, int CB, int R, int Q, int KIND, typename Acc, int MODE>
@@ -1622,9 +1640,11 @@ __global__ __launch_bounds__(kWave* Q) void k_expand_d(
     const Acc* __restrict__ Us, int OW, BwdArgs bw) {
   extern __shared__ float smem[];
   const PlaneSrc<CB> src{X, bw.ybar, c0, (int)geo.plane};
+  int bx, by;
+  xcd_block(bx, by);
   expand_tile<r, CB, R, Q, true, KIND, Acc, MODE, true>(G, Y, geo, wp, load_lambda(lam_dev, lam_host),
-                                                        c0, Us, OW, 0, bw, blockIdx.x, blockIdx.y,
-                                                        gridDim.x, smem, &src);
+                                                        c0, Us, OW, 0, bw, bx, by, gridDim.x, smem,
+                                                        &src);
 }
 
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE>
