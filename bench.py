@@ -20,6 +20,11 @@ Prints ONE JSON line:
   batched    64 grey images with sides in [256, 2048], r in {1, 2}, lambda in
              [0.5, 32], T = 3, in one batched call (hipGraph replay on a side
              stream, autotuned variant), against a loop of single-image calls
+  cold       single calls after a 512 MiB scratch write (Infinity Cache evicted)
+  stride3    the same workload with stride 3 (centres 2r+1 apart, no overlap)
+  ctx        1024x1024 RGB, r = 1, T = 4 (the paper's timing image size)
+  traffic    (in roofline) HBM bytes per k_expand_d launch from the committed
+             rocprofv3 counter summary, null when it was taken on other sources
 """
 from __future__ import annotations
 
@@ -44,10 +49,69 @@ def parse():
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--stride", type=int, default=1)
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--counters", action="store_true",
-                    help="for rocprofv3 --pmc runs: the tuned forward steps only, then three "
-                         "copies of 64 MiB (the counter calibration), one short JSON line")
+    ap.add_argument("--counters", choices=("fwd", "fwdbwd"), default=None,
+                    help="for rocprofv3 --pmc runs: the tuned forward (or forward + backward) "
+                         "steps only, then three copies of 64 MiB (the counter calibration), "
+                         "one short JSON line")
     return ap.parse_args()
+
+
+def sources_digest():
+    """SHA-256 over the sources the single-image kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1705_01674_amd", "csrc")
+    for name in ("sgwls_device.hpp", "sgwls_internal.hpp", "sgwls_pass_r1.hip"):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_expand_d_rgb1080p_r1_T3_counters.md")
+
+
+def counted_traffic(tuned):
+    """HBM bytes per k_expand_d launch (mean of the column and row frame) from
+    the committed counter summary, or None when it is missing, was taken on
+    other kernel sources, or lacks the tuned variants."""
+    try:
+        with open(COUNTERS_FILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    tag = "traffic-json:"
+    if tag not in text:
+        return None
+    data = json.loads(text.split(tag, 1)[1].split("-->", 1)[0])
+    if data.get("source_sha256") != sources_digest():
+        return None
+    per = data.get("bytes_per_launch", {})
+    col, row = per.get(str(tuned.get((0, 3)))), per.get(str(tuned.get((1, 3))))
+    if not col or not row or "col" not in col or "row" not in row:
+        return None
+    return round((col["col"] + row["row"]) / 2)
+
+
+def time_workload(torch, ops, w, dev, steps, warmup):
+    """Mean ms of one filter call on workload w (autotuned, inputs resident)."""
+    C, M, N = w.f.shape
+    p = ops.Params(**w.params)
+    f = torch.from_numpy(w.f).to(dev)
+    g = torch.from_numpy(w.g).to(dev)
+    u = torch.empty_like(f)
+    ws = torch.empty(ops.workspace_bytes(C, M, N, p), dtype=torch.uint8, device=dev)
+    if p.stride == 1:
+        ops.autotune(f, g, p, reps=10)
+
+    def step():
+        ops.sgwls_filter(f, g, p, out=u, workspace=ws)
+
+    for _ in range(warmup):
+        step()
+    ms = time_events(torch, step, steps)
+    return {"workload": w.name, "M": M, "N": N, "C": C, "r": p.r, "iters": p.iters,
+            "stride": p.stride, "ms_per_step": round(ms, 5),
+            "value": round(M * N / (ms * 1e-3) / 1e6, 2), "unit": "MPixel/s"}
 
 
 def counter_run(torch, step, args, ms_note):
@@ -156,7 +220,7 @@ def main():
     def step():
         ops.sgwls_filter(f, g, p, out=u, workspace=ws)
 
-    if args.counters:
+    if args.counters == "fwd":
         counter_run(torch, step, args, {"variants": {f"{'col' if d == 0 else 'row'}_c{cb}": v
                                                      for (d, cb), v in sorted(tuned.items())}})
         return
@@ -203,6 +267,21 @@ def main():
             t = time_events(torch, lambda: run(mask), max(10, args.steps))
             stage_ms[(direction, name)] = t
             per_filter_ms[name] = per_filter_ms.get(name, 0.0) + t * p.iters
+    # Cold calls: a 512 MiB scratch write before each call evicts the 256 MB
+    # Infinity Cache, so the first pass reads its inputs from HBM.
+    scratch = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device=dev)
+    cold = []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(max(5, args.steps // 5)):
+        scratch.fill_(1.0)
+        ev0.record()
+        step()
+        ev1.record()
+        torch.cuda.synchronize()
+        cold.append(ev0.elapsed_time(ev1))
+    ms_cold = sorted(cold)[len(cold) // 2]
+    del scratch
+
     dom = max(per_filter_ms, key=per_filter_ms.get)
     dom_launch_ms = per_filter_ms[dom] / (2 * p.iters)   # mean over column and row launches
     px = M * N
@@ -227,6 +306,9 @@ def main():
         ops.sgwls_backward(g, saved, ubar, p, grad_f=grad_f, grad_g=grad_g, grad_lambda=grad_l,
                            workspace=ws_b)
 
+    if args.counters == "fwdbwd":
+        counter_run(torch, step_fb, args, {})
+        return
     for _ in range(args.warmup):
         step_fb()
     torch.cuda.synchronize()
@@ -250,6 +332,11 @@ def main():
     ms64 = time_events(torch, step64, max(5, args.steps // 2))
 
     batched = None if args.no_batched else bench_batched(torch, ops, synth, args)
+    # The other reading of "tau = 3" (stride 3 = 2r+1, no overlap) and the
+    # 1024x1024 RGB T=4 context row.
+    alt_steps = max(5, args.steps // 2)
+    stride3 = time_workload(torch, ops, synth.rgb1080p(stride=3), dev, alt_steps, args.warmup)
+    ctx = time_workload(torch, ops, synth.rgb1024_ctx(), dev, alt_steps, args.warmup)
 
     # Accuracy of this very output against the oracle, and the CPU baseline.
     step()
@@ -304,7 +391,7 @@ def main():
                      "achieved": round(achieved, 1) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                     "traffic": None},
+                     "traffic": counted_traffic(tuned) if dom == "k_expand" else None},
         "kernels_ms_per_launch": {f"{'col' if d == 0 else 'row'}:{n}": round(t, 5)
                                   for (d, n), t in stage_ms.items()},
         "row_pass_as_transposed_column_pass": transposed,
@@ -318,6 +405,10 @@ def main():
                     "max_rel_err_vs_oracle": grad_err},
         "fp64_pivot": {"ms_per_step": round(ms64, 5), "value": round(M * N / (ms64 * 1e-3) / 1e6, 2),
                        "max_rel_err_vs_oracle": max_rel64},
+        "cold": {"ms_per_step": round(ms_cold, 5), "value": round(M * N / (ms_cold * 1e-3) / 1e6, 2),
+                 "note": "median of single calls, each after a 512 MiB scratch write"},
+        "stride3": stride3,
+        "ctx": ctx,
         "batched": batched,
         "cpu_baseline": cpu,
     }

@@ -1,6 +1,8 @@
 // Persistent kernels for batches of uneven images (every pass a direct-read
 // column pass storing transposed, as for single images).  Each workgroup
-// strides over the units of its stage (unit blockIdx.x, then + gridDim.x, ...),
+// strides over the units of its stage (unit s, then s + gridDim.x, ..., with
+// s its rank in the XCD-contiguous order, so that each XCD works on
+// neighbouring units whose halos share its L2),
 // locates each unit's image over the unit prefix sums and runs the same block
 // code as the single-image kernels for that image's geometry and lambda.
 // Units are ordered largest image first (the host sorts the table), so the
@@ -59,7 +61,8 @@ __global__ __launch_bounds__(kWave* Q) void k_batch_reduce(const BatchDesc* __re
   extern __shared__ float smem[];
   const int total = pre[B];
   Cursor cur;
-  for (int u = blockIdx.x; u < total; u += gridDim.x) {
+  const int slot = xcd_rank(blockIdx.x, gridDim.x);   // neighbouring units on one XCD
+  for (int u = slot; u < total; u += gridDim.x) {
     __syncthreads();   // the previous unit is finished with the LDS
     const int i = cur.locate(pre, B, u);
     const BatchDesc& D = tab[i];
@@ -110,7 +113,8 @@ __global__ __launch_bounds__(kWave* Q) void k_batch_expand(const BatchDesc* __re
   const int total = pre[B];
   const BwdArgs none{};
   Cursor cur;
-  for (int u = blockIdx.x; u < total; u += gridDim.x) {
+  const int slot = xcd_rank(blockIdx.x, gridDim.x);   // neighbouring units on one XCD
+  for (int u = slot; u < total; u += gridDim.x) {
     __syncthreads();   // the previous unit is finished with the LDS
     const int i = cur.locate(pre, B, u);
     const BatchDesc& D = tab[i];

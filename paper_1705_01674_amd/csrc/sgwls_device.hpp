@@ -1609,12 +1609,15 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
 // overlap in their halo columns and rows, and the overlap is an L2 hit only
 // when both run on one XCD (each XCD has its own L2).
 constexpr int kXcds = 8;
-DEV void xcd_block(int& bx, int& by) {
-  const int nx = gridDim.x, nb = nx * gridDim.y;
-  const int lin = blockIdx.y * nx + blockIdx.x;
+// Position of dispatch slot lin (of n) in that order: a bijection of [0, n).
+DEV int xcd_rank(int lin, int n) {
   const int x = lin % kXcds, idx = lin / kXcds;
-  const int q = nb / kXcds, rem = nb % kXcds;
-  const int logical = x * q + min(x, rem) + idx;
+  const int q = n / kXcds, rem = n % kXcds;
+  return x * q + min(x, rem) + idx;
+}
+DEV void xcd_block(int& bx, int& by) {
+  const int nx = gridDim.x;
+  const int logical = xcd_rank(blockIdx.y * nx + blockIdx.x, nx * gridDim.y);
   by = logical / nx;
   bx = logical - by * nx;
 }

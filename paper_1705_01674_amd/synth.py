@@ -99,6 +99,13 @@ def rgb1080p(r: int = 1, lam: float = 4.0, iters: int = 3, stride: int = 1,
                   seed, lam, r, iters, stride, sinus=True)
 
 
+def rgb1024_ctx(seed: int = 1000) -> Workload:
+    """1024x1024 RGB (the size of the paper's timing image), r = 1, T = 4, lambda = 4,
+    same generator as rgb1080p."""
+    return single("rgb1024_r1_T4_s1_lam4", 1024, 1024, 3, 200, 0.03, seed, 4.0, 1, 4, 1,
+                  sinus=True)
+
+
 def batch_uneven(B: int = 64, seed_base: int = 4000, min_side: int = 256,
                  max_side: int = 2048, iters: int = 3):
     """B grey images with independent sides U_int[min_side, max_side], 200 rectangles,
