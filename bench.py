@@ -23,6 +23,9 @@ Prints ONE JSON line:
   cold       single calls after a 512 MiB scratch write (Infinity Cache evicted)
   stride3    the same workload with stride 3 (centres 2r+1 apart, no overlap)
   ctx        1024x1024 RGB, r = 1, T = 4 (the paper's timing image size)
+  interpolation  guided sparse interpolation (Eq. 21): 8x depth upsampling of
+             a 1080x1920 depth map (r = 4, stride 4, lambda 400) and scribble
+             colourisation at 1024x1024 (r = 4, stride 2, lambda 900)
   traffic    (in roofline) HBM bytes per k_expand_d launch from the committed
              rocprofv3 counter summary, null when it was taken on other sources
 """
@@ -112,6 +115,28 @@ def time_workload(torch, ops, w, dev, steps, warmup):
     return {"workload": w.name, "M": M, "N": N, "C": C, "r": p.r, "iters": p.iters,
             "stride": p.stride, "ms_per_step": round(ms, 5),
             "value": round(M * N / (ms * 1e-3) / 1e6, 2), "unit": "MPixel/s"}
+
+
+def time_interpolation(torch, ops, w, dev, steps, warmup):
+    """Mean ms of one guided sparse interpolation (Eq. 21) on workload w."""
+    C, M, N = w.f.shape
+    p = ops.Params(**w.params)
+    f = torch.from_numpy(w.f).to(dev)
+    h = torch.from_numpy(w.h).to(dev)
+    g = torch.from_numpy(w.g).to(dev)
+    u = torch.empty_like(f)
+    ws = torch.empty(ops.interpolate_workspace_bytes(C, M, N, p), dtype=torch.uint8, device=dev)
+
+    def step():
+        ops.sgwls_interpolate(f, h, g, p, out=u, workspace=ws)
+
+    for _ in range(warmup):
+        step()
+    ms = time_events(torch, step, steps)
+    return {"workload": w.name, "M": M, "N": N, "C": C, "r": p.r, "iters": p.iters,
+            "stride": p.stride, "lambda": p.lam, "known": round(float(w.h.mean()), 4),
+            "ms_per_step": round(ms, 5), "value": round(M * N / (ms * 1e-3) / 1e6, 2),
+            "unit": "MPixel/s"}
 
 
 def counter_run(torch, step, args, ms_note):
@@ -337,6 +362,12 @@ def main():
     alt_steps = max(5, args.steps // 2)
     stride3 = time_workload(torch, ops, synth.rgb1080p(stride=3), dev, alt_steps, args.warmup)
     ctx = time_workload(torch, ops, synth.rgb1024_ctx(), dev, alt_steps, args.warmup)
+    # Guided sparse interpolation, Eq. (21): 8x depth upsampling at 1080p and
+    # scribble colourisation (two chrominance planes) at 1024x1024.
+    interp = [time_interpolation(torch, ops, synth.depth_upsample(1080, 1920, 8), dev, alt_steps,
+                                 args.warmup),
+              time_interpolation(torch, ops, synth.colorize_scribbles(1024, 1024, 120), dev,
+                                 alt_steps, args.warmup)]
 
     # Accuracy of this very output against the oracle, and the CPU baseline.
     step()
@@ -409,6 +440,7 @@ def main():
                  "note": "median of single calls, each after a 512 MiB scratch write"},
         "stride3": stride3,
         "ctx": ctx,
+        "interpolation": interp,
         "batched": batched,
         "cpu_baseline": cpu,
     }

@@ -151,6 +151,23 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u,
                           const float* lambda_dev, float* saved,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Guided sparse interpolation (Eq. 21) ----
+ * u = S(f) / S(h) channel by channel, where S is the SG-WLS filter with
+ * guidance g and parameters p (Sec. 2.3) standing in for the inverse of the
+ * WLS matrix: f holds the C sparse input planes (0 where no value is known)
+ * and h the index map (one M x N plane, 1 where f is known, 0 elsewhere).
+ * All pointers are device pointers; u (C planes) must not alias g or h and
+ * may alias f.  The quotient is a plain IEEE division: where S(h) is 0 (no
+ * known value reaches the pixel, e.g. weights underflowing to 0) u is inf
+ * or NaN.  ws: workspace of sgwls_interpolate_workspace_bytes(C, M, N, p)
+ * bytes (the C+1 stacked planes plus the filter's workspace).  Errors as for
+ * sgwls_filter. */
+size_t sgwls_interpolate_workspace_bytes(int C, int M, int N, const sgwls_params* p);
+sgwls_status sgwls_interpolate(const float* f, const float* h, const float* g, float* u,
+                               int C, int M, int N, const sgwls_params* p,
+                               const float* lambda_dev, void* ws, size_t ws_bytes,
+                               void* stream);
+
 /* ---- Kernel variants and autotuning (not in the paper) ----
  * Stride-1 passes can run several compiled kernel variants that differ in
  * how a subsystem is cut into chunks (rows per chunk) and how many chunks

@@ -22,7 +22,8 @@ EXPORTS = ["sgwls_status_str", "sgwls_version", "sgwls_validate", "sgwls_workspa
            "sgwls_tune_pin", "sgwls_tune_query", "sgwls_tune_clear", "sgwls_tune_size",
            "sgwls_autotune", "sgwls_tune_save", "sgwls_tune_load",
            "sgwls_batched_variant_count", "sgwls_filter_batched_variant",
-           "sgwls_autotune_batched", "sgwls_batched_graph_count", "sgwls_batched_graph_clear"]
+           "sgwls_autotune_batched", "sgwls_batched_graph_count", "sgwls_batched_graph_clear",
+           "sgwls_interpolate_workspace_bytes", "sgwls_interpolate"]
 
 
 class SgwlsParams(ctypes.Structure):
@@ -63,6 +64,10 @@ def _load():
     lib.sgwls_pass_stages.argtypes = [i, i, vp, vp, vp, i, i, i, P, vp, vp, sz, vp]
     lib.sgwls_filter.restype = i
     lib.sgwls_filter.argtypes = [vp, vp, vp, i, i, i, P, vp, vp, vp, sz, vp]
+    lib.sgwls_interpolate_workspace_bytes.restype = sz
+    lib.sgwls_interpolate_workspace_bytes.argtypes = [i, i, i, P]
+    lib.sgwls_interpolate.restype = i
+    lib.sgwls_interpolate.argtypes = [vp, vp, vp, vp, i, i, i, P, vp, vp, sz, vp]
     lib.sgwls_backward.restype = i
     lib.sgwls_backward.argtypes = [vp, vp, vp, vp, vp, vp, i, i, i, P, vp, vp, sz, vp]
     lib.sgwls_pass_backward.restype = i

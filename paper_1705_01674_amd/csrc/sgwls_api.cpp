@@ -886,6 +886,38 @@ sgwls_status sgwls_filter_batched_variant(const sgwls_image* imgs, const sgwls_p
   return batch_run(plan, ws, (hipStream_t)stream);
 }
 
+size_t sgwls_interpolate_workspace_bytes(int C, int M, int N, const sgwls_params* p) {
+  if (C < 1 || C >= (1 << 20)) return 0;
+  const size_t inner = sgwls_workspace_bytes(C + 1, M, N, p);
+  return inner ? image_bytes(C + 1, M, N) + inner : 0;
+}
+
+sgwls_status sgwls_interpolate(const float* f, const float* h, const float* g, float* u, int C,
+                               int M, int N, const sgwls_params* p, const float* lambda_dev,
+                               void* ws, size_t ws_bytes, void* stream) {
+  if (C < 1 || C >= (1 << 20)) return SGWLS_E_ARG;
+  sgwls_status st = sgwls_validate(C + 1, M, N, p);
+  if (st != SGWLS_OK) return st;
+  if (!f || !h || !g || !u || (const float*)u == g || (const float*)u == h) return SGWLS_E_ARG;
+  const size_t stack = image_bytes(C + 1, M, N);
+  const size_t need = sgwls_interpolate_workspace_bytes(C, M, N, p);
+  if (!ws || ws_bytes < need) return SGWLS_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  // [S(f); S(h)] by one filter call over the stacked planes, filtered in place.
+  float* X = reinterpret_cast<float*>(ws);
+  const size_t plane = (size_t)M * N;
+  if (hipMemcpyAsync(X, f, sizeof(float) * C * plane, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(X + C * plane, h, sizeof(float) * plane, hipMemcpyDeviceToDevice, s) !=
+          hipSuccess)
+    return SGWLS_E_HIP;
+  st = sgwls_filter(X, g, X, C + 1, M, N, p, lambda_dev, nullptr,
+                    reinterpret_cast<char*>(ws) + stack, ws_bytes - stack, stream);
+  if (st != SGWLS_OK) return st;
+  return launch_divide_planes(X, X + C * plane, u, C, (long long)plane, s) == hipSuccess
+             ? SGWLS_OK
+             : SGWLS_E_HIP;
+}
+
 sgwls_status sgwls_filter_batched(const sgwls_image* imgs, const sgwls_params* p, int B,
                                   void* ws, size_t ws_bytes, void* stream) {
   return sgwls_filter_batched_variant(imgs, p, B, -1, ws, ws_bytes, stream);

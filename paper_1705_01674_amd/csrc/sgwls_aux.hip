@@ -94,4 +94,23 @@ hipError_t launch_bwd_fixup(const float* side, float* gbar, const PassGeom& geo,
   return hipGetLastError();
 }
 
+// u[c] = num[c] / den for the C numerator planes (Eq. 21's quotient).
+__global__ __launch_bounds__(256) void k_divide_planes(const float* __restrict__ num,
+                                                       const float* __restrict__ den,
+                                                       float* __restrict__ u, int C,
+                                                       long long plane) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= plane) return;
+  const float d = den[i];
+  for (int c = 0; c < C; ++c) u[c * plane + i] = num[c * plane + i] / d;
+}
+
+hipError_t launch_divide_planes(const float* num, const float* den, float* u, int C,
+                                long long plane, hipStream_t s) {
+  if (plane <= 0 || C <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_divide_planes, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, s, num,
+                     den, u, C, plane);
+  return hipGetLastError();
+}
+
 }  // namespace sgwls

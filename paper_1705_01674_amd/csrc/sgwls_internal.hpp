@@ -218,6 +218,10 @@ hipError_t launch_batch_pass(int variant, int fp64, int kind, int r, const Batch
 hipError_t launch_transpose(const float* src, float* dst, int rows, int cols, hipStream_t stream,
                             int planes = 1, int accumulate = 0);
 
+// u[c] = num[c] / den for c < C (planes of `plane` floats).
+hipError_t launch_divide_planes(const float* num, const float* den, float* u, int C,
+                                long long plane, hipStream_t stream);
+
 // Transposed guidance of every image of a batch (pre_t: tile prefix sums).
 hipError_t launch_batch_transpose(const BatchDesc* tab, const int* pre_t, int B, int tiles,
                                   hipStream_t stream);

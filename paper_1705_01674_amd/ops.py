@@ -141,6 +141,40 @@ def sgwls_filter(f: torch.Tensor, g: torch.Tensor, p: Params, *,
     return out
 
 
+def interpolate_workspace_bytes(C: int, M: int, N: int, p: Params) -> int:
+    n = nat.lib.sgwls_interpolate_workspace_bytes(C, M, N, ctypes.byref(p.c()))
+    if n == 0:
+        raise ValueError("invalid interpolation arguments")
+    return int(n)
+
+
+def sgwls_interpolate(f: torch.Tensor, h: torch.Tensor, g: torch.Tensor, p: Params, *,
+                      lambda_dev: Optional[torch.Tensor] = None,
+                      out: Optional[torch.Tensor] = None,
+                      workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Guided sparse interpolation of Eq. (21): S(f) / S(h), with f the sparse
+    input (C x M x N or M x N, 0 where unknown), h the index map (M x N, 1
+    where f is known) and S the SG-WLS filter guided by g."""
+    C, M, N = _image(f, "f")
+    dev = f.device
+    _guidance(g, M, N, dev)
+    _guidance(h, M, N, dev)
+    lam = _lambda(lambda_dev, dev)
+    if out is None:
+        out = torch.empty_like(f)
+    elif out.shape != f.shape or out.dtype != f.dtype or not out.is_contiguous() or out.device != dev:
+        raise ValueError("out must match f")
+    nbytes = interpolate_workspace_bytes(C, M, N, p)
+    ws = workspace if workspace is not None else _workspace(nbytes, dev)
+    if ws.numel() < nbytes or ws.device != dev:
+        raise ValueError("workspace too small")
+    nat.check(nat.lib.sgwls_interpolate(_ptr(f), _ptr(h), _ptr(g), _ptr(out), C, M, N,
+                                        ctypes.byref(p.c()), _ptr(lam), _ptr(ws), ws.numel(),
+                                        _stream(dev)),
+              "sgwls_interpolate")
+    return out
+
+
 def sgwls_pass(direction: int, x: torch.Tensor, g: torch.Tensor, p: Params, *,
                lambda_dev: Optional[torch.Tensor] = None,
                out: Optional[torch.Tensor] = None) -> torch.Tensor:

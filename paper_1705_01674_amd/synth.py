@@ -106,6 +106,64 @@ def rgb1024_ctx(seed: int = 1000) -> Workload:
                   sinus=True)
 
 
+@dataclass
+class SparseWorkload:
+    """Inputs of guided sparse interpolation (Eq. 21)."""
+    name: str
+    f: np.ndarray            # (C, M, N) float32, 0 where unknown
+    h: np.ndarray            # (M, N) float32 index map
+    g: np.ndarray            # (M, N) float32 guidance
+    params: dict = field(default_factory=dict)
+
+
+def depth_upsample(M: int = 1080, N: int = 1920, factor: int = 8, seed: int = 1000,
+                   iters: int = 3) -> SparseWorkload:
+    """Guided depth upsampling stand-in: the depth is channel 0 of the
+    noise-free image with the same rectangles as the colour guidance; it is
+    known on the regular grid of every factor-th pixel (offset factor/2) with
+    N(0, 0.01^2) noise.  Guidance = 255 x luma of the noisy colour image, so
+    that sigma_r = 3 is on the scale the paper's setting assumes.  r = 4,
+    stride 4, sigma_s = 4, sigma_r = 3, lambda = 100 / 200 / 400 for factors
+    2 / 4 / 8 (the paper's depth-upsampling settings)."""
+    color = image(M, N, 3, 200, 0.03, seed, sinus=True)
+    depth = image(M, N, 3, 200, 0.0, seed)[0].astype(np.float64)
+    rng = np.random.default_rng(seed + 1)
+    h = np.zeros((M, N), dtype=np.float32)
+    h[factor // 2::factor, factor // 2::factor] = 1.0
+    f = (h * (depth + rng.normal(0.0, 0.01, size=(M, N)))).astype(np.float32)[None]
+    g = (255.0 * luma(color).astype(np.float64)).astype(np.float32)
+    lam = {2: 100.0, 4: 200.0, 8: 400.0}.get(factor, 400.0)
+    params = dict(lam=lam, r=4, iters=int(iters), stride=4, kind="exp", sigma_s=4.0, sigma_r=3.0,
+                  alpha_s=1.2, alpha_r=1.2, eps=1e-4)
+    return SparseWorkload(f"depth{M}x{N}_up{factor}", np.ascontiguousarray(f), h, g, params)
+
+
+def colorize_scribbles(M: int = 512, N: int = 512, n_strokes: int = 60, seed: int = 1000,
+                       iters: int = 3) -> SparseWorkload:
+    """Scribble colourisation stand-in: the two chrominance planes (BT.601
+    U, V) of a synthetic colour image are known on n_strokes random
+    horizontal or vertical strokes (length U_int[N/16, N/4], 3 pixels wide);
+    guidance = 255 x luma.  r = 4, stride 2, sigma_s = 4, sigma_r = 2,
+    lambda = 900 (the paper's colourisation settings)."""
+    color = image(M, N, 3, 200, 0.01, seed).astype(np.float64)
+    y = 0.299 * color[0] + 0.587 * color[1] + 0.114 * color[2]
+    uv = np.stack([0.492 * (color[2] - y), 0.877 * (color[0] - y)])
+    rng = np.random.default_rng(seed + 2)
+    h = np.zeros((M, N), dtype=np.float32)
+    for _ in range(n_strokes):
+        length = int(rng.integers(max(1, N // 16), max(2, N // 4) + 1))
+        i0, j0 = int(rng.integers(0, M)), int(rng.integers(0, N))
+        if rng.uniform() < 0.5:
+            h[max(0, i0 - 1):i0 + 2, j0:j0 + length] = 1.0
+        else:
+            h[i0:i0 + length, max(0, j0 - 1):j0 + 2] = 1.0
+    f = (h[None] * uv).astype(np.float32)
+    g = (255.0 * y).astype(np.float32)
+    params = dict(lam=900.0, r=4, iters=int(iters), stride=2, kind="exp", sigma_s=4.0,
+                  sigma_r=2.0, alpha_s=1.2, alpha_r=1.2, eps=1e-4)
+    return SparseWorkload(f"colorize{M}x{N}", np.ascontiguousarray(f), h, g, params)
+
+
 def batch_uneven(B: int = 64, seed_base: int = 4000, min_side: int = 256,
                  max_side: int = 2048, iters: int = 3):
     """B grey images with independent sides U_int[min_side, max_side], 200 rectangles,

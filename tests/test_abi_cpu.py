@@ -211,3 +211,26 @@ def test_tune_file_accepts_batched_entries(nat, tmp_path):
     bad.write_text(f"sgwls-tune {ver} gfx950\n0 0 1 0 2 41 1\n")           # fp64 has 1 variant
     assert lib.sgwls_tune_load(str(bad).encode(), b"gfx950") == 1
     assert lib.sgwls_tune_size() == 0
+
+
+def test_interpolate_workspace_and_error_paths(nat):
+    """Eq. (21) entry point: workspace = C+1 stacked planes + the filter's
+    workspace for C+1 channels; argument errors return before any HIP call."""
+    p = P(nat, r=4, stride=4, lam=400.0, sigma_s=4.0, sigma_r=3.0)
+    pp = ctypes.byref(p)
+    lib = nat.lib
+    n = lib.sgwls_interpolate_workspace_bytes(1, 1080, 1920, pp)
+    assert n >= 4 * 2 * 1080 * 1920 + lib.sgwls_workspace_bytes(2, 1080, 1920, pp)
+    assert lib.sgwls_interpolate_workspace_bytes(0, 64, 64, pp) == 0
+    assert lib.sgwls_interpolate_workspace_bytes(1, 8, 8, pp) == 0   # M, N < 2r+1
+    f, h, g, u, ws = (ctypes.c_void_p(a) for a in (0x1000, 0x2000, 0x3000, 0x4000, 0x5000))
+    big = 1 << 34
+    assert lib.sgwls_interpolate(None, h, g, u, 1, 64, 64, pp, None, ws, big, None) == 1
+    assert lib.sgwls_interpolate(f, None, g, u, 1, 64, 64, pp, None, ws, big, None) == 1
+    assert lib.sgwls_interpolate(f, h, g, g, 1, 64, 64, pp, None, ws, big, None) == 1
+    assert lib.sgwls_interpolate(f, h, g, h, 1, 64, 64, pp, None, ws, big, None) == 1
+    assert lib.sgwls_interpolate(f, h, g, u, 0, 64, 64, pp, None, ws, big, None) == 1
+    assert lib.sgwls_interpolate(f, h, g, u, 1, 64, 64, pp, None, ws, 16, None) == 3
+    assert lib.sgwls_interpolate(f, h, g, u, 1, 64, 64, pp, None, None, big, None) == 3
+    bad = ctypes.byref(P(nat, r=4, stride=10))
+    assert lib.sgwls_interpolate(f, h, g, u, 1, 64, 64, bad, None, ws, big, None) == 1
