@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--stride", type=int, default=1)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only the stride / radius sweep: 1024x1024 RGB, T=4, r = 1..4, "
+                         "stride 1..2r+1; one JSON line")
     ap.add_argument("--counters", choices=("fwd", "fwdbwd"), default=None,
                     help="for rocprofv3 --pmc runs: the tuned forward (or forward + backward) "
                          "steps only, then three copies of 64 MiB (the counter calibration), "
@@ -137,6 +140,23 @@ def time_interpolation(torch, ops, w, dev, steps, warmup):
             "stride": p.stride, "lambda": p.lam, "known": round(float(w.h.mean()), 4),
             "ms_per_step": round(ms, 5), "value": round(M * N / (ms * 1e-3) / 1e6, 2),
             "unit": "MPixel/s"}
+
+
+def stride_sweep(torch, ops, synth, dev, args):
+    """Filter time over radius and stride on the paper's timing shape (a 1 MP
+    RGB image, T = 4): the same sweep as the paper's timing figure."""
+    rows = []
+    for r in (1, 2, 3, 4):
+        for stride in range(1, 2 * r + 2):
+            w = synth.single(f"rgb1024_r{r}_T4_s{stride}", 1024, 1024, 3, 200, 0.03, 1000, 4.0, r,
+                             4, stride, sinus=True)
+            t = time_workload(torch, ops, w, dev, max(5, args.steps // 5), 2)
+            rows.append({"r": r, "stride": stride, "ms_per_step": t["ms_per_step"],
+                         "value": t["value"]})
+            print(f"[sweep] r={r} stride={stride} {t['ms_per_step']:.4f} ms", file=sys.stderr,
+                  flush=True)
+    return {"workload": "1024x1024 RGB, T=4, lambda 4, exp weights", "unit": "MPixel/s",
+            "rows": rows}
 
 
 def counter_run(torch, step, args, ms_note):
@@ -231,6 +251,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.sweep:
+        print(json.dumps({"sweep": stride_sweep(torch, ops, synth, dev, args)}), flush=True)
+        return
     w = synth.rgb1080p(stride=args.stride)
     C, M, N = w.f.shape
     p = ops.Params(**w.params)

@@ -563,7 +563,9 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u, int C, int M
   void* iface = reinterpret_cast<char*>(ws) + img + gimg;
   const size_t plane = (size_t)C * M * N;
   const int passes = 2 * p->iters;
-  if (frames_supported(C, p->r, p->stride, p->prec)) {
+  // Strided forward calls without saved inputs also run as frames: their
+  // column passes read directly and store through the LDS accumulators.
+  if (frames_supported(C, p->r, p->stride, p->prec) || (p->stride != 1 && !saved)) {
     // Every pass is a column pass that stores its output transposed: pass 2t
     // reads the image (M x N), pass 2t+1 its transpose (N x M) -- the row pass
     // -- and writes the image layout again.  Without saved, pass 2t writes tmp

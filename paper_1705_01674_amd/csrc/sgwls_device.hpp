@@ -811,6 +811,88 @@ struct SepReader {
   }
 };
 
+// The reduced system of one strip's separators after each lane eliminated
+// its own run (lane l keeps the last block of its run): block cyclic
+// reduction across the 64 lanes, then each lane's solution X and the one of
+// the lane before it (XT, zero on lane 0).
+template <int r, int CB, typename Acc>
+DEV void iface_pcr_levels(const Acc (&S)[r][r], const Acc (&Bt)[r][r], const Acc (&Rr)[r][CB],
+                          const Acc (&TT)[r][r], const Acc (&RT)[r][CB], bool active, int m,
+                          int n, int lane, Acc (&X)[r][CB], Acc (&XT)[r][CB]) {
+  // PCR level: lane l's unknown X_l = x_{e-1}:
+  //   A_l X_{l-1} + B_l X_l + C_l X_{l+1} = d_l with
+  //   A_l = Bt_l, B_l = S_l - TT_{l+1}, C_l = Bt_{l+1}^T, d_l = R_l - RT_{l+1}.
+  Acc A[r][r], B[r][r], Cc[r][r], d[r][CB];
+  {
+    Acc TTn[r][r], RTn[r][CB], Btn[r][r];
+    shfl_down_blk<r, r, Acc>(TT, TTn, 1, lane);
+    shfl_down_blk<r, CB, Acc>(RT, RTn, 1, lane);
+    shfl_down_blk<r, r, Acc>(Bt, Btn, 1, lane);
+    const bool nextActive = (lane + 1) * m < n;
+#pragma unroll
+    for (int a = 0; a < r; ++a) {
+#pragma unroll
+      for (int c = 0; c < r; ++c) {
+        A[a][c] = active ? Bt[a][c] : Acc(0);
+        B[a][c] = active ? S[a][c] - (nextActive ? TTn[a][c] : Acc(0)) : (a == c ? Acc(1) : Acc(0));
+        Cc[a][c] = (active && nextActive) ? Btn[c][a] : Acc(0);
+      }
+#pragma unroll
+      for (int h = 0; h < CB; ++h) d[a][h] = active ? Rr[a][h] - (nextActive ? RTn[a][h] : Acc(0)) : Acc(0);
+    }
+  }
+#pragma unroll
+  for (int delta = 1; delta < kWave; delta *= 2) {
+    Acc Bi[r][r];
+    spd_inverse<r, Acc>(B, Bi);
+    Acc Bim[r][r], Am[r][r], Cm[r][r], dm[r][CB];
+    Acc Bip[r][r], Ap[r][r], Cp[r][r], dp[r][CB];
+    shfl_up_blk<r, r, Acc>(Bi, Bim, delta, lane);
+    shfl_up_blk<r, r, Acc>(A, Am, delta, lane);
+    shfl_up_blk<r, r, Acc>(Cc, Cm, delta, lane);
+    shfl_up_blk<r, CB, Acc>(d, dm, delta, lane);
+    shfl_down_blk<r, r, Acc>(Bi, Bip, delta, lane);
+    shfl_down_blk<r, r, Acc>(A, Ap, delta, lane);
+    shfl_down_blk<r, r, Acc>(Cc, Cp, delta, lane);
+    shfl_down_blk<r, CB, Acc>(d, dp, delta, lane);
+    Acc al[r][r], ga[r][r];
+    mm<r, r, r, Acc>(A, Bim, al);
+    mm<r, r, r, Acc>(Cc, Bip, ga);
+    Acc An[r][r], Cn[r][r], t1[r][r], t2[r][r], e1[r][CB], e2[r][CB];
+    mm<r, r, r, Acc>(al, Am, An);
+    mm<r, r, r, Acc>(ga, Cp, Cn);
+    mm<r, r, r, Acc>(al, Cm, t1);
+    mm<r, r, r, Acc>(ga, Ap, t2);
+    mm<r, r, CB, Acc>(al, dm, e1);
+    mm<r, r, CB, Acc>(ga, dp, e2);
+#pragma unroll
+    for (int a = 0; a < r; ++a) {
+#pragma unroll
+      for (int c = 0; c < r; ++c) {
+        A[a][c] = -An[a][c];
+        Cc[a][c] = -Cn[a][c];
+        B[a][c] = B[a][c] - t1[a][c] - t2[a][c];
+      }
+#pragma unroll
+      for (int h = 0; h < CB; ++h) d[a][h] = d[a][h] - e1[a][h] - e2[a][h];
+    }
+  }
+  {
+    Acc Bc[r][r];
+#pragma unroll
+    for (int a = 0; a < r; ++a)
+#pragma unroll
+      for (int c = 0; c < r; ++c) Bc[a][c] = B[a][c];
+    chol<r, Acc>(Bc);
+#pragma unroll
+    for (int a = 0; a < r; ++a)
+#pragma unroll
+      for (int h = 0; h < CB; ++h) X[a][h] = d[a][h];
+    chol_solve<r, CB, Acc>(Bc, X);
+  }
+  shfl_up_blk<r, CB, Acc>(X, XT, 1, lane);
+}
+
 // k_interface_pcr: one wave per strip, lane l owns separator blocks
 // [l*m, min(l*m + m, P-1)); MM is the compiled maximum of m.
 // U receives the separator solutions strip-major: U[(ki*(P-1) + j)*r*CB + a*CB + h].
@@ -915,80 +997,8 @@ DEV void iface_pcr_strip(const Acc* __restrict__ sum, Acc* __restrict__ U, int P
     }
   }
 
-  // PCR level: lane l's unknown X_l = x_{e-1}:
-  //   A_l X_{l-1} + B_l X_l + C_l X_{l+1} = d_l with
-  //   A_l = Bt_l, B_l = S_l - TT_{l+1}, C_l = Bt_{l+1}^T, d_l = R_l - RT_{l+1}.
-  Acc A[r][r], B[r][r], Cc[r][r], d[r][CB];
-  {
-    Acc TTn[r][r], RTn[r][CB], Btn[r][r];
-    shfl_down_blk<r, r, Acc>(TT, TTn, 1, lane);
-    shfl_down_blk<r, CB, Acc>(RT, RTn, 1, lane);
-    shfl_down_blk<r, r, Acc>(Bt, Btn, 1, lane);
-    const bool nextActive = (lane + 1) * m < n;
-#pragma unroll
-    for (int a = 0; a < r; ++a) {
-#pragma unroll
-      for (int c = 0; c < r; ++c) {
-        A[a][c] = active ? Bt[a][c] : Acc(0);
-        B[a][c] = active ? S[a][c] - (nextActive ? TTn[a][c] : Acc(0)) : (a == c ? Acc(1) : Acc(0));
-        Cc[a][c] = (active && nextActive) ? Btn[c][a] : Acc(0);
-      }
-#pragma unroll
-      for (int h = 0; h < CB; ++h) d[a][h] = active ? Rr[a][h] - (nextActive ? RTn[a][h] : Acc(0)) : Acc(0);
-    }
-  }
-#pragma unroll
-  for (int delta = 1; delta < kWave; delta *= 2) {
-    Acc Bi[r][r];
-    spd_inverse<r, Acc>(B, Bi);
-    Acc Bim[r][r], Am[r][r], Cm[r][r], dm[r][CB];
-    Acc Bip[r][r], Ap[r][r], Cp[r][r], dp[r][CB];
-    shfl_up_blk<r, r, Acc>(Bi, Bim, delta, lane);
-    shfl_up_blk<r, r, Acc>(A, Am, delta, lane);
-    shfl_up_blk<r, r, Acc>(Cc, Cm, delta, lane);
-    shfl_up_blk<r, CB, Acc>(d, dm, delta, lane);
-    shfl_down_blk<r, r, Acc>(Bi, Bip, delta, lane);
-    shfl_down_blk<r, r, Acc>(A, Ap, delta, lane);
-    shfl_down_blk<r, r, Acc>(Cc, Cp, delta, lane);
-    shfl_down_blk<r, CB, Acc>(d, dp, delta, lane);
-    Acc al[r][r], ga[r][r];
-    mm<r, r, r, Acc>(A, Bim, al);
-    mm<r, r, r, Acc>(Cc, Bip, ga);
-    Acc An[r][r], Cn[r][r], t1[r][r], t2[r][r], e1[r][CB], e2[r][CB];
-    mm<r, r, r, Acc>(al, Am, An);
-    mm<r, r, r, Acc>(ga, Cp, Cn);
-    mm<r, r, r, Acc>(al, Cm, t1);
-    mm<r, r, r, Acc>(ga, Ap, t2);
-    mm<r, r, CB, Acc>(al, dm, e1);
-    mm<r, r, CB, Acc>(ga, dp, e2);
-#pragma unroll
-    for (int a = 0; a < r; ++a) {
-#pragma unroll
-      for (int c = 0; c < r; ++c) {
-        A[a][c] = -An[a][c];
-        Cc[a][c] = -Cn[a][c];
-        B[a][c] = B[a][c] - t1[a][c] - t2[a][c];
-      }
-#pragma unroll
-      for (int h = 0; h < CB; ++h) d[a][h] = d[a][h] - e1[a][h] - e2[a][h];
-    }
-  }
-  Acc X[r][CB];
-  {
-    Acc Bc[r][r];
-#pragma unroll
-    for (int a = 0; a < r; ++a)
-#pragma unroll
-      for (int c = 0; c < r; ++c) Bc[a][c] = B[a][c];
-    chol<r, Acc>(Bc);
-#pragma unroll
-    for (int a = 0; a < r; ++a)
-#pragma unroll
-      for (int h = 0; h < CB; ++h) X[a][h] = d[a][h];
-    chol_solve<r, CB, Acc>(Bc, X);
-  }
-  Acc XT[r][CB];
-  shfl_up_blk<r, CB, Acc>(X, XT, 1, lane);
+  Acc X[r][CB], XT[r][CB];
+  iface_pcr_levels<r, CB, Acc>(S, Bt, Rr, TT, RT, active, m, n, lane, X, XT);
   if (!active) return;
   Acc* out = U + (size_t)ki * n * r * CB;
 #pragma unroll
@@ -1034,77 +1044,198 @@ __global__ __launch_bounds__(kWave) void k_interface_pcr(const Acc* __restrict__
   iface_pcr_strip<r, CB, MM, Acc>(sum, U, P, m, blockIdx.x);
 }
 
-// k_interface_serial: one lane per strip, block Cholesky over all separators
-// (for runs too long for the wave solver).  Uses U as scratch for h_j and
-// gb for the G_j blocks.
+// Scratch values per separator block kept by iface_pcr_strip_long: the
+// Cholesky factor of the pivot block, the coupling to the next block, the
+// coupling to the previous lane's block and the right-hand side.
+template <int r, int CB>
+constexpr int kLongSlot = 3 * r * r + r * CB;
+
+// iface_pcr_strip for runs of any length: the same elimination, cyclic
+// reduction and back substitution, with the per-block values of each lane's
+// run kept in global scratch instead of registers (layout: strip ki, block i
+// of the run, value f, lane -> scr[((ki * m + i) * kLongSlot + f) * 64 + lane],
+// so that a wave's accesses are contiguous).  Used when the runs are longer
+// than the register version holds (long lines at r >= 3).
 template <int r, int CB, typename Acc>
-__global__ __launch_bounds__(kWave) void k_interface_serial(const Acc* __restrict__ sum,
-                                                            Acc* __restrict__ U,
-                                                            Acc* __restrict__ Gb, int nK,
-                                                            int P) {
-  const int ki = blockIdx.x * kWave + threadIdx.x;
-  if (ki >= nK) return;
+DEV void iface_pcr_strip_long(const Acc* __restrict__ sum, Acc* __restrict__ U, int P, int m,
+                              int ki, Acc* __restrict__ scr) {
   using LY = IfaceLayout<r, CB>;
-  SepReader<r, CB, Acc> rd{sum + (size_t)ki * P * LY::F, P};
+  constexpr int FS = kLongSlot<r, CB>;
+  const int lane = threadIdx.x % kWave;
   const int n = P - 1;
-  Acc* out = U + (size_t)ki * n * r * CB;
-  Acc* gb = Gb + (size_t)ki * n * r * r;
-  Acc Gp[r][r], hp[r][CB];
+  const int s = lane * m, e = min(s + m, n);
+  const bool active = s < n;
+  SepReader<r, CB, Acc> rd{sum + (size_t)ki * P * LY::F, P};
+  Acc* slots = scr + (size_t)ki * m * FS * kWave + lane;
+  auto at = [&](int i, int f) -> Acc& { return slots[((size_t)i * FS + f) * kWave]; };
+
+  Acc S[r][r], Bt[r][r], Rr[r][CB], TT[r][r], RT[r][CB];
 #pragma unroll
   for (int a = 0; a < r; ++a) {
 #pragma unroll
-    for (int b = 0; b < r; ++b) Gp[a][b] = Acc(0);
+    for (int c = 0; c < r; ++c) { TT[a][c] = Acc(0); S[a][c] = Acc(0); Bt[a][c] = Acc(0); }
 #pragma unroll
-    for (int h = 0; h < CB; ++h) hp[a][h] = Acc(0);
+    for (int h = 0; h < CB; ++h) { RT[a][h] = Acc(0); Rr[a][h] = Acc(0); }
   }
-  for (int j = 0; j < n; ++j) {
-    Acc A[r][r], y[r][CB];
-    rd.diag(j, A);
-    rd.rhs(j, y);
-    if (j > 0) {
-      Acc Up[r][r];
-      rd.off(j - 1, Up);
-      sub_AtB<r, r, r, Acc>(Up, Gp, A);
-      sub_AtB<r, r, CB, Acc>(Up, hp, y);
+  if (active) {
+    rd.diag(s, S);
+    rd.rhs(s, Rr);
+    if (s > 0) {
+      Acc U0[r][r];
+      rd.off(s - 1, U0);
+#pragma unroll
+      for (int a = 0; a < r; ++a)
+#pragma unroll
+        for (int c = 0; c < r; ++c) Bt[a][c] = U0[c][a];
     }
-    chol<r, Acc>(A);
-    Acc Gn[r][r];
-    rd.off(j, Gn);
-    chol_solve<r, r, Acc>(A, Gn);
-    chol_solve<r, CB, Acc>(A, y);
+  }
+  const int run = active ? e - 1 - s : 0;   // blocks eliminated locally
+  // The coupling of block b and the diagonal and right-hand side of block b+1
+  // are loaded one iteration ahead, so their latency overlaps the current
+  // block's elimination.
+  Acc Uc[r][r], Sn[r][r], Rn[r][CB];
+  if (run > 0) {
+    rd.off(s, Uc);
+    rd.diag(s + 1, Sn);
+    rd.rhs(s + 1, Rn);
+  }
+  for (int i = 0; i < run; ++i) {
+    Acc Uc2[r][r], Sn2[r][r], Rn2[r][CB];
+    if (i + 1 < run) {
+      rd.off(s + i + 1, Uc2);
+      rd.diag(s + i + 2, Sn2);
+      rd.rhs(s + i + 2, Rn2);
+    }
+    Acc Lc[r][r];
+#pragma unroll
+    for (int a = 0; a < r; ++a)
+#pragma unroll
+      for (int c = 0; c < r; ++c) Lc[a][c] = S[a][c];
+    chol<r, Acc>(Lc);
+    Acc V[r][r], Y[r][r], wv[r][CB];
+#pragma unroll
+    for (int a = 0; a < r; ++a) {
+#pragma unroll
+      for (int c = 0; c < r; ++c) { V[a][c] = Uc[a][c]; Y[a][c] = Bt[a][c]; }
+#pragma unroll
+      for (int h = 0; h < CB; ++h) wv[a][h] = Rr[a][h];
+    }
+    chol_solve<r, r, Acc>(Lc, V);    // S^-1 U
+    chol_solve<r, r, Acc>(Lc, Y);    // S^-1 Bt
+    chol_solve<r, CB, Acc>(Lc, wv);  // S^-1 R
 #pragma unroll
     for (int a = 0; a < r; ++a) {
 #pragma unroll
       for (int c = 0; c < r; ++c) {
-        gb[(size_t)j * r * r + a * r + c] = Gn[a][c];
-        Gp[a][c] = Gn[a][c];
+        Acc v = Acc(0);
+#pragma unroll
+        for (int t = 0; t < r; ++t) v += Bt[t][a] * Y[t][c];
+        TT[a][c] += v;
       }
 #pragma unroll
       for (int h = 0; h < CB; ++h) {
-        out[(size_t)j * r * CB + a * CB + h] = y[a][h];
-        hp[a][h] = y[a][h];
+        Acc v = Acc(0);
+#pragma unroll
+        for (int t = 0; t < r; ++t) v += Bt[t][a] * wv[t][h];
+        RT[a][h] += v;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < r; ++a) {
+#pragma unroll
+      for (int c = 0; c < r; ++c) {
+        at(i, a * r + c) = Lc[a][c];
+        at(i, r * r + a * r + c) = Uc[a][c];
+        at(i, 2 * r * r + a * r + c) = Bt[a][c];
+      }
+#pragma unroll
+      for (int h = 0; h < CB; ++h) at(i, 3 * r * r + a * CB + h) = Rr[a][h];
+    }
+    Acc Bn[r][r];
+#pragma unroll
+    for (int a = 0; a < r; ++a)
+#pragma unroll
+      for (int c = 0; c < r; ++c) Bn[a][c] = Acc(0);
+    sub_AtB<r, r, r, Acc>(Uc, V, Sn);
+    sub_AtB<r, r, r, Acc>(Uc, Y, Bn);
+    sub_AtB<r, r, CB, Acc>(Uc, wv, Rn);
+#pragma unroll
+    for (int a = 0; a < r; ++a) {
+#pragma unroll
+      for (int c = 0; c < r; ++c) {
+        S[a][c] = Sn[a][c];
+        Bt[a][c] = Bn[a][c];
+        Uc[a][c] = Uc2[a][c];
+        Sn[a][c] = Sn2[a][c];
+      }
+#pragma unroll
+      for (int h = 0; h < CB; ++h) {
+        Rr[a][h] = Rn[a][h];
+        Rn[a][h] = Rn2[a][h];
       }
     }
   }
-  for (int j = n - 2; j >= 0; --j) {
-    Acc u[r][CB];
+
+  Acc X[r][CB], XT[r][CB];
+  iface_pcr_levels<r, CB, Acc>(S, Bt, Rr, TT, RT, active, m, n, lane, X, XT);
+  if (!active) return;
+  Acc* out = U + (size_t)ki * n * r * CB;
 #pragma unroll
-    for (int a = 0; a < r; ++a)
+  for (int a = 0; a < r; ++a)
 #pragma unroll
-      for (int h = 0; h < CB; ++h) {
-        Acc v = out[(size_t)j * r * CB + a * CB + h];
+    for (int h = 0; h < CB; ++h) out[(size_t)(e - 1) * r * CB + a * CB + h] = X[a][h];
+  Acc xn[r][CB];
 #pragma unroll
-        for (int c = 0; c < r; ++c) v -= gb[(size_t)j * r * r + a * r + c] * hp[c][h];
-        u[a][h] = v;
-      }
+  for (int a = 0; a < r; ++a)
 #pragma unroll
-    for (int a = 0; a < r; ++a)
+    for (int h = 0; h < CB; ++h) xn[a][h] = X[a][h];
+  // back substitution x_b = S_b^-1 (R_b - U_b x_{b+1} - Bt_b x_T), the
+  // scratch values of block i-1 loaded while block i is solved
+  Acc cur[FS];
+  if (run > 0) {
 #pragma unroll
-      for (int h = 0; h < CB; ++h) {
-        out[(size_t)j * r * CB + a * CB + h] = u[a][h];
-        hp[a][h] = u[a][h];
-      }
+    for (int f = 0; f < FS; ++f) cur[f] = at(run - 1, f);
   }
+  for (int i = run - 1; i >= 0; --i) {
+    Acc nxt[FS];
+    if (i > 0) {
+#pragma unroll
+      for (int f = 0; f < FS; ++f) nxt[f] = at(i - 1, f);
+    }
+    Acc Lc[r][r], v[r][CB];
+#pragma unroll
+    for (int a = 0; a < r; ++a) {
+#pragma unroll
+      for (int c = 0; c < r; ++c) Lc[a][c] = cur[a * r + c];
+#pragma unroll
+      for (int h = 0; h < CB; ++h) {
+        Acc t = cur[3 * r * r + a * CB + h];
+#pragma unroll
+        for (int c = 0; c < r; ++c)
+          t -= cur[r * r + a * r + c] * xn[c][h] + cur[2 * r * r + a * r + c] * XT[c][h];
+        v[a][h] = t;
+      }
+    }
+    chol_solve<r, CB, Acc>(Lc, v);
+    const int b = s + i;
+#pragma unroll
+    for (int a = 0; a < r; ++a)
+#pragma unroll
+      for (int h = 0; h < CB; ++h) {
+        out[(size_t)b * r * CB + a * CB + h] = v[a][h];
+        xn[a][h] = v[a][h];
+      }
+#pragma unroll
+    for (int f = 0; f < FS; ++f) cur[f] = nxt[f];
+  }
+}
+
+template <int r, int CB, typename Acc>
+__global__ __launch_bounds__(kWave) void k_interface_pcr_long(const Acc* __restrict__ sum,
+                                                              Acc* __restrict__ U,
+                                                              Acc* __restrict__ scr, int P,
+                                                              int m) {
+  iface_pcr_strip_long<r, CB, Acc>(sum, U, P, m, blockIdx.x, scr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1195,9 +1326,9 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
   float gv[E + 2 * r];
   float om[E + r][r];
   const float lam = lam_in;
-  // Forward direct column pass: each output row is stored as soon as its
-  // back substitution is done, so the stores drain during the rest of it.
-  constexpr bool ROWWISE = DIRECT && !BWD;
+  // Forward direct stride-1 column pass: each output row is stored as soon as
+  // its back substitution is done, so the stores drain during the rest of it.
+  constexpr bool ROWWISE = DIRECT && !BWD && S1;
   if (active) {
     // Separator values first: their loads are the head of the dependency chain.
     const int n_sep = geo.P - 1;
@@ -1542,12 +1673,15 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
       }
     }
   } else {
+    // Accumulator planes: after the input tile in LDS mode (whose planes are
+    // consumed), from the start of the LDS with direct reads.
+    const int acc0 = DIRECT ? 0 : TA * pch;
     __syncthreads();   // all tile reads done: the image planes become accumulators
     constexpr int r0 = BWD ? 0 : 1;   // backward also accumulates the row above
-    for (int p = 1; p <= NO; ++p)
+    for (int p = 0; p < NO; ++p)
       for (int idx = threadIdx.x; idx < (nrow + 1 - r0) * TB; idx += kWave * Q) {
         const int ta = r0 + idx / TB, tb = idx - (ta - r0) * TB;
-        smem[p * TA * pch + ta * pch + tb] = 0.0f;
+        smem[acc0 + p * TA * pch + ta * pch + tb] = 0.0f;
       }
     __syncthreads();
     // Sum over the strips covering each pixel, in a fixed order (q = 0..2r).
@@ -1558,7 +1692,7 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
         for (int rho = 0; rho < R; ++rho) {
           if (rho < rows) {
             const int col = ((rho & 1) ? (k + r - q) : (k - r + q)) - colbase;
-            float* cell = smem + TA * pch + (wq * R + 1 + rho) * pch + col;
+            float* cell = smem + acc0 + (wq * R + 1 + rho) * pch + col;
 #pragma unroll
             for (int o = 0; o < NO; ++o) cell[o * TA * pch] += outval(rho * w + q, o);
           }
@@ -1571,14 +1705,16 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
 #pragma unroll
       for (int i = 0; i < r; ++i) {
         if (active && wantg)
-          smem[NO * TA * pch + (wq * R) * pch + (k - 1 - i - colbase)] += Gv[i];
+          smem[acc0 + (NO - 1) * TA * pch + (wq * R) * pch + (k - 1 - i - colbase)] += Gv[i];
         __syncthreads();
       }
     }
     const int ncols = b_hi - b_lo;
     for (int idx = threadIdx.x; idx < arows * ncols; idx += kWave * Q) {
+      // Row-major output walks rows; column-major output (row pass, or a
+      // transposed store, pixel (a, b) at b * L + a) walks columns.
       int tr, bc;
-      if (geo.sb == 1) {
+      if (geo.sb == 1 && !geo.out_t) {
         tr = idx / ncols;
         bc = idx - tr * ncols;
       } else {
@@ -1587,8 +1723,10 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
       }
       const int bb = b_lo + bc, a = a_lo + tr;
       const float inv = BWD ? 1.0f : 1.0f / float(cover_count(bb, geo, r));
-      const float* cell = smem + TA * pch + (tr + 1) * pch + (bb - colbase);
-      const int o = geo.sb == 1 ? a * (int)geo.sa + bb : a + bb * (int)geo.sb;
+      const float* cell = smem + acc0 + (tr + 1) * pch + (bb - colbase);
+      const int o = geo.out_t     ? a + bb * geo.L
+                    : geo.sb == 1 ? a * (int)geo.sa + bb
+                                  : a + bb * (int)geo.sb;
 #pragma unroll
       for (int h = 0; h < CB; ++h) Yc[h * plane + o] = cell[h * TA * pch] * inv;
       if constexpr (BWD) {
@@ -1598,7 +1736,8 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
     if constexpr (BWD) {
       if (wantg && j0 > 0 && j0 < geo.P)
         for (int bc = threadIdx.x; bc < ncols; bc += kWave * Q)
-          bw.side[(size_t)j0 * geo.W + b_lo + bc] = smem[NO * TA * pch + (b_lo + bc - colbase)];
+          bw.side[(size_t)j0 * geo.W + b_lo + bc] =
+              smem[acc0 + (NO - 1) * TA * pch + (b_lo + bc - colbase)];
     }
   }
 }
@@ -1622,8 +1761,8 @@ DEV void xcd_block(int& bx, int& by) {
   bx = logical - by * nx;
 }
 
-// Stride-1 column-pass kernels without an LDS tile (GlobalChunk views).
-template <int r, int CB, int R, int Q, int KIND, typename Acc, int MODE>
+// Column-pass kernels without an LDS tile (GlobalChunk views).
+template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE>
 __global__ __launch_bounds__(kWave* Q) void k_reduce_d(
     const float* __restrict__ X, const float* __restrict__ X2, const float* __restrict__ G,
     PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
@@ -1632,22 +1771,22 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce_d(
   const PlaneSrc<CB> src{X, X2, c0, (int)geo.plane};
   int bx, by;
   xcd_block(bx, by);
-  reduce_tile<r, CB, R, Q, true, KIND, Acc, MODE, true>(
+  reduce_tile<r, CB, R, Q, S1, KIND, Acc, MODE, true>(
       geo, wp, load_lambda(lam_dev, lam_host), 0, sum, bx, by, smem, G, &src);
 }
 
-template <int r, int CB, int R, int Q, int KIND, typename Acc, int MODE>
+template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE>
 __global__ __launch_bounds__(kWave* Q) void k_expand_d(
     const float* __restrict__ X, const float* __restrict__ G, float* __restrict__ Y,
     PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
-    const Acc* __restrict__ Us, int OW, BwdArgs bw) {
+    const Acc* __restrict__ Us, int OW, int pitch, BwdArgs bw) {
   extern __shared__ float smem[];
   const PlaneSrc<CB> src{X, bw.ybar, c0, (int)geo.plane};
   int bx, by;
   xcd_block(bx, by);
-  expand_tile<r, CB, R, Q, true, KIND, Acc, MODE, true>(G, Y, geo, wp, load_lambda(lam_dev, lam_host),
-                                                        c0, Us, OW, 0, bw, bx, by, gridDim.x, smem,
-                                                        &src);
+  expand_tile<r, CB, R, Q, S1, KIND, Acc, MODE, true>(G, Y, geo, wp, load_lambda(lam_dev, lam_host),
+                                                      c0, Us, OW, pitch, bw, bx, by, gridDim.x,
+                                                      smem, &src);
 }
 
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE>
@@ -1682,10 +1821,10 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
   if (geo.P > 1 && (stages & kStageReduce)) {
     const int gx = (geo.nK + kWave - 1) / kWave;
     bool direct = false;
-    if constexpr (S1 && D) {
+    if constexpr (D) {
       if (geo.sb == 1) {
         direct = true;
-        hipLaunchKernelGGL((k_reduce_d<r, CB, R, Q, KIND, Acc, MODE>), dim3(gx, gy),
+        hipLaunchKernelGGL((k_reduce_d<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(gx, gy),
                            dim3(kWave * Q), stage_out, stream, x, bw.ybar, g, geo, wp, lam_dev,
                            lam_host, c0, sum);
       }
@@ -1701,20 +1840,27 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
       hipLaunchKernelGGL((k_interface_pcr<r, NR, MM, Acc>), dim3(geo.nK), dim3(kWave), 0,
                          stream, (const Acc*)sum, us, geo.nK, geo.P, pl.iface_m);
     } else {
-      hipLaunchKernelGGL((k_interface_serial<r, NR, Acc>), dim3((geo.nK + kWave - 1) / kWave),
-                         dim3(kWave), 0, stream, (const Acc*)sum, us, gb, geo.nK, geo.P);
+      // Runs longer than the register solver holds: the same wave solver with
+      // its per-block values in the scratch part of the interface buffer.
+      const int m = (geo.P - 1 + kWave - 1) / kWave;
+      hipLaunchKernelGGL((k_interface_pcr_long<r, NR, Acc>), dim3(geo.nK), dim3(kWave), 0, stream,
+                         (const Acc*)sum, us, gb, geo.P, m);
     }
   }
   if (stages & kStageExpand) {
     const int ex = (geo.W + pl.OW - 1) / pl.OW;
     bool direct = false;
-    if constexpr (S1 && D) {
+    if constexpr (D) {
       if (geo.sb == 1) {
+        // Stride 1: LDS only to stage a transposed store.  Strided: LDS
+        // accumulator planes for the covering strips (one per output plane).
+        constexpr int NO = MODE == kModeBackward ? CB + 1 : CB;
+        const size_t lds = S1 ? (geo.out_t ? sizeof(float) * CB * Q * R * (kWave + 1) : 0)
+                              : sizeof(float) * (size_t)NO * (Q * R + 2) * pl.pitch;
         direct = true;
-        hipLaunchKernelGGL((k_expand_d<r, CB, R, Q, KIND, Acc, MODE>), dim3(ex, gy),
-                           dim3(kWave * Q),
-                           geo.out_t ? sizeof(float) * CB * Q * R * (kWave + 1) : 0, stream, x, g,
-                           y, geo, wp, lam_dev, lam_host, c0, (const Acc*)us, pl.OW, bw);
+        hipLaunchKernelGGL((k_expand_d<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(ex, gy),
+                           dim3(kWave * Q), lds, stream, x, g, y, geo, wp, lam_dev, lam_host, c0,
+                           (const Acc*)us, pl.OW, pl.pitch, bw);
       }
     }
     if (!direct) {
@@ -1751,9 +1897,11 @@ hipError_t launch_kind(const float* x, const float* g, float* y, int c0, const P
                        const PassPlan& pl, const WeightParams& wp, const float* lam_dev,
                        float lam_host, void* iface, hipStream_t s, int st, const BwdArgs& bw) {
   constexpr VariantSet VS = variants_for(MODE, r, CB, fp64);
+  // Strided forward column passes read their chunks directly (no input tile).
   if (geo.stride != 1)
-    return launch_impl<r, CB, fp64, false, KIND, VS.v[0].R, 1, MODE>(
-        x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st, bw);
+    return launch_impl<r, CB, fp64, false, KIND, VS.v[0].R, 1, MODE,
+                       MODE == kModeForward ? 1 : 0>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host,
+                                                     iface, s, st, bw);
   return launch_variant<r, CB, fp64, KIND, MODE, 0>(pl.variant, x, g, y, c0, geo, pl, wp,
                                                     lam_dev, lam_host, iface, s, st, bw);
 }

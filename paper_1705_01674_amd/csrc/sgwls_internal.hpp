@@ -113,6 +113,7 @@ struct PassPlan {
   int pitch;        // LDS row pitch (odd)
   int iface_m;      // separators per lane of the wave interface solver (0: serial solver)
   size_t sum_elems, u_elems;   // interface buffer sizes (elements)
+  size_t g_elems;              // scratch of the long-run interface solver (elements)
   int acc_bytes;    // 4 (float) or 8 (double) interface element size
 };
 

@@ -35,13 +35,18 @@ PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64, int varian
   pl.acc_bytes = fp64 ? 8 : 4;
   pl.sum_elems = (size_t)pl.P * F * pl.nK;
   pl.u_elems = (size_t)std::max(n, 1) * r * pl.nr * pl.nK;
+  // Runs longer than the register solver holds go to the long-run solver,
+  // whose per-block values (3r^2 + r*nr each, m blocks per lane, 64 lanes
+  // per strip) live in scratch after the separator solutions.
+  pl.g_elems = (n > 0 && pl.iface_m == 0)
+                   ? (size_t)std::max(m, 1) * kWave * (3 * r * r + r * pl.nr) * pl.nK
+                   : 0;
   return pl;
 }
 
 size_t interface_bytes(const PassPlan& pl) {
-  // chunk summaries, separator solutions, and (serial solver) the G_j blocks
-  const size_t g_elems = (size_t)std::max(pl.P - 1, 1) * kMaxR * kMaxR * pl.nK;
-  return (pl.sum_elems + pl.u_elems + g_elems) * (size_t)pl.acc_bytes + 256;
+  // chunk summaries, separator solutions, long-run solver scratch
+  return (pl.sum_elems + pl.u_elems + pl.g_elems) * (size_t)pl.acc_bytes + 256;
 }
 
 size_t interface_bytes_max(int L, int W, int r, int cb, int stride, int fp64, int mode) {

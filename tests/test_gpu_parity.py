@@ -78,6 +78,23 @@ def test_single_pass_small(ops, direction, r, stride, C):
     check(f"pass dir{direction} r{r} s{stride} C{C}", out.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("r,stride", [(1, 2), (1, 3), (2, 3), (2, 5), (3, 4), (3, 7), (4, 4), (4, 9)])
+@pytest.mark.parametrize("C", [1, 3])
+def test_strided_filter(ops, r, stride, C):
+    # the whole filter (both directions as transposed column passes) at a
+    # stride > 1: at least two expand blocks across each frame, several chunks
+    # along it and ragged ends, in float32 and with FP64 pivots
+    rng = np.random.default_rng(7000 + 100 * r + 10 * stride + C)
+    ow = 62 * stride - 2 * r
+    M, N = ow + 41 + 3 * r, 2 * ow + 17
+    f = rng.uniform(0, 1, (C, M, N)).astype(np.float32)
+    g = rng.uniform(0, 1, (M, N)).astype(np.float32)
+    pd = pdict(lam=4.0, r=r, iters=2, stride=stride, sigma_r=0.2)
+    ref = oracle_filter(f, g, pd)
+    check(f"filter r{r} s{stride} C{C}", run_filter(ops, f, g, pd), ref)
+    check(f"filter r{r} s{stride} C{C} fp64", run_filter(ops, f, g, pd, "fp64_pivot"), ref)
+
+
 @pytest.mark.parametrize("shape", [(3, 3), (3, 4), (4, 3), (5, 200), (200, 5), (7, 7), (2, 9, 9),
                                    (4, 33, 65), (5, 31, 17), (1, 130, 3)])
 @pytest.mark.parametrize("r", [1, 2])
