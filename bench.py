@@ -23,6 +23,8 @@ Prints ONE JSON line:
   cold       single calls after a 512 MiB scratch write (Infinity Cache evicted)
   stride3    the same workload with stride 3 (centres 2r+1 apart, no overlap)
   ctx        1024x1024 RGB, r = 1, T = 4 (the paper's timing image size)
+  wls2d      the 2D WLS model SG-WLS approximates (Eqs. 1-4) on the same
+             input, solved by GPU conjugate gradients: time and the SG-WLS gap
   interpolation  guided sparse interpolation (Eq. 21): 8x depth upsampling of
              a 1080x1920 depth map (r = 4, stride 4, lambda 400) and scribble
              colourisation at 1024x1024 (r = 4, stride 2, lambda 900)
@@ -157,6 +159,21 @@ def stride_sweep(torch, ops, synth, dev, args):
                   flush=True)
     return {"workload": "1024x1024 RGB, T=4, lambda 4, exp weights", "unit": "MPixel/s",
             "rows": rows}
+
+
+def time_wls2d(torch, ops, f, g, p, u_sg, steps):
+    """The 2D WLS model (Eqs. 1-4) on the same input, by the GPU conjugate-
+    gradient solver to a relative residual of 1e-6: its time and the SG-WLS
+    approximation gap (normwise max and mean over the output)."""
+    out = torch.empty_like(f)
+    ws = torch.empty(ops.wls2d_workspace_bytes(*f.shape, p), dtype=torch.uint8, device=f.device)
+    _, its, res = ops.wls2d(f, g, p, tol=1e-6, out=out, workspace=ws)
+    ms = time_events(torch, lambda: ops.wls2d(f, g, p, tol=1e-6, out=out, workspace=ws), steps)
+    scale = float(out.abs().max())
+    return {"solver": "Jacobi-preconditioned CG, float32 vectors, float64 dot products",
+            "iterations": its, "rel_residual": res, "ms_per_call": round(ms, 4),
+            "sgwls_gap_max": round(float((u_sg - out).abs().max()) / scale, 5),
+            "sgwls_gap_mean": round(float((u_sg - out).abs().mean()) / scale, 6)}
 
 
 def counter_run(torch, step, args, ms_note):
@@ -380,6 +397,8 @@ def main():
     ms64 = time_events(torch, step64, max(5, args.steps // 2))
 
     batched = None if args.no_batched else bench_batched(torch, ops, synth, args)
+    step()
+    wls = time_wls2d(torch, ops, f, g, p, u.clone(), max(3, args.steps // 10))
     # The other reading of "tau = 3" (stride 3 = 2r+1, no overlap) and the
     # 1024x1024 RGB T=4 context row.
     alt_steps = max(5, args.steps // 2)
@@ -464,6 +483,7 @@ def main():
         "stride3": stride3,
         "ctx": ctx,
         "interpolation": interp,
+        "wls2d": wls,
         "batched": batched,
         "cpu_baseline": cpu,
     }

@@ -168,6 +168,25 @@ sgwls_status sgwls_interpolate(const float* f, const float* h, const float* g, f
                                const float* lambda_dev, void* ws, size_t ws_bytes,
                                void* stream);
 
+/* ---- The 2D WLS model (Eqs. 1-4), reference solver ----
+ * u = (I + lambda L)^-1 f per channel, where L couples every pixel with the
+ * (2r+1) x (2r+1) patch around it (Eq. 1) with the weights of Eq. 2 and
+ * |i - j| the Euclidean distance of the two pixels: the global model that
+ * SG-WLS approximates, for measuring the approximation.  Solved by
+ * Jacobi-preconditioned conjugate gradients from u = 0, one per channel,
+ * until max over channels of ||f - A u|| / ||f|| <= tol or max_iters
+ * iterations.  p supplies lambda, r (1..4), kind and the weight parameters;
+ * iters, stride and prec are ignored.  1 <= C <= 4; u must not alias g (it
+ * may alias f).  Checks convergence every 8 iterations, each check a stream
+ * synchronisation, so the call cannot be captured into a graph.
+ * iters_done and rel_residual (nullable) receive the iterations run and
+ * the last checked relative residual.  ws: workspace of
+ * sgwls_wls2d_workspace_bytes(C, M, N, p) bytes. */
+size_t sgwls_wls2d_workspace_bytes(int C, int M, int N, const sgwls_params* p);
+sgwls_status sgwls_wls2d(const float* f, const float* g, float* u, int C, int M, int N,
+                         const sgwls_params* p, int max_iters, double tol, int* iters_done,
+                         double* rel_residual, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- Kernel variants and autotuning (not in the paper) ----
  * Stride-1 passes can run several compiled kernel variants that differ in
  * how a subsystem is cut into chunks (rows per chunk) and how many chunks

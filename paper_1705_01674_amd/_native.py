@@ -23,7 +23,8 @@ EXPORTS = ["sgwls_status_str", "sgwls_version", "sgwls_validate", "sgwls_workspa
            "sgwls_autotune", "sgwls_tune_save", "sgwls_tune_load",
            "sgwls_batched_variant_count", "sgwls_filter_batched_variant",
            "sgwls_autotune_batched", "sgwls_batched_graph_count", "sgwls_batched_graph_clear",
-           "sgwls_interpolate_workspace_bytes", "sgwls_interpolate"]
+           "sgwls_interpolate_workspace_bytes", "sgwls_interpolate",
+           "sgwls_wls2d_workspace_bytes", "sgwls_wls2d"]
 
 
 class SgwlsParams(ctypes.Structure):
@@ -68,6 +69,12 @@ def _load():
     lib.sgwls_interpolate_workspace_bytes.argtypes = [i, i, i, P]
     lib.sgwls_interpolate.restype = i
     lib.sgwls_interpolate.argtypes = [vp, vp, vp, vp, i, i, i, P, vp, vp, sz, vp]
+    lib.sgwls_wls2d_workspace_bytes.restype = sz
+    lib.sgwls_wls2d_workspace_bytes.argtypes = [i, i, i, P]
+    lib.sgwls_wls2d.restype = i
+    lib.sgwls_wls2d.argtypes = [vp, vp, vp, i, i, i, P, i, ctypes.c_double,
+                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                                vp, sz, vp]
     lib.sgwls_backward.restype = i
     lib.sgwls_backward.argtypes = [vp, vp, vp, vp, vp, vp, i, i, i, P, vp, vp, sz, vp]
     lib.sgwls_pass_backward.restype = i

@@ -175,6 +175,37 @@ def sgwls_interpolate(f: torch.Tensor, h: torch.Tensor, g: torch.Tensor, p: Para
     return out
 
 
+def wls2d_workspace_bytes(C: int, M: int, N: int, p: Params) -> int:
+    n = nat.lib.sgwls_wls2d_workspace_bytes(C, M, N, ctypes.byref(p.c()))
+    if n == 0:
+        raise ValueError("invalid 2D WLS arguments (1 <= C <= 4)")
+    return int(n)
+
+
+def wls2d(f: torch.Tensor, g: torch.Tensor, p: Params, *, max_iters: int = 1000,
+          tol: float = 1e-6, out: Optional[torch.Tensor] = None,
+          workspace: Optional[torch.Tensor] = None):
+    """The 2D WLS model SG-WLS approximates (Eqs. 1-4), solved by conjugate
+    gradients on the GPU.  Returns (u, iterations, relative residual)."""
+    C, M, N = _image(f, "f")
+    dev = f.device
+    _guidance(g, M, N, dev)
+    if out is None:
+        out = torch.empty_like(f)
+    elif out.shape != f.shape or out.dtype != f.dtype or not out.is_contiguous() or out.device != dev:
+        raise ValueError("out must match f")
+    nbytes = wls2d_workspace_bytes(C, M, N, p)
+    ws = workspace if workspace is not None else _workspace(nbytes, dev)
+    if ws.numel() < nbytes or ws.device != dev:
+        raise ValueError("workspace too small")
+    its, rel = ctypes.c_int(0), ctypes.c_double(0.0)
+    nat.check(nat.lib.sgwls_wls2d(_ptr(f), _ptr(g), _ptr(out), C, M, N, ctypes.byref(p.c()),
+                                  int(max_iters), float(tol), ctypes.byref(its),
+                                  ctypes.byref(rel), _ptr(ws), ws.numel(), _stream(dev)),
+              "sgwls_wls2d")
+    return out, its.value, rel.value
+
+
 def sgwls_pass(direction: int, x: torch.Tensor, g: torch.Tensor, p: Params, *,
                lambda_dev: Optional[torch.Tensor] = None,
                out: Optional[torch.Tensor] = None) -> torch.Tensor:

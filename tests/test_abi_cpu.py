@@ -19,7 +19,7 @@ def nat():
 def header_symbols():
     text = open(os.path.join(ROOT, "include", "sgwls.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sgwls_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(sgwls_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol(nat):
@@ -234,3 +234,25 @@ def test_interpolate_workspace_and_error_paths(nat):
     assert lib.sgwls_interpolate(f, h, g, u, 1, 64, 64, pp, None, None, big, None) == 3
     bad = ctypes.byref(P(nat, r=4, stride=10))
     assert lib.sgwls_interpolate(f, h, g, u, 1, 64, 64, bad, None, ws, big, None) == 1
+
+
+def test_wls2d_workspace_and_error_paths(nat):
+    """2D WLS reference solver: workspace sizes and argument errors before any
+    HIP call."""
+    p = P(nat, r=2, lam=4.0)
+    pp = ctypes.byref(p)
+    lib = nat.lib
+    n = lib.sgwls_wls2d_workspace_bytes(3, 256, 320, pp)
+    assert n >= 4 * (5 * 3 + 1) * 256 * 320
+    assert lib.sgwls_wls2d_workspace_bytes(5, 64, 64, pp) == 0     # at most 4 channels
+    assert lib.sgwls_wls2d_workspace_bytes(0, 64, 64, pp) == 0
+    f, g, u, ws = (ctypes.c_void_p(a) for a in (0x1000, 0x2000, 0x3000, 0x4000))
+    it, rel = ctypes.c_int(), ctypes.c_double()
+    big = 1 << 34
+    call = lambda *a: lib.sgwls_wls2d(*a, ctypes.byref(it), ctypes.byref(rel), ws, big, None)
+    assert call(None, g, u, 1, 64, 64, pp, 10, 1e-6) == 1
+    assert call(f, g, g, 1, 64, 64, pp, 10, 1e-6) == 1
+    assert call(f, g, u, 1, 64, 64, pp, 0, 1e-6) == 1
+    assert call(f, g, u, 1, 64, 64, pp, 10, float("nan")) == 1
+    assert call(f, g, u, 5, 64, 64, pp, 10, 1e-6) == 1
+    assert lib.sgwls_wls2d(f, g, u, 1, 64, 64, pp, 10, 1e-6, None, None, ws, 8, None) == 3
