@@ -430,10 +430,19 @@ def main():
             ref = oracle.filter(f64, g64, P)
             times.append(time.perf_counter() - t0)
         tmed = sorted(times)[len(times) // 2]
+        cores = oracle.num_threads()
+        # the same filter on one core (one run)
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        oracle.filter(f64, g64, P)
+        t1 = time.perf_counter() - t0
+        oracle.set_threads(cores)
         cpu = {"value": round(px / tmed / 1e6, 4), "unit": "MPixel/s",
-               "cores": oracle.num_threads(), "kind": "oracle",
+               "cores": cores, "kind": "oracle",
                "sample": f"the full workload (one {M}x{N}x{C} filter, T={p.iters}), "
-                         f"median of {args.cpu_reps} runs, {tmed:.2f} s each"}
+                         f"median of {args.cpu_reps} runs, {tmed:.2f} s each",
+               "single_core": {"value": round(px / t1 / 1e6, 4), "cores": 1,
+                               "sample": f"one run, {t1:.2f} s"}}
         max_rel = float(np.abs(gpu_out - ref).max() / np.abs(ref).max())
         max_rel64 = float(np.abs(u64.cpu().numpy().astype(np.float64) - ref).max() / np.abs(ref).max())
         _, ref_saved = oracle.filter(f64, g64, P, save=True)

@@ -84,6 +84,8 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         P = ctypes.POINTER(_Params)
         lib.orc_num_threads.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.restype = None
         lib.orc_centres.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I]
         lib.orc_snake_pixel.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I, _I]
         lib.orc_weight.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_double]
@@ -126,6 +128,11 @@ def _check(rc, what):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads used by later oracle calls."""
+    _load().orc_set_threads(int(n))
 
 
 def centres(n: int, r: int, stride: int) -> np.ndarray:

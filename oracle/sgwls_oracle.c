@@ -62,6 +62,15 @@ typedef struct {
 
 enum { ORC_OK = 0, ORC_E_ARG = -1, ORC_E_PIVOT = -2, ORC_E_MEM = -3 };
 
+/* Threads of the parallel loops of later calls (n >= 1). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();
