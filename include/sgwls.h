@@ -141,9 +141,9 @@ sgwls_status sgwls_pass_stages(int stages, int direction, const float* x, const 
  * (must not alias g).  lambda_dev: optional device override of p->lambda.
  * saved: NULL, or a device buffer of 2T*C*M*N floats that receives the
  * input of every pass in order (pass 2t = column pass of iteration t, 2t+1
- * its row pass) for sgwls_backward.  For stride 1 with r <= 2 the passes run
- * as column passes of the image and of its transpose, and the inputs of the
- * row passes (odd entries) are then stored transposed: C planes of N x M,
+ * its row pass) for sgwls_backward.  For stride 1 the passes run as column
+ * passes of the image and of its transpose, and the inputs of the row
+ * passes (odd entries) are then stored transposed: C planes of N x M,
  * pixel (i, j) at [c*M*N + j*M + i].  ws: workspace of
  * sgwls_workspace_bytes(C, M, N, p) bytes. */
 sgwls_status sgwls_filter(const float* f, const float* g, float* u,

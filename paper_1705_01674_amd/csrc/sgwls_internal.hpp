@@ -62,8 +62,8 @@ constexpr int kModeForward = 0, kModeBackward = 1;
 constexpr VariantSet variants_of(int r, int cb, int fp64) {
   if (fp64) {
     if (r == 1) return cb == 1 ? VariantSet{2, {{8, 4, 1}, {4, 4}}, 8} : VariantSet{2, {{4, 4, 1}, {4, 2}}, 8};
-    if (r == 2) return cb == 1 ? VariantSet{1, {{4, 4}}, 4} : VariantSet{1, {{2, 4}}, 4};
-    return VariantSet{1, {{2, 2}}, 0};
+    if (r == 2) return cb == 1 ? VariantSet{1, {{4, 4, 1}}, 4} : VariantSet{1, {{2, 4, 1}}, 4};
+    return VariantSet{1, {{2, 2, 1}}, 0};
   }
   // Variant 0 first; the row-pass tile loader keeps a lane per tile row, so
   // Q*R + 2 close to (and not above) 64 uses the lanes best.  Every tile
@@ -77,22 +77,22 @@ constexpr VariantSet variants_of(int r, int cb, int fp64) {
   if (r == 2)
     return cb == 1 ? VariantSet{5, {{6, 4, 1}, {6, 9}, {4, 8, 1}, {4, 4}, {6, 4}}, 8}
                    : VariantSet{5, {{4, 4, 1}, {4, 8}, {4, 8, 1}, {4, 2}, {4, 4}}, 8};
-  if (r == 3) return cb == 1 ? VariantSet{1, {{4, 2}}, 0} : VariantSet{1, {{2, 2}}, 0};
-  return VariantSet{1, {{2, 2}}, 0};
+  if (r == 3) return cb == 1 ? VariantSet{1, {{4, 2, 1}}, 0} : VariantSet{1, {{2, 2, 1}}, 0};
+  return VariantSet{1, {{2, 2, 1}}, 0};
 }
 
 // Backward variants: 2*cb right-hand sides per element.
 constexpr VariantSet bwd_variants_of(int r, int cb, int fp64) {
   if (fp64) {
     if (r == 1) return cb == 1 ? VariantSet{1, {{8, 4, 1}}, 8} : VariantSet{1, {{4, 4, 1}}, 8};
-    if (r == 2) return VariantSet{1, {{2, 4}}, 0};
-    return VariantSet{1, {{2, 2}}, 0};
+    if (r == 2) return VariantSet{1, {{2, 4, 1}}, 0};
+    return VariantSet{1, {{2, 2, 1}}, 0};
   }
   if (r == 1)
     return cb == 1 ? VariantSet{3, {{8, 4, 1}, {8, 4}, {4, 4}}, 8}
                    : VariantSet{3, {{6, 4, 1}, {4, 4, 1}, {4, 4}}, 8};
   if (r == 2) return VariantSet{2, {{4, 4, 1}, {4, 4}}, 8};
-  return VariantSet{1, {{2, 2}}, 0};
+  return VariantSet{1, {{2, 2, 1}}, 0};
 }
 
 constexpr VariantSet variants_for(int mode, int r, int cb, int fp64) {

@@ -190,7 +190,7 @@ def test_lambda_on_device_and_saved_inputs(ops):
                                    oracle.OracleParams(**w.params), save=True)
     check("lambda_dev", u.cpu().numpy(), ref)
     got = saved.cpu().numpy().reshape(ref_saved.shape).copy()
-    # stride 1, r <= 2: the row-pass inputs (odd entries) are stored transposed
+    # stride 1: the row-pass inputs (odd entries) are stored transposed
     C, M, N = w.f.shape
     for q in range(1, got.shape[0], 2):
         got[q] = got[q].reshape(C, N, M).transpose(0, 2, 1)
