@@ -131,6 +131,22 @@ def test_filter_backward_matches_oracle(ops, r, C, iters):
     check(f"grad_lambda {tag}", gl, rl, TOL_G)
 
 
+@pytest.mark.parametrize("r,C", [(1, 3), (3, 1)])
+def test_filter_backward_long_lines(ops, r, C):
+    """Tall images (4,000 rows): more separator blocks per lane than the
+    register interface solver holds, so the backward runs the scratch-backed
+    solver with its doubled right-hand sides; r = 3 takes it at any length."""
+    M, N = 4000, 29
+    f, g, ub = inputs(C, M, N, 77 + r)
+    pd = pdict(lam=8.0, r=r, iters=1)
+    gf, gg, gl = filter_grads(ops, f, g, pd, ub)
+    rf, rg, rl = oracle_grads(f, g, pd, ub)
+    tag = f"long r{r} C{C}"
+    check(f"grad_f {tag}", gf, rf, TOL_X)
+    check(f"grad_g {tag}", gg, rg, TOL_G)
+    check(f"grad_lambda {tag}", gl, rl, TOL_G)
+
+
 def test_backward_of_the_differentiation_config(ops):
     """One image of the 16 x 3 x 512 x 512 differentiation workload (r=1,
     T=3, lambda=8, MSE loss to the seeded noise-free target)."""

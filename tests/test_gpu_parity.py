@@ -95,6 +95,20 @@ def test_strided_filter(ops, r, stride, C):
     check(f"filter r{r} s{stride} C{C} fp64", run_filter(ops, f, g, pd, "fp64_pivot"), ref)
 
 
+@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("C", [1, 3])
+def test_long_lines_use_the_long_run_solver(ops, r, C):
+    # lines of 9,000 and 5,000 pixels: more separator blocks per lane than the
+    # register interface solver holds, so the scratch-backed solver runs in
+    # both directions (tall and wide images)
+    for M, N in ((9000, 37), (41, 5000)):
+        rng = np.random.default_rng(M + N + 10 * r + C)
+        f = rng.uniform(0, 1, (C, M, N)).astype(np.float32)
+        g = rng.uniform(0, 1, (M, N)).astype(np.float32)
+        pd = pdict(lam=5.0, r=r, iters=1, sigma_r=0.2)
+        check(f"long lines {M}x{N} r{r} C{C}", run_filter(ops, f, g, pd), oracle_filter(f, g, pd))
+
+
 @pytest.mark.parametrize("shape", [(3, 3), (3, 4), (4, 3), (5, 200), (200, 5), (7, 7), (2, 9, 9),
                                    (4, 33, 65), (5, 31, 17), (1, 130, 3)])
 @pytest.mark.parametrize("r", [1, 2])
