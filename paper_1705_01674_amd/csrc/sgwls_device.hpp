@@ -577,14 +577,11 @@ DEV void reduce_block(const float* __restrict__ X, const float* __restrict__ X2,
                       float* smem) {
   constexpr int NR = MODE == kModeBackward ? 2 * CB : CB;
   using CV = ChunkView<r, R, S1>;
-  using LY = IfaceLayout<r, NR>;
-  constexpr int E = CV::E;
   constexpr int TA = Q * R + 2;
   const int lane = threadIdx.x % kWave;
   const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int ki_lo = bx * kWave;
-  const int j0 = by * Q, j = j0 + wq;
-  const int a_lo = j0 * R;
+  const int a_lo = by * Q * R;
   const int colbase = centre_of(ki_lo, geo, r) - r;
   const int TB = S1 ? kWave + 2 * r : tile_width<r>(geo.stride);
   const int pch = S1 ? CV::PITCH1 : pitch;
@@ -1269,17 +1266,13 @@ DEV void expand_block(const float* __restrict__ X, const float* __restrict__ G,
                       const BwdArgs& bw, int bx, int by, int nbx, float* smem) {
   constexpr bool BWD = MODE == kModeBackward;
   constexpr int NR = BWD ? 2 * CB : CB;   // right-hand sides
-  constexpr int NO = BWD ? CB + 1 : CB;   // output planes (backward: + guidance gradient)
   using CV = ChunkView<r, R, S1>;
-  constexpr int E = CV::E, w = CV::w;
   constexpr int TA = Q * R + 2;
   const int lane = threadIdx.x % kWave;
   const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
-  const int b_lo = bx * OW, b_hi = min(b_lo + OW, geo.W);
   const int ki_lo = expand_first_strip(bx, OW, geo, r);
   const int colbase = centre_of(ki_lo, geo, r) - r;
-  const int j0 = by * Q, j = j0 + wq;
-  const int a_lo = j0 * R;
+  const int a_lo = by * Q * R;
   const int TB = S1 ? kWave + 2 * r : tile_width<r>(geo.stride);
   const int pch = S1 ? CV::PITCH1 : pitch;
   const PlaneSrc<CB> src{X, bw.ybar, c0, (int)geo.plane};
