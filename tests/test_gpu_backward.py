@@ -147,6 +147,27 @@ def test_filter_backward_long_lines(ops, r, C):
     check(f"grad_lambda {tag}", gl, rl, TOL_G)
 
 
+@pytest.mark.parametrize("r,stride,C", [(1, 1, 3), (2, 1, 1), (1, 3, 3), (3, 1, 1)])
+def test_dot_product_identity_on_gpu(ops, r, stride, C):
+    """The backward is the adjoint of the forward: for the filter S (linear in
+    f for a fixed guidance), <S f, v> = <f, S^T v>, both sides from the GPU
+    and summed in float64."""
+    M, N = 70, 95
+    f, g, v = inputs(C, M, N, 500 + 10 * r + stride)
+    pd = pdict(lam=5.0, r=r, iters=2, stride=stride)
+    p = ops.Params(**pd)
+    ft, gt = cuda(f), cuda(g)
+    saved = torch.empty((2 * p.iters, C, M, N), device="cuda")
+    u = ops.sgwls_filter(ft, gt, p, saved=saved)
+    gf, _, _ = ops.sgwls_backward(gt, saved, cuda(v), p)
+    torch.cuda.synchronize()
+    lhs = float(np.sum(u.cpu().numpy().astype(np.float64) * v))
+    rhs = float(np.sum(f.astype(np.float64) * gf.cpu().numpy()))
+    scale = float(np.sum(np.abs(u.cpu().numpy() * v)))
+    print(f"[backward] <Sf, v> {lhs:.9e} <f, S^T v> {rhs:.9e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-5 * scale
+
+
 def test_backward_of_the_differentiation_config(ops):
     """One image of the 16 x 3 x 512 x 512 differentiation workload (r=1,
     T=3, lambda=8, MSE loss to the seeded noise-free target)."""
