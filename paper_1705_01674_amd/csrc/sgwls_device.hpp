@@ -808,6 +808,54 @@ struct SepReader {
   }
 };
 
+// SepReader over records prefetched into registers: chunks s .. s + nrec - 1
+// of one strip (indices past the last chunk read the last one), loaded
+// together before the elimination so that their latency is paid once.
+// Calls index chunks absolutely; the indices are s plus compile-time offsets.
+template <int r, int CB, int NREC, typename Acc>
+struct PreReader {
+  using LY = IfaceLayout<r, CB>;
+  Acc rec[NREC][LY::F];
+  int s, P;
+  DEV void load(const Acc* __restrict__ S, int s_, int P_, int nrec) {
+    s = s_;
+    P = P_;
+#pragma unroll
+    for (int i = 0; i < NREC; ++i) {
+      if (i < nrec) {
+        const int jj = min(s + i, P - 1);
+#pragma unroll
+        for (int f = 0; f < LY::F; ++f) rec[i][f] = S[(size_t)jj * LY::F + f];
+      }
+    }
+  }
+  DEV Acc at(int j, int f) const { return rec[j - s][f]; }
+  DEV void diag(int j, Acc (&A)[r][r]) const {
+    int t = 0;
+#pragma unroll
+    for (int a = 0; a < r; ++a)
+#pragma unroll
+      for (int b = 0; b <= a; ++b) {
+        A[a][b] = at(j, LY::oW + t) - at(j + 1, LY::oTT + t);
+        A[b][a] = A[a][b];
+        ++t;
+      }
+  }
+  DEV void rhs(int j, Acc (&y)[r][CB]) const {
+#pragma unroll
+    for (int a = 0; a < r; ++a)
+#pragma unroll
+      for (int h = 0; h < CB; ++h)
+        y[a][h] = at(j, LY::oRf + a * CB + h) - at(j + 1, LY::oRT + a * CB + h);
+  }
+  DEV void off(int j, Acc (&U)[r][r]) const {
+#pragma unroll
+    for (int a = 0; a < r; ++a)
+#pragma unroll
+      for (int c = 0; c < r; ++c) U[a][c] = (j + 1 < P - 1) ? at(j + 1, LY::oTB + c * r + a) : Acc(0);
+  }
+};
+
 // The reduced system of one strip's separators after each lane eliminated
 // its own run (lane l keeps the last block of its run): block cyclic
 // reduction across the 64 lanes, then each lane's solution X and the one of
@@ -893,14 +941,12 @@ DEV void iface_pcr_levels(const Acc (&S)[r][r], const Acc (&Bt)[r][r], const Acc
 // k_interface_pcr: one wave per strip, lane l owns separator blocks
 // [l*m, min(l*m + m, P-1)); MM is the compiled maximum of m.
 // U receives the separator solutions strip-major: U[(ki*(P-1) + j)*r*CB + a*CB + h].
-template <int r, int CB, int MM, typename Acc>
-DEV void iface_pcr_strip(const Acc* __restrict__ sum, Acc* __restrict__ U, int P, int m, int ki) {
-  using LY = IfaceLayout<r, CB>;
+template <int r, int CB, int MM, typename Acc, class Reader>
+DEV void iface_pcr_run(const Reader& rd, Acc* __restrict__ U, int P, int m, int ki) {
   const int lane = threadIdx.x % kWave;
   const int n = P - 1;
   const int s = lane * m, e = min(s + m, n);
   const bool active = s < n;
-  SepReader<r, CB, Acc> rd{sum + (size_t)ki * P * LY::F, P};
 
   // Local bordered elimination of blocks s .. e-2 (T = block s-1 of the
   // previous lane, B = block e-1 is this lane's unknown at the PCR level).
@@ -1031,6 +1077,22 @@ DEV void iface_pcr_strip(const Acc* __restrict__ sum, Acc* __restrict__ U, int P
           xn[a][h] = v[a][h];
         }
     }
+  }
+}
+
+// The solver of one strip: its chunk records prefetched into registers
+// when the lane's run fits (MM + 1 records), else read as needed.
+template <int r, int CB, int MM, typename Acc>
+DEV void iface_pcr_strip(const Acc* __restrict__ sum, Acc* __restrict__ U, int P, int m, int ki) {
+  using LY = IfaceLayout<r, CB>;
+  const Acc* S = sum + (size_t)ki * P * LY::F;
+  if constexpr ((MM + 1) * LY::F <= 160) {
+    PreReader<r, CB, MM + 1, Acc> rd;
+    rd.load(S, (int)(threadIdx.x % kWave) * m, P, m + 1);
+    iface_pcr_run<r, CB, MM, Acc>(rd, U, P, m, ki);
+  } else {
+    const SepReader<r, CB, Acc> rd{S, P};
+    iface_pcr_run<r, CB, MM, Acc>(rd, U, P, m, ki);
   }
 }
 
