@@ -1347,6 +1347,43 @@ DEV void expand_block(const float* __restrict__ X, const float* __restrict__ G,
                                                 by, nbx, smem);
 }
 
+// Transposed store of a block's staged rows: LDS row tr (pitch kWave + 1,
+// one bank of padding), column bb - colbase, holds output (a_lo + tr, bb),
+// which goes to Yc[h*plane + bb*L + a_lo + tr].  A column's rows are
+// contiguous in the output, so consecutive threads take consecutive rows of
+// one column (the block's Q waves share the work): four rows per 16-byte
+// store when the runs are 16-byte aligned (a_lo is a multiple of QR), one row
+// per store otherwise.
+template <int CB, int Q, int R>
+DEV void store_transposed(const float* smem, float* __restrict__ Yc, const float* Ybase, int plane,
+                          int L, int a_lo, int arows, int b_lo, int b_hi, int colbase) {
+  constexpr int RP = kWave + 1, QR = Q * R, nthr = kWave * Q;
+  const int ncols = b_hi - b_lo;
+  if (QR % 4 == 0 && L % 4 == 0 && arows % 4 == 0 && plane % 4 == 0 &&
+      (reinterpret_cast<uintptr_t>(Ybase) & 15) == 0) {
+    const int q4 = arows / 4;
+    for (int idx = threadIdx.x; idx < q4 * ncols; idx += nthr) {
+      const int bc = idx / q4, tr = 4 * (idx - bc * q4);
+      const int bb = b_lo + bc;
+      const float* cell = smem + tr * RP + (bb - colbase);
+#pragma unroll
+      for (int h = 0; h < CB; ++h) {
+        const float* c = cell + h * QR * RP;
+        *reinterpret_cast<float4*>(Yc + h * plane + (size_t)bb * L + a_lo + tr) =
+            make_float4(c[0], c[RP], c[2 * RP], c[3 * RP]);
+      }
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < arows * ncols; idx += nthr) {
+      const int bc = idx / arows, tr = idx - bc * arows;
+      const int bb = b_lo + bc;
+      const float* cell = smem + tr * RP + (bb - colbase);
+#pragma unroll
+      for (int h = 0; h < CB; ++h) Yc[h * plane + (size_t)bb * L + a_lo + tr] = cell[h * QR * RP];
+    }
+  }
+}
+
 // The solve and output of a block whose tile is in LDS (see expand_block), or,
 // with DIRECT, whose chunks are read from global memory (stride-1 column pass).
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE, bool DIRECT>
@@ -1637,18 +1674,8 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
         }
       }
       if (geo.out_t) {
-        // Transposed output: column b of the block's rows is contiguous, so
-        // consecutive threads take consecutive rows of one column.
         __syncthreads();
-        const int ncols = b_hi - b_lo;
-        for (int idx = threadIdx.x; idx < arows * ncols; idx += kWave * Q) {
-          const int bc = idx / arows, tr = idx - bc * arows;
-          const int bb = b_lo + bc;
-          const float* cell = smem + tr * (kWave + 1) + (bb - colbase);
-#pragma unroll
-          for (int h = 0; h < CB; ++h)
-            Yc[h * plane + bb * geo.L + a_lo + tr] = cell[h * Q * R * (kWave + 1)];
-        }
+        store_transposed<CB, Q, R>(smem, Yc, Y, plane, geo.L, a_lo, arows, b_lo, b_hi, colbase);
       }
       return;
     }
@@ -1695,15 +1722,7 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
       }
       if (geo.out_t) {
         __syncthreads();
-        const int ncols = b_hi - b_lo;
-        for (int idx = threadIdx.x; idx < arows * ncols; idx += kWave * Q) {
-          const int bc = idx / arows, tr = idx - bc * arows;
-          const int bb = b_lo + bc;
-          const float* cell = smem + tr * (kWave + 1) + (bb - colbase);
-#pragma unroll
-          for (int h = 0; h < CB; ++h)
-            Yc[h * plane + bb * geo.L + a_lo + tr] = cell[h * Q * R * (kWave + 1)];
-        }
+        store_transposed<CB, Q, R>(smem, Yc, Y, plane, geo.L, a_lo, arows, b_lo, b_hi, colbase);
       }
     } else {             // row pass: transpose through the (consumed) image planes
       if (own) {
