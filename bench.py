@@ -30,6 +30,11 @@ Prints ONE JSON line:
              colourisation at 1024x1024 (r = 4, stride 2, lambda 900)
   traffic    (in roofline) HBM bytes per k_expand_d launch from the committed
              rocprofv3 counter summary, null when it was taken on other sources
+  radius     the same image at r = 2 and r = 3 (T = 3, lambda = 16): FP32 and
+             FP64-pivot time, algorithmic bytes / time vs 8 TB/s, and the
+             VALU-busy fraction of each stage from the committed counter
+             summary (null when it was taken on other sources); these radii
+             carry several times the arithmetic per byte of r = 1
 """
 from __future__ import annotations
 
@@ -57,10 +62,11 @@ def parse():
     ap.add_argument("--sweep", action="store_true",
                     help="only the stride / radius sweep: 1024x1024 RGB, T=4, r = 1..4, "
                          "stride 1..2r+1; one JSON line")
-    ap.add_argument("--counters", choices=("fwd", "fwdbwd"), default=None,
+    ap.add_argument("--counters", choices=("fwd", "fwdbwd", "radius"), default=None,
                     help="for rocprofv3 --pmc runs: the tuned forward (or forward + backward) "
                          "steps only, then three copies of 64 MiB (the counter calibration), "
-                         "one short JSON line")
+                         "one short JSON line; 'radius': three tuned forward calls at each of "
+                         "r = 1, 2, 3 on the 1080p RGB image (for the VALU-busy counter)")
     return ap.parse_args()
 
 
@@ -98,6 +104,134 @@ def counted_traffic(tuned):
     if not col or not row or "col" not in col or "row" not in row:
         return None
     return round((col["col"] + row["row"]) / 2)
+
+
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_rgb1080p_r1_r2_r3_T3.md")
+
+
+def radius_digest():
+    """SHA-256 over the sources the kernels at r = 1, 2, 3 are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1705_01674_amd", "csrc")
+    for name in ("sgwls_device.hpp", "sgwls_internal.hpp", "sgwls_pass_r1.hip",
+                 "sgwls_pass_r2.hip", "sgwls_pass_r3.hip"):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counted_valu(r):
+    """Per-stage VALU-busy fraction at radius r from the committed counter
+    summary (with the variants it was counted at), or None when the summary
+    is missing or was taken on other kernel sources."""
+    try:
+        with open(VALU_FILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    tag = "valu-json:"
+    if tag not in text:
+        return None
+    data = json.loads(text.split(tag, 1)[1].split("-->", 1)[0])
+    if data.get("source_sha256") != radius_digest():
+        return None
+    return data.get("rows", {}).get(str(r))
+
+
+def radius_rows(torch, ops, nat, synth, dev, args, counters=False):
+    """The metric image at r = 2 and r = 3 (T = 3, lambda = 16; the FP32
+    path's cost does not depend on lambda): per call FP32 and FP64-pivot time
+    and the algorithmic bytes / time.  With counters, only three tuned forward
+    calls at each of r = 1, 2, 3 (the dispatches a VALU-busy pass reads)."""
+    rows = []
+    for r in ((1, 2, 3) if counters else (2, 3)):
+        w = synth.rgb1080p(r=r, lam=16.0)
+        C, M, N = w.f.shape
+        p = ops.Params(**w.params)
+        f = torch.from_numpy(w.f).to(dev)
+        g = torch.from_numpy(w.g).to(dev)
+        u = torch.empty_like(f)
+        ws = torch.empty(ops.workspace_bytes(C, M, N, p), dtype=torch.uint8, device=dev)
+        tuned = ops.autotune(f, g, p, reps=10)
+        variants = {f"{'col' if d == 0 else 'row'}_c{cb}": v for (d, cb), v in sorted(tuned.items())}
+
+        def step():
+            ops.sgwls_filter(f, g, p, out=u, workspace=ws)
+
+        if counters:
+            for _ in range(3):
+                step()
+            torch.cuda.synchronize()
+            rows.append({"r": r, "variants": variants})
+            continue
+        for _ in range(args.warmup):
+            step()
+        ms = time_events(torch, step, max(5, args.steps // 2))
+        p64 = p.with_(prec="fp64_pivot")
+        ws64 = torch.empty(ops.workspace_bytes(C, M, N, p64), dtype=torch.uint8, device=dev)
+
+        def step64():
+            ops.sgwls_filter(f, g, p64, out=u, workspace=ws64)
+
+        for _ in range(args.warmup):
+            step64()
+        ms64 = time_events(torch, step64, max(5, args.steps // 5))
+        alg = (8 * C + 4) * M * N * 2 * p.iters
+        _, st, _ = stage_times(torch, nat, f, g, p, ws, max(10, args.steps // 5))
+        rows.append({"workload": w.name, "r": r, "iters": p.iters, "lambda": p.lam,
+                     "ms_per_step": round(ms, 5), "value": round(M * N / (ms * 1e-3) / 1e6, 2),
+                     "unit": "MPixel/s", "alg_GBps": round(alg / (ms * 1e-3) / 1e9, 1),
+                     "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "fp64_pivot_ms": round(ms64, 5), "variants": variants,
+                     "kernels_ms_per_launch": {f"{'col' if d == 0 else 'row'}:{n}": round(t, 5)
+                                               for (d, n), t in st.items()},
+                     "valu_busy": counted_valu(r)})
+    return rows
+
+
+def stage_times(torch, nat, f, g, p, ws, steps):
+    """Per-kernel timing: each stage of each pass launched alone on the current
+    stream, between HIP events, exactly as the filter launches it.  When the
+    filter runs every pass as a column pass (of the image, then of its
+    transpose, storing transposed), so does this timing.  Returns whether it
+    does, the mean ms per launch of each (frame, stage) and each stage's ms
+    per filter call."""
+    import ctypes
+    C, M, N = f.shape
+    cp = p.c()
+    stream = ctypes.c_void_p(torch.cuda.current_stream(f.device).cuda_stream)
+    y = torch.empty_like(f)
+
+    def stages_call(mask, direction, xx, gg, yy, MM, NN):
+        return nat.lib.sgwls_pass_stages(mask, direction, ctypes.c_void_p(xx.data_ptr()),
+                                         ctypes.c_void_p(gg.data_ptr()), ctypes.c_void_p(yy.data_ptr()),
+                                         C, MM, NN, ctypes.byref(cp), None,
+                                         ctypes.c_void_p(ws.data_ptr()), ws.numel(), stream)
+
+    transposed = stages_call(7 | 8, 0, f, g, y, M, N) == 0
+    if transposed:
+        fT = f.transpose(1, 2).contiguous()
+        gT = g.t().contiguous()
+        frames = [(0, f, g, M, N, 8), (0, fT, gT, N, M, 8)]
+    else:
+        frames = [(0, f, g, M, N, 0), (1, f, g, M, N, 0)]
+    stage_names = {1: "k_reduce", 2: "k_interface", 4: "k_expand"}
+    per_filter_ms = {}
+    stage_ms = {}
+    for direction, (dflag, xx, gg, MM, NN, extra) in enumerate(frames):
+        yy = torch.empty_like(xx)
+
+        def run(mask):
+            nat.check(stages_call(mask | extra, dflag, xx, gg, yy, MM, NN), "sgwls_pass_stages")
+        run(7)
+        for mask, name in stage_names.items():
+            for _ in range(3):
+                run(mask)
+            t = time_events(torch, lambda: run(mask), max(10, steps))
+            stage_ms[(direction, name)] = t
+            per_filter_ms[name] = per_filter_ms.get(name, 0.0) + t * p.iters
+    return transposed, stage_ms, per_filter_ms
 
 
 def time_workload(torch, ops, w, dev, steps, warmup):
@@ -258,7 +392,6 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
-    import ctypes
 
     import numpy as np
     import torch
@@ -270,6 +403,10 @@ def main():
     torch.cuda.set_device(dev)
     if args.sweep:
         print(json.dumps({"sweep": stride_sweep(torch, ops, synth, dev, args)}), flush=True)
+        return
+    if args.counters == "radius":
+        rows = radius_rows(torch, ops, nat, synth, dev, args, counters=True)
+        print(json.dumps({"counters_run": True, "radius": rows}), flush=True)
         return
     w = synth.rgb1080p(stride=args.stride)
     C, M, N = w.f.shape
@@ -296,42 +433,7 @@ def main():
     ms = time_events(torch, step, args.steps)
     mpix = M * N / (ms * 1e-3) / 1e6
 
-    # Per-kernel timing: each stage of each pass launched alone on the current
-    # stream, between HIP events, exactly as the filter launches it.  When the
-    # filter runs every pass as a column pass (of the image, then of its
-    # transpose, storing transposed), so does this timing.
-    cp = p.c()
-    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
-    y = torch.empty_like(f)
-
-    def stages_call(mask, direction, xx, gg, yy, MM, NN):
-        return nat.lib.sgwls_pass_stages(mask, direction, ctypes.c_void_p(xx.data_ptr()),
-                                         ctypes.c_void_p(gg.data_ptr()), ctypes.c_void_p(yy.data_ptr()),
-                                         C, MM, NN, ctypes.byref(cp), None,
-                                         ctypes.c_void_p(ws.data_ptr()), ws.numel(), stream)
-
-    transposed = stages_call(7 | 8, 0, f, g, y, M, N) == 0
-    if transposed:
-        fT = f.transpose(1, 2).contiguous()
-        gT = g.t().contiguous()
-        frames = [(0, f, g, M, N, 8), (0, fT, gT, N, M, 8)]
-    else:
-        frames = [(0, f, g, M, N, 0), (1, f, g, M, N, 0)]
-    stage_names = {1: "k_reduce", 2: "k_interface", 4: "k_expand"}
-    per_filter_ms = {}
-    stage_ms = {}
-    for direction, (dflag, xx, gg, MM, NN, extra) in enumerate(frames):
-        yy = torch.empty_like(xx)
-
-        def run(mask):
-            nat.check(stages_call(mask | extra, dflag, xx, gg, yy, MM, NN), "sgwls_pass_stages")
-        run(7)
-        for mask, name in stage_names.items():
-            for _ in range(3):
-                run(mask)
-            t = time_events(torch, lambda: run(mask), max(10, args.steps))
-            stage_ms[(direction, name)] = t
-            per_filter_ms[name] = per_filter_ms.get(name, 0.0) + t * p.iters
+    transposed, stage_ms, per_filter_ms = stage_times(torch, nat, f, g, p, ws, args.steps)
     # Cold calls: a 512 MiB scratch write before each call evicts the 256 MB
     # Infinity Cache, so the first pass reads its inputs from HBM.
     scratch = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -404,6 +506,7 @@ def main():
     alt_steps = max(5, args.steps // 2)
     stride3 = time_workload(torch, ops, synth.rgb1080p(stride=3), dev, alt_steps, args.warmup)
     ctx = time_workload(torch, ops, synth.rgb1024_ctx(), dev, alt_steps, args.warmup)
+    radius = radius_rows(torch, ops, nat, synth, dev, args)
     # Guided sparse interpolation, Eq. (21): 8x depth upsampling at 1080p and
     # scribble colourisation (two chrominance planes) at 1024x1024.
     interp = [time_interpolation(torch, ops, synth.depth_upsample(1080, 1920, 8), dev, alt_steps,
@@ -491,6 +594,7 @@ def main():
                  "note": "median of single calls, each after a 512 MiB scratch write"},
         "stride3": stride3,
         "ctx": ctx,
+        "radius": radius,
         "interpolation": interp,
         "wls2d": wls,
         "batched": batched,
