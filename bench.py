@@ -17,6 +17,8 @@ Prints ONE JSON line:
              (gradients for f, g and lambda) for a fixed output gradient, as
              MPixel/s and algorithmic bytes / time vs 8 TB/s
   fp64_pivot the same forward call with float64 pivots and recurrences
+  fp32_delta the same forward call in the cancellation-free float32 mode
+             (one serial solve per strip, pivots carried as their excess)
   batched    64 grey images with sides in [256, 2048], r in {1, 2}, lambda in
              [0.5, 32], T = 3, in one batched call (hipGraph replay on a side
              stream, autotuned variant), against a loop of single-image calls
@@ -498,6 +500,17 @@ def main():
         step64()
     ms64 = time_events(torch, step64, max(5, args.steps // 2))
 
+    # The cancellation-free float32 mode (serial strips, excess pivots).
+    pd = p.with_(prec="fp32_delta")
+    wsd = torch.empty(ops.workspace_bytes(C, M, N, pd), dtype=torch.uint8, device=dev)
+    ud = torch.empty_like(f)
+
+    def stepd():
+        ops.sgwls_filter(f, g, pd, out=ud, workspace=wsd)
+
+    stepd()
+    msd = time_events(torch, stepd, max(3, args.steps // 10))
+
     batched = None if args.no_batched else bench_batched(torch, ops, synth, args)
     step()
     wls = time_wls2d(torch, ops, f, g, p, u.clone(), max(3, args.steps // 10))
@@ -521,6 +534,7 @@ def main():
     cpu = None
     max_rel = None
     max_rel64 = None
+    max_reld = None
     grad_err = None
     if not args.no_cpu_baseline:
         import oracle
@@ -548,6 +562,7 @@ def main():
                                "sample": f"one run, {t1:.2f} s"}}
         max_rel = float(np.abs(gpu_out - ref).max() / np.abs(ref).max())
         max_rel64 = float(np.abs(u64.cpu().numpy().astype(np.float64) - ref).max() / np.abs(ref).max())
+        max_reld = float(np.abs(ud.cpu().numpy().astype(np.float64) - ref).max() / np.abs(ref).max())
         _, ref_saved = oracle.filter(f64, g64, P, save=True)
         rf, rg, rl = oracle.filter_backward(g64, ref_saved, ubar.cpu().numpy().astype(np.float64), P)
         grad_err = {"grad_f": float(np.abs(gpu_grads[0] - rf).max() / np.abs(rf).max()),
@@ -590,6 +605,9 @@ def main():
                     "max_rel_err_vs_oracle": grad_err},
         "fp64_pivot": {"ms_per_step": round(ms64, 5), "value": round(M * N / (ms64 * 1e-3) / 1e6, 2),
                        "max_rel_err_vs_oracle": max_rel64},
+        "fp32_delta": {"ms_per_step": round(msd, 5), "value": round(M * N / (msd * 1e-3) / 1e6, 2),
+                       "max_rel_err_vs_oracle": max_reld,
+                       "note": "serial strip solves with excess pivots (r = 1 precision mode)"},
         "cold": {"ms_per_step": round(ms_cold, 5), "value": round(M * N / (ms_cold * 1e-3) / 1e6, 2),
                  "note": "median of single calls, each after a 512 MiB scratch write"},
         "stride3": stride3,

@@ -65,10 +65,19 @@ typedef enum {
  * float32.  FP64_PIVOT: weights are computed in float32, but the diagonal
  * sums, the pivots, the elimination and the running recurrences are carried
  * in float64 (for large lambda*w, where float32 pivots lose digits to
- * cancellation).  Loads and stores stay float32 in both modes. */
+ * cancellation).  Loads and stores stay float32 in both modes.
+ * FP32_DELTA (r = 1 only, sgwls_filter / sgwls_interpolate only): float32
+ * throughout, each strip's tridiagonal system solved serially by the banded
+ * LDL^T of Sec. 2.2 with every pivot carried as its excess over the coupling
+ * still to be eliminated, delta_{p+1} = 1 + lambda w_p delta_p / alpha_p,
+ * alpha_p = delta_p + lambda w_p, which adds positive terms only (no
+ * cancellation).  One thread per strip: a precision reference, several
+ * times slower than the other modes.  Any other entry point, r != 1, and a
+ * non-NULL `saved` return SGWLS_E_UNSUPPORTED. */
 typedef enum {
   SGWLS_P_FP32 = 0,
-  SGWLS_P_FP64_PIVOT = 1
+  SGWLS_P_FP64_PIVOT = 1,
+  SGWLS_P_FP32_DELTA = 2
 } sgwls_precision;
 
 /* Filter parameters.  lambda: Eq. (1).  r: the neighbourhood is
@@ -104,7 +113,9 @@ sgwls_status sgwls_validate(int C, int M, int N, const sgwls_params* p);
  * sgwls_backward for one C x M x N image with parameters p; 0 if the
  * request is invalid.  save_for_backward is accepted for symmetry and does
  * not change the size (the saved pass inputs live in the caller's `saved`
- * buffer).  Makes no HIP call. */
+ * buffer).  For SGWLS_P_FP32_DELTA it is sgwls_filter's workspace in that
+ * mode (one image plus the eliminated strips of four channels).  Makes no
+ * HIP call. */
 size_t sgwls_workspace_bytes(int C, int M, int N, const sgwls_params* p);
 
 /* One pass of Sec. 2.3 (steps 1-4) on a C x M x N image: direction 0 is

@@ -21,6 +21,7 @@
 using namespace sgwls;
 
 namespace {
+sgwls_status validate_partitioned(int C, int M, int N, const sgwls_params* p);
 
 constexpr int kVersion = 201;          // 0.2.1
 constexpr int kMaxSide = 1 << 16;       // M, N limit (chunk grid dimension)
@@ -245,7 +246,7 @@ sgwls_status batch_plan(const sgwls_image* imgs, const sgwls_params* p, int B, i
   const sgwls_params& p0 = p[0];
   for (int b = 0; b < B; ++b) {
     const sgwls_image& im = imgs[b];
-    const sgwls_status st = sgwls_validate(im.C, im.M, im.N, &p[b]);
+    const sgwls_status st = validate_partitioned(im.C, im.M, im.N, &p[b]);
     if (st != SGWLS_OK) return st;
     if (p[b].iters != p0.iters || p[b].kind != p0.kind || p[b].prec != p0.prec) return SGWLS_E_ARG;
     if (p[b].stride != 1 || p[b].r > kBatchMaxR) return SGWLS_E_UNSUPPORTED;
@@ -510,16 +511,46 @@ sgwls_status sgwls_validate(int C, int M, int N, const sgwls_params* p) {
   } else {
     return SGWLS_E_ARG;
   }
-  if (p->prec != SGWLS_P_FP32 && p->prec != SGWLS_P_FP64_PIVOT) return SGWLS_E_ARG;
+  if (p->prec != SGWLS_P_FP32 && p->prec != SGWLS_P_FP64_PIVOT && p->prec != SGWLS_P_FP32_DELTA)
+    return SGWLS_E_ARG;
   if (C < 1 || M < 2 * p->r + 1 || N < 2 * p->r + 1) return SGWLS_E_SHAPE;
   // kernels address pixels with 32-bit element offsets
   if (M > kMaxSide || N > kMaxSide || (long long)C * M * N > 0x7fffffffLL) return SGWLS_E_SHAPE;
   if (p->r > kMaxR) return SGWLS_E_UNSUPPORTED;
+  if (p->prec == SGWLS_P_FP32_DELTA && p->r != 1) return SGWLS_E_UNSUPPORTED;
   return SGWLS_OK;
 }
 
+namespace {
+// Validation for the entry points of the partitioned kernels, which take the
+// precision as their float64 switch: the serial-strip mode is filter only.
+sgwls_status validate_partitioned(int C, int M, int N, const sgwls_params* p) {
+  const sgwls_status st = sgwls_validate(C, M, N, p);
+  if (st != SGWLS_OK) return st;
+  return p->prec == SGWLS_P_FP32_DELTA ? SGWLS_E_UNSUPPORTED : SGWLS_OK;
+}
+
+// Geometry of a pass of the serial-strip mode: column pass (direction 0) or
+// row pass over the M x N image, in place (no transposed frames).
+PassGeom delta_geom(int direction, int M, int N, int stride) {
+  PassGeom geo{};
+  geo.L = direction == 0 ? M : N;
+  geo.W = direction == 0 ? N : M;
+  geo.sa = direction == 0 ? N : 1;
+  geo.sb = direction == 0 ? 1 : N;
+  geo.plane = (long long)M * N;
+  geo.nK = strip_count(geo.W, 1, stride);
+  geo.stride = stride;
+  geo.R = geo.L;
+  geo.P = 1;
+  geo.out_t = 0;
+  return geo;
+}
+}  // namespace
+
 size_t sgwls_workspace_bytes(int C, int M, int N, const sgwls_params* p) {
   if (sgwls_validate(C, M, N, p) != SGWLS_OK) return 0;
+  if (p->prec == SGWLS_P_FP32_DELTA) return image_bytes(C, M, N) + delta_buffer_bytes(C, M, N, p->stride);
   return image_bytes(C, M, N) + image_bytes(1, M, N) + iface_bytes_all(C, M, N, *p);
 }
 
@@ -527,7 +558,7 @@ sgwls_status sgwls_pass_stages(int stages, int direction, const float* x, const 
                                float* y, int C, int M, int N, const sgwls_params* p,
                                const float* lambda_dev, void* ws, size_t ws_bytes,
                                void* stream) {
-  sgwls_status st = sgwls_validate(C, M, N, p);
+  sgwls_status st = validate_partitioned(C, M, N, p);
   if (st != SGWLS_OK) return st;
   if (direction != 0 && direction != 1) return SGWLS_E_ARG;
   if ((stages & kStageAll) == 0 || stages > (kStageAll | kStageTransposeOut)) return SGWLS_E_ARG;
@@ -554,6 +585,26 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u, int C, int M
   sgwls_status st = sgwls_validate(C, M, N, p);
   if (st != SGWLS_OK) return st;
   if (!f || !g || !u || (const float*)u == g) return SGWLS_E_ARG;
+  if (p->prec == SGWLS_P_FP32_DELTA) {
+    // Serial-strip solves: no saved pass inputs (there is no backward in
+    // this mode); passes ping-pong between tmp and u, the last one into u.
+    if (saved) return SGWLS_E_UNSUPPORTED;
+    const size_t img = image_bytes(C, M, N);
+    if (!ws || ws_bytes < img + delta_buffer_bytes(C, M, N, p->stride)) return SGWLS_E_WORKSPACE;
+    float* tmp = reinterpret_cast<float*>(ws);
+    float* buf = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + img);
+    const WeightParams wp = weight_params(*p);
+    const int passes = 2 * p->iters;
+    const float* x = f;
+    for (int q = 0; q < passes; ++q) {
+      float* y = q == passes - 1 ? u : ((passes - q) % 2 == 0) ? tmp : u;
+      if (launch_delta_pass(x, g, y, C, delta_geom(q % 2, M, N, p->stride), wp, lambda_dev,
+                            p->lambda, buf, (hipStream_t)stream) != hipSuccess)
+        return SGWLS_E_HIP;
+      x = y;
+    }
+    return SGWLS_OK;
+  }
   const size_t img = image_bytes(C, M, N), gimg = image_bytes(1, M, N);
   const size_t need = img + gimg + iface_bytes_all(C, M, N, *p);
   if (!ws || ws_bytes < need) return SGWLS_E_WORKSPACE;
@@ -614,7 +665,7 @@ int sgwls_variant_count(int r, int channel_block, int prec) {
 
 sgwls_status sgwls_tune_pin(int direction, int channel_block, int M, int N,
                             const sgwls_params* p, int variant) {
-  sgwls_status st = sgwls_validate(channel_block, M, N, p);
+  sgwls_status st = validate_partitioned(channel_block, M, N, p);
   if (st != SGWLS_OK) return st;
   if (direction != 0 && direction != 1) return SGWLS_E_ARG;
   if (channel_block != 1 && channel_block != 3) return SGWLS_E_ARG;
@@ -644,7 +695,7 @@ int sgwls_tune_size(void) {
 sgwls_status sgwls_autotune(const float* x, const float* g, float* y, int C, int M, int N,
                             const sgwls_params* p, void* ws, size_t ws_bytes, void* stream,
                             int reps, int* chosen) {
-  sgwls_status st = sgwls_validate(C, M, N, p);
+  sgwls_status st = validate_partitioned(C, M, N, p);
   if (st != SGWLS_OK) return st;
   if (!x || !g || !y || y == x || (const float*)y == g || reps < 1) return SGWLS_E_ARG;
   const size_t need = std::max(pass_iface_bytes(0, C, M, N, *p), pass_iface_bytes(1, C, M, N, *p));
@@ -767,7 +818,7 @@ sgwls_status sgwls_tune_load(const char* path, const char* arch) {
 }
 
 size_t sgwls_backward_workspace_bytes(int C, int M, int N, const sgwls_params* p) {
-  if (sgwls_validate(C, M, N, p) != SGWLS_OK) return 0;
+  if (validate_partitioned(C, M, N, p) != SGWLS_OK) return 0;
   return bwd_layout(C, M, N, *p).total;
 }
 
@@ -776,7 +827,7 @@ sgwls_status sgwls_pass_backward(int direction, const float* x, const float* g,
                                  double* grad_lambda, int C, int M, int N,
                                  const sgwls_params* p, const float* lambda_dev, void* ws,
                                  size_t ws_bytes, void* stream) {
-  sgwls_status st = sgwls_validate(C, M, N, p);
+  sgwls_status st = validate_partitioned(C, M, N, p);
   if (st != SGWLS_OK) return st;
   if (direction != 0 && direction != 1) return SGWLS_E_ARG;
   if (!x || !g || !ybar || !xbar || xbar == x || xbar == ybar || (const float*)xbar == g)
@@ -795,7 +846,7 @@ sgwls_status sgwls_backward(const float* g, const float* saved, const float* gra
                             float* grad_f, float* grad_g, double* grad_lambda, int C, int M,
                             int N, const sgwls_params* p, const float* lambda_dev, void* ws,
                             size_t ws_bytes, void* stream) {
-  sgwls_status st = sgwls_validate(C, M, N, p);
+  sgwls_status st = validate_partitioned(C, M, N, p);
   if (st != SGWLS_OK) return st;
   if (!g || !saved || !grad_u || !grad_f || (const float*)grad_f == g ||
       (const float*)grad_f == saved)

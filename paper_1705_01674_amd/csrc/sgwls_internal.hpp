@@ -117,6 +117,16 @@ struct PassPlan {
   int acc_bytes;    // 4 (float) or 8 (double) interface element size
 };
 
+// Cancellation-free float32 mode at r = 1 (sgwls_delta.hip): one serial
+// solve per strip with pivots carried as their excess over the remaining
+// coupling, channels in groups of kDeltaGroup.  The buffer holds one group's
+// eliminated strips of the larger pass direction.
+constexpr int kDeltaGroup = 4;
+size_t delta_buffer_bytes(int C, int M, int N, int stride);
+hipError_t launch_delta_pass(const float* x, const float* g, float* y, int C,
+                             const PassGeom& geo, const WeightParams& wp, const float* lam_dev,
+                             float lam_host, float* buf, hipStream_t s);
+
 // Host-side planning (sgwls_plan.cpp).
 int strip_count(int W, int r, int stride);
 PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64, int variant,

@@ -246,8 +246,19 @@ using namespace sgwls;
 
 extern "C" {
 
+namespace {
+// The 2D model uses lambda, r and the weights only: the precision field is
+// not validated against r.
+sgwls_status validate_model(int C, int M, int N, const sgwls_params* p) {
+  if (!p) return SGWLS_E_ARG;
+  sgwls_params q = *p;
+  q.prec = SGWLS_P_FP32;
+  return sgwls_validate(C, M, N, &q);
+}
+}  // namespace
+
 size_t sgwls_wls2d_workspace_bytes(int C, int M, int N, const sgwls_params* p) {
-  if (C < 1 || C > kCgMaxC || sgwls_validate(C, M, N, p) != SGWLS_OK) return 0;
+  if (C < 1 || C > kCgMaxC || validate_model(C, M, N, p) != SGWLS_OK) return 0;
   return cg_layout(C, M, N).total;
 }
 
@@ -255,7 +266,7 @@ sgwls_status sgwls_wls2d(const float* f, const float* g, float* u, int C, int M,
                          const sgwls_params* p, int max_iters, double tol, int* iters_done,
                          double* rel_residual, void* ws, size_t ws_bytes, void* stream) {
   if (C < 1 || C > kCgMaxC) return SGWLS_E_ARG;
-  sgwls_status st = sgwls_validate(C, M, N, p);
+  sgwls_status st = validate_model(C, M, N, p);
   if (st != SGWLS_OK) return st;
   if (!f || !g || !u || (const float*)u == g || max_iters < 1 || !(tol >= 0.0))
     return SGWLS_E_ARG;

@@ -18,7 +18,7 @@ import torch
 from . import _native as nat
 
 _KIND = {"exp": 0, "frac": 1}
-_PREC = {"fp32": 0, "fp64_pivot": 1}
+_PREC = {"fp32": 0, "fp64_pivot": 1, "fp32_delta": 2}
 
 
 @dataclass(frozen=True)

@@ -49,7 +49,8 @@ def P(nat, **kw):
     (dict(r=2, stride=5), 0), (dict(lam=-1.0), 1), (dict(lam=float("nan")), 1),
     (dict(lam=float("inf")), 1), (dict(sigma_s=0.0), 1), (dict(sigma_r=-1.0), 1),
     (dict(kind=1, eps=0.0), 1), (dict(kind=1, alpha_r=-0.5), 1), (dict(kind=1, sigma_r=0.0), 0),
-    (dict(kind=2), 1), (dict(prec=2), 1), (dict(prec=1), 0), (dict(r=5), 4), (dict(r=4), 0),
+    (dict(kind=2), 1), (dict(prec=3), 1), (dict(prec=1), 0), (dict(r=5), 4), (dict(r=4), 0),
+    (dict(prec=2), 0), (dict(prec=2, stride=3), 0), (dict(prec=2, r=2), 4),
 ])
 def test_validate_parameters(nat, kw, code):
     assert nat.lib.sgwls_validate(3, 64, 64, ctypes.byref(P(nat, **kw))) == code
@@ -256,3 +257,25 @@ def test_wls2d_workspace_and_error_paths(nat):
     assert call(f, g, u, 1, 64, 64, pp, 10, float("nan")) == 1
     assert call(f, g, u, 5, 64, 64, pp, 10, 1e-6) == 1
     assert lib.sgwls_wls2d(f, g, u, 1, 64, 64, pp, 10, 1e-6, None, None, ws, 8, None) == 3
+
+
+def test_delta_mode_is_filter_only(nat):
+    # The serial-strip float32 mode (r = 1) is accepted by the filter's
+    # validation and sized by sgwls_workspace_bytes, and every entry point of
+    # the partitioned kernels refuses it before touching a pointer or the GPU.
+    p = P(nat, prec=2)
+    C, M, N = 3, 40, 56
+    strips = max((N - 2) * 3 * M, (M - 2) * 3 * N)     # stride 1: W - 2 strips of 3L elements
+    want = 4 * C * M * N + 4 * (C + 1) * strips
+    assert nat.lib.sgwls_workspace_bytes(C, M, N, ctypes.byref(p)) == want
+    assert nat.lib.sgwls_workspace_bytes(C, M, N, ctypes.byref(P(nat, prec=2, r=2))) == 0
+    assert nat.lib.sgwls_backward_workspace_bytes(C, M, N, ctypes.byref(p)) == 0
+    assert nat.lib.sgwls_pass(0, None, None, None, C, M, N, ctypes.byref(p), None, None, 0,
+                              None) == 4
+    assert nat.lib.sgwls_pass_stages(7, 0, None, None, None, C, M, N, ctypes.byref(p), None, None,
+                                     0, None) == 4
+    assert nat.lib.sgwls_tune_pin(0, 3, M, N, ctypes.byref(p), 0) == 4
+    assert nat.lib.sgwls_backward(None, None, None, None, None, None, C, M, N, ctypes.byref(p),
+                                  None, None, 0, None) == 4
+    # the 2D model ignores the precision field
+    assert nat.lib.sgwls_wls2d_workspace_bytes(C, M, N, ctypes.byref(P(nat, prec=2, r=2))) > 0

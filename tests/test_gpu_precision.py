@@ -2,13 +2,16 @@
 omega^frac (Eq. 2) makes lambda * omega largest: detail enhancement (r = 1,
 alpha_s = alpha_r = 1.2, epsilon = 1e-4, lambda = 900) and the three HDR
 detail layers (lambda = 5 / 40 / 320 on log luminance).  Float32 pivots
-against FP64 pivots, both against the FP64 oracle.
+against FP64 pivots and, at r = 1, against the cancellation-free float32
+pivots (each pivot carried as its excess over the remaining coupling), all
+against the FP64 oracle.
 
 Where the guidance is flat, omega^frac reaches about 1/epsilon = 1e4, so
 the pivots are 1 + lambda*sum(omega) with lambda*omega up to 9e6: the 1
 that decides the solution along a flat run is about one float32 ulp of the
-pivot, and the recurrences cancel the rest.  The FP64 pivot mode is held to
-1e-5 (normwise max, as everywhere); float32 is reported, with only a
+pivot, and the recurrences cancel the rest.  The FP64 pivot mode and the
+float32 excess-pivot mode are held to 1e-5 (normwise max, as everywhere);
+plain float32 is reported, with only a
 finiteness check.  Guidance scales: 0..1 (the
 synthetic images), 0..255 (8-bit, as the sparse workloads) and natural-log
 luminance for HDR.
@@ -56,10 +59,17 @@ def case(ops, name, f, g, pd):
     e64, m64 = errors(run(ops, f, g, pd, "fp64_pivot"), ref)
     u32 = run(ops, f, g, pd, "fp32")
     e32, m32 = errors(u32, ref)
-    print(f"[precision] {name}: fp32 max {e32:.3e} mean {m32:.3e} | fp64 pivots max {e64:.3e} "
-          f"mean {m64:.3e}", flush=True)
+    line = (f"[precision] {name}: fp32 max {e32:.3e} mean {m32:.3e} | fp64 pivots max {e64:.3e} "
+            f"mean {m64:.3e}")
+    ed = None
+    if pd["r"] == 1:   # the cancellation-free float32 pivots exist for r = 1
+        ed, md = errors(run(ops, f, g, pd, "fp32_delta"), ref)
+        line += f" | fp32 delta pivots max {ed:.3e} mean {md:.3e}"
+    print(line, flush=True)
     assert np.isfinite(u32).all(), name
     assert e64 <= TOL64, f"{name}: fp64 pivots {e64:.3e}"
+    if ed is not None:
+        assert ed <= TOL64, f"{name}: fp32 delta pivots {ed:.3e}"
 
 
 @pytest.mark.parametrize("scale", [1.0, 255.0])
