@@ -99,3 +99,25 @@ def test_delta_refusals(ops):
     saved = torch.empty(4, 3, 16, 20, device="cuda")
     with pytest.raises(nat.SgwlsError):
         ops.sgwls_filter(f, g, ops.Params(**params(), prec="fp32_delta"), saved=saved)
+
+
+def test_delta_sparse_interpolation(ops):
+    # Eq. (21) at r = 1 in this mode (the one filter call over the stacked
+    # planes runs serial strips): against the oracle's S(F) / S(H) where the
+    # oracle denominator is at least 1e-3.
+    w = synth.depth_upsample(72, 96, 4, seed=3400)
+    pd = {**w.params, "r": 1, "stride": 1, "sigma_s": 1.0, "lam": 50.0}
+    P = oracle.OracleParams(**pd)
+    g64 = w.g.astype(np.float64)
+    num = oracle.filter(w.f.astype(np.float64), g64, P)
+    den = oracle.filter(w.h.astype(np.float64)[None], g64, P)[0]
+    mask = den >= 1e-3
+    want = num[:, mask] / den[mask]
+    p = ops.Params(**pd, prec="fp32_delta")
+    print(f"[delta] interpolation {w.f.shape} {pd}", flush=True)
+    u = ops.sgwls_interpolate(torch.from_numpy(w.f).cuda(), torch.from_numpy(w.h).cuda(),
+                              torch.from_numpy(w.g).cuda(), p)
+    torch.cuda.synchronize()
+    got = u.cpu().numpy().astype(np.float64)[:, mask]
+    assert mask.mean() > 0.9
+    assert rel(got, want) <= 1e-4
