@@ -109,6 +109,17 @@ def test_long_lines_use_the_long_run_solver(ops, r, C):
         check(f"long lines {M}x{N} r{r} C{C}", run_filter(ops, f, g, pd), oracle_filter(f, g, pd))
 
 
+@pytest.mark.parametrize("r,M,N", [(1, 65536, 5), (1, 5, 65536), (2, 65536, 7)])
+def test_maximum_side(ops, r, M, N):
+    # the longest lines the library accepts (65536 pixels): the column or row
+    # subsystems have (2r+1) * 65536 elements, solved by the long-run solver
+    rng = np.random.default_rng(M + 7 * N + r)
+    f = rng.uniform(0, 1, (1, M, N)).astype(np.float32)
+    g = rng.uniform(0, 1, (M, N)).astype(np.float32)
+    pd = pdict(lam=5.0, r=r, iters=1, sigma_r=0.2)
+    check(f"maximum side {M}x{N} r{r}", run_filter(ops, f, g, pd), oracle_filter(f, g, pd))
+
+
 @pytest.mark.parametrize("shape", [(3, 3), (3, 4), (4, 3), (5, 200), (200, 5), (7, 7), (2, 9, 9),
                                    (4, 33, 65), (5, 31, 17), (1, 130, 3)])
 @pytest.mark.parametrize("r", [1, 2])
