@@ -29,8 +29,21 @@ __global__ __launch_bounds__(kFixThreads) void k_bwd_fixup(const float* __restri
     return;
   }
   __shared__ double red[kFixThreads];
+  // Each thread sums partials threadIdx.x, + kFixThreads, ... in that order;
+  // kLoads of them are loaded before they are added, so that one memory
+  // latency covers the batch.
+  constexpr int kLoads = 16;
   double s = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += kFixThreads) s += lpart[i];
+  for (int i0 = threadIdx.x; i0 < nparts; i0 += kFixThreads * kLoads) {
+    double v[kLoads];
+#pragma unroll
+    for (int u = 0; u < kLoads; ++u) {
+      const int i = i0 + u * kFixThreads;
+      v[u] = i < nparts ? lpart[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kLoads; ++u) s += v[u];
+  }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int st = kFixThreads / 2; st > 0; st >>= 1) {
