@@ -2,8 +2,8 @@
 FP64 on the CPU.
 
 TEST INFRASTRUCTURE ONLY: the correctness reference for the GPU conjugate-
-gradient solver of the same model; only ``tests/`` and ``bench.py``'s
-reference legs may import it.  It shares no code with the GPU library.
+gradient solver of the same model; only ``tests/`` imports it.  It shares no
+code with the GPU library.
 
 Model: U minimises sum_i (u_i - f_i)^2 + lambda * sum over unordered pixel
 pairs {i, j} with j in the (2r+1) x (2r+1) patch around i of
