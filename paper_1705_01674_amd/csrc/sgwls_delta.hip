@@ -27,7 +27,11 @@
 namespace sgwls {
 namespace {
 
-constexpr int kDeltaBatch = 12;   // snake elements (four rows) loaded together
+// Values (guidance plus channels, or ratio plus channels) a thread loads per
+// batch of snake elements: one batch is in flight while the previous one is
+// eliminated, and a thread has a SIMD to itself (a pass has one thread per
+// strip), so the batch is as large as the registers allow.
+constexpr int kDeltaValues = 160;
 
 // Pixel offset of snake element p of the strip centred at k (r = 1).
 DEV long long delta_pixel(const PassGeom& geo, int k, int p) {
@@ -48,7 +52,7 @@ __global__ __launch_bounds__(kWave) void k_delta_solve(const float* __restrict__
   const float lamS = load_lambda(lam_dev, lam_host) * wp.spatial[1];
   const int s = 3 * geo.L;
   const size_t nK = geo.nK;
-  constexpr int D = kDeltaBatch, NV = NC + 1;
+  constexpr int NV = NC + 1, D = kDeltaValues / NV;
   const float* Xc = X + (size_t)c0 * geo.plane;
   auto slot = [&](int p, int v) -> float& { return buf[((size_t)p * NV + v) * nK + ki]; };
 
