@@ -550,7 +550,8 @@ PassGeom delta_geom(int direction, int M, int N, int stride) {
 
 size_t sgwls_workspace_bytes(int C, int M, int N, const sgwls_params* p) {
   if (sgwls_validate(C, M, N, p) != SGWLS_OK) return 0;
-  if (p->prec == SGWLS_P_FP32_DELTA) return image_bytes(C, M, N) + delta_buffer_bytes(C, M, N, p->stride);
+  if (p->prec == SGWLS_P_FP32_DELTA)   // + slack to align the strip buffer
+    return image_bytes(C, M, N) + delta_buffer_bytes(C, M, N, p->stride) + kAlign;
   return image_bytes(C, M, N) + image_bytes(1, M, N) + iface_bytes_all(C, M, N, *p);
 }
 
@@ -590,9 +591,12 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u, int C, int M
     // this mode); passes ping-pong between tmp and u, the last one into u.
     if (saved) return SGWLS_E_UNSUPPORTED;
     const size_t img = image_bytes(C, M, N);
-    if (!ws || ws_bytes < img + delta_buffer_bytes(C, M, N, p->stride)) return SGWLS_E_WORKSPACE;
+    if (!ws || ws_bytes < img + delta_buffer_bytes(C, M, N, p->stride) + kAlign)
+      return SGWLS_E_WORKSPACE;
     float* tmp = reinterpret_cast<float*>(ws);
-    float* buf = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + img);
+    // the strip buffer holds 16-byte records: start it on an aligned address
+    const uintptr_t b0 = reinterpret_cast<uintptr_t>(ws) + img;
+    float* buf = reinterpret_cast<float*>((b0 + kAlign - 1) / kAlign * kAlign);
     const WeightParams wp = weight_params(*p);
     const int passes = 2 * p->iters;
     const float* x = f;

@@ -18,14 +18,21 @@
 // The mode solves every strip serially, one thread per strip, as the paper
 // does: it is a precision reference for float32 arithmetic, not a fast path
 // (the partitioned kernels do not use it).  Thread ki keeps its strip's
-// elimination in a buffer laid out strip-minor (element p, value v of strip
-// ki at buf[(p * (NC + 1) + v) * nK + ki], v = 0 the ratio c_p / alpha_p,
-// v = 1.. the channels), so that the threads of a wave touch consecutive
-// words.  A second kernel averages the strips covering each pixel (Sec. 2.3).
+// elimination in a buffer of one 16-byte record per element (two for four
+// channels): element p of strip ki at buf[(p * nK + ki) * NVP + v], v = 0
+// the ratio c_p / alpha_p, v = 1.. the channels, so that each element costs
+// one vector store forward and one load and one store back, and the threads
+// of a wave touch consecutive records.  A second kernel averages the strips
+// covering each pixel (Sec. 2.3).
 #include "sgwls_device.hpp"
 
 namespace sgwls {
 namespace {
+
+// Floats per element record of the strip buffer (NC channels + the ratio,
+// padded to whole 16-byte words).
+template <int NC>
+constexpr int delta_record() { return NC + 1 <= 4 ? 4 : 8; }
 
 // Values (guidance plus channels, or ratio plus channels) a thread loads per
 // batch of snake elements: one batch is in flight while the previous one is
@@ -52,26 +59,49 @@ __global__ __launch_bounds__(kWave) void k_delta_solve(const float* __restrict__
   const float lamS = load_lambda(lam_dev, lam_host) * wp.spatial[1];
   const int s = 3 * geo.L;
   const size_t nK = geo.nK;
-  constexpr int NV = NC + 1, D = kDeltaValues / NV;
+  constexpr int NV = NC + 1, D = kDeltaValues / NV, NVP = delta_record<NC>();
   const float* Xc = X + (size_t)c0 * geo.plane;
-  auto slot = [&](int p, int v) -> float& { return buf[((size_t)p * NV + v) * nK + ki]; };
+  auto rec = [&](int p) -> float4* {
+    return reinterpret_cast<float4*>(buf + ((size_t)p * nK + ki) * NVP);
+  };
+  // record p <- (ratio, values[0..NC)), zero-padded
+  auto put = [&](int p, float ratio, const float (&vals)[NC]) {
+    float w[NVP] = {};
+    w[0] = ratio;
+#pragma unroll
+    for (int h = 0; h < NC; ++h) w[1 + h] = vals[h];
+    float4* d = rec(p);
+#pragma unroll
+    for (int q = 0; q < NVP / 4; ++q) d[q] = make_float4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+  };
+  auto get = [&](int p, float& ratio, float (&vals)[NC]) {
+    float w[NVP];
+    const float4* d = rec(p);
+#pragma unroll
+    for (int q = 0; q < NVP / 4; ++q) {
+      const float4 t = d[q];
+      w[4 * q] = t.x;
+      w[4 * q + 1] = t.y;
+      w[4 * q + 2] = t.z;
+      w[4 * q + 3] = t.w;
+    }
+    ratio = w[0];
+#pragma unroll
+    for (int h = 0; h < NC; ++h) vals[h] = w[1 + h];
+  };
 
-  // forward elimination, the loads of the next batch in flight meanwhile
+  // Forward elimination, the loads of the next batch in flight meanwhile.
+  // Loads past the end read the last element (clamped index, no branch) and
+  // the arithmetic runs unconditionally, so that no load is sunk into a
+  // per-element branch next to its use; only the stores are guarded.
   float gc[D], fc[D][NC], gn[D] = {}, fn[D][NC] = {};
   auto load = [&](int p0, float (&gg)[D], float (&ff)[D][NC]) {
 #pragma unroll
     for (int e = 0; e < D; ++e) {
-      const int p = p0 + e;
-      if (p < s) {
-        const long long o = delta_pixel(geo, k, p);
-        gg[e] = G[o];
+      const long long o = delta_pixel(geo, k, min(p0 + e, s - 1));
+      gg[e] = G[o];
 #pragma unroll
-        for (int h = 0; h < NC; ++h) ff[e][h] = Xc[(size_t)h * geo.plane + o];
-      } else {
-        gg[e] = 0.0f;
-#pragma unroll
-        for (int h = 0; h < NC; ++h) ff[e][h] = 0.0f;
-      }
+      for (int h = 0; h < NC; ++h) ff[e][h] = Xc[(size_t)h * geo.plane + o];
     }
   };
   load(0, gc, fc);
@@ -84,21 +114,20 @@ __global__ __launch_bounds__(kWave) void k_delta_solve(const float* __restrict__
 #pragma unroll
     for (int e = 0; e < D; ++e) {
       const int p = p0 + e;
-      if (p < s) {
-        const float gnext = e + 1 < D ? gc[e + 1 < D ? e + 1 : 0] : gn[0];   // next batch's first
-        const float c = p + 1 < s ? lamS * range_weight<KIND>(gnext - gc[e], wp) : 0.0f;
-        const float alpha = delta + c;
-        const float inv = 1.0f / alpha;
-        const float ratio = c * inv;
+      const float gnext = e + 1 < D ? gc[e + 1 < D ? e + 1 : 0] : gn[0];   // next batch's first
+      const float c = p + 1 < s ? lamS * range_weight<KIND>(gnext - gc[e], wp) : 0.0f;
+      const float alpha = delta + c;
+      const float inv = 1.0f / alpha;
+      const float ratio = c * inv;
+      float zs[NC];
 #pragma unroll
-        for (int h = 0; h < NC; ++h) {
-          z[h] = fc[e][h] + ratio_prev * z[h];
-          slot(p, 1 + h) = z[h] * inv;
-        }
-        slot(p, 0) = ratio;
-        delta = 1.0f + c * (delta * inv);
-        ratio_prev = ratio;
+      for (int h = 0; h < NC; ++h) {
+        z[h] = fc[e][h] + ratio_prev * z[h];
+        zs[h] = z[h] * inv;
       }
+      if (p < s) put(p, ratio, zs);
+      delta = 1.0f + c * (delta * inv);
+      ratio_prev = ratio;
     }
 #pragma unroll
     for (int e = 0; e < D; ++e) {
@@ -116,18 +145,7 @@ __global__ __launch_bounds__(kWave) void k_delta_solve(const float* __restrict__
   float rc[D], zc[D][NC], rn[D] = {}, zn[D][NC] = {};
   auto load_back = [&](int b, float (&rr)[D], float (&zz)[D][NC]) {
 #pragma unroll
-    for (int e = 0; e < D; ++e) {
-      const int p = b * D + e;
-      if (p < s) {
-        rr[e] = slot(p, 0);
-#pragma unroll
-        for (int h = 0; h < NC; ++h) zz[e][h] = slot(p, 1 + h);
-      } else {
-        rr[e] = 0.0f;
-#pragma unroll
-        for (int h = 0; h < NC; ++h) zz[e][h] = 0.0f;
-      }
-    }
+    for (int e = 0; e < D; ++e) get(min(b * D + e, s - 1), rr[e], zz[e]);
   };
   load_back(nb - 1, rc, zc);
   for (int b = nb - 1; b >= 0; --b) {
@@ -135,13 +153,11 @@ __global__ __launch_bounds__(kWave) void k_delta_solve(const float* __restrict__
 #pragma unroll
     for (int e = D - 1; e >= 0; --e) {
       const int p = b * D + e;
-      if (p < s) {
+      // elements past the end (the last batch's tail) leave u at 0
+      const bool live = p < s;
 #pragma unroll
-        for (int h = 0; h < NC; ++h) {
-          u[h] = zc[e][h] + rc[e] * u[h];
-          slot(p, 1 + h) = u[h];
-        }
-      }
+      for (int h = 0; h < NC; ++h) u[h] = live ? zc[e][h] + rc[e] * u[h] : 0.0f;
+      if (live) put(p, rc[e], u);
     }
 #pragma unroll
     for (int e = 0; e < D; ++e) {
@@ -163,7 +179,7 @@ __global__ __launch_bounds__(256) void k_delta_average(const float* __restrict__
   const int a = (int)(idx / geo.W), b = (int)(idx - (long long)a * geo.W);
   const int t = geo.stride, last = geo.nK - 1;
   const size_t nK = geo.nK;
-  constexpr int NV = NC + 1;
+  constexpr int NVP = delta_record<NC>();
   float acc[NC];
 #pragma unroll
   for (int h = 0; h < NC; ++h) acc[h] = 0.0f;
@@ -174,7 +190,7 @@ __global__ __launch_bounds__(256) void k_delta_average(const float* __restrict__
     const int q = (a & 1) ? k + 1 - b : b - (k - 1);
     const int p = 3 * a + q;
 #pragma unroll
-    for (int h = 0; h < NC; ++h) acc[h] += buf[((size_t)p * NV + 1 + h) * nK + ki];
+    for (int h = 0; h < NC; ++h) acc[h] += buf[((size_t)p * nK + ki) * NVP + 1 + h];
     ++cnt;
   };
   // regular centres 1 + ki t in [b - 1, b + 1], then the appended last one
@@ -207,7 +223,7 @@ hipError_t delta_group(const float* x, const float* g, float* y, int c0, const P
 }  // namespace
 
 size_t delta_buffer_bytes(int C, int M, int N, int stride) {
-  const size_t nv = (size_t)std::min(C, kDeltaGroup) + 1;
+  const size_t nv = std::min(C, kDeltaGroup) + 1 <= 4 ? 4 : 8;   // record floats (delta_record)
   const size_t col = (size_t)strip_count(N, 1, stride) * 3 * M;
   const size_t row = (size_t)strip_count(M, 1, stride) * 3 * N;
   return sizeof(float) * nv * std::max(col, row);
