@@ -530,20 +530,21 @@ sgwls_status validate_partitioned(int C, int M, int N, const sgwls_params* p) {
   return p->prec == SGWLS_P_FP32_DELTA ? SGWLS_E_UNSUPPORTED : SGWLS_OK;
 }
 
-// Geometry of a pass of the serial-strip mode: column pass (direction 0) or
-// row pass over the M x N image, in place (no transposed frames).
-PassGeom delta_geom(int direction, int M, int N, int stride) {
+// Geometry of a pass of the serial-strip mode: a column pass over an L x W
+// image (the image for even passes, its transpose for odd ones) that stores
+// its output transposed, so every pass reads along rows.
+PassGeom delta_geom(int L, int W, int stride) {
   PassGeom geo{};
-  geo.L = direction == 0 ? M : N;
-  geo.W = direction == 0 ? N : M;
-  geo.sa = direction == 0 ? N : 1;
-  geo.sb = direction == 0 ? 1 : N;
-  geo.plane = (long long)M * N;
-  geo.nK = strip_count(geo.W, 1, stride);
+  geo.L = L;
+  geo.W = W;
+  geo.sa = W;
+  geo.sb = 1;
+  geo.plane = (long long)L * W;
+  geo.nK = strip_count(W, 1, stride);
   geo.stride = stride;
-  geo.R = geo.L;
+  geo.R = L;
   geo.P = 1;
-  geo.out_t = 0;
+  geo.out_t = 1;
   return geo;
 }
 }  // namespace
@@ -551,7 +552,8 @@ PassGeom delta_geom(int direction, int M, int N, int stride) {
 size_t sgwls_workspace_bytes(int C, int M, int N, const sgwls_params* p) {
   if (sgwls_validate(C, M, N, p) != SGWLS_OK) return 0;
   if (p->prec == SGWLS_P_FP32_DELTA)   // + slack to align the strip buffer
-    return image_bytes(C, M, N) + delta_buffer_bytes(C, M, N, p->stride) + kAlign;
+    return image_bytes(C, M, N) + image_bytes(1, M, N) + delta_buffer_bytes(C, M, N, p->stride) +
+           kAlign;
   return image_bytes(C, M, N) + image_bytes(1, M, N) + iface_bytes_all(C, M, N, *p);
 }
 
@@ -588,22 +590,29 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u, int C, int M
   if (!f || !g || !u || (const float*)u == g) return SGWLS_E_ARG;
   if (p->prec == SGWLS_P_FP32_DELTA) {
     // Serial-strip solves: no saved pass inputs (there is no backward in
-    // this mode); passes ping-pong between tmp and u, the last one into u.
+    // this mode).  As for the partitioned kernels, every pass is a column
+    // pass storing transposed: pass 2t reads the image (guidance g) and
+    // writes tmp (N x M), pass 2t+1 reads tmp (guidance g^T) and writes u.
     if (saved) return SGWLS_E_UNSUPPORTED;
-    const size_t img = image_bytes(C, M, N);
-    if (!ws || ws_bytes < img + delta_buffer_bytes(C, M, N, p->stride) + kAlign)
+    const size_t img = image_bytes(C, M, N), gimg = image_bytes(1, M, N);
+    if (!ws || ws_bytes < img + gimg + delta_buffer_bytes(C, M, N, p->stride) + kAlign)
       return SGWLS_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
     float* tmp = reinterpret_cast<float*>(ws);
+    float* gT = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + img);
     // the strip buffer holds 16-byte records: start it on an aligned address
-    const uintptr_t b0 = reinterpret_cast<uintptr_t>(ws) + img;
+    const uintptr_t b0 = reinterpret_cast<uintptr_t>(ws) + img + gimg;
     float* buf = reinterpret_cast<float*>((b0 + kAlign - 1) / kAlign * kAlign);
+    if (launch_transpose(g, gT, M, N, s) != hipSuccess) return SGWLS_E_HIP;
     const WeightParams wp = weight_params(*p);
     const int passes = 2 * p->iters;
     const float* x = f;
     for (int q = 0; q < passes; ++q) {
-      float* y = q == passes - 1 ? u : ((passes - q) % 2 == 0) ? tmp : u;
-      if (launch_delta_pass(x, g, y, C, delta_geom(q % 2, M, N, p->stride), wp, lambda_dev,
-                            p->lambda, buf, (hipStream_t)stream) != hipSuccess)
+      const bool even = q % 2 == 0;
+      float* y = even ? tmp : u;
+      if (launch_delta_pass(x, even ? g : gT, y, C,
+                            even ? delta_geom(M, N, p->stride) : delta_geom(N, M, p->stride), wp,
+                            lambda_dev, p->lambda, buf, s) != hipSuccess)
         return SGWLS_E_HIP;
       x = y;
     }

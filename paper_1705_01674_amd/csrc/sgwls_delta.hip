@@ -169,7 +169,9 @@ __global__ __launch_bounds__(kWave) void k_delta_solve(const float* __restrict__
 }
 
 // Output pixel (a, b) of the pass: the mean over the strips whose centres
-// lie within one column of b (Sec. 2.3), in increasing strip order.
+// lie within one column of b (Sec. 2.3), in increasing strip order.  With
+// geo.out_t the output is stored transposed (pixel (a, b) at b * L + a),
+// which is the layout the next pass reads as a column pass.
 template <int NC>
 __global__ __launch_bounds__(256) void k_delta_average(const float* __restrict__ buf,
                                                        float* __restrict__ Y, int c0,
@@ -198,7 +200,7 @@ __global__ __launch_bounds__(256) void k_delta_average(const float* __restrict__
   const int hi = min(last, b / t);
   for (int ki = lo; ki <= hi; ++ki) add(ki);
   if (last > hi) add(last);
-  const long long o = (long long)a * geo.sa + (long long)b * geo.sb;
+  const long long o = geo.out_t ? (long long)b * geo.L + a : (long long)a * geo.sa + (long long)b * geo.sb;
 #pragma unroll
   for (int h = 0; h < NC; ++h) Y[(size_t)(c0 + h) * geo.plane + o] = acc[h] / (float)cnt;
 }

@@ -267,7 +267,8 @@ def test_delta_mode_is_filter_only(nat):
     C, M, N = 3, 40, 56
     strips = max((N - 2) * 3 * M, (M - 2) * 3 * N)     # stride 1: W - 2 strips of 3L elements
     img = (4 * C * M * N + 255) // 256 * 256
-    want = img + 4 * 4 * strips + 256                   # 16-byte records, aligned start
+    gimg = (4 * M * N + 255) // 256 * 256                # the transposed guidance
+    want = img + gimg + 4 * 4 * strips + 256            # 16-byte records, aligned start
     assert nat.lib.sgwls_workspace_bytes(C, M, N, ctypes.byref(p)) == want
     assert nat.lib.sgwls_workspace_bytes(C, M, N, ctypes.byref(P(nat, prec=2, r=2))) == 0
     assert nat.lib.sgwls_backward_workspace_bytes(C, M, N, ctypes.byref(p)) == 0
