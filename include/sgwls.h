@@ -71,9 +71,9 @@ typedef enum {
  * LDL^T of Sec. 2.2 with every pivot carried as its excess over the coupling
  * still to be eliminated, delta_{p+1} = 1 + lambda w_p delta_p / alpha_p,
  * alpha_p = delta_p + lambda w_p, which adds positive terms only (no
- * cancellation).  One thread per strip: a precision reference, several
- * times slower than the other modes.  Any other entry point, r != 1, and a
- * non-NULL `saved` return SGWLS_E_UNSUPPORTED. */
+ * cancellation).  One thread per strip: a precision reference, about 20x
+ * the time of FP64_PIVOT on a 1080p image.  Any other entry point, r != 1,
+ * and a non-NULL `saved` return SGWLS_E_UNSUPPORTED. */
 typedef enum {
   SGWLS_P_FP32 = 0,
   SGWLS_P_FP64_PIVOT = 1,
