@@ -17,7 +17,8 @@ def nat():
 
 
 def header_symbols():
-    text = open(os.path.join(ROOT, "include", "sgwls.h")).read()
+    with open(os.path.join(ROOT, "include", "sgwls.h")) as fh:
+        text = fh.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(sgwls_[a-z0-9_]+)\s*\(", text)))
 
@@ -124,7 +125,8 @@ def test_tune_table_pin_query_save_load(nat, tmp_path):
     assert lib.sgwls_tune_size() == 0
     assert lib.sgwls_tune_load(path, b"gfx950") == 0
     assert lib.sgwls_tune_query(0, 3, 1080, 1920, p) == 2
-    lines = open(path.decode()).read().splitlines()
+    with open(path.decode()) as fh:
+        lines = fh.read().splitlines()
     bad = tmp_path / "bad.txt"
     bad.write_text("\n".join(lines + ["1 3 0 0 0 41 77"]) + "\n")   # variant out of range
     lib.sgwls_tune_clear()

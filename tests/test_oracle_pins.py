@@ -44,7 +44,8 @@ def test_snake_matches_paper_example():
     # tests/golden/snake_3x3_r1.txt: Sec. 2.1, 3x3 image labelled 1..9 row-major.
     import os
     path = os.path.join(os.path.dirname(__file__), "golden", "snake_3x3_r1.txt")
-    lines = [ln for ln in open(path) if not ln.startswith("#") and ln.strip()]
+    with open(path) as fh:
+        lines = [ln for ln in fh if not ln.startswith("#") and ln.strip()]
     expected = [int(v) for v in lines[0].split()]
     labels = np.arange(1, 10).reshape(3, 3)
     got = [labels[oracle.snake_pixel(1, 1, p)] for p in range(9)]
