@@ -1,0 +1,68 @@
+"""Parity with the FP64 oracle over randomly drawn valid parameters (fixed
+seed): shapes from one window up to 160 pixels a side, r = 1..4, every
+stride 1..2r+1, 1-5 channels, T = 1..3, lambda log-uniform, both weight kinds
+(random alpha_r for omega^frac), and the three precision modes.
+
+The FP64-pivot and float32 excess-pivot modes are held to 1e-5 everywhere;
+plain float32 is held to 1e-5 with omega^exp up to lambda = 16 and otherwise
+only reported, since its pivots lose digits as lambda * omega grows (with
+uniform random guidance, omega^frac reaches about 1/epsilon between
+near-equal neighbours)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+N_CASES = 150
+
+
+@pytest.fixture(scope="module")
+def ops():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1705_01674_amd import ops as _ops
+    return _ops
+
+
+def draw(rng):
+    r = int(rng.integers(1, 5))
+    M, N = int(rng.integers(2 * r + 1, 160)), int(rng.integers(2 * r + 1, 160))
+    C, T = int(rng.integers(1, 6)), int(rng.integers(1, 4))
+    stride = int(rng.integers(1, 2 * r + 2))
+    kind = "exp" if rng.uniform() < 0.7 else "frac"
+    lam = float(2.0 ** rng.uniform(-3, 6 if kind == "exp" else 3))
+    prec = ["fp32", "fp64_pivot", "fp32_delta"][int(rng.integers(0, 3))]
+    if prec == "fp32_delta" and r != 1:
+        prec = "fp32"
+    pd = dict(lam=lam, r=r, iters=T, stride=stride, kind=kind, sigma_s=float(r),
+              sigma_r=float(rng.uniform(0.05, 0.5)), alpha_s=1.2,
+              alpha_r=float(rng.uniform(0.8, 1.5)), eps=1e-4)
+    f = rng.uniform(0, 1, (C, M, N)).astype(np.float32)
+    g = rng.uniform(0, 1, (M, N)).astype(np.float32)
+    return f, g, pd, prec
+
+
+def test_random_parameters_match_oracle(ops):
+    rng = np.random.default_rng(20261202)
+    worst = {}
+    bad = []
+    for i in range(N_CASES):
+        f, g, pd, prec = draw(rng)
+        print(f"[random] {i} {f.shape} {pd} {prec}", flush=True)
+        u = ops.sgwls_filter(torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda(),
+                             ops.Params(**pd, prec=prec))
+        torch.cuda.synchronize()
+        ref = oracle.filter(f.astype(np.float64), g.astype(np.float64), oracle.OracleParams(**pd))
+        e = float(np.abs(u.cpu().numpy().astype(np.float64) - ref).max() / np.abs(ref).max())
+        key = f"{prec}/{pd['kind']}"
+        worst[key] = max(worst.get(key, 0.0), e)
+        held = prec != "fp32" or (pd["kind"] == "exp" and pd["lam"] <= 16.0)
+        if not np.isfinite(e) or (held and e > TOL):
+            bad.append((i, prec, pd, e))
+    print("[random] worst", {k: f"{v:.2e}" for k, v in sorted(worst.items())}, flush=True)
+    assert not bad, bad
