@@ -547,14 +547,18 @@ DEV void chunk_omega(const V& cv, const WeightParams& wp, float (&gv)[V::E + 2 *
 
 // d omega / d dG for dG = G_p - G_q, given omega.  exp: -omega dG / sigma_r^2.
 // frac: -omega alpha_r |dG|^alpha_r / (dG (|dG|^alpha_r + eps)), taken as 0 at
-// dG = 0 where it is not differentiable for alpha_r <= 1.
+// dG = 0 where it is not differentiable for alpha_r <= 1.  The factor
+// |dG|^a / (|dG|^a + eps) is formed as 1 / (1 + eps / |dG|^a): |dG|^a
+// overflows float32 for the sentinel guidance of rows outside the image once
+// alpha_r > 38.5 / 30, and the other form would then be inf * 0.
 template <int KIND>
 DEV float domega(float w, float dg, const WeightParams& wp) {
   if (KIND == 0) return -w * dg * wp.inv_sr2;
   const float ad = fabsf(dg);
   if (!(ad > 0.0f) || wp.alpha_r == 0.0f) return 0.0f;
   const float pw = __builtin_amdgcn_exp2f(wp.alpha_r * __builtin_amdgcn_logf(ad));
-  return -w * wp.alpha_r * pw * __builtin_amdgcn_rcpf(pw + wp.eps) / dg;
+  const float share = __builtin_amdgcn_rcpf(1.0f + wp.eps * __builtin_amdgcn_rcpf(pw));
+  return -w * wp.alpha_r * share / dg;
 }
 
 // ---------------------------------------------------------------------------
