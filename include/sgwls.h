@@ -35,7 +35,10 @@
  *     on any error nothing is enqueued and outputs are untouched.  HIP launch
  *     errors are reported as SGWLS_E_HIP.  No entry point aborts or exits.
  *   - NaN or Inf in f propagate to the outputs of the strips that read them;
- *     NaN or Inf in g make the affected weights NaN (not trapped).
+ *     NaN or Inf in g make the affected weights NaN (not trapped).  Guidance
+ *     values must stay below 1e28 in magnitude: the kernels pad the image
+ *     with a guidance of 1e30 and give every edge whose guidance difference
+ *     reaches 1e29 a weight of 0.
  */
 #ifndef SGWLS_H
 #define SGWLS_H

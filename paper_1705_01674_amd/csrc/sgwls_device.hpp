@@ -53,11 +53,20 @@ namespace {
 // ---------------------------------------------------------------------------
 // Arithmetic helpers.
 
+// Guidance value of tile rows outside the subsystem (see load_tile), and the
+// guidance difference from which an edge is taken to reach such a row.
+constexpr float kSentinel = 1.0e30f;
+constexpr float kSentinelGap = 1.0e29f;
+
 // Range factor of Eq. (2); the spatial factor is folded into lambda*S(d).
 // exp: 2^(-dG^2 * log2(e)/(2 sigma_r^2)); frac: 1/(|dG|^alpha_r + eps) with
 // |dG|^alpha_r = 2^(alpha_r log2|dG|).  Hardware exp2/log2/rcp (about 1 ulp).
+// 0 for an edge to a row outside the image (|dG| >= kSentinelGap), for every
+// weight kind and exponent (omega^frac with a small alpha_r would otherwise
+// couple the border pixels to the padding).
 template <int KIND>
 DEV float range_weight(float dg, const WeightParams& wp) {
+  if (fabsf(dg) >= kSentinelGap) return 0.0f;
   if (KIND == 0) return __builtin_amdgcn_exp2f(-(dg * dg) * wp.range_c2);
   const float ad = fabsf(dg);
   float pw;
@@ -240,8 +249,6 @@ DEV int cover_count(int b, const PassGeom& geo, int r) {
   return c;
 }
 
-// Guidance value of tile rows outside the subsystem (see load_tile).
-constexpr float kSentinel = 1.0e30f;
 
 // ---------------------------------------------------------------------------
 // Source planes of a tile: NX channels of X, then channels of X2, both from
@@ -289,7 +296,7 @@ DEV void load_tile(float* lds, const float* __restrict__ G, const PlaneSrc<NX>& 
       dst[u] = idx < total ? ta * pitch + tb : -1;
       const float gv = G[o];
       // Rows outside the subsystem hold a sentinel guidance value: every edge
-      // to them gets weight 0 (exp underflows, frac is below 1e-30).
+      // to them gets weight 0 (see range_weight).
       v[0][u] = in ? gv : (rowok ? 0.0f : kSentinel);
 #pragma unroll
       for (int p = 1; p <= NP; ++p) {

@@ -66,3 +66,23 @@ def test_random_parameters_match_oracle(ops):
             bad.append((i, prec, pd, e))
     print("[random] worst", {k: f"{v:.2e}" for k, v in sorted(worst.items())}, flush=True)
     assert not bad, bad
+
+
+@pytest.mark.parametrize("alpha_r", [0.0, 0.1, 0.2])
+@pytest.mark.parametrize("prec", ["fp32", "fp64_pivot"])
+def test_frac_small_alpha_at_the_border(ops, alpha_r, prec):
+    # Regression: rows outside the image carry a padding guidance, and with
+    # omega^frac and a small alpha_r the edges to them kept a weight (up to
+    # 1 / (1 + eps) at alpha_r = 0), which coupled the border pixels to the
+    # padding: 72 % error at the image corner.
+    rng = np.random.default_rng(5)
+    f = rng.uniform(0, 1, (2, 37, 45)).astype(np.float32)
+    g = rng.uniform(0, 1, (37, 45)).astype(np.float32)
+    pd = dict(lam=10.0, r=1, iters=1, stride=1, kind="frac", sigma_s=1.0, sigma_r=0.1,
+              alpha_s=1.2, alpha_r=alpha_r, eps=1e-4)
+    u = ops.sgwls_filter(torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda(),
+                         ops.Params(**pd, prec=prec))
+    torch.cuda.synchronize()
+    ref = oracle.filter(f.astype(np.float64), g.astype(np.float64), oracle.OracleParams(**pd))
+    e = float(np.abs(u.cpu().numpy().astype(np.float64) - ref).max() / np.abs(ref).max())
+    assert e <= TOL, e
