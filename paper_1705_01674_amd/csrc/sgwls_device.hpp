@@ -61,14 +61,15 @@ constexpr float kSentinelGap = 1.0e29f;
 // Range factor of Eq. (2); the spatial factor is folded into lambda*S(d).
 // exp: 2^(-dG^2 * log2(e)/(2 sigma_r^2)); frac: 1/(|dG|^alpha_r + eps) with
 // |dG|^alpha_r = 2^(alpha_r log2|dG|).  Hardware exp2/log2/rcp (about 1 ulp).
-// 0 for an edge to a row outside the image (|dG| >= kSentinelGap), for every
-// weight kind and exponent (omega^frac with a small alpha_r would otherwise
-// couple the border pixels to the padding).
+// An edge to a row outside the image gets 0: exp underflows (dG^2 is
+// infinite), and frac is set to 0 from |dG| >= kSentinelGap (with a small
+// alpha_r its formula would otherwise couple the border pixels to the
+// padding).
 template <int KIND>
 DEV float range_weight(float dg, const WeightParams& wp) {
-  if (fabsf(dg) >= kSentinelGap) return 0.0f;
   if (KIND == 0) return __builtin_amdgcn_exp2f(-(dg * dg) * wp.range_c2);
   const float ad = fabsf(dg);
+  if (ad >= kSentinelGap) return 0.0f;
   float pw;
   if (wp.alpha_r == 0.0f) pw = 1.0f;
   else pw = ad > 0.0f ? __builtin_amdgcn_exp2f(wp.alpha_r * __builtin_amdgcn_logf(ad)) : 0.0f;
