@@ -34,6 +34,10 @@
  *   - all arguments are validated on the host before anything is enqueued;
  *     on any error nothing is enqueued and outputs are untouched.  HIP launch
  *     errors are reported as SGWLS_E_HIP.  No entry point aborts or exits.
+ *   - lambda_dev (where accepted) is a device float that overrides p->lambda
+ *     without a host synchronisation.  The kernels clamp a negative device
+ *     lambda to 0 (A_s = I + lambda L is only positive definite for
+ *     lambda >= 0); a NaN device lambda propagates to every output.
  *   - NaN or Inf in f propagate to the outputs of the strips that read them;
  *     NaN or Inf in g make the affected weights NaN (not trapped).  Guidance
  *     values must stay below 1e28 in magnitude: the kernels pad the image
@@ -76,12 +80,33 @@ typedef enum {
  * alpha_p = delta_p + lambda w_p, which adds positive terms only (no
  * cancellation).  One thread per strip: a precision reference, about 20x
  * the time of FP64_PIVOT on a 1080p image.  Any other entry point, r != 1,
- * and a non-NULL `saved` return SGWLS_E_UNSUPPORTED. */
+ * and a non-NULL `saved` return SGWLS_E_UNSUPPORTED.
+ * AUTO: each call picks FP32 or FP64_PIVOT on the host (sgwls_resolve_precision):
+ *   - from the bound kappa = 1 + 2 lambda sum_{d=1..r} S(d) R_max on the
+ *     largest diagonal entry of A_s (Eq. 4 with the weights of Eq. 2; S(d) the
+ *     spatial factor, R_max the largest range factor: 1 for omega^exp, 1/eps
+ *     for omega^frac, reached where neighbouring guidance values are equal),
+ *     FP32 when kappa <= SGWLS_AUTO_KAPPA_MAX and FP64_PIVOT above it (float32
+ *     pivots lose about kappa float32 ulps of the solution);
+ *   - FP64_PIVOT for every backward call that asks for the lambda gradient,
+ *     and for every sgwls_filter call that saves its pass inputs (they feed a
+ *     backward that may ask for it): that gradient is a sum over all edges
+ *     of terms of both signs, whose cancellation no host bound can predict,
+ *     and it inherits the error of the saved inputs.  A caller that needs
+ *     no lambda gradient can resolve the precision itself
+ *     (sgwls_resolve_precision(p, 0)) and pass it explicitly to both calls.
+ *   With lambda_dev, the decision uses p->lambda, which should then bound the
+ *   device value.  The workspace queries size an AUTO request for the
+ *   precision the call resolves to (backward: for both). */
 typedef enum {
   SGWLS_P_FP32 = 0,
   SGWLS_P_FP64_PIVOT = 1,
-  SGWLS_P_FP32_DELTA = 2
+  SGWLS_P_FP32_DELTA = 2,
+  SGWLS_P_AUTO = 3
 } sgwls_precision;
+
+/* The kappa threshold of SGWLS_P_AUTO. */
+#define SGWLS_AUTO_KAPPA_MAX 64.0
 
 /* Filter parameters.  lambda: Eq. (1).  r: the neighbourhood is
  * (2r+1)x(2r+1) (Eq. 1), 1 <= r <= 4 in this build.  iters: T >= 1 column+row
@@ -113,13 +138,21 @@ int sgwls_version(void);
 sgwls_status sgwls_validate(int C, int M, int N, const sgwls_params* p);
 
 /* Device workspace bytes needed by sgwls_filter / sgwls_pass /
- * sgwls_backward for one C x M x N image with parameters p; 0 if the
- * request is invalid.  save_for_backward is accepted for symmetry and does
- * not change the size (the saved pass inputs live in the caller's `saved`
- * buffer).  For SGWLS_P_FP32_DELTA it is sgwls_filter's workspace in that
- * mode (one image plus the eliminated strips of four channels).  Makes no
- * HIP call. */
-size_t sgwls_workspace_bytes(int C, int M, int N, const sgwls_params* p);
+ * sgwls_pass_stages for one C x M x N image with parameters p; 0 if the
+ * request is invalid.  save_for_backward (0 or 1) says whether the filter
+ * call will pass `saved`: it decides the precision an SGWLS_P_AUTO call
+ * resolves to (the saved pass inputs themselves live in the caller's
+ * `saved` buffer).  For
+ * SGWLS_P_FP32_DELTA it is sgwls_filter's workspace in that mode (one image
+ * plus the eliminated strips of four channels).  Makes no HIP call. */
+size_t sgwls_workspace_bytes(int C, int M, int N, const sgwls_params* p, int save_for_backward);
+
+/* The precision a call with parameters p runs in: p->prec itself unless it
+ * is SGWLS_P_AUTO, which resolves as described at sgwls_precision
+ * (want_lambda_grad = 1 for a backward call that writes the lambda
+ * gradient and for a filter call that saves its pass inputs).  -1 (cast)
+ * for a NULL p.  Host only. */
+sgwls_precision sgwls_resolve_precision(const sgwls_params* p, int want_lambda_grad);
 
 /* One pass of Sec. 2.3 (steps 1-4) on a C x M x N image: direction 0 is
  * the column direction (strips of 2r+1 columns, Sec. 2.1), 1 the row

@@ -84,6 +84,29 @@ WeightParams weight_params(const sgwls_params& p) {
   return wp;
 }
 
+// Bound on the largest diagonal entry of A_s (Eq. 4 with the weights of
+// Eq. 2): every element has at most two edges at each distance d = 1..r, each
+// weighing at most S(d) times the largest range factor (1 for omega^exp,
+// 1 / eps for omega^frac at equal guidance).
+double auto_kappa(const sgwls_params& p) {
+  double s = 0.0;
+  for (int d = 1; d <= p.r; ++d)
+    s += p.kind == SGWLS_W_EXP ? std::exp(-(double)d * d / (2.0 * (double)p.sigma_s * p.sigma_s))
+                               : 1.0 / (std::pow((double)d, (double)p.alpha_s) + (double)p.eps);
+  const double rmax = p.kind == SGWLS_W_EXP ? 1.0 : 1.0 / (double)p.eps;
+  return 1.0 + 2.0 * (double)p.lambda * s * rmax;
+}
+
+// The parameters a call runs with: SGWLS_P_AUTO replaced by the precision it
+// resolves to (see sgwls_precision in sgwls.h).
+sgwls_params resolved(const sgwls_params& p, int want_lambda_grad) {
+  sgwls_params q = p;
+  if (p.prec == SGWLS_P_AUTO)
+    q.prec = (want_lambda_grad || auto_kappa(p) > SGWLS_AUTO_KAPPA_MAX) ? SGWLS_P_FP64_PIVOT
+                                                                       : SGWLS_P_FP32;
+  return q;
+}
+
 PassGeom pass_geom(int direction, int M, int N, const PassPlan& pl, int stride) {
   PassGeom g{};
   if (direction == 0) {
@@ -252,7 +275,9 @@ sgwls_status batch_plan(const sgwls_image* imgs, const sgwls_params* p, int B, i
     if (p[b].stride != 1 || p[b].r > kBatchMaxR) return SGWLS_E_UNSUPPORTED;
     if (ws && (!im.f || !im.g || !im.u || (const float*)im.u == im.g)) return SGWLS_E_ARG;
   }
-  const int fp64 = p0.prec == SGWLS_P_FP64_PIVOT ? 1 : 0;
+  int fp64 = p0.prec == SGWLS_P_FP64_PIVOT ? 1 : 0;
+  for (int b = 0; b < B && p0.prec == SGWLS_P_AUTO; ++b)   // AUTO: float64 if any image needs it
+    if (resolved(p[b], 0).prec == SGWLS_P_FP64_PIVOT) fp64 = 1;
   if (variant < 0 || variant >= batch_variant_count(fp64)) return SGWLS_E_ARG;
   const BatchVariant bv = batch_variant(variant, fp64);
   plan.B = B;
@@ -511,7 +536,8 @@ sgwls_status sgwls_validate(int C, int M, int N, const sgwls_params* p) {
   } else {
     return SGWLS_E_ARG;
   }
-  if (p->prec != SGWLS_P_FP32 && p->prec != SGWLS_P_FP64_PIVOT && p->prec != SGWLS_P_FP32_DELTA)
+  if (p->prec != SGWLS_P_FP32 && p->prec != SGWLS_P_FP64_PIVOT && p->prec != SGWLS_P_FP32_DELTA &&
+      p->prec != SGWLS_P_AUTO)
     return SGWLS_E_ARG;
   if (C < 1 || M < 2 * p->r + 1 || N < 2 * p->r + 1) return SGWLS_E_SHAPE;
   // kernels address pixels with 32-bit element offsets
@@ -549,8 +575,15 @@ PassGeom delta_geom(int L, int W, int stride) {
 }
 }  // namespace
 
-size_t sgwls_workspace_bytes(int C, int M, int N, const sgwls_params* p) {
+sgwls_precision sgwls_resolve_precision(const sgwls_params* p, int want_lambda_grad) {
+  if (!p) return (sgwls_precision)-1;
+  return resolved(*p, want_lambda_grad).prec;
+}
+
+size_t sgwls_workspace_bytes(int C, int M, int N, const sgwls_params* p, int save_for_backward) {
   if (sgwls_validate(C, M, N, p) != SGWLS_OK) return 0;
+  const sgwls_params pr = resolved(*p, save_for_backward ? 1 : 0);
+  p = &pr;
   if (p->prec == SGWLS_P_FP32_DELTA)   // + slack to align the strip buffer
     return image_bytes(C, M, N) + image_bytes(1, M, N) + delta_buffer_bytes(C, M, N, p->stride) +
            kAlign;
@@ -563,6 +596,8 @@ sgwls_status sgwls_pass_stages(int stages, int direction, const float* x, const 
                                void* stream) {
   sgwls_status st = validate_partitioned(C, M, N, p);
   if (st != SGWLS_OK) return st;
+  const sgwls_params pr = resolved(*p, 0);
+  p = &pr;
   if (direction != 0 && direction != 1) return SGWLS_E_ARG;
   if ((stages & kStageAll) == 0 || stages > (kStageAll | kStageTransposeOut)) return SGWLS_E_ARG;
   if ((stages & kStageTransposeOut) &&
@@ -587,6 +622,9 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u, int C, int M
                           void* ws, size_t ws_bytes, void* stream) {
   sgwls_status st = sgwls_validate(C, M, N, p);
   if (st != SGWLS_OK) return st;
+  // Saved pass inputs feed a backward that may ask for the lambda gradient.
+  const sgwls_params pr = resolved(*p, saved ? 1 : 0);
+  p = &pr;
   if (!f || !g || !u || (const float*)u == g) return SGWLS_E_ARG;
   if (p->prec == SGWLS_P_FP32_DELTA) {
     // Serial-strip solves: no saved pass inputs (there is no backward in
@@ -680,6 +718,8 @@ sgwls_status sgwls_tune_pin(int direction, int channel_block, int M, int N,
                             const sgwls_params* p, int variant) {
   sgwls_status st = validate_partitioned(channel_block, M, N, p);
   if (st != SGWLS_OK) return st;
+  const sgwls_params pr = resolved(*p, 0);
+  p = &pr;
   if (direction != 0 && direction != 1) return SGWLS_E_ARG;
   if (channel_block != 1 && channel_block != 3) return SGWLS_E_ARG;
   if (variant < 0 || variant >= variants_of(p->r, channel_block, p->prec).n) return SGWLS_E_ARG;
@@ -691,6 +731,8 @@ sgwls_status sgwls_tune_pin(int direction, int channel_block, int M, int N,
 
 int sgwls_tune_query(int direction, int channel_block, int M, int N, const sgwls_params* p) {
   if (!p || (direction != 0 && direction != 1)) return -1;
+  const sgwls_params pr = resolved(*p, 0);
+  p = &pr;
   const int L = direction == 0 ? M : N, W = direction == 0 ? N : M;
   return tuned_variant(p->r, channel_block, p->prec, (int)p->kind, direction, L, W);
 }
@@ -710,6 +752,8 @@ sgwls_status sgwls_autotune(const float* x, const float* g, float* y, int C, int
                             int reps, int* chosen) {
   sgwls_status st = validate_partitioned(C, M, N, p);
   if (st != SGWLS_OK) return st;
+  const sgwls_params pr = resolved(*p, 0);
+  p = &pr;
   if (!x || !g || !y || y == x || (const float*)y == g || reps < 1) return SGWLS_E_ARG;
   const size_t need = std::max(pass_iface_bytes(0, C, M, N, *p), pass_iface_bytes(1, C, M, N, *p));
   if (!ws || ws_bytes < need) return SGWLS_E_WORKSPACE;
@@ -832,7 +876,9 @@ sgwls_status sgwls_tune_load(const char* path, const char* arch) {
 
 size_t sgwls_backward_workspace_bytes(int C, int M, int N, const sgwls_params* p) {
   if (validate_partitioned(C, M, N, p) != SGWLS_OK) return 0;
-  return bwd_layout(C, M, N, *p).total;
+  // AUTO resolves per call (the lambda gradient decides): room for both.
+  return std::max(bwd_layout(C, M, N, resolved(*p, 0)).total,
+                  bwd_layout(C, M, N, resolved(*p, 1)).total);
 }
 
 sgwls_status sgwls_pass_backward(int direction, const float* x, const float* g,
@@ -842,6 +888,8 @@ sgwls_status sgwls_pass_backward(int direction, const float* x, const float* g,
                                  size_t ws_bytes, void* stream) {
   sgwls_status st = validate_partitioned(C, M, N, p);
   if (st != SGWLS_OK) return st;
+  const sgwls_params pr = resolved(*p, grad_lambda != nullptr);
+  p = &pr;
   if (direction != 0 && direction != 1) return SGWLS_E_ARG;
   if (!x || !g || !ybar || !xbar || xbar == x || xbar == ybar || (const float*)xbar == g)
     return SGWLS_E_ARG;
@@ -861,6 +909,8 @@ sgwls_status sgwls_backward(const float* g, const float* saved, const float* gra
                             size_t ws_bytes, void* stream) {
   sgwls_status st = validate_partitioned(C, M, N, p);
   if (st != SGWLS_OK) return st;
+  const sgwls_params pr = resolved(*p, grad_lambda != nullptr);
+  p = &pr;
   if (!g || !saved || !grad_u || !grad_f || (const float*)grad_f == g ||
       (const float*)grad_f == saved)
     return SGWLS_E_ARG;
@@ -919,9 +969,10 @@ sgwls_status sgwls_backward(const float* g, const float* saved, const float* gra
 
 size_t sgwls_batched_workspace_bytes(const sgwls_image* imgs, const sgwls_params* p, int B) {
   if (!imgs || !p || B < 1) return 0;
-  const int fp64 = p[0].prec == SGWLS_P_FP64_PIVOT ? 1 : 0;
+  BatchPlan probe;
+  if (batch_plan(imgs, p, B, 0, nullptr, probe) != SGWLS_OK) return 0;
   size_t need = 0;
-  for (int v = 0; v < batch_variant_count(fp64); ++v) {
+  for (int v = 0; v < batch_variant_count(probe.fp64); ++v) {
     BatchPlan plan;
     if (batch_plan(imgs, p, B, v, nullptr, plan) != SGWLS_OK) return 0;
     need = std::max(need, plan.total);
@@ -954,7 +1005,7 @@ sgwls_status sgwls_filter_batched_variant(const sgwls_image* imgs, const sgwls_p
 
 size_t sgwls_interpolate_workspace_bytes(int C, int M, int N, const sgwls_params* p) {
   if (C < 1 || C >= (1 << 20)) return 0;
-  const size_t inner = sgwls_workspace_bytes(C + 1, M, N, p);
+  const size_t inner = sgwls_workspace_bytes(C + 1, M, N, p, 0);
   return inner ? image_bytes(C + 1, M, N) + inner : 0;
 }
 

@@ -231,8 +231,13 @@ struct IfaceLayout {
   static constexpr int F = 2 * T2 + 2 * r * CB + r * r;
 };
 
+// lambda of the pass: the device override when given, else the host value
+// (validated on the host).  A negative device value is clamped to 0, where
+// A_s = I + lambda L stops being positive definite; NaN passes through.
 DEV float load_lambda(const float* lam_dev, float lam_host) {
-  return lam_dev ? *lam_dev : lam_host;
+  if (!lam_dev) return lam_host;
+  const float v = *lam_dev;
+  return v < 0.0f ? 0.0f : v;
 }
 
 DEV int centre_of(int ki, const PassGeom& geo, int r) {

@@ -18,7 +18,8 @@ import torch
 from . import _native as nat
 
 _KIND = {"exp": 0, "frac": 1}
-_PREC = {"fp32": 0, "fp64_pivot": 1, "fp32_delta": 2}
+_PREC = {"fp32": 0, "fp64_pivot": 1, "fp32_delta": 2, "auto": 3}
+_PREC_NAME = {v: k for k, v in _PREC.items()}
 
 
 @dataclass(frozen=True)
@@ -33,7 +34,7 @@ class Params:
     alpha_s: float = 1.2
     alpha_r: float = 1.2
     eps: float = 1e-4
-    prec: str = "fp32"
+    prec: str = "auto"      # float32 unless the host bound on lambda*omega asks for FP64 pivots
 
     def c(self) -> nat.SgwlsParams:
         if self.kind not in _KIND:
@@ -94,8 +95,16 @@ def _lambda(lambda_dev: Optional[torch.Tensor], dev):
     return lambda_dev
 
 
-def workspace_bytes(C: int, M: int, N: int, p: Params) -> int:
-    n = nat.lib.sgwls_workspace_bytes(C, M, N, ctypes.byref(p.c()))
+def resolve_precision(p: Params, want_lambda_grad: bool = False) -> str:
+    """The precision a call with p runs in ("fp32", "fp64_pivot" or
+    "fp32_delta"): p.prec unless it is "auto", which the library resolves
+    from its bound on lambda * omega (and to "fp64_pivot" for a backward call
+    that asks for the lambda gradient)."""
+    return _PREC_NAME[int(nat.lib.sgwls_resolve_precision(ctypes.byref(p.c()), int(want_lambda_grad)))]
+
+
+def workspace_bytes(C: int, M: int, N: int, p: Params, save_for_backward: bool = False) -> int:
+    n = nat.lib.sgwls_workspace_bytes(C, M, N, ctypes.byref(p.c()), int(save_for_backward))
     if n == 0:
         nat.check(nat.lib.sgwls_validate(C, M, N, ctypes.byref(p.c())), "sgwls_workspace_bytes")
     return int(n)
@@ -130,7 +139,7 @@ def sgwls_filter(f: torch.Tensor, g: torch.Tensor, p: Params, *,
         if (saved.dtype != torch.float32 or not saved.is_contiguous() or saved.device != dev
                 or saved.numel() != 2 * p.iters * C * M * N):
             raise ValueError("saved must be a contiguous float32 tensor of 2T*C*M*N elements")
-    nbytes = workspace_bytes(C, M, N, p)
+    nbytes = workspace_bytes(C, M, N, p, saved is not None)
     ws = workspace if workspace is not None else _workspace(nbytes, dev)
     if ws.numel() < nbytes or ws.device != dev:
         raise ValueError("workspace too small")
@@ -323,9 +332,15 @@ class SGWLSFunction(torch.autograd.Function):
             raise ValueError("f must be (C,M,N) or (B,C,M,N) with g (M,N) or (B,M,N)")
         B, C, M, N = fb.shape
         lam_dev = lam.detach().reshape(1).to(torch.float32).contiguous()
+        if p.prec == "auto":
+            # The automatic precision is decided here, once for the forward and
+            # the backward, from lambda (one host sync) and from whether lambda
+            # needs a gradient (which asks for FP64 pivots in both calls).
+            p = p.with_(lam=max(float(lam_dev.item()), 0.0))
+            p = p.with_(prec=resolve_precision(p, bool(ctx.needs_input_grad[2])))
         out = torch.empty_like(fb)
         saved = torch.empty((B, 2 * p.iters, C, M, N), dtype=torch.float32, device=f.device)
-        ws = _workspace(workspace_bytes(C, M, N, p), f.device)
+        ws = _workspace(workspace_bytes(C, M, N, p, True), f.device)
         for b in range(B):
             sgwls_filter(fb[b], gb[b], p, lambda_dev=lam_dev, saved=saved[b], out=out[b], workspace=ws)
         ctx.p = p

@@ -50,7 +50,7 @@ def P(nat, **kw):
     (dict(r=2, stride=5), 0), (dict(lam=-1.0), 1), (dict(lam=float("nan")), 1),
     (dict(lam=float("inf")), 1), (dict(sigma_s=0.0), 1), (dict(sigma_r=-1.0), 1),
     (dict(kind=1, eps=0.0), 1), (dict(kind=1, alpha_r=-0.5), 1), (dict(kind=1, sigma_r=0.0), 0),
-    (dict(kind=2), 1), (dict(prec=3), 1), (dict(prec=1), 0), (dict(r=5), 4), (dict(r=4), 0),
+    (dict(kind=2), 1), (dict(prec=4), 1), (dict(prec=3), 0), (dict(prec=1), 0), (dict(r=5), 4), (dict(r=4), 0),
     (dict(prec=2), 0), (dict(prec=2, stride=3), 0), (dict(prec=2, r=2), 4),
 ])
 def test_validate_parameters(nat, kw, code):
@@ -69,10 +69,58 @@ def test_validate_null_params(nat):
 
 def test_workspace_bytes(nat):
     p = P(nat)
-    n = nat.lib.sgwls_workspace_bytes(3, 1080, 1920, ctypes.byref(p))
+    n = nat.lib.sgwls_workspace_bytes(3, 1080, 1920, ctypes.byref(p), 0)
     assert n >= 4 * 3 * 1080 * 1920
-    assert nat.lib.sgwls_workspace_bytes(3, 2, 2, ctypes.byref(p)) == 0
-    assert nat.lib.sgwls_workspace_bytes(3, 64, 64, None) == 0
+    assert nat.lib.sgwls_workspace_bytes(3, 2, 2, ctypes.byref(p), 0) == 0
+    assert nat.lib.sgwls_workspace_bytes(3, 64, 64, None, 0) == 0
+
+
+def test_workspace_bytes_save_flag(nat):
+    # explicit precisions: the saved inputs live in the caller's buffer
+    p = ctypes.byref(P(nat))
+    assert nat.lib.sgwls_workspace_bytes(3, 300, 200, p, 1) == nat.lib.sgwls_workspace_bytes(3, 300, 200, p, 0)
+    # AUTO with saved inputs resolves to FP64 pivots and is sized for them
+    a, d = ctypes.byref(P(nat, prec=3)), ctypes.byref(P(nat, prec=1))
+    assert nat.lib.sgwls_workspace_bytes(3, 300, 200, a, 1) == nat.lib.sgwls_workspace_bytes(3, 300, 200, d, 0)
+
+
+def kappa(lam, r, kind="exp", sigma_s=None, alpha_s=1.2, eps=1e-4):
+    """1 + 2 lambda sum_d S(d) R_max, written out here from Eq. (2) and Eq. (4)."""
+    import math
+    sigma_s = float(r) if sigma_s is None else sigma_s
+    if kind == "exp":
+        return 1 + 2 * lam * sum(math.exp(-d * d / (2 * sigma_s ** 2)) for d in range(1, r + 1))
+    return 1 + 2 * lam * sum(1 / (d ** alpha_s + eps) for d in range(1, r + 1)) / eps
+
+
+@pytest.mark.parametrize("lam,r,kind", [
+    (4.0, 1, 0), (16.0, 2, 0), (64.0, 2, 0), (16.0, 3, 0), (64.0, 3, 0), (20.9, 2, 0),
+    (21.5, 2, 0), (1e-4, 1, 1), (0.01, 1, 1), (1.0, 1, 1), (900.0, 1, 1), (0.0, 4, 1),
+])
+def test_auto_precision_follows_the_kappa_bound(nat, lam, r, kind):
+    p = P(nat, lam=lam, r=r, kind=kind, sigma_s=float(r), prec=3)
+    k = kappa(lam, r, "exp" if kind == 0 else "frac", sigma_s=float(r))
+    want = 0 if k <= 64.0 else 1
+    assert nat.lib.sgwls_resolve_precision(ctypes.byref(p), 0) == want
+    # a backward call that writes the lambda gradient always takes FP64 pivots
+    assert nat.lib.sgwls_resolve_precision(ctypes.byref(p), 1) == 1
+    # explicit precisions are kept
+    for prec in (0, 1, 2):
+        q = P(nat, lam=lam, r=r, kind=kind, prec=prec)
+        assert nat.lib.sgwls_resolve_precision(ctypes.byref(q), 1) == prec
+
+
+def test_auto_precision_workspaces(nat):
+    C, M, N = 3, 200, 300
+    for lam in (4.0, 500.0):
+        auto = P(nat, lam=lam, prec=3)
+        res = P(nat, lam=lam, prec=nat.lib.sgwls_resolve_precision(ctypes.byref(auto), 0))
+        assert nat.lib.sgwls_workspace_bytes(C, M, N, ctypes.byref(auto), 0) == \
+            nat.lib.sgwls_workspace_bytes(C, M, N, ctypes.byref(res), 0)
+        both = max(nat.lib.sgwls_backward_workspace_bytes(C, M, N, ctypes.byref(P(nat, lam=lam, prec=q)))
+                   for q in (0, 1))
+        assert nat.lib.sgwls_backward_workspace_bytes(C, M, N, ctypes.byref(auto)) >= both
+    assert nat.lib.sgwls_resolve_precision(None, 0) == -1
 
 
 def test_filter_error_paths_return_before_any_launch(nat):
@@ -223,7 +271,7 @@ def test_interpolate_workspace_and_error_paths(nat):
     pp = ctypes.byref(p)
     lib = nat.lib
     n = lib.sgwls_interpolate_workspace_bytes(1, 1080, 1920, pp)
-    assert n >= 4 * 2 * 1080 * 1920 + lib.sgwls_workspace_bytes(2, 1080, 1920, pp)
+    assert n >= 4 * 2 * 1080 * 1920 + lib.sgwls_workspace_bytes(2, 1080, 1920, pp, 0)
     assert lib.sgwls_interpolate_workspace_bytes(0, 64, 64, pp) == 0
     assert lib.sgwls_interpolate_workspace_bytes(1, 8, 8, pp) == 0   # M, N < 2r+1
     f, h, g, u, ws = (ctypes.c_void_p(a) for a in (0x1000, 0x2000, 0x3000, 0x4000, 0x5000))
@@ -271,8 +319,8 @@ def test_delta_mode_is_filter_only(nat):
     img = (4 * C * M * N + 255) // 256 * 256
     gimg = (4 * M * N + 255) // 256 * 256                # the transposed guidance
     want = img + gimg + 4 * 4 * strips + 256            # 16-byte records, aligned start
-    assert nat.lib.sgwls_workspace_bytes(C, M, N, ctypes.byref(p)) == want
-    assert nat.lib.sgwls_workspace_bytes(C, M, N, ctypes.byref(P(nat, prec=2, r=2))) == 0
+    assert nat.lib.sgwls_workspace_bytes(C, M, N, ctypes.byref(p), 0) == want
+    assert nat.lib.sgwls_workspace_bytes(C, M, N, ctypes.byref(P(nat, prec=2, r=2)), 0) == 0
     assert nat.lib.sgwls_backward_workspace_bytes(C, M, N, ctypes.byref(p)) == 0
     assert nat.lib.sgwls_pass(0, None, None, None, C, M, N, ctypes.byref(p), None, None, 0,
                               None) == 4

@@ -10,10 +10,11 @@ float32), so a region enclosed by such edges and holding no known sample
 gets S(H) = 0 in the oracle or on the GPU, and the quotient 0/0 is undefined
 in both; where S(H) is tiny but not 0 the quotient amplifies the rounding of
 both filters by 1/S(H).  Those pixels (a fraction of a percent here) are
-counted and printed, not compared (at least 90 % of the pixels are).  Bars: 1e-5 with FP64 pivots; with
-float32 arithmetic the pivots of the r = 4, lambda = 200..900 bands lose
-accuracy in proportion to lambda (the growth the dense filter shows at
-r = 3, lambda = 64), so the float32 bar is 2e-4.
+counted and printed, not compared (at least 90 % of the pixels are).  Bars:
+1e-5 for the default (automatic) precision, which takes FP64 pivots for these
+r = 4, lambda = 100..900 bands, and for FP64 pivots; with explicit float32
+arithmetic the pivots lose accuracy in proportion to lambda (the growth the
+dense filter shows at r = 3, lambda = 64), so the float32 bar is 2e-4.
 """
 import numpy as np
 import pytest
@@ -47,7 +48,7 @@ def rel_err(gpu, ref):
     return d.max() / scale, d.mean() / scale
 
 
-def run(ops, w, prec="fp32", f=None, h=None):
+def run(ops, w, prec="auto", f=None, h=None):
     p = ops.Params(**w.params, prec=prec)
     ft = torch.from_numpy(np.ascontiguousarray(w.f if f is None else f)).cuda()
     ht = torch.from_numpy(np.ascontiguousarray(w.h if h is None else h)).cuda()
@@ -82,6 +83,7 @@ def check(name, gpu, ref_mask, tol):
 def test_depth_upsampling_small(ops, factor):
     w = synth.depth_upsample(120, 161, factor=factor, seed=1100 + factor)
     ref = reference(w)
+    check(f"depth x{factor} default", run(ops, w), ref, TOL64)
     check(f"depth x{factor} fp64 pivots", run(ops, w, "fp64_pivot"), ref, TOL64)
     check(f"depth x{factor} fp32", run(ops, w, "fp32"), ref, TOL32)
 
@@ -89,6 +91,7 @@ def test_depth_upsampling_small(ops, factor):
 def test_colorization_small(ops):
     w = synth.colorize_scribbles(96, 131, n_strokes=120, seed=1200)
     ref = reference(w)
+    check("colorize default", run(ops, w), ref, TOL64)
     check("colorize fp64 pivots", run(ops, w, "fp64_pivot"), ref, TOL64)
     check("colorize fp32", run(ops, w, "fp32"), ref, TOL32)
 
@@ -98,6 +101,7 @@ def test_depth_upsampling_1080p(ops):
     oracle output."""
     w = synth.depth_upsample(1080, 1920, factor=8, seed=1000)
     ref = reference(w)
+    check("depth 1080p x8 default", run(ops, w), ref, TOL64)
     check("depth 1080p x8 fp64 pivots", run(ops, w, "fp64_pivot"), ref, TOL64)
     check("depth 1080p x8 fp32", run(ops, w, "fp32"), ref, TOL32)
 

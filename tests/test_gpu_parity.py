@@ -1,7 +1,10 @@
 """GPU parity: the HIP library against the FP64 CPU oracle, element by element.
 
 Error measure: normwise relative, max|gpu - oracle| / max|oracle| per output
-(the mean is printed beside it).  Bar: 1e-5 for float32 arithmetic.
+(the mean is printed beside it).  Bar: 1e-5 for the default precision
+(automatic: float32 unless the host bound on lambda * omega asks for FP64
+pivots) and for FP64 pivots; explicit float32 is reported where its pivots
+lose digits.
 """
 import numpy as np
 import pytest
@@ -31,7 +34,7 @@ def rel_err(gpu, ref):
     return d.max() / scale, d.mean() / scale
 
 
-def run_filter(ops, f, g, pd, prec="fp32", **kw):
+def run_filter(ops, f, g, pd, prec="auto", **kw):
     p = ops.Params(**pd, prec=prec)
     ft = torch.from_numpy(np.ascontiguousarray(f)).cuda()
     gt = torch.from_numpy(np.ascontiguousarray(g)).cuda()
@@ -138,7 +141,7 @@ def test_edge_shapes(ops, shape, r):
 
 
 @pytest.mark.parametrize("kind,lam", [("exp", 0.5), ("exp", 30.0), ("frac", 1.0), ("frac", 5.0)])
-@pytest.mark.parametrize("prec", ["fp32", "fp64_pivot"])
+@pytest.mark.parametrize("prec", ["auto", "fp32", "fp64_pivot"])
 def test_kinds_and_precisions(ops, kind, lam, prec):
     f = synth.image(96, 80, 3, 30, 0.05, seed=11)
     g = synth.luma(f)
@@ -172,6 +175,9 @@ def test_rgb1080p_large_radius_fp64_pivot(ops, r, lam):
     w = synth.rgb1080p(r=r, lam=lam, seed=1002)
     ref = oracle_filter(w.f, w.g, w.params)
     check(f"rgb1080p r{r} lam{lam} fp64_pivot", run_filter(ops, w.f, w.g, w.params, "fp64_pivot"), ref)
+    picked = ops.resolve_precision(ops.Params(**w.params, prec="auto"))
+    check(f"rgb1080p r{r} lam{lam} auto ({picked})", run_filter(ops, w.f, w.g, w.params), ref)
+    # explicit float32: reported (its pivots lose about kappa ulps), sanity bound
     mx, mean = rel_err(run_filter(ops, w.f, w.g, w.params, "fp32"), ref)
     print(f"[parity] rgb1080p r{r} lam{lam} fp32: max {mx:.3e} mean {mean:.3e}", flush=True)
     assert mx <= 1e-4
@@ -257,3 +263,21 @@ def test_autotune_picks_a_variant_and_keeps_parity(ops):
         check("autotuned filter", u.cpu().numpy(), oracle_filter(w.f, w.g, w.params))
     finally:
         ops.tune_clear()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64_pivot"])
+def test_negative_and_nan_device_lambda(ops, prec):
+    """A negative device lambda is clamped to 0 by the kernels (A_s = I + lambda L
+    is positive definite only for lambda >= 0), which makes every pass the
+    identity; a NaN device lambda propagates to the output."""
+    rng = np.random.default_rng(41)
+    f = rng.uniform(0, 1, (3, 40, 72)).astype(np.float32)
+    g = rng.uniform(0, 1, (40, 72)).astype(np.float32)
+    p = ops.Params(**pdict(lam=4.0, r=2, iters=2), prec=prec)
+    ft, gt = torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda()
+    u = ops.sgwls_filter(ft, gt, p, lambda_dev=torch.tensor([-5.0], device="cuda"))
+    torch.cuda.synchronize()
+    assert np.abs(u.cpu().numpy() - f).max() <= 4 * np.finfo(np.float32).eps
+    u = ops.sgwls_filter(ft, gt, p, lambda_dev=torch.tensor([float("nan")], device="cuda"))
+    torch.cuda.synchronize()
+    assert np.isnan(u.cpu().numpy()).all()

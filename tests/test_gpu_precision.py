@@ -9,7 +9,8 @@ against the FP64 oracle.
 Where the guidance is flat, omega^frac reaches about 1/epsilon = 1e4, so
 the pivots are 1 + lambda*sum(omega) with lambda*omega up to 9e6: the 1
 that decides the solution along a flat run is about one float32 ulp of the
-pivot, and the recurrences cancel the rest.  The FP64 pivot mode and the
+pivot, and the recurrences cancel the rest.  The default (automatic)
+precision, which takes FP64 pivots here, the FP64 pivot mode and the
 float32 excess-pivot mode are held to 1e-5 (normwise max, as everywhere);
 plain float32 is reported, with only a
 finiteness check.  Guidance scales: 0..1 (the
@@ -57,10 +58,11 @@ def errors(gpu, ref):
 def case(ops, name, f, g, pd):
     ref = oracle.filter(f.astype(np.float64), g.astype(np.float64), oracle.OracleParams(**pd))
     e64, m64 = errors(run(ops, f, g, pd, "fp64_pivot"), ref)
+    ea, ma = errors(run(ops, f, g, pd, "auto"), ref)
     u32 = run(ops, f, g, pd, "fp32")
     e32, m32 = errors(u32, ref)
     line = (f"[precision] {name}: fp32 max {e32:.3e} mean {m32:.3e} | fp64 pivots max {e64:.3e} "
-            f"mean {m64:.3e}")
+            f"mean {m64:.3e} | default max {ea:.3e} mean {ma:.3e}")
     ed = None
     if pd["r"] == 1:   # the cancellation-free float32 pivots exist for r = 1
         ed, md = errors(run(ops, f, g, pd, "fp32_delta"), ref)
@@ -68,6 +70,7 @@ def case(ops, name, f, g, pd):
     print(line, flush=True)
     assert np.isfinite(u32).all(), name
     assert e64 <= TOL64, f"{name}: fp64 pivots {e64:.3e}"
+    assert ea <= TOL64, f"{name}: default precision {ea:.3e}"
     if ed is not None:
         assert ed <= TOL64, f"{name}: fp32 delta pivots {ed:.3e}"
 
