@@ -175,9 +175,17 @@ sgwls_status sgwls_pass(int direction, const float* x, const float* g, float* y,
  * ws and stream computes exactly sgwls_pass.  Adding 8 to the mask (direction 0,
  * stride 1, only when the tuned column-pass variants read chunks directly)
  * stores the output transposed: y becomes C planes of N x M, pixel (i, j) of
- * the pass output at y[c*M*N + j*M + i].  sgwls_filter uses this form
- * internally when it saves nothing: every pass is then a column pass, of the
- * image or of its transpose.  Other arguments as sgwls_pass. */
+ * the pass output at y[c*M*N + j*M + i].  sgwls_filter uses this form for
+ * every stride-1 pass: each pass is then a column pass, of the image or of
+ * its transpose.  With mask 7 + 8 the three stages run as ONE launch where
+ * that applies (radius 1-2 and FP32 or FP64 pivots, separator runs short
+ * enough for the register solver, and the units of one 64-strip window
+ * fitting in an eighth of the chip): each workgroup keeps its chunks in
+ * registers, and the window's workgroups wait for each other through
+ * counters in the workspace, which are cleared first (one extra launch)
+ * unless 16 is added to the mask, which asserts that the previous one-launch
+ * pass on this workspace completed (it leaves them zero).  Other arguments
+ * as sgwls_pass. */
 sgwls_status sgwls_pass_stages(int stages, int direction, const float* x, const float* g,
                                float* y, int C, int M, int N, const sgwls_params* p,
                                const float* lambda_dev, void* ws, size_t ws_bytes,
@@ -197,6 +205,19 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u,
                           int C, int M, int N, const sgwls_params* p,
                           const float* lambda_dev, float* saved,
                           void* ws, size_t ws_bytes, void* stream);
+
+/* Workspaces of sgwls_filter, sgwls_pass, sgwls_pass_stages and
+ * sgwls_interpolate begin with a synchronisation area for the one-launch
+ * pass: every wait there is bounded by a spin limit, and a wait that
+ * exceeds it gives up (its pass output is then wrong) and marks the
+ * workspace.  sgwls_workspace_status synchronises `stream`, returns
+ * SGWLS_E_HIP if a call on ws gave up since the last check (and clears the
+ * mark), SGWLS_OK otherwise. */
+sgwls_status sgwls_workspace_status(void* ws, void* stream);
+
+/* Polls per wait of the one-launch pass before it gives up (process-wide;
+ * default 2^17, a fraction of a second).  For tests of the error path. */
+void sgwls_set_spin_limit(unsigned int polls);
 
 /* ---- Guided sparse interpolation (Eq. 21) ----
  * u = S(f) / S(h) channel by channel, where S is the SG-WLS filter with

@@ -24,7 +24,8 @@ EXPORTS = ["sgwls_status_str", "sgwls_version", "sgwls_validate", "sgwls_workspa
            "sgwls_batched_variant_count", "sgwls_filter_batched_variant",
            "sgwls_autotune_batched", "sgwls_batched_graph_count", "sgwls_batched_graph_clear",
            "sgwls_interpolate_workspace_bytes", "sgwls_interpolate",
-           "sgwls_wls2d_workspace_bytes", "sgwls_wls2d", "sgwls_resolve_precision"]
+           "sgwls_wls2d_workspace_bytes", "sgwls_wls2d", "sgwls_resolve_precision",
+           "sgwls_workspace_status", "sgwls_set_spin_limit"]
 
 
 class SgwlsParams(ctypes.Structure):
@@ -61,6 +62,10 @@ def _load():
     lib.sgwls_workspace_bytes.argtypes = [i, i, i, P, i]
     lib.sgwls_resolve_precision.restype = i
     lib.sgwls_resolve_precision.argtypes = [P, i]
+    lib.sgwls_workspace_status.restype = i
+    lib.sgwls_workspace_status.argtypes = [vp, vp]
+    lib.sgwls_set_spin_limit.restype = None
+    lib.sgwls_set_spin_limit.argtypes = [ctypes.c_uint]
     lib.sgwls_pass.restype = i
     lib.sgwls_pass.argtypes = [i, vp, vp, vp, i, i, i, P, vp, vp, sz, vp]
     lib.sgwls_pass_stages.restype = i

@@ -7,6 +7,7 @@
 #include "sgwls_internal.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -141,10 +142,27 @@ size_t iface_bytes_all(int C, int M, int N, const sgwls_params& p) {
 
 size_t image_bytes(int C, int M, int N) { return align_up(sizeof(float) * (size_t)C * M * N); }
 
+// Launch errors are read with hipGetLastError, which also returns an error
+// left by an earlier, unrelated runtime call of the thread: clear it first.
+void clear_hip_error() { (void)hipGetLastError(); }
+
+std::atomic<unsigned int>& spin_limit_value() {
+  static std::atomic<unsigned int> v{1u << 17};
+  return v;
+}
+
+// Counter words a filter call zeroes at its start: those of every window of
+// the wider frame (windows of 64 - 2r output columns).
+int sync_words(int M, int N, int r) {
+  return std::min(kSyncWords,
+                  kSyncStride * ((std::max(M, N) + kWave - 2 * r - 1) / (kWave - 2 * r) + 1));
+}
+
 // variant < 0: the tuned variant of the case (variant 0 when none is tuned).
 sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* y, int C, int M,
                           int N, const sgwls_params& p, const float* lam_dev, void* iface,
-                          hipStream_t stream, int stages = kStageAll, int variant = -1) {
+                          hipStream_t stream, int stages = kStageAll, int variant = -1,
+                          const FusedCtl* fused = nullptr) {
   const int L = direction == 0 ? M : N, W = direction == 0 ? N : M;
   const WeightParams wp = weight_params(p);
   const int out_t = (stages & kStageTransposeOut) ? 1 : 0;
@@ -153,7 +171,8 @@ sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* 
     int v = variant >= 0 ? variant
                          : tuned_variant(p.r, cb, p.prec, (int)p.kind, direction, L, W);
     if (out_t && !variants_of(p.r, cb, p.prec).v[v].D) v = 0;   // variant 0 reads directly
-    const PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, v);
+    PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, v);
+    pl.fused = fused;
     PassGeom geo = pass_geom(direction, M, N, pl, p.stride);
     geo.out_t = out_t;
     stages &= kStageAll;
@@ -191,8 +210,8 @@ BwdLayout bwd_layout(int C, int M, int N, const sgwls_params& p) {
     }
   }
   BwdLayout l{};
-  l.img_off = 0;
-  l.iface_off = image_bytes(C, M, N);
+  l.img_off = kSyncBytes;
+  l.iface_off = l.img_off + image_bytes(C, M, N);
   l.side_off = l.iface_off + align_up(iface);
   l.lpart_off = l.side_off + align_up(side * sizeof(float));
   l.gt_off = l.lpart_off + align_up(blocks * sizeof(double));
@@ -585,9 +604,9 @@ size_t sgwls_workspace_bytes(int C, int M, int N, const sgwls_params* p, int sav
   const sgwls_params pr = resolved(*p, save_for_backward ? 1 : 0);
   p = &pr;
   if (p->prec == SGWLS_P_FP32_DELTA)   // + slack to align the strip buffer
-    return image_bytes(C, M, N) + image_bytes(1, M, N) + delta_buffer_bytes(C, M, N, p->stride) +
-           kAlign;
-  return image_bytes(C, M, N) + image_bytes(1, M, N) + iface_bytes_all(C, M, N, *p);
+    return kSyncBytes + image_bytes(C, M, N) + image_bytes(1, M, N) +
+           delta_buffer_bytes(C, M, N, p->stride) + kAlign;
+  return kSyncBytes + image_bytes(C, M, N) + image_bytes(1, M, N) + iface_bytes_all(C, M, N, *p);
 }
 
 sgwls_status sgwls_pass_stages(int stages, int direction, const float* x, const float* g,
@@ -599,15 +618,20 @@ sgwls_status sgwls_pass_stages(int stages, int direction, const float* x, const 
   const sgwls_params pr = resolved(*p, 0);
   p = &pr;
   if (direction != 0 && direction != 1) return SGWLS_E_ARG;
-  if ((stages & kStageAll) == 0 || stages > (kStageAll | kStageTransposeOut)) return SGWLS_E_ARG;
+  if ((stages & kStageAll) == 0 || stages > (kStageAll | kStageTransposeOut | kStageSyncZero))
+    return SGWLS_E_ARG;
   if ((stages & kStageTransposeOut) &&
       (direction != 0 || p->stride != 1 || !frames_supported(C, p->r, p->stride, p->prec)))
     return SGWLS_E_UNSUPPORTED;
   if (!x || !g || !y || y == x || (const float*)y == g) return SGWLS_E_ARG;
-  const size_t need = pass_iface_bytes(direction, C, M, N, *p);
+  const size_t need = kSyncBytes + pass_iface_bytes(direction, C, M, N, *p);
   if (!ws || ws_bytes < need) return SGWLS_E_WORKSPACE;
-  return enqueue_pass(direction, x, g, y, C, M, N, *p, lambda_dev, ws, (hipStream_t)stream,
-                      stages);
+  clear_hip_error();
+  bool zeroed = (stages & kStageSyncZero) != 0;
+  const FusedCtl ctl{ws, &zeroed, spin_limit_value().load()};
+  return enqueue_pass(direction, x, g, y, C, M, N, *p, lambda_dev,
+                      reinterpret_cast<char*>(ws) + kSyncBytes, (hipStream_t)stream,
+                      stages & ~kStageSyncZero, -1, &ctl);
 }
 
 sgwls_status sgwls_pass(int direction, const float* x, const float* g, float* y, int C, int M,
@@ -633,13 +657,15 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u, int C, int M
     // writes tmp (N x M), pass 2t+1 reads tmp (guidance g^T) and writes u.
     if (saved) return SGWLS_E_UNSUPPORTED;
     const size_t img = image_bytes(C, M, N), gimg = image_bytes(1, M, N);
-    if (!ws || ws_bytes < img + gimg + delta_buffer_bytes(C, M, N, p->stride) + kAlign)
+    if (!ws || ws_bytes < kSyncBytes + img + gimg + delta_buffer_bytes(C, M, N, p->stride) + kAlign)
       return SGWLS_E_WORKSPACE;
+    clear_hip_error();
     hipStream_t s = (hipStream_t)stream;
-    float* tmp = reinterpret_cast<float*>(ws);
-    float* gT = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + img);
+    char* base = reinterpret_cast<char*>(ws) + kSyncBytes;
+    float* tmp = reinterpret_cast<float*>(base);
+    float* gT = reinterpret_cast<float*>(base + img);
     // the strip buffer holds 16-byte records: start it on an aligned address
-    const uintptr_t b0 = reinterpret_cast<uintptr_t>(ws) + img + gimg;
+    const uintptr_t b0 = reinterpret_cast<uintptr_t>(base) + img + gimg;
     float* buf = reinterpret_cast<float*>((b0 + kAlign - 1) / kAlign * kAlign);
     if (launch_transpose(g, gT, M, N, s) != hipSuccess) return SGWLS_E_HIP;
     const WeightParams wp = weight_params(*p);
@@ -657,12 +683,14 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u, int C, int M
     return SGWLS_OK;
   }
   const size_t img = image_bytes(C, M, N), gimg = image_bytes(1, M, N);
-  const size_t need = img + gimg + iface_bytes_all(C, M, N, *p);
+  const size_t need = kSyncBytes + img + gimg + iface_bytes_all(C, M, N, *p);
   if (!ws || ws_bytes < need) return SGWLS_E_WORKSPACE;
+  clear_hip_error();
   hipStream_t s = (hipStream_t)stream;
-  float* tmp = reinterpret_cast<float*>(ws);
-  float* gT = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + img);
-  void* iface = reinterpret_cast<char*>(ws) + img + gimg;
+  char* base = reinterpret_cast<char*>(ws) + kSyncBytes;
+  float* tmp = reinterpret_cast<float*>(base);
+  float* gT = reinterpret_cast<float*>(base + img);
+  void* iface = base + img + gimg;
   const size_t plane = (size_t)C * M * N;
   const int passes = 2 * p->iters;
   // Strided forward calls without saved inputs also run as frames: their
@@ -673,7 +701,13 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u, int C, int M
     // -- and writes the image layout again.  Without saved, pass 2t writes tmp
     // and pass 2t+1 writes u; with saved, pass q writes saved[q+1] (so odd
     // entries hold transposed images) and the last pass writes u.
-    if (launch_transpose(g, gT, M, N, s) != hipSuccess) return SGWLS_E_HIP;
+    // The guidance transpose also zeroes the window counters of the
+    // one-launch passes (each completed pass leaves them zero).
+    if (launch_transpose(g, gT, M, N, s, 1, 0, sync_counters(ws), sync_words(M, N, p->r)) !=
+        hipSuccess)
+      return SGWLS_E_HIP;
+    bool zeroed = true;
+    const FusedCtl ctl{ws, &zeroed, spin_limit_value().load()};
     if (saved && hipMemcpyAsync(saved, f, sizeof(float) * plane, hipMemcpyDeviceToDevice, s) !=
                      hipSuccess)
       return SGWLS_E_HIP;
@@ -682,7 +716,7 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u, int C, int M
       const bool even = q % 2 == 0;
       float* y = q == passes - 1 ? u : saved ? saved + (size_t)(q + 1) * plane : even ? tmp : u;
       st = enqueue_pass(0, x, even ? g : gT, y, C, even ? M : N, even ? N : M, *p, lambda_dev,
-                        iface, s, kStageAll | kStageTransposeOut);
+                        iface, s, kStageAll | kStageTransposeOut, -1, &ctl);
       if (st != SGWLS_OK) return st;
       x = y;
     }
@@ -755,8 +789,13 @@ sgwls_status sgwls_autotune(const float* x, const float* g, float* y, int C, int
   const sgwls_params pr = resolved(*p, 0);
   p = &pr;
   if (!x || !g || !y || y == x || (const float*)y == g || reps < 1) return SGWLS_E_ARG;
-  const size_t need = std::max(pass_iface_bytes(0, C, M, N, *p), pass_iface_bytes(1, C, M, N, *p));
+  const size_t need =
+      kSyncBytes + std::max(pass_iface_bytes(0, C, M, N, *p), pass_iface_bytes(1, C, M, N, *p));
   if (!ws || ws_bytes < need) return SGWLS_E_WORKSPACE;
+  clear_hip_error();
+  void* iface = reinterpret_cast<char*>(ws) + kSyncBytes;
+  bool zeroed = false;
+  const FusedCtl ctl{ws, &zeroed, spin_limit_value().load()};
   if (chosen)
     for (int i = 0; i < 4; ++i) chosen[i] = -1;
   if (p->stride != 1) return SGWLS_OK;   // strided passes have a single kernel
@@ -792,11 +831,12 @@ sgwls_status sgwls_autotune(const float* x, const float* g, float* y, int C, int
           for (int f = 0; f < (frames ? 2 : 1); ++f) {
             const int Mf = f == 0 ? M : N, Nf = f == 0 ? N : M;
             const int Lf = dir == 0 ? Mf : Nf, Wf = dir == 0 ? Nf : Mf;
-            const PassPlan pl = make_plan(Lf, Wf, p->r, cb, p->stride, p->prec, v);
+            PassPlan pl = make_plan(Lf, Wf, p->r, cb, p->stride, p->prec, v);
+            if (frames) pl.fused = &ctl;   // the filter's passes run as one launch where they can
             PassGeom geo = pass_geom(dir, Mf, Nf, pl, p->stride);
             geo.out_t = frames ? 1 : 0;
             const hipError_t e = launch_pass(p->r, cb, p->prec, x, g, y, c0, geo, pl, wp, nullptr,
-                                             p->lambda, ws, s, kStageAll);
+                                             p->lambda, iface, s, kStageAll);
             if (e != hipSuccess) return e;
           }
           return hipSuccess;
@@ -898,6 +938,7 @@ sgwls_status sgwls_pass_backward(int direction, const float* x, const float* g,
     return SGWLS_E_ARG;
   const BwdLayout lay = bwd_layout(C, M, N, *p);
   if (!ws || ws_bytes < lay.total) return SGWLS_E_WORKSPACE;
+  clear_hip_error();
   bool first = true;
   return enqueue_pass_backward(direction, x, g, ybar, xbar, gbar, grad_lambda, C, M, N, *p,
                                lambda_dev, ws, lay, (hipStream_t)stream, first);
@@ -919,6 +960,7 @@ sgwls_status sgwls_backward(const float* g, const float* saved, const float* gra
     return SGWLS_E_ARG;
   const BwdLayout lay = bwd_layout(C, M, N, *p);
   if (!ws || ws_bytes < lay.total) return SGWLS_E_WORKSPACE;
+  clear_hip_error();
   hipStream_t s = (hipStream_t)stream;
   float* tmp = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + lay.img_off);
   const size_t plane = (size_t)C * M * N;
@@ -997,6 +1039,7 @@ sgwls_status sgwls_filter_batched_variant(const sgwls_image* imgs, const sgwls_p
   }
   if (variant >= batch_variant_count(probe.fp64)) return SGWLS_E_ARG;
   if (!ws || ws_bytes < sgwls_batched_workspace_bytes(imgs, p, B)) return SGWLS_E_WORKSPACE;
+  clear_hip_error();
   BatchPlan plan;
   st = batch_plan(imgs, p, B, variant, ws, plan);
   if (st != SGWLS_OK) return st;
@@ -1019,16 +1062,19 @@ sgwls_status sgwls_interpolate(const float* f, const float* h, const float* g, f
   const size_t stack = image_bytes(C + 1, M, N);
   const size_t need = sgwls_interpolate_workspace_bytes(C, M, N, p);
   if (!ws || ws_bytes < need) return SGWLS_E_WORKSPACE;
+  clear_hip_error();
   hipStream_t s = (hipStream_t)stream;
-  // [S(f); S(h)] by one filter call over the stacked planes, filtered in place.
-  float* X = reinterpret_cast<float*>(ws);
+  // [S(f); S(h)] by one filter call over the stacked planes, filtered in
+  // place; the filter's workspace comes first (its synchronisation area at
+  // the start of ws), the stacked planes after it.
+  const size_t inner = need - stack;
+  float* X = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + inner);
   const size_t plane = (size_t)M * N;
   if (hipMemcpyAsync(X, f, sizeof(float) * C * plane, hipMemcpyDeviceToDevice, s) != hipSuccess ||
       hipMemcpyAsync(X + C * plane, h, sizeof(float) * plane, hipMemcpyDeviceToDevice, s) !=
           hipSuccess)
     return SGWLS_E_HIP;
-  st = sgwls_filter(X, g, X, C + 1, M, N, p, lambda_dev, nullptr,
-                    reinterpret_cast<char*>(ws) + stack, ws_bytes - stack, stream);
+  st = sgwls_filter(X, g, X, C + 1, M, N, p, lambda_dev, nullptr, ws, inner, stream);
   if (st != SGWLS_OK) return st;
   return launch_divide_planes(X, X + C * plane, u, C, (long long)plane, s) == hipSuccess
              ? SGWLS_OK
@@ -1048,6 +1094,7 @@ sgwls_status sgwls_autotune_batched(const sgwls_image* imgs, const sgwls_params*
   if (st != SGWLS_OK) return st;
   if (reps < 1) return SGWLS_E_ARG;
   if (!ws || ws_bytes < sgwls_batched_workspace_bytes(imgs, p, B)) return SGWLS_E_WORKSPACE;
+  clear_hip_error();
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -1081,6 +1128,22 @@ sgwls_status sgwls_autotune_batched(const sgwls_image* imgs, const sgwls_params*
   }
   if (chosen) *chosen = best;
   return SGWLS_OK;
+}
+
+void sgwls_set_spin_limit(unsigned int polls) { spin_limit_value().store(polls); }
+
+sgwls_status sgwls_workspace_status(void* ws, void* stream) {
+  if (!ws) return SGWLS_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned int word = 0;
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipMemcpy(&word, sync_err(ws), sizeof(word), hipMemcpyDeviceToHost) != hipSuccess)
+    return SGWLS_E_HIP;
+  if (word != kSyncErrMagic) return SGWLS_OK;
+  const unsigned int clear = 0;
+  if (hipMemcpy(sync_err(ws), &clear, sizeof(clear), hipMemcpyHostToDevice) != hipSuccess)
+    return SGWLS_E_HIP;
+  return SGWLS_E_HIP;
 }
 
 int sgwls_batched_graph_count(void) {

@@ -790,15 +790,31 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce(
                                                  c0, pitch, sum, blockIdx.x, blockIdx.y, smem);
 }
 
+// Loads and stores of interface data.  COH: the data is exchanged between
+// workgroups of one launch (possibly on different XCDs, whose L2 caches are
+// not coherent with each other), so it is written through to and read from
+// the device-coherent level (agent-scope relaxed atomic accesses, one word
+// each); otherwise plain accesses (the data crosses a kernel boundary).
+template <bool COH, typename T>
+DEV T ld(const T* p) {
+  if constexpr (COH) return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return *p;
+}
+template <bool COH, typename T>
+DEV void st(T* p, T v) {
+  if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else *p = v;
+}
+
 // ---------------------------------------------------------------------------
 // Separator system of one strip: Sigma_jj = W_j - TT_{j+1},
 // Sigma_{j,j+1}[a][c] = TB_{j+1}[c][a], rhs_j = Rf_j - RT_{j+1}, j = 0..P-2.
-template <int r, int CB, typename Acc>
+template <int r, int CB, typename Acc, bool COH = false>
 struct SepReader {
   using LY = IfaceLayout<r, CB>;
   const Acc* S;   // this strip's contributions
   int P;
-  DEV Acc at(int j, int f) const { return S[(size_t)j * LY::F + f]; }
+  DEV Acc at(int j, int f) const { return ld<COH>(S + (size_t)j * LY::F + f); }
   DEV void diag(int j, Acc (&A)[r][r]) const {
     int t = 0;
 #pragma unroll
@@ -829,7 +845,7 @@ struct SepReader {
 // of one strip (indices past the last chunk read the last one), loaded
 // together before the elimination so that their latency is paid once.
 // Calls index chunks absolutely; the indices are s plus compile-time offsets.
-template <int r, int CB, int NREC, typename Acc>
+template <int r, int CB, int NREC, typename Acc, bool COH = false>
 struct PreReader {
   using LY = IfaceLayout<r, CB>;
   Acc rec[NREC][LY::F];
@@ -842,7 +858,7 @@ struct PreReader {
       if (i < nrec) {
         const int jj = min(s + i, P - 1);
 #pragma unroll
-        for (int f = 0; f < LY::F; ++f) rec[i][f] = S[(size_t)jj * LY::F + f];
+        for (int f = 0; f < LY::F; ++f) rec[i][f] = ld<COH>(S + (size_t)jj * LY::F + f);
       }
     }
   }
@@ -958,7 +974,7 @@ DEV void iface_pcr_levels(const Acc (&S)[r][r], const Acc (&Bt)[r][r], const Acc
 // k_interface_pcr: one wave per strip, lane l owns separator blocks
 // [l*m, min(l*m + m, P-1)); MM is the compiled maximum of m.
 // U receives the separator solutions strip-major: U[(ki*(P-1) + j)*r*CB + a*CB + h].
-template <int r, int CB, int MM, typename Acc, class Reader>
+template <int r, int CB, int MM, typename Acc, class Reader, bool COH = false>
 DEV void iface_pcr_run(const Reader& rd, Acc* __restrict__ U, int P, int m, int ki) {
   const int lane = threadIdx.x % kWave;
   const int n = P - 1;
@@ -1064,7 +1080,7 @@ DEV void iface_pcr_run(const Reader& rd, Acc* __restrict__ U, int P, int m, int 
 #pragma unroll
   for (int a = 0; a < r; ++a)
 #pragma unroll
-    for (int h = 0; h < CB; ++h) out[(size_t)(e - 1) * r * CB + a * CB + h] = X[a][h];
+    for (int h = 0; h < CB; ++h) st<COH>(out + (size_t)(e - 1) * r * CB + a * CB + h, X[a][h]);
   // back substitution: x_b = S_b^-1 (R_b - U_b x_{b+1} - Bt_b x_T)
   Acc xn[r][CB];
 #pragma unroll
@@ -1090,7 +1106,7 @@ DEV void iface_pcr_run(const Reader& rd, Acc* __restrict__ U, int P, int m, int 
       for (int a = 0; a < r; ++a)
 #pragma unroll
         for (int h = 0; h < CB; ++h) {
-          out[(size_t)b * r * CB + a * CB + h] = v[a][h];
+          st<COH>(out + (size_t)b * r * CB + a * CB + h, v[a][h]);
           xn[a][h] = v[a][h];
         }
     }
@@ -1099,17 +1115,17 @@ DEV void iface_pcr_run(const Reader& rd, Acc* __restrict__ U, int P, int m, int 
 
 // The solver of one strip: its chunk records prefetched into registers
 // when the lane's run fits (MM + 1 records), else read as needed.
-template <int r, int CB, int MM, typename Acc>
+template <int r, int CB, int MM, typename Acc, bool COH = false>
 DEV void iface_pcr_strip(const Acc* __restrict__ sum, Acc* __restrict__ U, int P, int m, int ki) {
   using LY = IfaceLayout<r, CB>;
   const Acc* S = sum + (size_t)ki * P * LY::F;
   if constexpr ((MM + 1) * LY::F <= 160) {
-    PreReader<r, CB, MM + 1, Acc> rd;
+    PreReader<r, CB, MM + 1, Acc, COH> rd;
     rd.load(S, (int)(threadIdx.x % kWave) * m, P, m + 1);
-    iface_pcr_run<r, CB, MM, Acc>(rd, U, P, m, ki);
+    iface_pcr_run<r, CB, MM, Acc, PreReader<r, CB, MM + 1, Acc, COH>, COH>(rd, U, P, m, ki);
   } else {
-    const SepReader<r, CB, Acc> rd{S, P};
-    iface_pcr_run<r, CB, MM, Acc>(rd, U, P, m, ki);
+    const SepReader<r, CB, Acc, COH> rd{S, P};
+    iface_pcr_run<r, CB, MM, Acc, SepReader<r, CB, Acc, COH>, COH>(rd, U, P, m, ki);
   }
 }
 

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#define DEV_HOST_INLINE __host__ __device__ inline
+
 namespace sgwls {
 
 constexpr int kMaxR = 4;     // largest neighbourhood radius compiled in
@@ -99,6 +101,29 @@ constexpr VariantSet variants_for(int mode, int r, int cb, int fp64) {
   return mode == kModeBackward ? bwd_variants_of(r, cb, fp64) : variants_of(r, cb, fp64);
 }
 
+// Synchronisation area at the start of every single-image workspace: the
+// sticky error word of the one-launch pass (kSyncErrMagic after a wait gave
+// up; any other value means no error), then three counters per window
+// (contributions written, separators written, units done), each window's on
+// a line of its own.  The last unit of
+// a window to finish zeroes its counters, so a completed one-launch pass
+// leaves them zero for the next one.
+constexpr int kMaxWindows = 2048;   // windows of a pass: ceil(65536 / (64 - 2r)) < 2048
+constexpr int kSyncStride = 64;     // words between the counters of two windows (own line)
+constexpr int kSyncWords = kSyncStride * kMaxWindows;
+constexpr size_t kSyncBytes = 256 + sizeof(unsigned int) * kSyncWords;
+constexpr unsigned int kSyncErrMagic = 0x53475731u;
+DEV_HOST_INLINE unsigned int* sync_err(void* ws) { return reinterpret_cast<unsigned int*>(ws); }
+DEV_HOST_INLINE unsigned int* sync_counters(void* ws) {
+  return reinterpret_cast<unsigned int*>(reinterpret_cast<char*>(ws) + 256);
+}
+
+// Host state of the one-launch pass within one call.
+struct FusedCtl {
+  void* ws;              // workspace (synchronisation area at its start)
+  bool* zeroed;          // whether the counters are known to be zero on the stream
+  unsigned int limit;    // polls per wait before giving up
+};
 // Launch configuration of one (r, channel block, precision, stride, variant).
 struct PassPlan {
   int mode;         // kModeForward or kModeBackward
@@ -115,6 +140,7 @@ struct PassPlan {
   size_t sum_elems, u_elems;   // interface buffer sizes (elements)
   size_t g_elems;              // scratch of the long-run interface solver (elements)
   int acc_bytes;    // 4 (float) or 8 (double) interface element size
+  const FusedCtl* fused;       // set by the caller to allow the one-launch pass
 };
 
 // Cancellation-free float32 mode at r = 1 (sgwls_delta.hip): one serial
@@ -147,6 +173,9 @@ bool frames_supported(int C, int r, int stride, int fp64);
 constexpr int kStageReduce = 1, kStageInterface = 2, kStageExpand = 4, kStageAll = 7;
 // With the stage mask: store the pass output transposed (see PassGeom::out_t).
 constexpr int kStageTransposeOut = 8;
+// With the stage mask: the window counters of the workspace are known to be
+// zero (a one-launch pass on it completed), so they are not cleared first.
+constexpr int kStageSyncZero = 16;
 
 // Extra operands of a backward pass (all device pointers).
 struct BwdArgs {
@@ -227,7 +256,10 @@ hipError_t launch_batch_pass(int variant, int fp64, int kind, int r, const Batch
 // dst (cols x rows) = transpose of src (rows x cols), `planes` planes; with
 // accumulate, dst += the transpose.
 hipError_t launch_transpose(const float* src, float* dst, int rows, int cols, hipStream_t stream,
-                            int planes = 1, int accumulate = 0);
+                            int planes = 1, int accumulate = 0, unsigned int* zero = nullptr,
+                            int nzero = 0);
+// dst[0..n) = 0, ordered on the stream (no memset node in captured graphs).
+hipError_t launch_zero_words(unsigned int* dst, int n, hipStream_t stream);
 
 // u[c] = num[c] / den for c < C (planes of `plane` floats).
 hipError_t launch_divide_planes(const float* num, const float* den, float* u, int C,

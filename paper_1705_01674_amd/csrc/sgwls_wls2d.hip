@@ -272,6 +272,7 @@ sgwls_status sgwls_wls2d(const float* f, const float* g, float* u, int C, int M,
     return SGWLS_E_ARG;
   const CgLayout l = cg_layout(C, M, N);
   if (!ws || ws_bytes < l.total) return SGWLS_E_WORKSPACE;
+  (void)hipGetLastError();   // report only this call's launch errors
   hipStream_t s = (hipStream_t)stream;
   char* base = reinterpret_cast<char*>(ws);
   float* res = reinterpret_cast<float*>(base + l.res);

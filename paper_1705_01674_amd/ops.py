@@ -233,6 +233,40 @@ def sgwls_pass(direction: int, x: torch.Tensor, g: torch.Tensor, p: Params, *,
     return out
 
 
+def sgwls_pass_stages(stages: int, direction: int, x: torch.Tensor, g: torch.Tensor, p: Params, *,
+                      lambda_dev: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                      workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """The stages of one pass (see sgwls_pass_stages in sgwls.h): mask bits
+    1 reduce, 2 interface, 4 expand, 8 transposed output, 16 counters known
+    zero.  With a shared workspace, masks 1, 2 and 4 called in order compute
+    one pass; mask 7 + 8 runs it as one launch where that applies."""
+    C, M, N = _image(x, "x")
+    dev = x.device
+    _guidance(g, M, N, dev)
+    lam = _lambda(lambda_dev, dev)
+    if out is None:
+        out = torch.empty_like(x)
+    nbytes = workspace_bytes(C, M, N, p)
+    ws = workspace if workspace is not None else _workspace(nbytes, dev)
+    if ws.numel() < nbytes or ws.device != dev:
+        raise ValueError("workspace too small")
+    nat.check(nat.lib.sgwls_pass_stages(int(stages), int(direction), _ptr(x), _ptr(g), _ptr(out), C, M,
+                                        N, ctypes.byref(p.c()), _ptr(lam), _ptr(ws), ws.numel(),
+                                        _stream(dev)),
+              "sgwls_pass_stages")
+    return out
+
+
+def workspace_status(workspace: torch.Tensor) -> int:
+    """Synchronises the current stream; 0 if no wait of a one-launch pass on
+    this workspace gave up since the last check, else the error status."""
+    return int(nat.lib.sgwls_workspace_status(_ptr(workspace), _stream(workspace.device)))
+
+
+def set_spin_limit(polls: int) -> None:
+    nat.lib.sgwls_set_spin_limit(int(polls))
+
+
 # ---------------------------------------------------------------------------
 # Gradients.
 

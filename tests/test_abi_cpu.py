@@ -318,7 +318,8 @@ def test_delta_mode_is_filter_only(nat):
     strips = max((N - 2) * 3 * M, (M - 2) * 3 * N)     # stride 1: W - 2 strips of 3L elements
     img = (4 * C * M * N + 255) // 256 * 256
     gimg = (4 * M * N + 255) // 256 * 256                # the transposed guidance
-    want = img + gimg + 4 * 4 * strips + 256            # 16-byte records, aligned start
+    sync = 256 + 4 * 64 * 2048                          # the one-launch pass's counters
+    want = sync + img + gimg + 4 * 4 * strips + 256     # 16-byte records, aligned start
     assert nat.lib.sgwls_workspace_bytes(C, M, N, ctypes.byref(p), 0) == want
     assert nat.lib.sgwls_workspace_bytes(C, M, N, ctypes.byref(P(nat, prec=2, r=2)), 0) == 0
     assert nat.lib.sgwls_backward_workspace_bytes(C, M, N, ctypes.byref(p)) == 0

@@ -101,7 +101,7 @@ def test_graph_capture_and_replays(ops):
     side = torch.cuda.Stream()
     fs = [torch.from_numpy(f).cuda() for f, _, _ in items]
     gs = [torch.from_numpy(g).cuda() for _, g, _ in items]
-    ps = [ops.Params(**pd) for _, _, pd in items]
+    ps = [ops.Params(**pd, prec="fp32") for _, _, pd in items]   # as run_batch's eager call
     outs = [torch.empty_like(f) for f in fs]
     ws = torch.empty(ops.batched_workspace_bytes(fs, gs, ps), dtype=torch.uint8, device="cuda")
     for rep in range(4):
