@@ -219,6 +219,21 @@ sgwls_status sgwls_workspace_status(void* ws, void* stream);
  * default 2^17, a fraction of a second).  For tests of the error path. */
 void sgwls_set_spin_limit(unsigned int polls);
 
+/* ---- sgwls_filter without a caller workspace ----
+ * For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): sgwls_filter with
+ * its workspace in a static device array of SGWLS_NOALLOC_MAX_BYTES bytes
+ * that the library holds on every device it runs on until the process ends.
+ * The call allocates nothing.  Arguments as sgwls_filter; SGWLS_E_WORKSPACE
+ * (nothing enqueued) when sgwls_workspace_bytes(C, M, N, p, saved != NULL)
+ * exceeds the array (1080 x 1920 RGB fits with either precision).  Every call
+ * on one device uses the same array: calls that overlap on one device (other
+ * streams, other host threads) race and must be serialised by the caller. */
+#define SGWLS_NOALLOC_MAX_BYTES ((size_t)96 << 20)
+sgwls_status sgwls_filter_noalloc(const float* f, const float* g, float* u,
+                                  int C, int M, int N, const sgwls_params* p,
+                                  const float* lambda_dev, float* saved, void* stream);
+
 /* ---- Guided sparse interpolation (Eq. 21) ----
  * u = S(f) / S(h) channel by channel, where S is the SG-WLS filter with
  * guidance g and parameters p (Sec. 2.3) standing in for the inverse of the

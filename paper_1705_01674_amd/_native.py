@@ -25,7 +25,7 @@ EXPORTS = ["sgwls_status_str", "sgwls_version", "sgwls_validate", "sgwls_workspa
            "sgwls_autotune_batched", "sgwls_batched_graph_count", "sgwls_batched_graph_clear",
            "sgwls_interpolate_workspace_bytes", "sgwls_interpolate",
            "sgwls_wls2d_workspace_bytes", "sgwls_wls2d", "sgwls_resolve_precision",
-           "sgwls_workspace_status", "sgwls_set_spin_limit"]
+           "sgwls_workspace_status", "sgwls_set_spin_limit", "sgwls_filter_noalloc"]
 
 
 class SgwlsParams(ctypes.Structure):
@@ -64,6 +64,8 @@ def _load():
     lib.sgwls_resolve_precision.argtypes = [P, i]
     lib.sgwls_workspace_status.restype = i
     lib.sgwls_workspace_status.argtypes = [vp, vp]
+    lib.sgwls_filter_noalloc.restype = i
+    lib.sgwls_filter_noalloc.argtypes = [vp, vp, vp, i, i, i, P, vp, vp, vp]
     lib.sgwls_set_spin_limit.restype = None
     lib.sgwls_set_spin_limit.argtypes = [ctypes.c_uint]
     lib.sgwls_pass.restype = i

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsgwls.so")
 SOURCES = ["sgwls_pass_r1.hip", "sgwls_pass_r2.hip", "sgwls_pass_r3.hip", "sgwls_pass_r4.hip",
            "sgwls_aux.hip", "sgwls_batch.hip", "sgwls_wls2d.hip", "sgwls_delta.hip",
-           "sgwls_plan.cpp", "sgwls_api.cpp"]
+           "sgwls_noalloc.hip", "sgwls_plan.cpp", "sgwls_api.cpp"]
 ARCH = os.environ.get("SGWLS_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled for all device code.
