@@ -37,6 +37,15 @@ Prints ONE JSON line:
              VALU-busy fraction of each stage from the committed counter
              summary (null when it was taken on other sources); these radii
              carry several times the arithmetic per byte of r = 1
+  configs    the other workloads: grey 256x256 (r = 1, T = 1, lambda 1), RGB
+             768x1024 (r = 1, T = 3, lambda 4) forward, and 16 RGB 512x512
+             images (r = 1, T = 3, learnable lambda = 8, MSE loss) forward +
+             backward through the autograd function; MPixel/s and algorithmic
+             bytes / time vs 8 TB/s each
+The default precision is automatic (float32 where the host bound on
+lambda * omega allows it; FP64 pivots for calls that save pass inputs for a
+lambda gradient): fwd_bwd is that default, fwd_bwd_fp32 the same step in
+explicit float32.
 """
 from __future__ import annotations
 
@@ -150,7 +159,7 @@ def radius_rows(torch, ops, nat, synth, dev, args, counters=False):
     for r in ((1, 2, 3) if counters else (2, 3)):
         w = synth.rgb1080p(r=r, lam=16.0)
         C, M, N = w.f.shape
-        p = ops.Params(**w.params)
+        p = ops.Params(**w.params, prec="fp32")
         f = torch.from_numpy(w.f).to(dev)
         g = torch.from_numpy(w.g).to(dev)
         u = torch.empty_like(f)
@@ -181,7 +190,8 @@ def radius_rows(torch, ops, nat, synth, dev, args, counters=False):
         ms64 = time_events(torch, step64, max(5, args.steps // 5))
         alg = (8 * C + 4) * M * N * 2 * p.iters
         _, st, _ = stage_times(torch, nat, f, g, p, ws, max(10, args.steps // 5))
-        rows.append({"workload": w.name, "r": r, "iters": p.iters, "lambda": p.lam,
+        rows.append({"workload": w.name, "r": r, "iters": p.iters, "lambda": p.lam, "prec": "fp32",
+                     "default_precision": ops.resolve_precision(ops.Params(**w.params)),
                      "ms_per_step": round(ms, 5), "value": round(M * N / (ms * 1e-3) / 1e6, 2),
                      "unit": "MPixel/s", "alg_GBps": round(alg / (ms * 1e-3) / 1e9, 1),
                      "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -388,6 +398,49 @@ def bench_batched(torch, ops, synth, args):
             "per_image_loop_ms": round(ms_loop, 4), "speedup_vs_loop": round(ms_loop / ms, 3)}
 
 
+def config_rows(torch, ops, synth, dev, args):
+    """The other workloads: grey 256^2 (r=1, T=1) and RGB 768x1024 (r=1, T=3)
+    forward, and the 16 x 3 x 512^2 differentiation batch forward + backward
+    through the autograd function (learnable lambda, MSE loss to the seeded
+    noise-free targets), in the default precision and in float32."""
+    rows = []
+    for w in (synth.grey256(), synth.rgb768x1024()):
+        t = time_workload(torch, ops, w, dev, args.steps, args.warmup)
+        C, M, N = w.f.shape
+        alg = (8 * C + 4) * M * N * 2 * w.params["iters"]
+        t["precision"] = ops.resolve_precision(ops.Params(**w.params))
+        t["hbm_frac"] = round(alg / (t["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        rows.append(t)
+    B, C, M, N = 16, 3, 512, 512
+    fs, gs, ts = synth.rgb_batch_with_target(B=B, M=M, N=N)
+    f = torch.from_numpy(fs).to(dev)
+    g = torch.from_numpy(gs).to(dev)
+    tgt = torch.from_numpy(ts).to(dev)
+    alg = ((8 * C + 4) + (12 * C + 8)) * M * N * B * 2 * 3
+    for prec in ("auto", "fp32"):
+        p = ops.Params(lam=8.0, r=1, iters=3, sigma_r=0.1, prec=prec)
+        ft = f.clone().requires_grad_(True)
+        gt = g.clone().requires_grad_(True)
+        lam = torch.tensor([8.0], device=dev, requires_grad=True)
+
+        def step():
+            ft.grad = gt.grad = lam.grad = None
+            u = ops.sgwls(ft, gt, lam, p)
+            ((u - tgt) ** 2).mean().backward()
+
+        for _ in range(max(2, args.warmup // 2)):
+            step()
+        ms = time_events(torch, step, max(3, args.steps // 4))
+        rows.append({"workload": "diff16x3x512x512_r1_T3_lam8", "B": B, "C": C, "M": M, "N": N,
+                     "r": 1, "iters": 3, "prec": prec,
+                     "precision": ops.resolve_precision(p.with_(lam=8.0), True) if prec == "auto" else prec,
+                     "step": "forward + MSE loss + backward (grad f, g, lambda) via ops.sgwls",
+                     "ms_per_step": round(ms, 4), "value": round(B * M * N / (ms * 1e-3) / 1e6, 2),
+                     "unit": "MPixel/s", "alg_GBps": round(alg / (ms * 1e-3) / 1e9, 1),
+                     "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+    return rows
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -463,7 +516,8 @@ def main():
     # loss to a seeded target, computed once outside the timed region).
     saved = torch.empty((2 * p.iters, C, M, N), dtype=torch.float32, device=dev)
     ws_b = torch.empty(ops.backward_workspace_bytes(C, M, N, p), dtype=torch.uint8, device=dev)
-    ops.sgwls_filter(f, g, p, saved=saved, out=u, workspace=ws)
+    ws_s = torch.empty(ops.workspace_bytes(C, M, N, p, True), dtype=torch.uint8, device=dev)
+    ops.sgwls_filter(f, g, p, saved=saved, out=u, workspace=ws_s)
     tgt = torch.from_numpy(synth.image(M, N, C, 200, 0.0, 1000, sinus=True)).to(dev)
     ubar = (2.0 / u.numel()) * (u - tgt)
     grad_f = torch.empty_like(f)
@@ -471,7 +525,7 @@ def main():
     grad_l = torch.empty(1, dtype=torch.float64, device=dev)
 
     def step_fb():
-        ops.sgwls_filter(f, g, p, saved=saved, out=u, workspace=ws)
+        ops.sgwls_filter(f, g, p, saved=saved, out=u, workspace=ws_s)
         ops.sgwls_backward(g, saved, ubar, p, grad_f=grad_f, grad_g=grad_g, grad_lambda=grad_l,
                            workspace=ws_b)
 
@@ -487,6 +541,27 @@ def main():
     torch.cuda.synchronize()
     gpu_grads = (grad_f.cpu().numpy().astype(np.float64), grad_g.cpu().numpy().astype(np.float64),
                  float(grad_l.item()))
+
+    # The same step in explicit float32 (no lambda-gradient precision rule).
+    p32 = p.with_(prec="fp32")
+    ws_s32 = torch.empty(ops.workspace_bytes(C, M, N, p32, True), dtype=torch.uint8, device=dev)
+    ws_b32 = torch.empty(ops.backward_workspace_bytes(C, M, N, p32), dtype=torch.uint8, device=dev)
+    grad_f32, grad_g32 = torch.empty_like(f), torch.empty_like(g)
+    grad_l32 = torch.empty(1, dtype=torch.float64, device=dev)
+    u32 = torch.empty_like(f)
+
+    def step_fb32():
+        ops.sgwls_filter(f, g, p32, saved=saved, out=u32, workspace=ws_s32)
+        ops.sgwls_backward(g, saved, ubar, p32, grad_f=grad_f32, grad_g=grad_g32,
+                           grad_lambda=grad_l32, workspace=ws_b32)
+
+    for _ in range(args.warmup):
+        step_fb32()
+    ms_fb32 = time_events(torch, step_fb32, args.steps)
+    step_fb32()
+    torch.cuda.synchronize()
+    gpu_grads32 = (grad_f32.cpu().numpy().astype(np.float64),
+                   grad_g32.cpu().numpy().astype(np.float64), float(grad_l32.item()))
 
     # Float64 pivots and recurrences on the same workload.
     p64 = p.with_(prec="fp64_pivot")
@@ -527,6 +602,8 @@ def main():
               time_interpolation(torch, ops, synth.colorize_scribbles(1024, 1024, 120), dev,
                                  alt_steps, args.warmup)]
 
+    configs = config_rows(torch, ops, synth, dev, args)
+
     # Accuracy of this very output against the oracle, and the CPU baseline.
     step()
     torch.cuda.synchronize()
@@ -536,6 +613,7 @@ def main():
     max_rel64 = None
     max_reld = None
     grad_err = None
+    grad_err32 = None
     if not args.no_cpu_baseline:
         import oracle
         P = oracle.OracleParams(**w.params)
@@ -565,9 +643,12 @@ def main():
         max_reld = float(np.abs(ud.cpu().numpy().astype(np.float64) - ref).max() / np.abs(ref).max())
         _, ref_saved = oracle.filter(f64, g64, P, save=True)
         rf, rg, rl = oracle.filter_backward(g64, ref_saved, ubar.cpu().numpy().astype(np.float64), P)
-        grad_err = {"grad_f": float(np.abs(gpu_grads[0] - rf).max() / np.abs(rf).max()),
-                    "grad_g": float(np.abs(gpu_grads[1] - rg).max() / np.abs(rg).max()),
-                    "grad_lambda": abs(gpu_grads[2] - rl) / abs(rl)}
+        def gerr(gr):
+            return {"grad_f": float(np.abs(gr[0] - rf).max() / np.abs(rf).max()),
+                    "grad_g": float(np.abs(gr[1] - rg).max() / np.abs(rg).max()),
+                    "grad_lambda": abs(gr[2] - rl) / abs(rl)}
+        grad_err = gerr(gpu_grads)
+        grad_err32 = gerr(gpu_grads32)
 
     line = {
         "metric": "MPixel/s per SG-WLS filter (1080p RGB, r=1, tau=3) fwd",
@@ -596,13 +677,22 @@ def main():
                                   for (d, n), t in stage_ms.items()},
         "row_pass_as_transposed_column_pass": transposed,
         "filter_alg_GBps": round((8 * C + 4) * px * 2 * p.iters / (ms * 1e-3) / 1e9, 1),
+        "filter_hbm_frac": round((8 * C + 4) * px * 2 * p.iters / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "precision": ops.resolve_precision(p),
         "max_rel_err_vs_oracle": max_rel,
         "fwd_bwd": {"metric": "MPixel/s per SG-WLS filter (1080p RGB, r=1, tau=3) fwd+bwd",
+                    "precision": {"forward": ops.resolve_precision(p, True),
+                                  "backward": ops.resolve_precision(p, True)},
                     "value": round(M * N / (ms_fb * 1e-3) / 1e6, 2), "ms_per_step": round(ms_fb, 5),
                     "alg_bytes": fb_bytes,
                     "alg_GBps": round(fb_bytes / (ms_fb * 1e-3) / 1e9, 1),
                     "hbm_frac": round(fb_bytes / (ms_fb * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                     "max_rel_err_vs_oracle": grad_err},
+        "fwd_bwd_fp32": {"value": round(M * N / (ms_fb32 * 1e-3) / 1e6, 2),
+                         "ms_per_step": round(ms_fb32, 5),
+                         "alg_GBps": round(fb_bytes / (ms_fb32 * 1e-3) / 1e9, 1),
+                         "hbm_frac": round(fb_bytes / (ms_fb32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "max_rel_err_vs_oracle": grad_err32},
         "fp64_pivot": {"ms_per_step": round(ms64, 5), "value": round(M * N / (ms64 * 1e-3) / 1e6, 2),
                        "max_rel_err_vs_oracle": max_rel64},
         "fp32_delta": {"ms_per_step": round(msd, 5), "value": round(M * N / (msd * 1e-3) / 1e6, 2),
@@ -616,6 +706,7 @@ def main():
         "interpolation": interp,
         "wls2d": wls,
         "batched": batched,
+        "configs": configs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

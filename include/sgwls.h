@@ -311,7 +311,11 @@ sgwls_status sgwls_autotune(const float* x, const float* g, float* y, int C, int
 /* Persist / restore the tuning table (single-image and batched entries) as text, tagged with the library
  * version and the caller's device architecture name (e.g. "gfx950").  Load
  * rejects (SGWLS_E_ARG, table unchanged) a file with another version or
- * architecture or any malformed line. */
+ * architecture or any malformed line.  With the environment variable
+ * SGWLS_TUNE_CACHE naming a file, the library loads it at the first tuning
+ * lookup of the process (for the current device's architecture; a missing,
+ * stale or corrupt file is ignored) and saves the table to it after every
+ * sgwls_autotune / sgwls_autotune_batched call. */
 sgwls_status sgwls_tune_save(const char* path, const char* arch);
 sgwls_status sgwls_tune_load(const char* path, const char* arch);
 

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <list>
@@ -56,7 +57,9 @@ int size_bucket(int L, int W) {
 TuneKey tune_key(int r, int cb, int fp64, int kind, int dir, int L, int W) {
   return TuneKey(r, cb, fp64, kind, dir, size_bucket(L, W));
 }
+void tune_cache_load_once();
 int tuned_variant(int r, int cb, int fp64, int kind, int dir, int L, int W) {
+  tune_cache_load_once();
   std::lock_guard<std::mutex> lk(tune_mutex());
   auto it = tune_table().find(tune_key(r, cb, fp64, kind, dir, L, W));
   return it == tune_table().end() ? 0 : it->second;
@@ -517,6 +520,44 @@ sgwls_status batch_run(const BatchPlan& plan, void* ws, hipStream_t s) {
   return hipGraphLaunch(exec, s) == hipSuccess ? SGWLS_OK : SGWLS_E_HIP;
 }
 
+// Persisted tuning table: with SGWLS_TUNE_CACHE naming a file, the table is
+// loaded from it at the first lookup of a process (when the file matches this
+// library version and the current device's architecture; otherwise it is
+// ignored) and saved to it after every autotune call.
+std::string device_arch_name() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return "";
+  }
+  const std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+const char* tune_cache_path() {
+  const char* path = std::getenv("SGWLS_TUNE_CACHE");
+  return path && *path ? path : nullptr;
+}
+
+void tune_cache_load_once() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const char* path = tune_cache_path();
+    if (!path) return;
+    const std::string arch = device_arch_name();
+    if (!arch.empty()) (void)sgwls_tune_load(path, arch.c_str());
+  });
+}
+
+void tune_cache_save() {
+  const char* path = tune_cache_path();
+  if (!path) return;
+  const std::string arch = device_arch_name();
+  if (!arch.empty()) (void)sgwls_tune_save(path, arch.c_str());
+}
+
 double batch_pixels(const sgwls_image* imgs, int B) {
   double px = 0.0;
   for (int b = 0; b < B; ++b) px += (double)imgs[b].C * imgs[b].M * imgs[b].N;
@@ -799,6 +840,7 @@ sgwls_status sgwls_autotune(const float* x, const float* g, float* y, int C, int
   if (chosen)
     for (int i = 0; i < 4; ++i) chosen[i] = -1;
   if (p->stride != 1) return SGWLS_OK;   // strided passes have a single kernel
+  tune_cache_load_once();
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -862,6 +904,7 @@ sgwls_status sgwls_autotune(const float* x, const float* g, float* y, int C, int
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (result == SGWLS_OK) tune_cache_save();
   return result;
 }
 
@@ -1033,6 +1076,7 @@ sgwls_status sgwls_filter_batched_variant(const sgwls_image* imgs, const sgwls_p
   sgwls_status st = batch_plan(imgs, p, B, 0, nullptr, probe);
   if (st != SGWLS_OK) return st;
   if (variant < 0) {
+    tune_cache_load_once();
     std::lock_guard<std::mutex> lk(tune_mutex());
     auto it = tune_table().find(batch_tune_key(probe.fp64, probe.kind, batch_pixels(imgs, B)));
     variant = it == tune_table().end() ? 0 : it->second;
@@ -1126,6 +1170,7 @@ sgwls_status sgwls_autotune_batched(const sgwls_image* imgs, const sgwls_params*
     std::lock_guard<std::mutex> lk(tune_mutex());
     tune_table()[batch_tune_key(probe.fp64, probe.kind, batch_pixels(imgs, B))] = best;
   }
+  tune_cache_save();
   if (chosen) *chosen = best;
   return SGWLS_OK;
 }
