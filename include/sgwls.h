@@ -177,15 +177,10 @@ sgwls_status sgwls_pass(int direction, const float* x, const float* g, float* y,
  * stores the output transposed: y becomes C planes of N x M, pixel (i, j) of
  * the pass output at y[c*M*N + j*M + i].  sgwls_filter uses this form for
  * every stride-1 pass: each pass is then a column pass, of the image or of
- * its transpose.  With mask 7 + 8 the three stages run as ONE launch where
- * that applies (radius 1-2 and FP32 or FP64 pivots, separator runs short
- * enough for the register solver, and the units of one 64-strip window
- * fitting in an eighth of the chip): each workgroup keeps its chunks in
- * registers, and the window's workgroups wait for each other through
- * counters in the workspace, which are cleared first (one extra launch)
- * unless 16 is added to the mask, which asserts that the previous one-launch
- * pass on this workspace completed (it leaves them zero).  Other arguments
- * as sgwls_pass. */
+ * its transpose.  Calling masks 1, 2, 4 one at a time computes sgwls_pass
+ * for a channel count of one channel block (C = 1 or 3): with more, each
+ * stage runs over every block and the interface buffers hold the last one.
+ * Other arguments as sgwls_pass. */
 sgwls_status sgwls_pass_stages(int stages, int direction, const float* x, const float* g,
                                float* y, int C, int M, int N, const sgwls_params* p,
                                const float* lambda_dev, void* ws, size_t ws_bytes,
@@ -206,19 +201,6 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u,
                           const float* lambda_dev, float* saved,
                           void* ws, size_t ws_bytes, void* stream);
 
-/* Workspaces of sgwls_filter, sgwls_pass, sgwls_pass_stages and
- * sgwls_interpolate begin with a synchronisation area for the one-launch
- * pass: every wait there is bounded by a spin limit, and a wait that
- * exceeds it gives up (its pass output is then wrong) and marks the
- * workspace.  sgwls_workspace_status synchronises `stream`, returns
- * SGWLS_E_HIP if a call on ws gave up since the last check (and clears the
- * mark), SGWLS_OK otherwise. */
-sgwls_status sgwls_workspace_status(void* ws, void* stream);
-
-/* Polls per wait of the one-launch pass before it gives up (process-wide;
- * default 2^17, a fraction of a second).  For tests of the error path. */
-void sgwls_set_spin_limit(unsigned int polls);
-
 /* ---- sgwls_filter without a caller workspace ----
  * For callers that cannot allocate device memory (code under graph capture,
  * tight serving loops, harnesses that forbid allocation): sgwls_filter with
@@ -233,6 +215,27 @@ void sgwls_set_spin_limit(unsigned int polls);
 sgwls_status sgwls_filter_noalloc(const float* f, const float* g, float* u,
                                   int C, int M, int N, const sgwls_params* p,
                                   const float* lambda_dev, float* saved, void* stream);
+
+/* ---- NCHW batches of equal-shape images ----
+ * sgwls_filter and sgwls_backward over B images of one shape in each launch
+ * (the images stacked, blockIdx.z = image), with their own guidance images:
+ * f, u, grad_u, grad_f are B x C x M x N; g, grad_g are B x M x N; saved is
+ * B x 2T x C x M x N (image b's pass inputs at [b*2T*C*M*N ...], in the
+ * layout sgwls_filter documents).  grad_lambda receives the sum over the B
+ * images of their lambda gradients (one lambda shared by the batch, as for a
+ * learnable lambda), reduced in a fixed order.  Workspaces from the _nchw
+ * queries (0 if invalid).  B = 1 is exactly sgwls_filter / sgwls_backward.
+ * SGWLS_P_FP32_DELTA is single-image only (SGWLS_E_UNSUPPORTED for B > 1). */
+size_t sgwls_workspace_bytes_nchw(int B, int C, int M, int N, const sgwls_params* p,
+                                  int save_for_backward);
+sgwls_status sgwls_filter_nchw(const float* f, const float* g, float* u, int B, int C, int M,
+                               int N, const sgwls_params* p, const float* lambda_dev,
+                               float* saved, void* ws, size_t ws_bytes, void* stream);
+size_t sgwls_backward_workspace_bytes_nchw(int B, int C, int M, int N, const sgwls_params* p);
+sgwls_status sgwls_backward_nchw(const float* g, const float* saved, const float* grad_u,
+                                 float* grad_f, float* grad_g, double* grad_lambda, int B, int C,
+                                 int M, int N, const sgwls_params* p, const float* lambda_dev,
+                                 void* ws, size_t ws_bytes, void* stream);
 
 /* ---- Guided sparse interpolation (Eq. 21) ----
  * u = S(f) / S(h) channel by channel, where S is the SG-WLS filter with

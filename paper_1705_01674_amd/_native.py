@@ -25,7 +25,8 @@ EXPORTS = ["sgwls_status_str", "sgwls_version", "sgwls_validate", "sgwls_workspa
            "sgwls_autotune_batched", "sgwls_batched_graph_count", "sgwls_batched_graph_clear",
            "sgwls_interpolate_workspace_bytes", "sgwls_interpolate",
            "sgwls_wls2d_workspace_bytes", "sgwls_wls2d", "sgwls_resolve_precision",
-           "sgwls_workspace_status", "sgwls_set_spin_limit", "sgwls_filter_noalloc"]
+           "sgwls_filter_noalloc", "sgwls_workspace_bytes_nchw", "sgwls_filter_nchw",
+           "sgwls_backward_workspace_bytes_nchw", "sgwls_backward_nchw"]
 
 
 class SgwlsParams(ctypes.Structure):
@@ -62,12 +63,16 @@ def _load():
     lib.sgwls_workspace_bytes.argtypes = [i, i, i, P, i]
     lib.sgwls_resolve_precision.restype = i
     lib.sgwls_resolve_precision.argtypes = [P, i]
-    lib.sgwls_workspace_status.restype = i
-    lib.sgwls_workspace_status.argtypes = [vp, vp]
+    lib.sgwls_workspace_bytes_nchw.restype = sz
+    lib.sgwls_workspace_bytes_nchw.argtypes = [i, i, i, i, P, i]
+    lib.sgwls_filter_nchw.restype = i
+    lib.sgwls_filter_nchw.argtypes = [vp, vp, vp, i, i, i, i, P, vp, vp, vp, sz, vp]
+    lib.sgwls_backward_workspace_bytes_nchw.restype = sz
+    lib.sgwls_backward_workspace_bytes_nchw.argtypes = [i, i, i, i, P]
+    lib.sgwls_backward_nchw.restype = i
+    lib.sgwls_backward_nchw.argtypes = [vp, vp, vp, vp, vp, vp, i, i, i, i, P, vp, vp, sz, vp]
     lib.sgwls_filter_noalloc.restype = i
     lib.sgwls_filter_noalloc.argtypes = [vp, vp, vp, i, i, i, P, vp, vp, vp]
-    lib.sgwls_set_spin_limit.restype = None
-    lib.sgwls_set_spin_limit.argtypes = [ctypes.c_uint]
     lib.sgwls_pass.restype = i
     lib.sgwls_pass.argtypes = [i, vp, vp, vp, i, i, i, P, vp, vp, sz, vp]
     lib.sgwls_pass_stages.restype = i

@@ -149,23 +149,11 @@ size_t image_bytes(int C, int M, int N) { return align_up(sizeof(float) * (size_
 // left by an earlier, unrelated runtime call of the thread: clear it first.
 void clear_hip_error() { (void)hipGetLastError(); }
 
-std::atomic<unsigned int>& spin_limit_value() {
-  static std::atomic<unsigned int> v{1u << 17};
-  return v;
-}
-
-// Counter words a filter call zeroes at its start: those of every window of
-// the wider frame (windows of 64 - 2r output columns).
-int sync_words(int M, int N, int r) {
-  return std::min(kSyncWords,
-                  kSyncStride * ((std::max(M, N) + kWave - 2 * r - 1) / (kWave - 2 * r) + 1));
-}
-
 // variant < 0: the tuned variant of the case (variant 0 when none is tuned).
 sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* y, int C, int M,
                           int N, const sgwls_params& p, const float* lam_dev, void* iface,
                           hipStream_t stream, int stages = kStageAll, int variant = -1,
-                          const FusedCtl* fused = nullptr) {
+                          const Batch* bt = nullptr) {
   const int L = direction == 0 ? M : N, W = direction == 0 ? N : M;
   const WeightParams wp = weight_params(p);
   const int out_t = (stages & kStageTransposeOut) ? 1 : 0;
@@ -174,10 +162,10 @@ sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* 
     int v = variant >= 0 ? variant
                          : tuned_variant(p.r, cb, p.prec, (int)p.kind, direction, L, W);
     if (out_t && !variants_of(p.r, cb, p.prec).v[v].D) v = 0;   // variant 0 reads directly
-    PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, v);
-    pl.fused = fused;
+    const PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, v);
     PassGeom geo = pass_geom(direction, M, N, pl, p.stride);
     geo.out_t = out_t;
+    if (bt) set_batch(geo, *bt);
     stages &= kStageAll;
     hipError_t e = launch_pass(p.r, cb, p.prec, x, g, y, c0, geo, pl, wp, lam_dev, p.lambda,
                                iface, stream, stages);
@@ -193,9 +181,11 @@ sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* 
 struct BwdLayout {
   size_t img_off, iface_off, side_off, lpart_off, total;
   size_t gt_off, gtacc_off, yt_off;   // transposed-frame buffers (frames only)
+  size_t iface_img, side_img;         // per-image strides: bytes, floats
 };
 
-BwdLayout bwd_layout(int C, int M, int N, const sgwls_params& p) {
+// B images (an NCHW batch): every buffer holds B per-image parts.
+BwdLayout bwd_layout(int C, int M, int N, const sgwls_params& p, int B = 1) {
   size_t iface = 0, side = 0, blocks = 0;
   for (int dir = 0; dir < 2; ++dir) {
     const int L = dir == 0 ? M : N, W = dir == 0 ? N : M;
@@ -213,14 +203,17 @@ BwdLayout bwd_layout(int C, int M, int N, const sgwls_params& p) {
     }
   }
   BwdLayout l{};
-  l.img_off = kSyncBytes;
-  l.iface_off = l.img_off + image_bytes(C, M, N);
-  l.side_off = l.iface_off + align_up(iface);
-  l.lpart_off = l.side_off + align_up(side * sizeof(float));
-  l.gt_off = l.lpart_off + align_up(blocks * sizeof(double));
-  l.gtacc_off = l.gt_off + image_bytes(1, M, N);
-  l.yt_off = l.gtacc_off + image_bytes(1, M, N);
-  l.total = l.yt_off + image_bytes(C, M, N);
+  const size_t nb = (size_t)B;
+  l.iface_img = align_up(iface);
+  l.side_img = align_up(side * sizeof(float)) / sizeof(float);
+  l.img_off = 0;
+  l.iface_off = l.img_off + align_up(nb * sizeof(float) * C * M * N);
+  l.side_off = l.iface_off + nb * l.iface_img;
+  l.lpart_off = l.side_off + nb * l.side_img * sizeof(float);
+  l.gt_off = l.lpart_off + align_up(nb * blocks * sizeof(double));
+  l.gtacc_off = l.gt_off + align_up(nb * sizeof(float) * M * N);
+  l.yt_off = l.gtacc_off + align_up(nb * sizeof(float) * M * N);
+  l.total = l.yt_off + align_up(nb * sizeof(float) * C * M * N);
   return l;
 }
 
@@ -232,7 +225,8 @@ sgwls_status enqueue_pass_backward(int direction, const float* x, const float* g
                                    double* grad_lambda, int C, int M, int N,
                                    const sgwls_params& p, const float* lam_dev, void* ws,
                                    const BwdLayout& lay, hipStream_t stream, bool& first,
-                                   bool* gfirst = nullptr, int out_t = 0) {
+                                   bool* gfirst = nullptr, int out_t = 0,
+                                   const Batch* bt = nullptr) {
   const int L = direction == 0 ? M : N, W = direction == 0 ? N : M;
   const WeightParams wp = weight_params(p);
   char* base = reinterpret_cast<char*>(ws);
@@ -246,6 +240,15 @@ sgwls_status enqueue_pass_backward(int direction, const float* x, const float* g
     const PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, 0, kModeBackward);
     PassGeom geo = pass_geom(direction, M, N, pl, p.stride);
     geo.out_t = out_t;
+    if (bt) {
+      // per image: its interface buffers, side terms and lambda partials (the
+      // fix-up reduces the partials of every image together, in order)
+      Batch b = *bt;
+      b.iface = (long long)lay.iface_img;
+      b.side = (long long)lay.side_img;
+      b.lpart = expand_blocks(geo, pl);
+      set_batch(geo, b);
+    }
     bool& gf = gfirst ? *gfirst : first;   // first write of this guidance-gradient buffer
     bw.gacc = gf ? 0 : 1;
     hipError_t e = launch_pass(p.r, cb, p.prec, x, g, xbar, c0, geo, pl, wp, lam_dev, p.lambda,
@@ -641,13 +644,19 @@ sgwls_precision sgwls_resolve_precision(const sgwls_params* p, int want_lambda_g
 }
 
 size_t sgwls_workspace_bytes(int C, int M, int N, const sgwls_params* p, int save_for_backward) {
-  if (sgwls_validate(C, M, N, p) != SGWLS_OK) return 0;
+  return sgwls_workspace_bytes_nchw(1, C, M, N, p, save_for_backward);
+}
+
+size_t sgwls_workspace_bytes_nchw(int B, int C, int M, int N, const sgwls_params* p,
+                                  int save_for_backward) {
+  if (B < 1 || sgwls_validate(C, M, N, p) != SGWLS_OK) return 0;
   const sgwls_params pr = resolved(*p, save_for_backward ? 1 : 0);
   p = &pr;
-  if (p->prec == SGWLS_P_FP32_DELTA)   // + slack to align the strip buffer
-    return kSyncBytes + image_bytes(C, M, N) + image_bytes(1, M, N) +
-           delta_buffer_bytes(C, M, N, p->stride) + kAlign;
-  return kSyncBytes + image_bytes(C, M, N) + image_bytes(1, M, N) + iface_bytes_all(C, M, N, *p);
+  if (p->prec == SGWLS_P_FP32_DELTA)   // one image; + slack to align the strip buffer
+    return B == 1 ? image_bytes(C, M, N) + image_bytes(1, M, N) +
+                        delta_buffer_bytes(C, M, N, p->stride) + kAlign
+                  : 0;
+  return (size_t)B * (image_bytes(C, M, N) + image_bytes(1, M, N) + iface_bytes_all(C, M, N, *p));
 }
 
 sgwls_status sgwls_pass_stages(int stages, int direction, const float* x, const float* g,
@@ -659,20 +668,16 @@ sgwls_status sgwls_pass_stages(int stages, int direction, const float* x, const 
   const sgwls_params pr = resolved(*p, 0);
   p = &pr;
   if (direction != 0 && direction != 1) return SGWLS_E_ARG;
-  if ((stages & kStageAll) == 0 || stages > (kStageAll | kStageTransposeOut | kStageSyncZero))
-    return SGWLS_E_ARG;
+  if ((stages & kStageAll) == 0 || stages > (kStageAll | kStageTransposeOut)) return SGWLS_E_ARG;
   if ((stages & kStageTransposeOut) &&
       (direction != 0 || p->stride != 1 || !frames_supported(C, p->r, p->stride, p->prec)))
     return SGWLS_E_UNSUPPORTED;
   if (!x || !g || !y || y == x || (const float*)y == g) return SGWLS_E_ARG;
-  const size_t need = kSyncBytes + pass_iface_bytes(direction, C, M, N, *p);
+  const size_t need = pass_iface_bytes(direction, C, M, N, *p);
   if (!ws || ws_bytes < need) return SGWLS_E_WORKSPACE;
   clear_hip_error();
-  bool zeroed = (stages & kStageSyncZero) != 0;
-  const FusedCtl ctl{ws, &zeroed, spin_limit_value().load()};
-  return enqueue_pass(direction, x, g, y, C, M, N, *p, lambda_dev,
-                      reinterpret_cast<char*>(ws) + kSyncBytes, (hipStream_t)stream,
-                      stages & ~kStageSyncZero, -1, &ctl);
+  return enqueue_pass(direction, x, g, y, C, M, N, *p, lambda_dev, ws, (hipStream_t)stream,
+                      stages);
 }
 
 sgwls_status sgwls_pass(int direction, const float* x, const float* g, float* y, int C, int M,
@@ -685,24 +690,31 @@ sgwls_status sgwls_pass(int direction, const float* x, const float* g, float* y,
 sgwls_status sgwls_filter(const float* f, const float* g, float* u, int C, int M, int N,
                           const sgwls_params* p, const float* lambda_dev, float* saved,
                           void* ws, size_t ws_bytes, void* stream) {
+  return sgwls_filter_nchw(f, g, u, 1, C, M, N, p, lambda_dev, saved, ws, ws_bytes, stream);
+}
+
+sgwls_status sgwls_filter_nchw(const float* f, const float* g, float* u, int B, int C, int M,
+                               int N, const sgwls_params* p, const float* lambda_dev,
+                               float* saved, void* ws, size_t ws_bytes, void* stream) {
   sgwls_status st = sgwls_validate(C, M, N, p);
   if (st != SGWLS_OK) return st;
+  if (B < 1) return SGWLS_E_SHAPE;
   // Saved pass inputs feed a backward that may ask for the lambda gradient.
   const sgwls_params pr = resolved(*p, saved ? 1 : 0);
   p = &pr;
   if (!f || !g || !u || (const float*)u == g) return SGWLS_E_ARG;
   if (p->prec == SGWLS_P_FP32_DELTA) {
     // Serial-strip solves: no saved pass inputs (there is no backward in
-    // this mode).  As for the partitioned kernels, every pass is a column
-    // pass storing transposed: pass 2t reads the image (guidance g) and
-    // writes tmp (N x M), pass 2t+1 reads tmp (guidance g^T) and writes u.
-    if (saved) return SGWLS_E_UNSUPPORTED;
+    // this mode), one image.  As for the partitioned kernels, every pass is a
+    // column pass storing transposed: pass 2t reads the image (guidance g)
+    // and writes tmp (N x M), pass 2t+1 reads tmp (guidance g^T) and writes u.
+    if (saved || B != 1) return SGWLS_E_UNSUPPORTED;
     const size_t img = image_bytes(C, M, N), gimg = image_bytes(1, M, N);
-    if (!ws || ws_bytes < kSyncBytes + img + gimg + delta_buffer_bytes(C, M, N, p->stride) + kAlign)
+    if (!ws || ws_bytes < img + gimg + delta_buffer_bytes(C, M, N, p->stride) + kAlign)
       return SGWLS_E_WORKSPACE;
     clear_hip_error();
     hipStream_t s = (hipStream_t)stream;
-    char* base = reinterpret_cast<char*>(ws) + kSyncBytes;
+    char* base = reinterpret_cast<char*>(ws);
     float* tmp = reinterpret_cast<float*>(base);
     float* gT = reinterpret_cast<float*>(base + img);
     // the strip buffer holds 16-byte records: start it on an aligned address
@@ -723,17 +735,42 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u, int C, int M
     }
     return SGWLS_OK;
   }
+  // Workspace: B intermediate images, B transposed guidance planes, then B
+  // per-image interface buffers.
   const size_t img = image_bytes(C, M, N), gimg = image_bytes(1, M, N);
-  const size_t need = kSyncBytes + img + gimg + iface_bytes_all(C, M, N, *p);
-  if (!ws || ws_bytes < need) return SGWLS_E_WORKSPACE;
+  const size_t iface_img = iface_bytes_all(C, M, N, *p);
+  const size_t nb = (size_t)B;
+  if (!ws || ws_bytes < nb * (img + gimg + iface_img)) return SGWLS_E_WORKSPACE;
   clear_hip_error();
   hipStream_t s = (hipStream_t)stream;
-  char* base = reinterpret_cast<char*>(ws) + kSyncBytes;
+  char* base = reinterpret_cast<char*>(ws);
   float* tmp = reinterpret_cast<float*>(base);
-  float* gT = reinterpret_cast<float*>(base + img);
-  void* iface = base + img + gimg;
+  float* gT = reinterpret_cast<float*>(base + nb * img);
+  void* iface = base + nb * (img + gimg);
   const size_t plane = (size_t)C * M * N;
   const int passes = 2 * p->iters;
+  // Per-image strides (floats): inputs and outputs C*M*N apart, the
+  // intermediate images img/4 apart, the saved pass inputs 2T*C*M*N apart
+  // (image b, pass q at (b*2T + q)*C*M*N), guidance planes (and their
+  // transposes, written plane after plane) M*N apart.
+  const long long sx = (long long)plane, ss = (long long)passes * (long long)plane;
+  const long long stmp = (long long)(img / sizeof(float));
+  auto stride_of = [&](const float* a) -> long long {
+    if (saved && a >= saved && a < saved + (size_t)ss) return ss;
+    return a == tmp ? stmp : sx;
+  };
+  auto batch = [&](const float* x, const float* y) {
+    Batch b;
+    b.n = B;
+    b.x = stride_of(x);
+    b.y = stride_of(y);
+    b.g = (long long)M * N;
+    b.iface = (long long)iface_img;
+    return b;
+  };
+  if (saved && hipMemcpy2DAsync(saved, sizeof(float) * ss, f, sizeof(float) * plane,
+                                sizeof(float) * plane, nb, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return SGWLS_E_HIP;
   // Strided forward calls without saved inputs also run as frames: their
   // column passes read directly and store through the LDS accumulators.
   if (frames_supported(C, p->r, p->stride, p->prec) || (p->stride != 1 && !saved)) {
@@ -742,22 +779,14 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u, int C, int M
     // -- and writes the image layout again.  Without saved, pass 2t writes tmp
     // and pass 2t+1 writes u; with saved, pass q writes saved[q+1] (so odd
     // entries hold transposed images) and the last pass writes u.
-    // The guidance transpose also zeroes the window counters of the
-    // one-launch passes (each completed pass leaves them zero).
-    if (launch_transpose(g, gT, M, N, s, 1, 0, sync_counters(ws), sync_words(M, N, p->r)) !=
-        hipSuccess)
-      return SGWLS_E_HIP;
-    bool zeroed = true;
-    const FusedCtl ctl{ws, &zeroed, spin_limit_value().load()};
-    if (saved && hipMemcpyAsync(saved, f, sizeof(float) * plane, hipMemcpyDeviceToDevice, s) !=
-                     hipSuccess)
-      return SGWLS_E_HIP;
+    if (launch_transpose(g, gT, M, N, s, B) != hipSuccess) return SGWLS_E_HIP;
     const float* x = saved ? saved : f;
     for (int q = 0; q < passes; ++q) {
       const bool even = q % 2 == 0;
       float* y = q == passes - 1 ? u : saved ? saved + (size_t)(q + 1) * plane : even ? tmp : u;
+      const Batch bt = batch(x, y);
       st = enqueue_pass(0, x, even ? g : gT, y, C, even ? M : N, even ? N : M, *p, lambda_dev,
-                        iface, s, kStageAll | kStageTransposeOut, -1, &ctl);
+                        iface, s, kStageAll | kStageTransposeOut, -1, &bt);
       if (st != SGWLS_OK) return st;
       x = y;
     }
@@ -766,17 +795,14 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u, int C, int M
   // Pass q reads x_q and writes x_{q+1}; x_0 = f and x_{2T} = u.  With saved,
   // x_q lives in saved[q] (q < 2T); otherwise passes ping-pong between tmp
   // and u so that the last one lands in u.
-  if (saved) {
-    if (hipMemcpyAsync(saved, f, sizeof(float) * plane, hipMemcpyDeviceToDevice, s) != hipSuccess)
-      return SGWLS_E_HIP;
-  }
   const float* x = saved ? saved : f;
   for (int q = 0; q < passes; ++q) {
     float* y;
     if (q == passes - 1) y = u;
     else if (saved) y = saved + (size_t)(q + 1) * plane;
     else y = ((passes - q) % 2 == 0) ? tmp : u;
-    st = enqueue_pass(q % 2, x, g, y, C, M, N, *p, lambda_dev, iface, s);
+    const Batch bt = batch(x, y);
+    st = enqueue_pass(q % 2, x, g, y, C, M, N, *p, lambda_dev, iface, s, kStageAll, -1, &bt);
     if (st != SGWLS_OK) return st;
     x = y;
   }
@@ -830,13 +856,10 @@ sgwls_status sgwls_autotune(const float* x, const float* g, float* y, int C, int
   const sgwls_params pr = resolved(*p, 0);
   p = &pr;
   if (!x || !g || !y || y == x || (const float*)y == g || reps < 1) return SGWLS_E_ARG;
-  const size_t need =
-      kSyncBytes + std::max(pass_iface_bytes(0, C, M, N, *p), pass_iface_bytes(1, C, M, N, *p));
+  const size_t need = std::max(pass_iface_bytes(0, C, M, N, *p), pass_iface_bytes(1, C, M, N, *p));
   if (!ws || ws_bytes < need) return SGWLS_E_WORKSPACE;
   clear_hip_error();
-  void* iface = reinterpret_cast<char*>(ws) + kSyncBytes;
-  bool zeroed = false;
-  const FusedCtl ctl{ws, &zeroed, spin_limit_value().load()};
+  void* iface = ws;
   if (chosen)
     for (int i = 0; i < 4; ++i) chosen[i] = -1;
   if (p->stride != 1) return SGWLS_OK;   // strided passes have a single kernel
@@ -873,8 +896,7 @@ sgwls_status sgwls_autotune(const float* x, const float* g, float* y, int C, int
           for (int f = 0; f < (frames ? 2 : 1); ++f) {
             const int Mf = f == 0 ? M : N, Nf = f == 0 ? N : M;
             const int Lf = dir == 0 ? Mf : Nf, Wf = dir == 0 ? Nf : Mf;
-            PassPlan pl = make_plan(Lf, Wf, p->r, cb, p->stride, p->prec, v);
-            if (frames) pl.fused = &ctl;   // the filter's passes run as one launch where they can
+            const PassPlan pl = make_plan(Lf, Wf, p->r, cb, p->stride, p->prec, v);
             PassGeom geo = pass_geom(dir, Mf, Nf, pl, p->stride);
             geo.out_t = frames ? 1 : 0;
             const hipError_t e = launch_pass(p->r, cb, p->prec, x, g, y, c0, geo, pl, wp, nullptr,
@@ -958,10 +980,14 @@ sgwls_status sgwls_tune_load(const char* path, const char* arch) {
 }
 
 size_t sgwls_backward_workspace_bytes(int C, int M, int N, const sgwls_params* p) {
-  if (validate_partitioned(C, M, N, p) != SGWLS_OK) return 0;
+  return sgwls_backward_workspace_bytes_nchw(1, C, M, N, p);
+}
+
+size_t sgwls_backward_workspace_bytes_nchw(int B, int C, int M, int N, const sgwls_params* p) {
+  if (B < 1 || validate_partitioned(C, M, N, p) != SGWLS_OK) return 0;
   // AUTO resolves per call (the lambda gradient decides): room for both.
-  return std::max(bwd_layout(C, M, N, resolved(*p, 0)).total,
-                  bwd_layout(C, M, N, resolved(*p, 1)).total);
+  return std::max(bwd_layout(C, M, N, resolved(*p, 0), B).total,
+                  bwd_layout(C, M, N, resolved(*p, 1), B).total);
 }
 
 sgwls_status sgwls_pass_backward(int direction, const float* x, const float* g,
@@ -991,8 +1017,17 @@ sgwls_status sgwls_backward(const float* g, const float* saved, const float* gra
                             float* grad_f, float* grad_g, double* grad_lambda, int C, int M,
                             int N, const sgwls_params* p, const float* lambda_dev, void* ws,
                             size_t ws_bytes, void* stream) {
+  return sgwls_backward_nchw(g, saved, grad_u, grad_f, grad_g, grad_lambda, 1, C, M, N, p,
+                             lambda_dev, ws, ws_bytes, stream);
+}
+
+sgwls_status sgwls_backward_nchw(const float* g, const float* saved, const float* grad_u,
+                                 float* grad_f, float* grad_g, double* grad_lambda, int B, int C,
+                                 int M, int N, const sgwls_params* p, const float* lambda_dev,
+                                 void* ws, size_t ws_bytes, void* stream) {
   sgwls_status st = validate_partitioned(C, M, N, p);
   if (st != SGWLS_OK) return st;
+  if (B < 1) return SGWLS_E_SHAPE;
   const sgwls_params pr = resolved(*p, grad_lambda != nullptr);
   p = &pr;
   if (!g || !saved || !grad_u || !grad_f || (const float*)grad_f == g ||
@@ -1001,16 +1036,25 @@ sgwls_status sgwls_backward(const float* g, const float* saved, const float* gra
   if (grad_g && ((const float*)grad_g == g || grad_g == grad_f || (const float*)grad_g == grad_u ||
                  (const float*)grad_g == saved))
     return SGWLS_E_ARG;
-  const BwdLayout lay = bwd_layout(C, M, N, *p);
+  const BwdLayout lay = bwd_layout(C, M, N, *p, B);
   if (!ws || ws_bytes < lay.total) return SGWLS_E_WORKSPACE;
   clear_hip_error();
   hipStream_t s = (hipStream_t)stream;
-  float* tmp = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + lay.img_off);
+  char* base = reinterpret_cast<char*>(ws);
+  float* tmp = reinterpret_cast<float*>(base + lay.img_off);
   const size_t plane = (size_t)C * M * N;
   const int passes = 2 * p->iters;
+  // Per-image strides (floats): gradients and intermediates C*M*N apart,
+  // saved pass inputs 2T*C*M*N apart, guidance planes M*N apart.
+  Batch bt;
+  bt.n = B;
+  bt.x = (long long)passes * (long long)plane;
+  bt.x2 = bt.y = (long long)plane;
+  bt.g = bt.gb = (long long)M * N;
   // Passes in reverse order.  Pass q reads the gradient of its output (grad_u
   // for the last pass) and writes that of its input: into grad_f for even q,
   // tmp for odd q, so pass 0 ends in grad_f and grad_u may alias grad_f.
+  // grad_lambda receives the sum over the B images (lambda is shared).
   bool first = true;
   if (frames_supported(C, p->r, p->stride, p->prec)) {
     // The saved inputs of odd (row) passes are transposed (see sgwls_filter).
@@ -1019,12 +1063,11 @@ sgwls_status sgwls_backward(const float* g, const float* saved, const float* gra
     // i.e. in the frame of pass q-1; pass 0 stores it as the image.  The
     // guidance gradient of odd passes accumulates transposed and is added to
     // grad_g at the end.
-    char* base = reinterpret_cast<char*>(ws);
     float* gT = reinterpret_cast<float*>(base + lay.gt_off);
     float* gTacc = reinterpret_cast<float*>(base + lay.gtacc_off);
     float* yT = reinterpret_cast<float*>(base + lay.yt_off);
-    if (launch_transpose(g, gT, M, N, s) != hipSuccess ||
-        launch_transpose(grad_u, yT, M, N, s, C) != hipSuccess)
+    if (launch_transpose(g, gT, M, N, s, B) != hipSuccess ||
+        launch_transpose(grad_u, yT, M, N, s, B * C) != hipSuccess)
       return SGWLS_E_HIP;
     const float* ybar = yT;
     bool gfirst[2] = {true, true};
@@ -1034,18 +1077,19 @@ sgwls_status sgwls_backward(const float* g, const float* saved, const float* gra
       st = enqueue_pass_backward(0, saved + (size_t)q * plane, odd ? gT : g, ybar, xbar,
                                  grad_g ? (odd ? gTacc : grad_g) : nullptr, grad_lambda, C,
                                  odd ? N : M, odd ? M : N, *p, lambda_dev, ws, lay, s, first,
-                                 &gfirst[odd ? 1 : 0], q > 0 ? 1 : 0);
+                                 &gfirst[odd ? 1 : 0], q > 0 ? 1 : 0, &bt);
       if (st != SGWLS_OK) return st;
       ybar = xbar;
     }
-    if (grad_g && launch_transpose(gTacc, grad_g, N, M, s, 1, 1) != hipSuccess) return SGWLS_E_HIP;
+    if (grad_g && launch_transpose(gTacc, grad_g, N, M, s, B, 1) != hipSuccess) return SGWLS_E_HIP;
     return SGWLS_OK;
   }
   const float* ybar = grad_u;
   for (int q = passes - 1; q >= 0; --q) {
     float* xbar = (q % 2 == 0) ? grad_f : tmp;
     st = enqueue_pass_backward(q % 2, saved + (size_t)q * plane, g, ybar, xbar, grad_g,
-                               grad_lambda, C, M, N, *p, lambda_dev, ws, lay, s, first);
+                               grad_lambda, C, M, N, *p, lambda_dev, ws, lay, s, first, nullptr, 0,
+                               &bt);
     if (st != SGWLS_OK) return st;
     ybar = xbar;
   }
@@ -1173,22 +1217,6 @@ sgwls_status sgwls_autotune_batched(const sgwls_image* imgs, const sgwls_params*
   tune_cache_save();
   if (chosen) *chosen = best;
   return SGWLS_OK;
-}
-
-void sgwls_set_spin_limit(unsigned int polls) { spin_limit_value().store(polls); }
-
-sgwls_status sgwls_workspace_status(void* ws, void* stream) {
-  if (!ws) return SGWLS_E_ARG;
-  hipStream_t s = (hipStream_t)stream;
-  unsigned int word = 0;
-  if (hipStreamSynchronize(s) != hipSuccess ||
-      hipMemcpy(&word, sync_err(ws), sizeof(word), hipMemcpyDeviceToHost) != hipSuccess)
-    return SGWLS_E_HIP;
-  if (word != kSyncErrMagic) return SGWLS_OK;
-  const unsigned int clear = 0;
-  if (hipMemcpy(sync_err(ws), &clear, sizeof(clear), hipMemcpyHostToDevice) != hipSuccess)
-    return SGWLS_E_HIP;
-  return SGWLS_E_HIP;
 }
 
 int sgwls_batched_graph_count(void) {

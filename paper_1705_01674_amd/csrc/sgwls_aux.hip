@@ -17,7 +17,11 @@ __global__ __launch_bounds__(kFixThreads) void k_bwd_fixup(const float* __restri
                                                            const double* __restrict__ lpart,
                                                            int nparts, double* glam,
                                                            int lam_acc) {
+  // blockIdx.z: image of a batched launch (side terms per image; the lambda
+  // partials of every image are reduced together by block (nfix, 0, 0))
   if ((int)blockIdx.x < nfix) {
+    side = zmove(side, geo.zside, (int)blockIdx.z);
+    gbar = zmove(gbar, geo.zgb, (int)blockIdx.z);
     const int idx = blockIdx.x * kFixThreads + threadIdx.x;
     const int n = (geo.P - 1) * geo.W;
     if (idx < n) {
@@ -28,6 +32,7 @@ __global__ __launch_bounds__(kFixThreads) void k_bwd_fixup(const float* __restri
     }
     return;
   }
+  if (blockIdx.z != 0) return;
   __shared__ double red[kFixThreads];
   // Each thread sums partials threadIdx.x, + kFixThreads, ... in that order;
   // kLoads of them are loaded before they are added, so that one memory
@@ -60,11 +65,8 @@ __global__ __launch_bounds__(256) void k_write_words(unsigned int* __restrict__ 
 // 32 x 32 tiles through LDS (padded row), coalesced reads and writes.
 __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ src,
                                                    float* __restrict__ dst, int rows, int cols,
-                                                   int accumulate, unsigned int* zero,
-                                                   int nzero) {
+                                                   int accumulate) {
   __shared__ float t[32][33];
-  if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0)
-    for (int i = threadIdx.x; i < nzero; i += 256) zero[i] = 0u;
   const size_t plane = (size_t)rows * cols;
   src += blockIdx.z * plane;
   dst += blockIdx.z * plane;
@@ -87,20 +89,9 @@ __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ src
 }  // namespace
 
 hipError_t launch_transpose(const float* src, float* dst, int rows, int cols, hipStream_t stream,
-                            int planes, int accumulate, unsigned int* zero, int nzero) {
+                            int planes, int accumulate) {
   hipLaunchKernelGGL(k_transpose, dim3((cols + 31) / 32, (rows + 31) / 32, planes), dim3(256), 0,
-                     stream, src, dst, rows, cols, accumulate, zero, nzero);
-  return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void k_zero_words(unsigned int* __restrict__ dst, int n) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) dst[i] = 0u;
-}
-
-hipError_t launch_zero_words(unsigned int* dst, int n, hipStream_t stream) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_words, dim3((n + 255) / 256), dim3(256), 0, stream, dst, n);
+                     stream, src, dst, rows, cols, accumulate);
   return hipGetLastError();
 }
 
@@ -116,8 +107,9 @@ hipError_t launch_bwd_fixup(const float* side, float* gbar, const PassGeom& geo,
   const int nfix = gbar && geo.P > 1 ? ((geo.P - 1) * geo.W + kFixThreads - 1) / kFixThreads : 0;
   const int nlam = (lpart && glam) ? 1 : 0;
   if (nfix + nlam == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bwd_fixup, dim3(nfix + nlam), dim3(kFixThreads), 0, stream, side, gbar,
-                     geo, nfix, lpart, nparts, glam, lam_acc);
+  const int nz = geo.nimg > 0 ? geo.nimg : 1;
+  hipLaunchKernelGGL(k_bwd_fixup, dim3(nfix + nlam, 1, nz), dim3(kFixThreads), 0, stream, side,
+                     gbar, geo, nfix, lpart, nparts * nz, glam, lam_acc);
   return hipGetLastError();
 }
 

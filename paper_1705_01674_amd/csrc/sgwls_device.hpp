@@ -786,35 +786,22 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce(
     PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
     int pitch, Acc* __restrict__ sum) {
   extern __shared__ float smem[];
-  reduce_block<r, CB, R, Q, S1, KIND, Acc, MODE>(X, X2, G, geo, wp, load_lambda(lam_dev, lam_host),
-                                                 c0, pitch, sum, blockIdx.x, blockIdx.y, smem);
-}
-
-// Loads and stores of interface data.  COH: the data is exchanged between
-// workgroups of one launch (possibly on different XCDs, whose L2 caches are
-// not coherent with each other), so it is written through to and read from
-// the device-coherent level (agent-scope relaxed atomic accesses, one word
-// each); otherwise plain accesses (the data crosses a kernel boundary).
-template <bool COH, typename T>
-DEV T ld(const T* p) {
-  if constexpr (COH) return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  else return *p;
-}
-template <bool COH, typename T>
-DEV void st(T* p, T v) {
-  if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  else *p = v;
+  const int z = blockIdx.z;
+  reduce_block<r, CB, R, Q, S1, KIND, Acc, MODE>(
+      zmove(X, geo.zx, z), zmove(X2, geo.zx2, z), zmove(G, geo.zg, z), geo,
+      wp, load_lambda(lam_dev, lam_host), c0, pitch, zmove_bytes(sum, geo.zi, z), blockIdx.x,
+      blockIdx.y, smem);
 }
 
 // ---------------------------------------------------------------------------
 // Separator system of one strip: Sigma_jj = W_j - TT_{j+1},
 // Sigma_{j,j+1}[a][c] = TB_{j+1}[c][a], rhs_j = Rf_j - RT_{j+1}, j = 0..P-2.
-template <int r, int CB, typename Acc, bool COH = false>
+template <int r, int CB, typename Acc>
 struct SepReader {
   using LY = IfaceLayout<r, CB>;
   const Acc* S;   // this strip's contributions
   int P;
-  DEV Acc at(int j, int f) const { return ld<COH>(S + (size_t)j * LY::F + f); }
+  DEV Acc at(int j, int f) const { return S[(size_t)j * LY::F + f]; }
   DEV void diag(int j, Acc (&A)[r][r]) const {
     int t = 0;
 #pragma unroll
@@ -845,7 +832,7 @@ struct SepReader {
 // of one strip (indices past the last chunk read the last one), loaded
 // together before the elimination so that their latency is paid once.
 // Calls index chunks absolutely; the indices are s plus compile-time offsets.
-template <int r, int CB, int NREC, typename Acc, bool COH = false>
+template <int r, int CB, int NREC, typename Acc>
 struct PreReader {
   using LY = IfaceLayout<r, CB>;
   Acc rec[NREC][LY::F];
@@ -858,7 +845,7 @@ struct PreReader {
       if (i < nrec) {
         const int jj = min(s + i, P - 1);
 #pragma unroll
-        for (int f = 0; f < LY::F; ++f) rec[i][f] = ld<COH>(S + (size_t)jj * LY::F + f);
+        for (int f = 0; f < LY::F; ++f) rec[i][f] = S[(size_t)jj * LY::F + f];
       }
     }
   }
@@ -974,7 +961,7 @@ DEV void iface_pcr_levels(const Acc (&S)[r][r], const Acc (&Bt)[r][r], const Acc
 // k_interface_pcr: one wave per strip, lane l owns separator blocks
 // [l*m, min(l*m + m, P-1)); MM is the compiled maximum of m.
 // U receives the separator solutions strip-major: U[(ki*(P-1) + j)*r*CB + a*CB + h].
-template <int r, int CB, int MM, typename Acc, class Reader, bool COH = false>
+template <int r, int CB, int MM, typename Acc, class Reader>
 DEV void iface_pcr_run(const Reader& rd, Acc* __restrict__ U, int P, int m, int ki) {
   const int lane = threadIdx.x % kWave;
   const int n = P - 1;
@@ -1080,7 +1067,7 @@ DEV void iface_pcr_run(const Reader& rd, Acc* __restrict__ U, int P, int m, int 
 #pragma unroll
   for (int a = 0; a < r; ++a)
 #pragma unroll
-    for (int h = 0; h < CB; ++h) st<COH>(out + (size_t)(e - 1) * r * CB + a * CB + h, X[a][h]);
+    for (int h = 0; h < CB; ++h) out[(size_t)(e - 1) * r * CB + a * CB + h] = X[a][h];
   // back substitution: x_b = S_b^-1 (R_b - U_b x_{b+1} - Bt_b x_T)
   Acc xn[r][CB];
 #pragma unroll
@@ -1106,7 +1093,7 @@ DEV void iface_pcr_run(const Reader& rd, Acc* __restrict__ U, int P, int m, int 
       for (int a = 0; a < r; ++a)
 #pragma unroll
         for (int h = 0; h < CB; ++h) {
-          st<COH>(out + (size_t)b * r * CB + a * CB + h, v[a][h]);
+          out[(size_t)b * r * CB + a * CB + h] = v[a][h];
           xn[a][h] = v[a][h];
         }
     }
@@ -1115,25 +1102,26 @@ DEV void iface_pcr_run(const Reader& rd, Acc* __restrict__ U, int P, int m, int 
 
 // The solver of one strip: its chunk records prefetched into registers
 // when the lane's run fits (MM + 1 records), else read as needed.
-template <int r, int CB, int MM, typename Acc, bool COH = false>
+template <int r, int CB, int MM, typename Acc>
 DEV void iface_pcr_strip(const Acc* __restrict__ sum, Acc* __restrict__ U, int P, int m, int ki) {
   using LY = IfaceLayout<r, CB>;
   const Acc* S = sum + (size_t)ki * P * LY::F;
   if constexpr ((MM + 1) * LY::F <= 160) {
-    PreReader<r, CB, MM + 1, Acc, COH> rd;
+    PreReader<r, CB, MM + 1, Acc> rd;
     rd.load(S, (int)(threadIdx.x % kWave) * m, P, m + 1);
-    iface_pcr_run<r, CB, MM, Acc, PreReader<r, CB, MM + 1, Acc, COH>, COH>(rd, U, P, m, ki);
+    iface_pcr_run<r, CB, MM, Acc>(rd, U, P, m, ki);
   } else {
-    const SepReader<r, CB, Acc, COH> rd{S, P};
-    iface_pcr_run<r, CB, MM, Acc, SepReader<r, CB, Acc, COH>, COH>(rd, U, P, m, ki);
+    const SepReader<r, CB, Acc> rd{S, P};
+    iface_pcr_run<r, CB, MM, Acc>(rd, U, P, m, ki);
   }
 }
 
 template <int r, int CB, int MM, typename Acc>
 __global__ __launch_bounds__(kWave) void k_interface_pcr(const Acc* __restrict__ sum,
                                                          Acc* __restrict__ U, int nK, int P,
-                                                         int m) {
-  iface_pcr_strip<r, CB, MM, Acc>(sum, U, P, m, blockIdx.x);
+                                                         int m, long long zi) {
+  const int z = blockIdx.z;   // image of a batched launch (interface buffers zi bytes apart)
+  iface_pcr_strip<r, CB, MM, Acc>(zmove_bytes(sum, zi, z), zmove_bytes(U, zi, z), P, m, blockIdx.x);
 }
 
 // Scratch values per separator block kept by iface_pcr_strip_long: the
@@ -1326,8 +1314,10 @@ template <int r, int CB, typename Acc>
 __global__ __launch_bounds__(kWave) void k_interface_pcr_long(const Acc* __restrict__ sum,
                                                               Acc* __restrict__ U,
                                                               Acc* __restrict__ scr, int P,
-                                                              int m) {
-  iface_pcr_strip_long<r, CB, Acc>(sum, U, P, m, blockIdx.x, scr);
+                                                              int m, long long zi) {
+  const int z = blockIdx.z;
+  iface_pcr_strip_long<r, CB, Acc>(zmove_bytes(sum, zi, z), zmove_bytes(U, zi, z), P, m,
+                                   blockIdx.x, zmove_bytes(scr, zi, z));
 }
 
 // ---------------------------------------------------------------------------
@@ -1875,11 +1865,22 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce_d(
     PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
     Acc* __restrict__ sum) {
   extern __shared__ float smem[];
-  const PlaneSrc<CB> src{X, X2, c0, (int)geo.plane};
+  const int z = blockIdx.z;
+  const PlaneSrc<CB> src{zmove(X, geo.zx, z), zmove(X2, geo.zx2, z), c0, (int)geo.plane};
   int bx, by;
   xcd_block(bx, by);
   reduce_tile<r, CB, R, Q, S1, KIND, Acc, MODE, true>(
-      geo, wp, load_lambda(lam_dev, lam_host), 0, sum, bx, by, smem, G, &src);
+      geo, wp, load_lambda(lam_dev, lam_host), 0, zmove_bytes(sum, geo.zi, z), bx, by, smem,
+      zmove(G, geo.zg, z), &src);
+}
+
+// The backward operands of image z of a batched launch.
+DEV BwdArgs bwd_at(BwdArgs bw, const PassGeom& geo, int z) {
+  bw.ybar = zmove(bw.ybar, geo.zx2, z);
+  bw.gbar = zmove(bw.gbar, geo.zgb, z);
+  bw.side = zmove(bw.side, geo.zside, z);
+  bw.lpart = zmove(bw.lpart, (long long)geo.zlpart, z);
+  return bw;
 }
 
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE>
@@ -1888,12 +1889,14 @@ __global__ __launch_bounds__(kWave* Q) void k_expand_d(
     PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
     const Acc* __restrict__ Us, int OW, int pitch, BwdArgs bw) {
   extern __shared__ float smem[];
-  const PlaneSrc<CB> src{X, bw.ybar, c0, (int)geo.plane};
+  const int z = blockIdx.z;
+  const BwdArgs bz = bwd_at(bw, geo, z);
+  const PlaneSrc<CB> src{zmove(X, geo.zx, z), bz.ybar, c0, (int)geo.plane};
   int bx, by;
   xcd_block(bx, by);
-  expand_tile<r, CB, R, Q, S1, KIND, Acc, MODE, true>(G, Y, geo, wp, load_lambda(lam_dev, lam_host),
-                                                      c0, Us, OW, pitch, bw, bx, by, gridDim.x,
-                                                      smem, &src);
+  expand_tile<r, CB, R, Q, S1, KIND, Acc, MODE, true>(
+      zmove(G, geo.zg, z), zmove(Y, geo.zy, z), geo, wp, load_lambda(lam_dev, lam_host), c0,
+      zmove_bytes(Us, geo.zi, z), OW, pitch, bz, bx, by, gridDim.x, smem, &src);
 }
 
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE>
@@ -1902,9 +1905,11 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
     PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
     const Acc* __restrict__ Us, int OW, int pitch, BwdArgs bw) {
   extern __shared__ float smem[];
-  expand_block<r, CB, R, Q, S1, KIND, Acc, MODE>(X, G, Y, geo, wp, load_lambda(lam_dev, lam_host),
-                                                 c0, Us, OW, pitch, bw, blockIdx.x, blockIdx.y,
-                                                 gridDim.x, smem);
+  const int z = blockIdx.z;
+  expand_block<r, CB, R, Q, S1, KIND, Acc, MODE>(
+      zmove(X, geo.zx, z), zmove(G, geo.zg, z), zmove(Y, geo.zy, z), geo, wp,
+      load_lambda(lam_dev, lam_host), c0, zmove_bytes(Us, geo.zi, z), OW, pitch,
+      bwd_at(bw, geo, z), blockIdx.x, blockIdx.y, gridDim.x, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1925,33 +1930,34 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
   const size_t tile = sizeof(float) * (size_t)(NR + 1) * (Q * R + 2) * pl.pitch;
   const size_t stage_out = sizeof(Acc) * (size_t)kWave * Q * LY::F;
   const int gy = (geo.P + Q - 1) / Q;
+  const int nz = geo.nimg > 0 ? geo.nimg : 1;   // images of an NCHW batch (blockIdx.z)
   if (geo.P > 1 && (stages & kStageReduce)) {
     const int gx = (geo.nK + kWave - 1) / kWave;
     bool direct = false;
     if constexpr (D) {
       if (geo.sb == 1) {
         direct = true;
-        hipLaunchKernelGGL((k_reduce_d<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(gx, gy),
+        hipLaunchKernelGGL((k_reduce_d<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(gx, gy, nz),
                            dim3(kWave * Q), stage_out, stream, x, bw.ybar, g, geo, wp, lam_dev,
                            lam_host, c0, sum);
       }
     }
     if (!direct)
-      hipLaunchKernelGGL((k_reduce<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(gx, gy),
+      hipLaunchKernelGGL((k_reduce<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(gx, gy, nz),
                          dim3(kWave * Q), std::max(tile, stage_out), stream, x, bw.ybar, g, geo,
                          wp, lam_dev, lam_host, c0, pl.pitch, sum);
   }
   if (geo.P > 1 && (stages & kStageInterface)) {
     if (VS.MM > 0 && pl.iface_m > 0 && pl.iface_m <= VS.MM) {
       constexpr int MM = VS.MM > 0 ? VS.MM : 1;
-      hipLaunchKernelGGL((k_interface_pcr<r, NR, MM, Acc>), dim3(geo.nK), dim3(kWave), 0,
-                         stream, (const Acc*)sum, us, geo.nK, geo.P, pl.iface_m);
+      hipLaunchKernelGGL((k_interface_pcr<r, NR, MM, Acc>), dim3(geo.nK, 1, nz), dim3(kWave), 0,
+                         stream, (const Acc*)sum, us, geo.nK, geo.P, pl.iface_m, geo.zi);
     } else {
       // Runs longer than the register solver holds: the same wave solver with
       // its per-block values in the scratch part of the interface buffer.
       const int m = (geo.P - 1 + kWave - 1) / kWave;
-      hipLaunchKernelGGL((k_interface_pcr_long<r, NR, Acc>), dim3(geo.nK), dim3(kWave), 0, stream,
-                         (const Acc*)sum, us, gb, geo.P, m);
+      hipLaunchKernelGGL((k_interface_pcr_long<r, NR, Acc>), dim3(geo.nK, 1, nz), dim3(kWave), 0,
+                         stream, (const Acc*)sum, us, gb, geo.P, m, geo.zi);
     }
   }
   if (stages & kStageExpand) {
@@ -1965,14 +1971,14 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
         const size_t lds = S1 ? (geo.out_t ? sizeof(float) * CB * Q * R * (kWave + 1) : 0)
                               : sizeof(float) * (size_t)NO * (Q * R + 2) * pl.pitch;
         direct = true;
-        hipLaunchKernelGGL((k_expand_d<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(ex, gy),
+        hipLaunchKernelGGL((k_expand_d<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(ex, gy, nz),
                            dim3(kWave * Q), lds, stream, x, g, y, geo, wp, lam_dev, lam_host, c0,
                            (const Acc*)us, pl.OW, pl.pitch, bw);
       }
     }
     if (!direct) {
       if (geo.out_t) return hipErrorInvalidValue;   // needs the direct forward kernels
-      hipLaunchKernelGGL((k_expand<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(ex, gy),
+      hipLaunchKernelGGL((k_expand<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(ex, gy, nz),
                          dim3(kWave * Q), tile, stream, x, g, y, geo, wp, lam_dev, lam_host, c0,
                          (const Acc*)us, pl.OW, pl.pitch, bw);
     }

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #define DEV_HOST_INLINE __host__ __device__ inline
 
 namespace sgwls {
@@ -39,7 +41,45 @@ struct PassGeom {
   int P;            // chunks per subsystem = ceil(L / R)
   int out_t;        // 1: the output is stored transposed, pixel (a, b) at b*L + a
                     // (stride-1 column passes with direct reads only)
+  // An NCHW batch of equal-shape images in one launch (blockIdx.z = image):
+  // per-image strides, in floats, of the input x, the second source (the
+  // backward's output gradient), the output y, the guidance g, the guidance
+  // gradient and the backward side buffer; in bytes of the interface
+  // buffers; in entries of the lambda partials.  nimg = 1 and zero strides
+  // for one image.
+  int nimg;
+  long long zx, zx2, zy, zg, zgb, zside, zi;
+  int zlpart;
 };
+
+// Image z of a batched launch: p moved by z * stride elements (or bytes).
+template <typename T>
+DEV_HOST_INLINE T* zmove(T* p, long long stride, int z) {
+  return p ? p + (long long)z * stride : p;
+}
+template <typename T>
+DEV_HOST_INLINE T* zmove_bytes(T* p, long long bytes, int z) {
+  using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return p ? reinterpret_cast<T*>(reinterpret_cast<B*>(p) + (long long)z * bytes) : p;
+}
+
+// Per-image strides of a batched call (see PassGeom); n = 1: one image.
+struct Batch {
+  int n = 1;
+  long long x = 0, x2 = 0, y = 0, g = 0, gb = 0, side = 0, iface = 0;
+  int lpart = 0;
+};
+DEV_HOST_INLINE void set_batch(PassGeom& geo, const Batch& b) {
+  geo.nimg = b.n;
+  geo.zx = b.x;
+  geo.zx2 = b.x2;
+  geo.zy = b.y;
+  geo.zg = b.g;
+  geo.zgb = b.gb;
+  geo.zside = b.side;
+  geo.zi = b.iface;
+  geo.zlpart = b.lpart;
+}
 
 // Kernel variants: rows per chunk R (even) and chunks per block Q.  Stride-1
 // passes may use any variant of their case; strided passes always use
@@ -101,29 +141,6 @@ constexpr VariantSet variants_for(int mode, int r, int cb, int fp64) {
   return mode == kModeBackward ? bwd_variants_of(r, cb, fp64) : variants_of(r, cb, fp64);
 }
 
-// Synchronisation area at the start of every single-image workspace: the
-// sticky error word of the one-launch pass (kSyncErrMagic after a wait gave
-// up; any other value means no error), then three counters per window
-// (contributions written, separators written, units done), each window's on
-// a line of its own.  The last unit of
-// a window to finish zeroes its counters, so a completed one-launch pass
-// leaves them zero for the next one.
-constexpr int kMaxWindows = 2048;   // windows of a pass: ceil(65536 / (64 - 2r)) < 2048
-constexpr int kSyncStride = 64;     // words between the counters of two windows (own line)
-constexpr int kSyncWords = kSyncStride * kMaxWindows;
-constexpr size_t kSyncBytes = 256 + sizeof(unsigned int) * kSyncWords;
-constexpr unsigned int kSyncErrMagic = 0x53475731u;
-DEV_HOST_INLINE unsigned int* sync_err(void* ws) { return reinterpret_cast<unsigned int*>(ws); }
-DEV_HOST_INLINE unsigned int* sync_counters(void* ws) {
-  return reinterpret_cast<unsigned int*>(reinterpret_cast<char*>(ws) + 256);
-}
-
-// Host state of the one-launch pass within one call.
-struct FusedCtl {
-  void* ws;              // workspace (synchronisation area at its start)
-  bool* zeroed;          // whether the counters are known to be zero on the stream
-  unsigned int limit;    // polls per wait before giving up
-};
 // Launch configuration of one (r, channel block, precision, stride, variant).
 struct PassPlan {
   int mode;         // kModeForward or kModeBackward
@@ -140,7 +157,6 @@ struct PassPlan {
   size_t sum_elems, u_elems;   // interface buffer sizes (elements)
   size_t g_elems;              // scratch of the long-run interface solver (elements)
   int acc_bytes;    // 4 (float) or 8 (double) interface element size
-  const FusedCtl* fused;       // set by the caller to allow the one-launch pass
 };
 
 // Cancellation-free float32 mode at r = 1 (sgwls_delta.hip): one serial
@@ -173,9 +189,7 @@ bool frames_supported(int C, int r, int stride, int fp64);
 constexpr int kStageReduce = 1, kStageInterface = 2, kStageExpand = 4, kStageAll = 7;
 // With the stage mask: store the pass output transposed (see PassGeom::out_t).
 constexpr int kStageTransposeOut = 8;
-// With the stage mask: the window counters of the workspace are known to be
-// zero (a one-launch pass on it completed), so they are not cleared first.
-constexpr int kStageSyncZero = 16;
+
 
 // Extra operands of a backward pass (all device pointers).
 struct BwdArgs {
@@ -256,10 +270,7 @@ hipError_t launch_batch_pass(int variant, int fp64, int kind, int r, const Batch
 // dst (cols x rows) = transpose of src (rows x cols), `planes` planes; with
 // accumulate, dst += the transpose.
 hipError_t launch_transpose(const float* src, float* dst, int rows, int cols, hipStream_t stream,
-                            int planes = 1, int accumulate = 0, unsigned int* zero = nullptr,
-                            int nzero = 0);
-// dst[0..n) = 0, ordered on the stream (no memset node in captured graphs).
-hipError_t launch_zero_words(unsigned int* dst, int n, hipStream_t stream);
+                            int planes = 1, int accumulate = 0);
 
 // u[c] = num[c] / den for c < C (planes of `plane` floats).
 hipError_t launch_divide_planes(const float* num, const float* den, float* u, int C,

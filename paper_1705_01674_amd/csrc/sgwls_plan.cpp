@@ -41,7 +41,6 @@ PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64, int varian
   pl.g_elems = (n > 0 && pl.iface_m == 0)
                    ? (size_t)std::max(m, 1) * kWave * (3 * r * r + r * pl.nr) * pl.nK
                    : 0;
-  pl.fused = nullptr;
   return pl;
 }
 

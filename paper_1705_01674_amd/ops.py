@@ -237,9 +237,9 @@ def sgwls_pass_stages(stages: int, direction: int, x: torch.Tensor, g: torch.Ten
                       lambda_dev: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
                       workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
     """The stages of one pass (see sgwls_pass_stages in sgwls.h): mask bits
-    1 reduce, 2 interface, 4 expand, 8 transposed output, 16 counters known
-    zero.  With a shared workspace, masks 1, 2 and 4 called in order compute
-    one pass; mask 7 + 8 runs it as one launch where that applies."""
+    1 reduce, 2 interface, 4 expand, 8 transposed output.  With a shared
+    workspace and one channel block (C = 1 or 3), masks 1, 2 and 4 called in
+    order compute one pass."""
     C, M, N = _image(x, "x")
     dev = x.device
     _guidance(g, M, N, dev)
@@ -255,16 +255,6 @@ def sgwls_pass_stages(stages: int, direction: int, x: torch.Tensor, g: torch.Ten
                                         _stream(dev)),
               "sgwls_pass_stages")
     return out
-
-
-def workspace_status(workspace: torch.Tensor) -> int:
-    """Synchronises the current stream; 0 if no wait of a one-launch pass on
-    this workspace gave up since the last check, else the error status."""
-    return int(nat.lib.sgwls_workspace_status(_ptr(workspace), _stream(workspace.device)))
-
-
-def set_spin_limit(polls: int) -> None:
-    nat.lib.sgwls_set_spin_limit(int(polls))
 
 
 # ---------------------------------------------------------------------------
@@ -349,13 +339,75 @@ def sgwls_backward(g: torch.Tensor, saved: torch.Tensor, grad_u: torch.Tensor, p
     return grad_f, gbar, glam
 
 
+def _batch4(x: torch.Tensor, name: str):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float32:
+        raise TypeError(f"{name} must be a float32 CUDA (HIP) tensor")
+    if not x.is_contiguous() or x.dim() != 4:
+        raise ValueError(f"{name} must be a contiguous (B, C, M, N) tensor")
+    return tuple(x.shape)
+
+
+def sgwls_filter_nchw(f: torch.Tensor, g: torch.Tensor, p: Params, *,
+                      lambda_dev: Optional[torch.Tensor] = None,
+                      saved: Optional[torch.Tensor] = None,
+                      out: Optional[torch.Tensor] = None,
+                      workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """The filter of B equal-shape images in each launch: f (B, C, M, N), g
+    (B, M, N); saved (optional) B x 2T x C x M x N."""
+    B, C, M, N = _batch4(f, "f")
+    dev = f.device
+    if g.shape != (B, M, N) or not g.is_contiguous() or g.dtype != torch.float32 or g.device != dev:
+        raise ValueError(f"g must be a contiguous float32 ({B}, {M}, {N}) tensor on the device of f")
+    lam = _lambda(lambda_dev, dev)
+    out = torch.empty_like(f) if out is None else out
+    if out.shape != f.shape or not out.is_contiguous() or out.device != dev:
+        raise ValueError("out must match f")
+    if saved is not None and (saved.numel() != B * 2 * p.iters * C * M * N or not saved.is_contiguous()
+                              or saved.dtype != torch.float32 or saved.device != dev):
+        raise ValueError("saved must be a contiguous float32 tensor of B*2T*C*M*N elements")
+    nbytes = nat.lib.sgwls_workspace_bytes_nchw(B, C, M, N, ctypes.byref(p.c()), int(saved is not None))
+    if nbytes == 0:
+        nat.check(nat.lib.sgwls_validate(C, M, N, ctypes.byref(p.c())) or 4, "sgwls_workspace_bytes_nchw")
+    ws = workspace if workspace is not None else _workspace(nbytes, dev)
+    if ws.numel() < nbytes or ws.device != dev:
+        raise ValueError("workspace too small")
+    nat.check(nat.lib.sgwls_filter_nchw(_ptr(f), _ptr(g), _ptr(out), B, C, M, N, ctypes.byref(p.c()),
+                                        _ptr(lam), _ptr(saved), _ptr(ws), ws.numel(), _stream(dev)),
+              "sgwls_filter_nchw")
+    return out
+
+
+def sgwls_backward_nchw(g: torch.Tensor, saved: torch.Tensor, grad_u: torch.Tensor, p: Params, *,
+                        lambda_dev: Optional[torch.Tensor] = None, want_g: bool = True,
+                        want_lambda: bool = True, workspace: Optional[torch.Tensor] = None):
+    """Adjoint of sgwls_filter_nchw: returns (grad_f (B, C, M, N), grad_g
+    (B, M, N) or None, grad_lambda summed over the batch (float64 device
+    tensor) or None)."""
+    B, C, M, N = _batch4(grad_u, "grad_u")
+    dev = grad_u.device
+    lam = _lambda(lambda_dev, dev)
+    grad_f = torch.empty_like(grad_u)
+    gbar = torch.empty_like(g) if want_g else None
+    glam = torch.empty(1, dtype=torch.float64, device=dev) if want_lambda else None
+    nbytes = nat.lib.sgwls_backward_workspace_bytes_nchw(B, C, M, N, ctypes.byref(p.c()))
+    ws = workspace if workspace is not None else _workspace(nbytes, dev)
+    if ws.numel() < nbytes or ws.device != dev:
+        raise ValueError("workspace too small")
+    nat.check(nat.lib.sgwls_backward_nchw(_ptr(g), _ptr(saved), _ptr(grad_u), _ptr(grad_f), _ptr(gbar),
+                                          _ptr(glam), B, C, M, N, ctypes.byref(p.c()), _ptr(lam),
+                                          _ptr(ws), ws.numel(), _stream(dev)),
+              "sgwls_backward_nchw")
+    return grad_f, gbar, glam
+
+
 class SGWLSFunction(torch.autograd.Function):
     """u = SG-WLS(f, g, lambda) with gradients for f, g and lambda.
 
     f: (C, M, N) or (B, C, M, N) float32; g: (M, N) or (B, M, N) float32;
     lam: one-element float32 tensor on the device (a learnable scalar).  The
     forward pass saves every pass input (2T images per image); the backward
-    pass runs the adjoint kernels, which recompute the weights from g."""
+    pass runs the adjoint kernels, which recompute the weights from g.  A
+    batch runs as one NCHW call each way (every launch covers all images)."""
 
     @staticmethod
     def forward(ctx, f, g, lam, p: Params):
@@ -372,11 +424,8 @@ class SGWLSFunction(torch.autograd.Function):
             # needs a gradient (which asks for FP64 pivots in both calls).
             p = p.with_(lam=max(float(lam_dev.item()), 0.0))
             p = p.with_(prec=resolve_precision(p, bool(ctx.needs_input_grad[2])))
-        out = torch.empty_like(fb)
         saved = torch.empty((B, 2 * p.iters, C, M, N), dtype=torch.float32, device=f.device)
-        ws = _workspace(workspace_bytes(C, M, N, p, True), f.device)
-        for b in range(B):
-            sgwls_filter(fb[b], gb[b], p, lambda_dev=lam_dev, saved=saved[b], out=out[b], workspace=ws)
+        out = sgwls_filter_nchw(fb, gb, p, lambda_dev=lam_dev, saved=saved)
         ctx.p = p
         ctx.batched = batched
         ctx.lam_shape = lam.shape
@@ -388,21 +437,10 @@ class SGWLSFunction(torch.autograd.Function):
         gb, saved, lam_dev = ctx.saved_tensors
         p = ctx.p
         go = grad_out.contiguous() if ctx.batched else grad_out.contiguous().unsqueeze(0)
-        B, C, M, N = go.shape
         want_f, want_g, want_l = ctx.needs_input_grad[0], ctx.needs_input_grad[1], ctx.needs_input_grad[2]
-        grad_f = torch.empty_like(go)
-        grad_g = torch.empty_like(gb) if want_g else None
-        glam = torch.zeros(B, dtype=torch.float64, device=go.device) if want_l else None
-        ws = _workspace(backward_workspace_bytes(C, M, N, p), go.device)
-        for b in range(B):
-            _, gg, gl = sgwls_backward(gb[b], saved[b], go[b], p, lambda_dev=lam_dev,
-                                       want_g=want_g, want_lambda=want_l, grad_f=grad_f[b],
-                                       workspace=ws)
-            if want_g:
-                grad_g[b].copy_(gg)
-            if want_l:
-                glam[b:b + 1].copy_(gl)
-        gl_out = glam.sum().to(torch.float32).reshape(ctx.lam_shape) if want_l else None
+        grad_f, grad_g, glam = sgwls_backward_nchw(gb, saved, go, p, lambda_dev=lam_dev,
+                                                   want_g=want_g, want_lambda=want_l)
+        gl_out = glam.to(torch.float32).reshape(ctx.lam_shape) if want_l else None
         if not ctx.batched:
             grad_f = grad_f[0]
             grad_g = grad_g[0] if want_g else None

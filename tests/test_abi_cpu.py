@@ -318,8 +318,7 @@ def test_delta_mode_is_filter_only(nat):
     strips = max((N - 2) * 3 * M, (M - 2) * 3 * N)     # stride 1: W - 2 strips of 3L elements
     img = (4 * C * M * N + 255) // 256 * 256
     gimg = (4 * M * N + 255) // 256 * 256                # the transposed guidance
-    sync = 256 + 4 * 64 * 2048                          # the one-launch pass's counters
-    want = sync + img + gimg + 4 * 4 * strips + 256     # 16-byte records, aligned start
+    want = img + gimg + 4 * 4 * strips + 256            # 16-byte records, aligned start
     assert nat.lib.sgwls_workspace_bytes(C, M, N, ctypes.byref(p), 0) == want
     assert nat.lib.sgwls_workspace_bytes(C, M, N, ctypes.byref(P(nat, prec=2, r=2)), 0) == 0
     assert nat.lib.sgwls_backward_workspace_bytes(C, M, N, ctypes.byref(p)) == 0
@@ -332,3 +331,25 @@ def test_delta_mode_is_filter_only(nat):
                                   None, None, 0, None) == 4
     # the 2D model ignores the precision field
     assert nat.lib.sgwls_wls2d_workspace_bytes(C, M, N, ctypes.byref(P(nat, prec=2, r=2))) > 0
+
+
+def test_nchw_workspaces_and_errors(nat):
+    p = ctypes.byref(P(nat))
+    lib = nat.lib
+    one = lib.sgwls_workspace_bytes(3, 100, 120, p, 0)
+    assert lib.sgwls_workspace_bytes_nchw(1, 3, 100, 120, p, 0) == one
+    assert lib.sgwls_workspace_bytes_nchw(5, 3, 100, 120, p, 0) == 5 * one
+    assert lib.sgwls_workspace_bytes_nchw(0, 3, 100, 120, p, 0) == 0
+    b1 = lib.sgwls_backward_workspace_bytes_nchw(1, 3, 100, 120, p)
+    assert b1 == lib.sgwls_backward_workspace_bytes(3, 100, 120, p)
+    assert lib.sgwls_backward_workspace_bytes_nchw(4, 3, 100, 120, p) >= 4 * (b1 - 4096)
+    # the serial-strip mode is single-image only
+    assert lib.sgwls_workspace_bytes_nchw(2, 3, 40, 56, ctypes.byref(P(nat, prec=2)), 0) == 0
+    f, g, u, ws = (ctypes.c_void_p(a) for a in (0x1000, 0x2000, 0x3000, 0x4000))
+    big = 1 << 34
+    assert lib.sgwls_filter_nchw(f, g, u, 0, 3, 64, 64, p, None, None, ws, big, None) == 2
+    assert lib.sgwls_filter_nchw(f, g, g, 2, 3, 64, 64, p, None, None, ws, big, None) == 1
+    assert lib.sgwls_filter_nchw(f, g, u, 2, 3, 64, 64, ctypes.byref(P(nat, prec=2)), None, None,
+                                 ws, big, None) == 4
+    assert lib.sgwls_filter_nchw(f, g, u, 2, 3, 64, 64, p, None, None, ws, 16, None) == 3
+    assert lib.sgwls_backward_nchw(g, u, u, f, None, None, 0, 3, 64, 64, p, None, ws, big, None) == 2
