@@ -23,6 +23,8 @@ Prints ONE JSON line:
              [0.5, 32], T = 3, in one batched call (hipGraph replay on a side
              stream, autotuned variant), against a loop of single-image calls
   cold       single calls after a 512 MiB scratch write (Infinity Cache evicted)
+  fused_passes  the same call with fused passes (one launch per pass, or two)
+             against the default three launches per pass
   stride3    the same workload with stride 3 (centres 2r+1 apart, no overlap)
   ctx        1024x1024 RGB, r = 1, T = 4 (the paper's timing image size)
   wls2d      the 2D WLS model SG-WLS approximates (Eqs. 1-4) on the same
@@ -73,6 +75,9 @@ def parse():
     ap.add_argument("--sweep", action="store_true",
                     help="only the stride / radius sweep: 1024x1024 RGB, T=4, r = 1..4, "
                          "stride 1..2r+1; one JSON line")
+    ap.add_argument("--fused", action="store_true",
+                    help="only the fused-pass comparison on the 1080p RGB workload (tuned "
+                         "variants): one JSON line")
     ap.add_argument("--counters", choices=("fwd", "fwdbwd", "radius"), default=None,
                     help="for rocprofv3 --pmc runs: the tuned forward (or forward + backward) "
                          "steps only, then three copies of 64 MiB (the counter calibration), "
@@ -338,6 +343,27 @@ def counter_run(torch, step, args, ms_note):
                       "calibration_copy_bytes": 64 * 1024 * 1024, **ms_note}), flush=True)
 
 
+def fused_rows(torch, ops, f, g, p, ws, reps):
+    """The filter call with its passes fused (SGWLS_ONE_LAUNCH = 1: one launch
+    per pass; 2: elimination + separator systems in one launch, re-solve in a
+    second) against the default three launches, at the tuned variants."""
+    old = os.environ.get("SGWLS_ONE_LAUNCH")
+    out = {}
+    try:
+        for mode, key in (("0", "three_launch_ms"), ("2", "two_launch_ms"), ("1", "one_launch_ms")):
+            os.environ["SGWLS_ONE_LAUNCH"] = mode
+            fn = lambda: ops.sgwls_filter(f, g, p, workspace=ws)
+            fn()
+            out[key] = round(time_events(torch, fn, reps), 5)
+            ops.filter_status(ws)
+    finally:
+        if old is None:
+            os.environ.pop("SGWLS_ONE_LAUNCH", None)
+        else:
+            os.environ["SGWLS_ONE_LAUNCH"] = old
+    return out
+
+
 def time_events(torch, fn, reps):
     """Mean milliseconds of fn() over reps calls, HIP events on the current stream."""
     start = torch.cuda.Event(enable_timing=True)
@@ -481,6 +507,10 @@ def main():
         counter_run(torch, step, args, {"variants": {f"{'col' if d == 0 else 'row'}_c{cb}": v
                                                      for (d, cb), v in sorted(tuned.items())}})
         return
+    if args.fused:
+        print(json.dumps({"fused_passes": fused_rows(torch, ops, f, g, p, ws, args.steps)}),
+              flush=True)
+        return
 
     for _ in range(args.warmup):
         step()
@@ -603,6 +633,7 @@ def main():
                                  alt_steps, args.warmup)]
 
     configs = config_rows(torch, ops, synth, dev, args)
+    fused = fused_rows(torch, ops, f, g, p, ws, args.steps)
 
     # Accuracy of this very output against the oracle, and the CPU baseline.
     step()
@@ -700,6 +731,7 @@ def main():
                        "note": "serial strip solves with excess pivots (r = 1 precision mode)"},
         "cold": {"ms_per_step": round(ms_cold, 5), "value": round(M * N / (ms_cold * 1e-3) / 1e6, 2),
                  "note": "median of single calls, each after a 512 MiB scratch write"},
+        "fused_passes": fused,
         "stride3": stride3,
         "ctx": ctx,
         "radius": radius,

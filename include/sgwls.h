@@ -201,6 +201,22 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u,
                           const float* lambda_dev, float* saved,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Fused passes (opt-in) ----
+ * The environment variable SGWLS_ONE_LAUNCH, read at every sgwls_filter /
+ * sgwls_filter_nchw call, replaces the three kernels of each stride-1 pass
+ * (Sec. 2.3: chunk elimination, separator systems, re-solve and averaging)
+ * by fused launches: 1 = one launch per pass, 2 = chunk elimination and
+ * separator systems in one launch, the re-solve in a second; unset or 0 =
+ * three launches (the default, and the fastest on MI355X at 1080p).  Fused
+ * launches hand data between workgroups through per-strip-group counters in
+ * the workspace, with bounded waits: a wait that gives up (after about two
+ * seconds, or SGWLS_FUSED_SPIN_LIMIT polls) leaves the results undefined and
+ * sets an error word at the start of ws.  sgwls_filter_status synchronises
+ * `stream`, returns SGWLS_E_HIP (and clears the word) if it is set, else
+ * SGWLS_OK; ws is the workspace of the filter calls to check.  Every call
+ * with fused passes clears the word when it starts. */
+sgwls_status sgwls_filter_status(void* ws, void* stream);
+
 /* ---- sgwls_filter without a caller workspace ----
  * For callers that cannot allocate device memory (code under graph capture,
  * tight serving loops, harnesses that forbid allocation): sgwls_filter with

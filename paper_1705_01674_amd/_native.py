@@ -25,7 +25,8 @@ EXPORTS = ["sgwls_status_str", "sgwls_version", "sgwls_validate", "sgwls_workspa
            "sgwls_autotune_batched", "sgwls_batched_graph_count", "sgwls_batched_graph_clear",
            "sgwls_interpolate_workspace_bytes", "sgwls_interpolate",
            "sgwls_wls2d_workspace_bytes", "sgwls_wls2d", "sgwls_resolve_precision",
-           "sgwls_filter_noalloc", "sgwls_workspace_bytes_nchw", "sgwls_filter_nchw",
+           "sgwls_filter_noalloc", "sgwls_filter_status", "sgwls_workspace_bytes_nchw",
+           "sgwls_filter_nchw",
            "sgwls_backward_workspace_bytes_nchw", "sgwls_backward_nchw"]
 
 
@@ -73,6 +74,8 @@ def _load():
     lib.sgwls_backward_nchw.argtypes = [vp, vp, vp, vp, vp, vp, i, i, i, i, P, vp, vp, sz, vp]
     lib.sgwls_filter_noalloc.restype = i
     lib.sgwls_filter_noalloc.argtypes = [vp, vp, vp, i, i, i, P, vp, vp, vp]
+    lib.sgwls_filter_status.restype = i
+    lib.sgwls_filter_status.argtypes = [vp, vp]
     lib.sgwls_pass.restype = i
     lib.sgwls_pass.argtypes = [i, vp, vp, vp, i, i, i, P, vp, vp, sz, vp]
     lib.sgwls_pass_stages.restype = i

@@ -145,6 +145,22 @@ size_t iface_bytes_all(int C, int M, int N, const sgwls_params& p) {
 
 size_t image_bytes(int C, int M, int N) { return align_up(sizeof(float) * (size_t)C * M * N); }
 
+// Fused forward passes (stage-ordered units with counter waits) in place of
+// the three stage kernels, read at every call from SGWLS_ONE_LAUNCH: unset
+// or 0 = three launches per pass, 1 = one launch, 2 = reduce and interface
+// in one launch, expand in a second.
+int one_launch_mode() {
+  const char* e = std::getenv("SGWLS_ONE_LAUNCH");
+  return (e && (e[0] == '1' || e[0] == '2')) ? e[0] - '0' : 0;
+}
+// Polls of one counter wait before it gives up: about two seconds, or
+// SGWLS_FUSED_SPIN_LIMIT (a test of the error path sets it small).
+unsigned int one_launch_spin_limit() {
+  const char* e = std::getenv("SGWLS_FUSED_SPIN_LIMIT");
+  if (e && e[0]) return (unsigned int)std::strtoul(e, nullptr, 10);
+  return 1u << 20;
+}
+
 // Launch errors are read with hipGetLastError, which also returns an error
 // left by an earlier, unrelated runtime call of the thread: clear it first.
 void clear_hip_error() { (void)hipGetLastError(); }
@@ -153,7 +169,7 @@ void clear_hip_error() { (void)hipGetLastError(); }
 sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* y, int C, int M,
                           int N, const sgwls_params& p, const float* lam_dev, void* iface,
                           hipStream_t stream, int stages = kStageAll, int variant = -1,
-                          const Batch* bt = nullptr) {
+                          const Batch* bt = nullptr, OneCtl* one = nullptr) {
   const int L = direction == 0 ? M : N, W = direction == 0 ? N : M;
   const WeightParams wp = weight_params(p);
   const int out_t = (stages & kStageTransposeOut) ? 1 : 0;
@@ -162,7 +178,8 @@ sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* 
     int v = variant >= 0 ? variant
                          : tuned_variant(p.r, cb, p.prec, (int)p.kind, direction, L, W);
     if (out_t && !variants_of(p.r, cb, p.prec).v[v].D) v = 0;   // variant 0 reads directly
-    const PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, v);
+    PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, v);
+    pl.one = one;
     PassGeom geo = pass_geom(direction, M, N, pl, p.stride);
     geo.out_t = out_t;
     if (bt) set_batch(geo, *bt);
@@ -653,10 +670,11 @@ size_t sgwls_workspace_bytes_nchw(int B, int C, int M, int N, const sgwls_params
   const sgwls_params pr = resolved(*p, save_for_backward ? 1 : 0);
   p = &pr;
   if (p->prec == SGWLS_P_FP32_DELTA)   // one image; + slack to align the strip buffer
-    return B == 1 ? image_bytes(C, M, N) + image_bytes(1, M, N) +
+    return B == 1 ? sync_bytes(1, M, N) + image_bytes(C, M, N) + image_bytes(1, M, N) +
                         delta_buffer_bytes(C, M, N, p->stride) + kAlign
                   : 0;
-  return (size_t)B * (image_bytes(C, M, N) + image_bytes(1, M, N) + iface_bytes_all(C, M, N, *p));
+  return sync_bytes(B, M, N) +
+         (size_t)B * (image_bytes(C, M, N) + image_bytes(1, M, N) + iface_bytes_all(C, M, N, *p));
 }
 
 sgwls_status sgwls_pass_stages(int stages, int direction, const float* x, const float* g,
@@ -693,6 +711,19 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u, int C, int M
   return sgwls_filter_nchw(f, g, u, 1, C, M, N, p, lambda_dev, saved, ws, ws_bytes, stream);
 }
 
+sgwls_status sgwls_filter_status(void* ws, void* stream) {
+  if (!ws) return SGWLS_E_ARG;
+  clear_hip_error();
+  unsigned int v = 0;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess ||
+      hipMemcpy(&v, ws, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
+    return SGWLS_E_HIP;
+  if (v != kSyncErrMagic) return SGWLS_OK;
+  const unsigned int zero = 0;
+  (void)hipMemcpy(ws, &zero, sizeof(zero), hipMemcpyHostToDevice);
+  return SGWLS_E_HIP;
+}
+
 sgwls_status sgwls_filter_nchw(const float* f, const float* g, float* u, int B, int C, int M,
                                int N, const sgwls_params* p, const float* lambda_dev,
                                float* saved, void* ws, size_t ws_bytes, void* stream) {
@@ -710,11 +741,12 @@ sgwls_status sgwls_filter_nchw(const float* f, const float* g, float* u, int B, 
     // and writes tmp (N x M), pass 2t+1 reads tmp (guidance g^T) and writes u.
     if (saved || B != 1) return SGWLS_E_UNSUPPORTED;
     const size_t img = image_bytes(C, M, N), gimg = image_bytes(1, M, N);
-    if (!ws || ws_bytes < img + gimg + delta_buffer_bytes(C, M, N, p->stride) + kAlign)
+    const size_t sb = sync_bytes(1, M, N);
+    if (!ws || ws_bytes < sb + img + gimg + delta_buffer_bytes(C, M, N, p->stride) + kAlign)
       return SGWLS_E_WORKSPACE;
     clear_hip_error();
     hipStream_t s = (hipStream_t)stream;
-    char* base = reinterpret_cast<char*>(ws);
+    char* base = reinterpret_cast<char*>(ws) + sb;
     float* tmp = reinterpret_cast<float*>(base);
     float* gT = reinterpret_cast<float*>(base + img);
     // the strip buffer holds 16-byte records: start it on an aligned address
@@ -735,15 +767,17 @@ sgwls_status sgwls_filter_nchw(const float* f, const float* g, float* u, int B, 
     }
     return SGWLS_OK;
   }
-  // Workspace: B intermediate images, B transposed guidance planes, then B
-  // per-image interface buffers.
+  // Workspace: the synchronisation area, B intermediate images, B transposed
+  // guidance planes, then B per-image interface buffers.
   const size_t img = image_bytes(C, M, N), gimg = image_bytes(1, M, N);
   const size_t iface_img = iface_bytes_all(C, M, N, *p);
   const size_t nb = (size_t)B;
-  if (!ws || ws_bytes < nb * (img + gimg + iface_img)) return SGWLS_E_WORKSPACE;
+  const size_t sb = sync_bytes(B, M, N);
+  if (!ws || ws_bytes < sb + nb * (img + gimg + iface_img)) return SGWLS_E_WORKSPACE;
   clear_hip_error();
   hipStream_t s = (hipStream_t)stream;
-  char* base = reinterpret_cast<char*>(ws);
+  unsigned int* sync = reinterpret_cast<unsigned int*>(ws);
+  char* base = reinterpret_cast<char*>(ws) + sb;
   float* tmp = reinterpret_cast<float*>(base);
   float* gT = reinterpret_cast<float*>(base + nb * img);
   void* iface = base + nb * (img + gimg);
@@ -779,14 +813,32 @@ sgwls_status sgwls_filter_nchw(const float* f, const float* g, float* u, int B, 
     // -- and writes the image layout again.  Without saved, pass 2t writes tmp
     // and pass 2t+1 writes u; with saved, pass q writes saved[q+1] (so odd
     // entries hold transposed images) and the last pass writes u.
-    if (launch_transpose(g, gT, M, N, s, B) != hipSuccess) return SGWLS_E_HIP;
+    // One-launch passes: the transpose of g also clears the error word and
+    // both counter banks.
+    OneCtl one{};
+    OneCtl* onep = nullptr;
+    int nzero = 0;
+    const int fuse = one_launch_mode();
+    if (fuse && p->stride == 1) {
+      one.full = fuse == 1;
+      one.err = sync;
+      one.banks = sync + kSyncHead / sizeof(unsigned int);
+      one.counters = sync_counters(B, M, N);
+      one.bank = 0;
+      one.zeroed[0] = one.zeroed[1] = true;
+      one.limit = one_launch_spin_limit();
+      nzero = (int)(kSyncHead / sizeof(unsigned int)) + 2 * one.bank_words();
+      onep = &one;
+    }
+    if (launch_transpose(g, gT, M, N, s, B, 0, onep ? sync : nullptr, nzero) != hipSuccess)
+      return SGWLS_E_HIP;
     const float* x = saved ? saved : f;
     for (int q = 0; q < passes; ++q) {
       const bool even = q % 2 == 0;
       float* y = q == passes - 1 ? u : saved ? saved + (size_t)(q + 1) * plane : even ? tmp : u;
       const Batch bt = batch(x, y);
       st = enqueue_pass(0, x, even ? g : gT, y, C, even ? M : N, even ? N : M, *p, lambda_dev,
-                        iface, s, kStageAll | kStageTransposeOut, -1, &bt);
+                        iface, s, kStageAll | kStageTransposeOut, -1, &bt, onep);
       if (st != SGWLS_OK) return st;
       x = y;
     }

@@ -65,8 +65,11 @@ __global__ __launch_bounds__(256) void k_write_words(unsigned int* __restrict__ 
 // 32 x 32 tiles through LDS (padded row), coalesced reads and writes.
 __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ src,
                                                    float* __restrict__ dst, int rows, int cols,
-                                                   int accumulate) {
+                                                   int accumulate, unsigned int* zero,
+                                                   int nzero) {
   __shared__ float t[32][33];
+  if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0)
+    for (int i = threadIdx.x; i < nzero; i += 256) zero[i] = 0u;
   const size_t plane = (size_t)rows * cols;
   src += blockIdx.z * plane;
   dst += blockIdx.z * plane;
@@ -89,9 +92,20 @@ __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ src
 }  // namespace
 
 hipError_t launch_transpose(const float* src, float* dst, int rows, int cols, hipStream_t stream,
-                            int planes, int accumulate) {
+                            int planes, int accumulate, unsigned int* zero, int nzero) {
   hipLaunchKernelGGL(k_transpose, dim3((cols + 31) / 32, (rows + 31) / 32, planes), dim3(256), 0,
-                     stream, src, dst, rows, cols, accumulate);
+                     stream, src, dst, rows, cols, accumulate, zero, nzero);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_zero_words(unsigned int* __restrict__ dst, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = 0u;
+}
+
+hipError_t launch_zero_words(unsigned int* dst, int n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_words, dim3((n + 255) / 256), dim3(256), 0, stream, dst, n);
   return hipGetLastError();
 }
 

@@ -543,6 +543,22 @@ DEV int expand_first_strip(int bx, int OW, const PassGeom& geo, int r) {
   return min(ki, geo.nK - 1);
 }
 
+// Loads and stores of interface data.  COH: the data passes between
+// workgroups of one launch (possibly on different XCDs, whose L2 caches are
+// not coherent with each other), so it is written through to and read from
+// the device-coherent level (agent-scope relaxed atomic accesses, one word
+// each); otherwise plain accesses (the data crosses a kernel boundary).
+template <bool COH, typename T>
+DEV T ld_if(const T* p) {
+  if constexpr (COH) return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return *p;
+}
+template <bool COH, typename T>
+DEV void st_if(T* p, T v) {
+  if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else *p = v;
+}
+
 // Guidance of the chunk elements m in [-r, E + r) (gv[m + r]) and the weights
 // omega(m, m+d) of Eq. (2) without lambda (om[m + r][d - 1], m in [-r, E)).
 template <int r, int KIND, class V>
@@ -580,7 +596,7 @@ DEV float domega(float w, float dg, const WeightParams& wp) {
 // CB channels of the output gradient X2 divided by the cover counts, so the
 // pass solution and the adjoint solve share one elimination (NR = 2 CB).
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE,
-          bool DIRECT = false>
+          bool DIRECT = false, bool COH = false>
 DEV void reduce_tile(const PassGeom& geo, const WeightParams& wp, float lam, int pch,
                      Acc* __restrict__ sum, int bx, int by, float* smem,
                      const float* G = nullptr, const PlaneSrc<CB>* src = nullptr);
@@ -613,7 +629,8 @@ DEV void reduce_block(const float* __restrict__ X, const float* __restrict__ X2,
 
 // The elimination of a block whose tile is in LDS (see reduce_block), or, with
 // DIRECT, whose chunks are read from global memory (stride-1 column pass).
-template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE, bool DIRECT>
+template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE, bool DIRECT,
+          bool COH>
 DEV void reduce_tile(const PassGeom& geo, const WeightParams& wp, float lam, int pch,
                      Acc* __restrict__ sum, int bx, int by, float* smem, const float* G,
                      const PlaneSrc<CB>* src) {
@@ -776,7 +793,7 @@ DEV void reduce_tile(const PassGeom& geo, const WeightParams& wp, float lam, int
   for (int idx = threadIdx.x; idx < kWave * Q * LY::F; idx += kWave * Q) {
     const int s = idx / (Q * LY::F), t = idx - s * (Q * LY::F);
     if (ki_lo + s < geo.nK && t < qv * LY::F)
-      sum[((size_t)(ki_lo + s) * geo.P + j0) * LY::F + t] = stg[idx];
+      st_if<COH>(sum + ((size_t)(ki_lo + s) * geo.P + j0) * LY::F + t, stg[idx]);
   }
 }
 
@@ -796,12 +813,12 @@ __global__ __launch_bounds__(kWave* Q) void k_reduce(
 // ---------------------------------------------------------------------------
 // Separator system of one strip: Sigma_jj = W_j - TT_{j+1},
 // Sigma_{j,j+1}[a][c] = TB_{j+1}[c][a], rhs_j = Rf_j - RT_{j+1}, j = 0..P-2.
-template <int r, int CB, typename Acc>
+template <int r, int CB, typename Acc, bool COH = false>
 struct SepReader {
   using LY = IfaceLayout<r, CB>;
   const Acc* S;   // this strip's contributions
   int P;
-  DEV Acc at(int j, int f) const { return S[(size_t)j * LY::F + f]; }
+  DEV Acc at(int j, int f) const { return ld_if<COH>(S + (size_t)j * LY::F + f); }
   DEV void diag(int j, Acc (&A)[r][r]) const {
     int t = 0;
 #pragma unroll
@@ -832,7 +849,7 @@ struct SepReader {
 // of one strip (indices past the last chunk read the last one), loaded
 // together before the elimination so that their latency is paid once.
 // Calls index chunks absolutely; the indices are s plus compile-time offsets.
-template <int r, int CB, int NREC, typename Acc>
+template <int r, int CB, int NREC, typename Acc, bool COH = false>
 struct PreReader {
   using LY = IfaceLayout<r, CB>;
   Acc rec[NREC][LY::F];
@@ -845,7 +862,7 @@ struct PreReader {
       if (i < nrec) {
         const int jj = min(s + i, P - 1);
 #pragma unroll
-        for (int f = 0; f < LY::F; ++f) rec[i][f] = S[(size_t)jj * LY::F + f];
+        for (int f = 0; f < LY::F; ++f) rec[i][f] = ld_if<COH>(S + (size_t)jj * LY::F + f);
       }
     }
   }
@@ -961,7 +978,7 @@ DEV void iface_pcr_levels(const Acc (&S)[r][r], const Acc (&Bt)[r][r], const Acc
 // k_interface_pcr: one wave per strip, lane l owns separator blocks
 // [l*m, min(l*m + m, P-1)); MM is the compiled maximum of m.
 // U receives the separator solutions strip-major: U[(ki*(P-1) + j)*r*CB + a*CB + h].
-template <int r, int CB, int MM, typename Acc, class Reader>
+template <int r, int CB, int MM, typename Acc, class Reader, bool COH = false>
 DEV void iface_pcr_run(const Reader& rd, Acc* __restrict__ U, int P, int m, int ki) {
   const int lane = threadIdx.x % kWave;
   const int n = P - 1;
@@ -1067,7 +1084,7 @@ DEV void iface_pcr_run(const Reader& rd, Acc* __restrict__ U, int P, int m, int 
 #pragma unroll
   for (int a = 0; a < r; ++a)
 #pragma unroll
-    for (int h = 0; h < CB; ++h) out[(size_t)(e - 1) * r * CB + a * CB + h] = X[a][h];
+    for (int h = 0; h < CB; ++h) st_if<COH>(out + (size_t)(e - 1) * r * CB + a * CB + h, X[a][h]);
   // back substitution: x_b = S_b^-1 (R_b - U_b x_{b+1} - Bt_b x_T)
   Acc xn[r][CB];
 #pragma unroll
@@ -1093,7 +1110,7 @@ DEV void iface_pcr_run(const Reader& rd, Acc* __restrict__ U, int P, int m, int 
       for (int a = 0; a < r; ++a)
 #pragma unroll
         for (int h = 0; h < CB; ++h) {
-          out[(size_t)b * r * CB + a * CB + h] = v[a][h];
+          st_if<COH>(out + (size_t)b * r * CB + a * CB + h, v[a][h]);
           xn[a][h] = v[a][h];
         }
     }
@@ -1102,17 +1119,17 @@ DEV void iface_pcr_run(const Reader& rd, Acc* __restrict__ U, int P, int m, int 
 
 // The solver of one strip: its chunk records prefetched into registers
 // when the lane's run fits (MM + 1 records), else read as needed.
-template <int r, int CB, int MM, typename Acc>
+template <int r, int CB, int MM, typename Acc, bool COH = false>
 DEV void iface_pcr_strip(const Acc* __restrict__ sum, Acc* __restrict__ U, int P, int m, int ki) {
   using LY = IfaceLayout<r, CB>;
   const Acc* S = sum + (size_t)ki * P * LY::F;
   if constexpr ((MM + 1) * LY::F <= 160) {
-    PreReader<r, CB, MM + 1, Acc> rd;
+    PreReader<r, CB, MM + 1, Acc, COH> rd;
     rd.load(S, (int)(threadIdx.x % kWave) * m, P, m + 1);
-    iface_pcr_run<r, CB, MM, Acc>(rd, U, P, m, ki);
+    iface_pcr_run<r, CB, MM, Acc, PreReader<r, CB, MM + 1, Acc, COH>, COH>(rd, U, P, m, ki);
   } else {
-    const SepReader<r, CB, Acc> rd{S, P};
-    iface_pcr_run<r, CB, MM, Acc>(rd, U, P, m, ki);
+    const SepReader<r, CB, Acc, COH> rd{S, P};
+    iface_pcr_run<r, CB, MM, Acc, SepReader<r, CB, Acc, COH>, COH>(rd, U, P, m, ki);
   }
 }
 
@@ -1338,7 +1355,7 @@ __global__ __launch_bounds__(kWave) void k_interface_pcr_long(const Acc* __restr
 // the block owns (a strip is solved by the two blocks whose columns it
 // touches, and owned by the first).
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE,
-          bool DIRECT = false>
+          bool DIRECT = false, bool COH = false>
 DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const PassGeom& geo,
                      const WeightParams& wp, float lam_in, int c0, const Acc* __restrict__ Us,
                      int OW, int pch, const BwdArgs& bw, int bx, int by, int nbx, float* smem,
@@ -1409,7 +1426,8 @@ DEV void store_transposed(const float* smem, float* __restrict__ Yc, const float
 
 // The solve and output of a block whose tile is in LDS (see expand_block), or,
 // with DIRECT, whose chunks are read from global memory (stride-1 column pass).
-template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE, bool DIRECT>
+template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE, bool DIRECT,
+          bool COH>
 DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const PassGeom& geo,
                      const WeightParams& wp, float lam_in, int c0, const Acc* __restrict__ Us,
                      int OW, int pch, const BwdArgs& bw, int bx, int by, int nbx, float* smem,
@@ -1452,8 +1470,8 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
     for (int a = 0; a < r; ++a)
 #pragma unroll
       for (int h = 0; h < NR; ++h) {
-        uT[a][h] = hasT ? us[(size_t)(j - 1) * r * NR + a * NR + h] : Acc(0);
-        uB[a][h] = hasB ? us[(size_t)j * r * NR + a * NR + h] : Acc(0);
+        uT[a][h] = hasT ? ld_if<COH>(us + (size_t)(j - 1) * r * NR + a * NR + h) : Acc(0);
+        uB[a][h] = hasB ? ld_if<COH>(us + (size_t)j * r * NR + a * NR + h) : Acc(0);
       }
     typename std::conditional<DIRECT, GlobalChunk<r, R, NR>, CV>::type cv;
     if constexpr (DIRECT) {
@@ -1913,6 +1931,115 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
 }
 
 // ---------------------------------------------------------------------------
+// One launch per pass (forward, stride 1, direct reads, transposed output).
+//
+// The three kernels of a pass run as the units of one grid, ordered by stage:
+// gx*gy reduce units first, strip group by strip group (each XCD takes a
+// contiguous range of groups), then the expand units.  The last `nlast`
+// reduce units of a strip group to finish solve the group's separator
+// systems (one wave per strip, the block cyclic reduction of
+// k_interface_pcr), while the units of later groups are still reducing.  An
+// expand unit waits until the interfaces of the one or two groups its strips
+// belong to are solved.  Every wait is on units that precede the waiter in
+// the grid: workgroups start in order, so each waited-for unit has started,
+// and a waiting last finisher only waits for its own group's reduce units;
+// the host admits the launch only while those waiters fill at most half of
+// one XCD's resident workgroups.  Waits are bounded (the error word is set
+// and the wait abandoned past the spin limit).  Contributions and separators
+// pass between workgroups through the device-coherent level (ld / st with
+// COH), with no cache-wide fence.
+//
+// Counters (workspace, zeroed before the launch): red[z * gx + g] counts the
+// reduce units of group g of image z that have written their contributions,
+// ifc[z * gx + g] the interface units that have written its separators.
+// Block 0 of image 0 zeroes the other bank, which the next pass uses.
+struct OneSync {
+  unsigned int* red;
+  unsigned int* ifc;
+  unsigned int* next;    // the other bank (nzero words)
+  int nzero;
+  unsigned int* err;     // kSyncErrMagic after a wait gave up
+  unsigned int limit;    // polls per wait before giving up
+};
+
+// One lane polls until *c >= target (bounded); no fence: the data it guards
+// is read through the coherent level afterwards.
+DEV void wait_count(const unsigned int* c, unsigned int target, const OneSync& os) {
+  unsigned int it = 0;
+  while (__hip_atomic_load(const_cast<unsigned int*>(c), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (++it > os.limit) {
+      __hip_atomic_store(os.err, kSyncErrMagic, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    __builtin_amdgcn_s_sleep(16);
+  }
+}
+
+template <int r, int CB, int R, int Q, int KIND, typename Acc, int MM, bool EXPAND>
+__global__ __launch_bounds__(kWave* Q) void k_pass_one(
+    const float* __restrict__ X, const float* __restrict__ G, float* __restrict__ Y,
+    PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
+    Acc* __restrict__ sum, Acc* __restrict__ Us, int OW, int pitch, int gx, int gy, int ex,
+    int nlast, OneSync os) {
+  extern __shared__ float smem[];
+  const int z = blockIdx.z;
+  if (blockIdx.x == 0 && z == 0)
+    for (int i = threadIdx.x; i < os.nzero; i += kWave * Q) os.next[i] = 0u;
+  const float lam = load_lambda(lam_dev, lam_host);
+  const float* Xz = zmove(X, geo.zx, z);
+  const float* Gz = zmove(G, geo.zg, z);
+  Acc* sumz = zmove_bytes(sum, geo.zi, z);
+  Acc* Usz = zmove_bytes(Us, geo.zi, z);
+  const PlaneSrc<CB> src{Xz, nullptr, c0, (int)geo.plane};
+  const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int nred = geo.P > 1 ? gx * gy : 0;
+  __shared__ unsigned int ticket;
+  if ((int)blockIdx.x < nred) {
+    const int logical = xcd_rank(blockIdx.x, nred);
+    const int bx = logical / gy, by = logical - bx * gy;   // group-major
+    reduce_tile<r, CB, R, Q, true, KIND, Acc, kModeForward, true, true>(
+        geo, wp, lam, 0, sumz, bx, by, smem, Gz, &src);
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's contributions are stored
+    __syncthreads();
+    unsigned int* red = os.red + ((size_t)z * gx + bx) * kCounterStride;
+    if (threadIdx.x == 0)
+      ticket = __hip_atomic_fetch_add(red, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int t = (int)ticket - (gy - nlast);
+    if (t < 0) return;
+    // one of the group's last nlast units: the separator systems of its strips
+    if (threadIdx.x == 0) wait_count(red, (unsigned int)gy, os);
+    __syncthreads();
+    const int k0 = bx * kWave, nstr = min(kWave, geo.nK - k0);
+    const int m = (geo.P - 1 + kWave - 1) / kWave;
+    for (int l = t * Q + wq; l < nstr; l += nlast * Q)
+      iface_pcr_strip<r, CB, MM, Acc, true>(sumz, Usz, geo.P, m, k0 + l);
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's separators are stored
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(os.ifc + ((size_t)z * gx + bx) * kCounterStride, 1u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  if constexpr (EXPAND) {
+  const int e = blockIdx.x - nred;
+  const int logical = xcd_rank(e, ex * gy);
+  const int bx = logical / gy, by = logical - bx * gy;     // group-major
+  if (geo.P > 1 && threadIdx.x == 0) {
+    const int ki_lo = expand_first_strip(bx, OW, geo, r);
+    const int ki_hi = min(ki_lo + kWave - 1, geo.nK - 1);
+    wait_count(os.ifc + ((size_t)z * gx + ki_lo / kWave) * kCounterStride, (unsigned int)nlast, os);
+    wait_count(os.ifc + ((size_t)z * gx + ki_hi / kWave) * kCounterStride, (unsigned int)nlast, os);
+  }
+  __syncthreads();
+  const BwdArgs none{};
+  expand_tile<r, CB, R, Q, true, KIND, Acc, kModeForward, true, true>(
+      Gz, zmove(Y, geo.zy, z), geo, wp, lam, c0, Usz, OW, pitch, none, bx, by, ex, smem, &src);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Launch of one pass for one (r, channel block, precision, stride class,
 // weight kind, variant, mode).
 template <int r, int CB, int fp64, bool S1, int KIND, int R, int Q, int MODE, int D = 0>
@@ -1931,6 +2058,56 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
   const size_t stage_out = sizeof(Acc) * (size_t)kWave * Q * LY::F;
   const int gy = (geo.P + Q - 1) / Q;
   const int nz = geo.nimg > 0 ? geo.nimg : 1;   // images of an NCHW batch (blockIdx.z)
+  if constexpr (D != 0 && S1 && MODE == kModeForward && VS.MM > 0) {
+    if (pl.one && geo.sb == 1 && geo.out_t && stages == kStageAll && geo.P > 1 &&
+        pl.iface_m > 0 && pl.iface_m <= VS.MM) {
+      constexpr int MM = VS.MM;
+      const bool full = pl.one->full;
+      auto kern = full ? k_pass_one<r, CB, R, Q, KIND, Acc, MM, true>
+                       : k_pass_one<r, CB, R, Q, KIND, Acc, MM, false>;
+      const int gx = (geo.nK + kWave - 1) / kWave;
+      const int ex = (geo.W + pl.OW - 1) / pl.OW;
+      const int nlast = std::min(gy, (kWave + Q - 1) / Q);
+      const size_t lds = std::max(stage_out, sizeof(float) * CB * Q * R * (kWave + 1));
+      static int per_cu_of[2] = {-1, -1};   // resident workgroups per CU of each form
+      int& per_cu = per_cu_of[full ? 1 : 0];
+      if (per_cu < 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kern),
+                                                         kWave * Q, lds) != hipSuccess) {
+          (void)hipGetLastError();
+          nb = 0;
+        }
+        per_cu = nb;
+      }
+      int dev = 0, cus = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        cus = 0;
+      }
+      // Waiting last finishers take at most half of one XCD's resident
+      // workgroups, and the counters fit their bank.
+      if (2LL * nlast * 8 <= (long long)per_cu * cus && (long long)nz * gx <= pl.one->counters) {
+        OneCtl& ctl = *pl.one;
+        if (!ctl.zeroed[ctl.bank]) {
+          const hipError_t e = launch_zero_words(ctl.bank_ptr(ctl.bank), ctl.bank_words(), stream);
+          if (e != hipSuccess) return e;
+        }
+        OneSync os{ctl.bank_ptr(ctl.bank), ctl.bank_ptr(ctl.bank) + ctl.counters * kCounterStride,
+                   ctl.bank_ptr(1 - ctl.bank), ctl.bank_words(), ctl.err, ctl.limit};
+        ctl.zeroed[1 - ctl.bank] = true;   // this launch zeroes the other bank
+        ctl.zeroed[ctl.bank] = false;
+        ctl.bank = 1 - ctl.bank;
+        const int nred = gx * gy;
+        hipLaunchKernelGGL(kern, dim3(nred + (full ? ex * gy : 0), 1, nz), dim3(kWave * Q),
+                           full ? lds : stage_out, stream, x, g, y, geo, wp, lam_dev, lam_host, c0,
+                           sum, us, pl.OW, pl.pitch, gx, gy, ex, nlast, os);
+        if (full) return hipGetLastError();
+        stages = kStageExpand;   // the separators are solved: expand in a launch of its own
+      }
+    }
+  }
   if (geo.P > 1 && (stages & kStageReduce)) {
     const int gx = (geo.nK + kWave - 1) / kWave;
     bool direct = false;

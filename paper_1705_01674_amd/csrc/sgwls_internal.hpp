@@ -141,6 +141,39 @@ constexpr VariantSet variants_for(int mode, int r, int cb, int fp64) {
   return mode == kModeBackward ? bwd_variants_of(r, cb, fp64) : variants_of(r, cb, fp64);
 }
 
+// Synchronisation area at the start of the workspaces of sgwls_filter and
+// sgwls_filter_nchw: the error word of the fused passes (kSyncErrMagic after
+// a wait gave up; any other value means no error), then two banks of
+// counters used by alternate fused passes (two counters per image and strip
+// group; each launch zeroes the other bank for the next).
+constexpr unsigned int kSyncErrMagic = 0x53475731u;
+constexpr size_t kSyncHead = 256;
+// Counters sit 256 bytes apart, so that the polls of different strip groups
+// go to different memory channels.
+constexpr int kCounterStride = 64;
+
+// Host state of the one-launch passes of one call.
+struct OneCtl {
+  unsigned int* err;      // error word
+  unsigned int* banks;    // two banks of bank_words() words
+  long long counters;     // counters of each kind per bank (images x strip groups)
+  int bank;               // bank of the next one-launch pass
+  bool zeroed[2];         // whether each bank is known to be zero on the stream
+  unsigned int limit;     // polls per wait before giving up
+  bool full;              // expand in the same launch (else a launch of its own)
+  DEV_HOST_INLINE int bank_words() const { return (int)(2 * counters * kCounterStride); }
+  DEV_HOST_INLINE unsigned int* bank_ptr(int b) const { return banks + (size_t)b * bank_words(); }
+};
+// Synchronisation bytes of a call over B images of M x N (strip groups of 64
+// strips across the wider frame).
+inline size_t sync_bytes(int B, int M, int N) {
+  const long long groups = (long long)B * ((M > N ? M : N) / 64 + 1);
+  return kSyncHead + sizeof(unsigned int) * 4 * (size_t)kCounterStride * (size_t)groups;
+}
+inline long long sync_counters(int B, int M, int N) {
+  return (long long)B * ((M > N ? M : N) / 64 + 1);
+}
+
 // Launch configuration of one (r, channel block, precision, stride, variant).
 struct PassPlan {
   int mode;         // kModeForward or kModeBackward
@@ -157,6 +190,7 @@ struct PassPlan {
   size_t sum_elems, u_elems;   // interface buffer sizes (elements)
   size_t g_elems;              // scratch of the long-run interface solver (elements)
   int acc_bytes;    // 4 (float) or 8 (double) interface element size
+  OneCtl* one;      // set by the caller to allow the one-launch pass
 };
 
 // Cancellation-free float32 mode at r = 1 (sgwls_delta.hip): one serial
@@ -270,7 +304,10 @@ hipError_t launch_batch_pass(int variant, int fp64, int kind, int r, const Batch
 // dst (cols x rows) = transpose of src (rows x cols), `planes` planes; with
 // accumulate, dst += the transpose.
 hipError_t launch_transpose(const float* src, float* dst, int rows, int cols, hipStream_t stream,
-                            int planes = 1, int accumulate = 0);
+                            int planes = 1, int accumulate = 0, unsigned int* zero = nullptr,
+                            int nzero = 0);
+// dst[0..n) = 0, ordered on the stream (no memset node in captured graphs).
+hipError_t launch_zero_words(unsigned int* dst, int n, hipStream_t stream);
 
 // u[c] = num[c] / den for c < C (planes of `plane` floats).
 hipError_t launch_divide_planes(const float* num, const float* den, float* u, int C,

@@ -33,6 +33,7 @@ PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64, int varian
   const int T2 = r * (r + 1) / 2;
   const int F = 2 * T2 + 2 * r * pl.nr + r * r;
   pl.acc_bytes = fp64 ? 8 : 4;
+  pl.one = nullptr;
   pl.sum_elems = (size_t)pl.P * F * pl.nK;
   pl.u_elems = (size_t)std::max(n, 1) * r * pl.nr * pl.nK;
   // Runs longer than the register solver holds go to the long-run solver,

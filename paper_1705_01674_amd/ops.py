@@ -150,6 +150,14 @@ def sgwls_filter(f: torch.Tensor, g: torch.Tensor, p: Params, *,
     return out
 
 
+def filter_status(workspace: torch.Tensor) -> None:
+    """Raise if a fused pass of an earlier filter call on ``workspace`` gave
+    up a wait (its results are then undefined); synchronises the current
+    stream.  Fused passes run only when SGWLS_ONE_LAUNCH is 1 or 2."""
+    nat.check(nat.lib.sgwls_filter_status(_ptr(workspace), _stream(workspace.device)),
+              "sgwls_filter_status")
+
+
 def interpolate_workspace_bytes(C: int, M: int, N: int, p: Params) -> int:
     n = nat.lib.sgwls_interpolate_workspace_bytes(C, M, N, ctypes.byref(p.c()))
     if n == 0:
@@ -345,6 +353,15 @@ def _batch4(x: torch.Tensor, name: str):
     if not x.is_contiguous() or x.dim() != 4:
         raise ValueError(f"{name} must be a contiguous (B, C, M, N) tensor")
     return tuple(x.shape)
+
+
+def workspace_bytes_nchw(B: int, C: int, M: int, N: int, p: Params,
+                         save_for_backward: bool = False) -> int:
+    """Workspace bytes of sgwls_filter_nchw over B images of C x M x N."""
+    n = nat.lib.sgwls_workspace_bytes_nchw(B, C, M, N, ctypes.byref(p.c()), int(save_for_backward))
+    if n == 0:
+        raise ValueError("invalid batch or parameters")
+    return int(n)
 
 
 def sgwls_filter_nchw(f: torch.Tensor, g: torch.Tensor, p: Params, *,

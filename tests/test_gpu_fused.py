@@ -1,0 +1,85 @@
+"""Fused forward passes (SGWLS_ONE_LAUNCH = 1: one launch per pass, 2:
+elimination and separator systems in one launch, re-solve in a second)
+against the default three launches per pass: the same per-unit arithmetic, so
+the outputs agree to float32 rounding (the fused kernels are compiled
+separately and may contract multiply-adds differently).  The error path of the
+bounded waits is forced from the host with a zero spin limit: every wait that
+is not satisfied at its first poll gives up, the kernels still exit, and
+sgwls_filter_status reports the failure."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ops():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1705_01674_amd import ops as _ops
+    return _ops
+
+
+def _run(ops, monkeypatch, mode, f, g, p, saved=None):
+    monkeypatch.setenv("SGWLS_ONE_LAUNCH", mode)
+    ws = torch.empty(ops.workspace_bytes_nchw(f.shape[0], *f.shape[1:], p, saved is not None),
+                     dtype=torch.uint8, device="cuda")
+    u = ops.sgwls_filter_nchw(f, g, p, saved=saved, workspace=ws)
+    ops.filter_status(ws)
+    return u
+
+
+@pytest.mark.parametrize("mode", ["1", "2"])
+@pytest.mark.parametrize("B,C,M,N,r,prec,save", [
+    (1, 3, 300, 520, 1, "fp32", False), (1, 1, 257, 190, 2, "fp32", False),
+    (1, 4, 130, 200, 1, "fp32", False), (2, 3, 120, 260, 1, "fp64_pivot", True),
+    (1, 3, 90, 140, 3, "fp32", False), (1, 3, 1080, 1920, 1, "auto", False),
+])
+def test_fused_matches_three_launches(ops, monkeypatch, mode, B, C, M, N, r, prec, save):
+    print(f"[fused] mode{mode} B{B} C{C} {M}x{N} r{r} {prec} save={save}", flush=True)
+    rng = np.random.default_rng(M * 7 + N + r)
+    f = torch.from_numpy(rng.uniform(0, 1, (B, C, M, N)).astype(np.float32)).cuda()
+    g = torch.from_numpy(rng.uniform(0, 1, (B, M, N)).astype(np.float32)).cuda()
+    p = ops.Params(lam=6.0, r=r, iters=2, sigma_r=0.15, prec=prec)
+    T2 = 2 * p.iters
+    s0 = torch.empty((B, T2, C, M, N), device="cuda") if save else None
+    s1 = torch.empty((B, T2, C, M, N), device="cuda") if save else None
+    u0 = _run(ops, monkeypatch, "0", f, g, p, s0)
+    u1 = _run(ops, monkeypatch, mode, f, g, p, s1)
+    torch.cuda.synchronize()
+    assert torch.isfinite(u1).all()
+    assert (u1 - u0).abs().max().item() <= 2e-6
+    if save:
+        assert (s1 - s0).abs().max().item() <= 2e-6
+
+
+def test_fused_wait_error_is_reported(ops, monkeypatch):
+    M, N = 1080, 1920
+    rng = np.random.default_rng(5)
+    f = torch.from_numpy(rng.uniform(0, 1, (1, 3, M, N)).astype(np.float32)).cuda()
+    g = torch.from_numpy(rng.uniform(0, 1, (1, M, N)).astype(np.float32)).cuda()
+    p = ops.Params(lam=4.0, r=1, iters=3, sigma_r=0.1, prec="fp32")
+    ws = torch.empty(ops.workspace_bytes_nchw(1, 3, M, N, p), dtype=torch.uint8, device="cuda")
+    monkeypatch.setenv("SGWLS_ONE_LAUNCH", "1")
+    monkeypatch.setenv("SGWLS_FUSED_SPIN_LIMIT", "0")
+    print("[fused] zero spin limit", flush=True)
+    failures = 0
+    for _ in range(3):
+        ops.sgwls_filter_nchw(f, g, p, workspace=ws)
+        try:
+            ops.filter_status(ws)
+        except ops.nat.SgwlsError as e:
+            assert e.code == 5        # SGWLS_E_HIP
+            failures += 1
+    assert failures >= 1
+    # the word is cleared by the report; normal waits work again on the same workspace
+    monkeypatch.delenv("SGWLS_FUSED_SPIN_LIMIT")
+    ops.filter_status(ws)
+    u1 = ops.sgwls_filter_nchw(f, g, p, workspace=ws)
+    ops.filter_status(ws)
+    monkeypatch.setenv("SGWLS_ONE_LAUNCH", "0")
+    u0 = ops.sgwls_filter_nchw(f, g, p, workspace=ws)
+    torch.cuda.synchronize()
+    assert (u1 - u0).abs().max().item() <= 2e-6
