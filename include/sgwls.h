@@ -381,10 +381,13 @@ sgwls_status sgwls_backward(const float* g, const float* saved, const float* gra
 /* ---- Batches of uneven images (not in the paper) ----
  * B images of independent sizes, each with its own parameters p[b] (host
  * arrays of B entries), are filtered together: every kernel stage of a pass
- * is one persistent launch per radius over all images of that radius, whose
- * workgroups stride over the work units (image, channel, block of strips and
- * chunks), largest image first.  Requirements (else SGWLS_E_UNSUPPORTED or
- * SGWLS_E_ARG): every p[b].iters, kind and prec equal; stride 1; r <= 2;
+ * is one persistent launch per (precision, radius) group over all images of
+ * that group, whose workgroups stride over the work units (image, channel,
+ * block of strips and chunks), largest image first.  With SGWLS_P_AUTO each
+ * image resolves its own precision (float32 images keep float32 even when
+ * others of the batch need FP64 pivots).  Requirements (else
+ * SGWLS_E_UNSUPPORTED or SGWLS_E_ARG): every p[b].iters, kind and prec
+ * equal; stride 1; r <= 2;
  * each side at most about 64*8 chunks long (2052 pixels for r = 2 and 4104
  * for r = 1 with the default variant).  Images with several channels are
  * filtered channel by channel (the guidance weights are recomputed per
@@ -406,7 +409,8 @@ typedef struct {
 size_t sgwls_batched_workspace_bytes(const sgwls_image* imgs, const sgwls_params* p, int B);
 
 /* Filter B images.  Uses the variant the tuning table holds for this
- * precision, weight kind and total pixel count (variant 0 if none). */
+ * precision, weight kind and total pixel count (variant 0 if none).  The
+ * variant applies to the float32 groups; float64 groups have one. */
 sgwls_status sgwls_filter_batched(const sgwls_image* imgs, const sgwls_params* p, int B,
                                   void* ws, size_t ws_bytes, void* stream);
 

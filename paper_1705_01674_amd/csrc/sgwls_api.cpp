@@ -290,18 +290,29 @@ TuneKey batch_tune_key(int fp64, int kind, double pixels) {
   return TuneKey(0, 0, fp64, kind, kBatchDir, (int)std::lround(2.0 * std::log2(std::max(pixels, 1.0))));
 }
 
+// Images are grouped by precision (float32 groups first) and radius: group
+// k = prec * kBatchMaxR + (r - 1), one launch per group, stage and pass.
+constexpr int kBatchGroups = 2 * kBatchMaxR;
+
 struct BatchPlan {
-  int B = 0, passes = 0, fp64 = 0, kind = 0, variant = 0;
-  std::vector<BatchDesc> tab;      // by radius, then largest image first
-  int first[kBatchMaxR + 1] = {};  // images of radius r: tab[first[r-1], first[r])
-  std::vector<int> pre;            // [radius][dir][stage][B + 1] unit prefix sums over
-                                   // the images of that radius, then the [B + 1]
+  int B = 0, passes = 0, kind = 0, variant = 0;
+  int fp64 = 0;                    // every image in float64 (the variant count and tuning key)
+  std::vector<BatchDesc> tab;      // by group, then largest image first
+  int first[kBatchGroups + 1] = {};  // images of group k: tab[first[k], first[k+1])
+  std::vector<int> pre;            // [group][dir][stage][B + 1] unit prefix sums over
+                                   // the images of that group, then the [B + 1]
                                    // tile prefix sums of the guidance transposes
-  int totals[kBatchMaxR][2][3] = {};
+  int totals[kBatchGroups][2][3] = {};
   int tiles_t = 0;                 // 32 x 32 tiles of all guidance transposes
-  size_t pre_at(int r, int dir, int st) const { return (size_t)(((r - 1) * 2 + dir) * 3 + st) * (B + 1); }
-  size_t pre_tiles() const { return (size_t)kBatchMaxR * 6 * (B + 1); }
-  size_t off_tab = 0, off_pre = 0, off_tmp = 0, off_gt = 0, off_iface = 0, total = 0;
+  size_t pre_at(int k, int dir, int st) const { return (size_t)((k * 2 + dir) * 3 + st) * (B + 1); }
+  size_t pre_tiles() const { return (size_t)kBatchGroups * 6 * (B + 1); }
+  size_t off_tab = 0, off_pre = 0, off_tmp = 0, off_gt = 0, off_iface = 0, off_iface64 = 0,
+         total = 0;
+  static int group_prec(int k) { return k / kBatchMaxR; }
+  static int group_r(int k) { return k % kBatchMaxR + 1; }
+  // float32 groups run the chosen variant, float64 groups their only one
+  int group_variant(int k) const { return group_prec(k) ? 0 : variant; }
+  size_t group_iface(int k) const { return group_prec(k) ? off_iface64 : off_iface; }
 };
 
 // Validates the batch and lays out its workspace (ws may be NULL: sizes only).
@@ -317,29 +328,32 @@ sgwls_status batch_plan(const sgwls_image* imgs, const sgwls_params* p, int B, i
     if (p[b].stride != 1 || p[b].r > kBatchMaxR) return SGWLS_E_UNSUPPORTED;
     if (ws && (!im.f || !im.g || !im.u || (const float*)im.u == im.g)) return SGWLS_E_ARG;
   }
-  int fp64 = p0.prec == SGWLS_P_FP64_PIVOT ? 1 : 0;
-  for (int b = 0; b < B && p0.prec == SGWLS_P_AUTO; ++b)   // AUTO: float64 if any image needs it
-    if (resolved(p[b], 0).prec == SGWLS_P_FP64_PIVOT) fp64 = 1;
-  if (variant < 0 || variant >= batch_variant_count(fp64)) return SGWLS_E_ARG;
-  const BatchVariant bv = batch_variant(variant, fp64);
+  // Precision of every image: AUTO resolves image by image.
+  std::vector<int> prec(B);
+  int all64 = 1;
+  for (int b = 0; b < B; ++b) {
+    prec[b] = resolved(p[b], 0).prec == SGWLS_P_FP64_PIVOT ? 1 : 0;
+    all64 &= prec[b];
+  }
+  if (variant < 0 || variant >= batch_variant_count(all64)) return SGWLS_E_ARG;
   plan.B = B;
   plan.passes = 2 * p0.iters;
-  plan.fp64 = fp64;
+  plan.fp64 = all64;
   plan.kind = (int)p0.kind;
   plan.variant = variant;
+  auto group_of = [&](int b) { return prec[b] * kBatchMaxR + p[b].r - 1; };
   std::vector<int> order(B);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    if (p[a].r != p[b].r) return p[a].r < p[b].r;
+    if (group_of(a) != group_of(b)) return group_of(a) < group_of(b);
     return (long long)imgs[a].C * imgs[a].M * imgs[a].N > (long long)imgs[b].C * imgs[b].M * imgs[b].N;
   });
-  for (int r = 0; r <= kBatchMaxR; ++r) plan.first[r] = 0;
+  for (int k = 0; k <= kBatchGroups; ++k) plan.first[k] = 0;
   for (int b = 0; b < B; ++b)
-    for (int r = p[b].r; r <= kBatchMaxR; ++r) ++plan.first[r];
-  const size_t acc = fp64 ? 8 : 4;
+    for (int k = group_of(b) + 1; k <= kBatchGroups; ++k) ++plan.first[k];
   plan.off_tab = 0;
   plan.off_pre = align_up(sizeof(BatchDesc) * B);
-  plan.off_tmp = plan.off_pre + align_up(sizeof(int) * (kBatchMaxR * 6 + 1) * (B + 1));
+  plan.off_tmp = plan.off_pre + align_up(sizeof(int) * (kBatchGroups * 6 + 1) * (B + 1));
   size_t tmp_bytes = 0, gt_bytes = 0;
   for (int b = 0; b < B; ++b) {
     tmp_bytes += image_bytes(imgs[b].C, imgs[b].M, imgs[b].N);
@@ -349,13 +363,16 @@ sgwls_status batch_plan(const sgwls_image* imgs, const sgwls_params* p, int B, i
   plan.off_iface = plan.off_gt + gt_bytes;
   char* base = reinterpret_cast<char*>(ws);
   plan.tab.assign(B, BatchDesc{});
-  plan.pre.assign((kBatchMaxR * 6 + 1) * (B + 1), 0);
-  size_t tmp_off = plan.off_tmp, gt_off = plan.off_gt, iface_elems = 0;
-  long long units[kBatchMaxR][2][3] = {}, tiles = 0;
+  plan.pre.assign((kBatchGroups * 6 + 1) * (B + 1), 0);
+  size_t tmp_off = plan.off_tmp, gt_off = plan.off_gt;
+  size_t iface_elems[2] = {0, 0};   // float32 and float64 interface regions
+  long long units[kBatchGroups][2][3] = {}, tiles = 0;
   for (int t = 0; t < B; ++t) {
     const int b = order[t];
     const sgwls_image& im = imgs[b];
     const sgwls_params& pb = p[b];
+    const int k = group_of(b);
+    const BatchVariant bv = batch_variant(prec[b] ? 0 : variant, prec[b]);
     BatchDesc& D = plan.tab[t];
     D.f = im.f;
     D.g = im.g;
@@ -399,32 +416,34 @@ sgwls_status batch_plan(const sgwls_image* imgs, const sgwls_params* p, int B, i
       D.nby[dir] = (g.P + bv.Q - 1) / bv.Q;
       sum_max = std::max(sum_max, (long long)g.P * F * g.nK);
       us_max = std::max(us_max, (long long)std::max(n, 1) * pb.r * g.nK);
-      // Prefix sums of the radius' sub-table: entry t - first + 1.
+      // Prefix sums of the group's sub-table: entry t - first + 1.
       const bool split = g.P > 1;
-      long long* un = units[pb.r - 1][dir];
+      long long* un = units[k][dir];
       un[0] += split ? (long long)im.C * D.nbx_red[dir] * D.nby[dir] : 0;
       un[1] += split ? (long long)im.C * g.nK : 0;
       un[2] += (long long)im.C * D.nbx_exp[dir] * D.nby[dir];
-      const int tl = t - plan.first[pb.r - 1];
+      const int tl = t - plan.first[k];
       for (int st = 0; st < 3; ++st)
-        plan.pre[plan.pre_at(pb.r, dir, st) + tl + 1] = (int)std::min<long long>(un[st], 0x7fffffff);
+        plan.pre[plan.pre_at(k, dir, st) + tl + 1] = (int)std::min<long long>(un[st], 0x7fffffff);
     }
     D.sum_ch = sum_max;
     D.us_ch = us_max;
-    D.sum_base = (long long)iface_elems;
-    iface_elems += (size_t)im.C * sum_max;
-    D.us_base = (long long)iface_elems;
-    iface_elems += (size_t)im.C * us_max;
+    size_t& ie = iface_elems[prec[b]];
+    D.sum_base = (long long)ie;
+    ie += (size_t)im.C * sum_max;
+    D.us_base = (long long)ie;
+    ie += (size_t)im.C * us_max;
   }
-  for (int r = 0; r < kBatchMaxR; ++r)
+  for (int k = 0; k < kBatchGroups; ++k)
     for (int dir = 0; dir < 2; ++dir)
       for (int st = 0; st < 3; ++st) {
-        if (units[r][dir][st] > 0x7fffffffLL) return SGWLS_E_SHAPE;
-        plan.totals[r][dir][st] = (int)units[r][dir][st];
+        if (units[k][dir][st] > 0x7fffffffLL) return SGWLS_E_SHAPE;
+        plan.totals[k][dir][st] = (int)units[k][dir][st];
       }
   if (tiles > 0x7fffffffLL) return SGWLS_E_SHAPE;
   plan.tiles_t = (int)tiles;
-  plan.total = plan.off_iface + align_up(iface_elems * acc);
+  plan.off_iface64 = plan.off_iface + align_up(iface_elems[0] * 4);
+  plan.total = plan.off_iface64 + align_up(iface_elems[1] * 8);
   return SGWLS_OK;
 }
 
@@ -456,13 +475,14 @@ sgwls_status batch_enqueue(const BatchPlan& plan, void* ws, hipStream_t s) {
     return SGWLS_E_HIP;
   for (int q = 0; q < plan.passes; ++q) {
     const int dir = q % 2;
-    for (int r = 1; r <= kBatchMaxR; ++r) {
-      const int b0 = plan.first[r - 1], nb = plan.first[r] - b0;
+    for (int k = 0; k < kBatchGroups; ++k) {
+      const int b0 = plan.first[k], nb = plan.first[k + 1] - b0;
       if (nb == 0) continue;
-      if (launch_batch_pass(plan.variant, plan.fp64, plan.kind, r, tab + b0,
-                            pre + plan.pre_at(r, dir, 0), pre + plan.pre_at(r, dir, 1),
-                            pre + plan.pre_at(r, dir, 2), plan.totals[r - 1][dir], nb, q, dir,
-                            base + plan.off_iface, s) != hipSuccess)
+      if (launch_batch_pass(plan.group_variant(k), BatchPlan::group_prec(k), plan.kind,
+                            BatchPlan::group_r(k), tab + b0, pre + plan.pre_at(k, dir, 0),
+                            pre + plan.pre_at(k, dir, 1), pre + plan.pre_at(k, dir, 2),
+                            plan.totals[k][dir], nb, q, dir, base + plan.group_iface(k),
+                            s) != hipSuccess)
         return SGWLS_E_HIP;
     }
   }
@@ -504,10 +524,11 @@ std::string graph_key(const BatchPlan& plan, void* ws, hipStream_t s) {
 sgwls_status batch_run(const BatchPlan& plan, void* ws, hipStream_t s) {
   // Prepare the persistent grid sizes outside any capture (no launch).
   const int none[3] = {0, 0, 0};
-  for (int r = 1; r <= kBatchMaxR; ++r)
-    if (plan.first[r] > plan.first[r - 1] &&
-        launch_batch_pass(plan.variant, plan.fp64, plan.kind, r, nullptr, nullptr, nullptr, nullptr,
-                          none, 0, 0, 0, nullptr, s) != hipSuccess)
+  for (int k = 0; k < kBatchGroups; ++k)
+    if (plan.first[k + 1] > plan.first[k] &&
+        launch_batch_pass(plan.group_variant(k), BatchPlan::group_prec(k), plan.kind,
+                          BatchPlan::group_r(k), nullptr, nullptr, nullptr, nullptr, none, 0, 0, 0,
+                          nullptr, s) != hipSuccess)
       return SGWLS_E_HIP;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (s == nullptr || hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)

@@ -166,3 +166,21 @@ def test_autotune_batched(ops):
         check_all("autotuned", run_batch(ops, items), oracle_outs(items))
     finally:
         ops.tune_clear()
+
+
+@pytest.mark.parametrize("variant", [0, 2])
+def test_auto_precision_per_image(ops, variant):
+    # lambda from 0.5 to 900 over both radii: under AUTO some images resolve
+    # to float32 and others to FP64 pivots in the same batch.  Every image is
+    # held to the oracle, and runs in the precision it resolves to alone.
+    items = small_batch(seed=4)
+    lams = [0.5, 900.0, 2.0, 300.0, 8.0, 600.0, 1.0, 150.0]
+    items = [(f, g, dict(pd, lam=lam)) for (f, g, pd), lam in zip(items, lams)]
+    precs = {ops.resolve_precision(ops.Params(**pd, prec="auto")) for _, _, pd in items}
+    assert precs == {"fp32", "fp64_pivot"}
+    check_all(f"auto variant {variant}", run_batch(ops, items, prec="auto", variant=variant),
+              oracle_outs(items))
+    # a float32 image of the mixed batch gives exactly its float32-only batch result
+    mixed = run_batch(ops, items, prec="auto", variant=variant)
+    alone = run_batch(ops, [items[0]], prec="fp32", variant=variant)
+    assert np.array_equal(mixed[0], alone[0])
