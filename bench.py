@@ -26,6 +26,8 @@ Prints ONE JSON line:
   fused_passes  the same call with fused passes (one launch per pass, or two)
              against the default three launches per pass
   stride3    the same workload with stride 3 (centres 2r+1 apart, no overlap)
+  stride_sweep  1024x1024 RGB, T = 4: filter time at (r, stride) = (1, 1),
+             (1, 3), (2, 1), (2, 5), (4, 1), (4, 4), (4, 9), each autotuned
   ctx        1024x1024 RGB, r = 1, T = 4 (the paper's timing image size)
   wls2d      the 2D WLS model SG-WLS approximates (Eqs. 1-4) on the same
              input, solved by GPU conjugate gradients: time and the SG-WLS gap
@@ -259,8 +261,7 @@ def time_workload(torch, ops, w, dev, steps, warmup):
     g = torch.from_numpy(w.g).to(dev)
     u = torch.empty_like(f)
     ws = torch.empty(ops.workspace_bytes(C, M, N, p), dtype=torch.uint8, device=dev)
-    if p.stride == 1:
-        ops.autotune(f, g, p, reps=10)
+    ops.autotune(f, g, p, reps=10)
 
     def step():
         ops.sgwls_filter(f, g, p, out=u, workspace=ws)
@@ -295,19 +296,23 @@ def time_interpolation(torch, ops, w, dev, steps, warmup):
             "unit": "MPixel/s"}
 
 
-def stride_sweep(torch, ops, synth, dev, args):
+COMPACT_SWEEP = ((1, 1), (1, 3), (2, 1), (2, 5), (4, 1), (4, 4), (4, 9))
+
+
+def stride_sweep(torch, ops, synth, dev, args, compact=False):
     """Filter time over radius and stride on the paper's timing shape (a 1 MP
-    RGB image, T = 4): the same sweep as the paper's timing figure."""
+    RGB image, T = 4): the same sweep as the paper's timing figure (compact:
+    the (r, stride) pairs of COMPACT_SWEEP only).  Every point autotuned."""
     rows = []
-    for r in (1, 2, 3, 4):
-        for stride in range(1, 2 * r + 2):
-            w = synth.single(f"rgb1024_r{r}_T4_s{stride}", 1024, 1024, 3, 200, 0.03, 1000, 4.0, r,
-                             4, stride, sinus=True)
-            t = time_workload(torch, ops, w, dev, max(5, args.steps // 5), 2)
-            rows.append({"r": r, "stride": stride, "ms_per_step": t["ms_per_step"],
-                         "value": t["value"]})
-            print(f"[sweep] r={r} stride={stride} {t['ms_per_step']:.4f} ms", file=sys.stderr,
-                  flush=True)
+    pairs = COMPACT_SWEEP if compact else [(r, s) for r in (1, 2, 3, 4) for s in range(1, 2 * r + 2)]
+    for r, stride in pairs:
+        w = synth.single(f"rgb1024_r{r}_T4_s{stride}", 1024, 1024, 3, 200, 0.03, 1000, 4.0, r,
+                         4, stride, sinus=True)
+        t = time_workload(torch, ops, w, dev, max(5, args.steps // 5), 2)
+        rows.append({"r": r, "stride": stride, "ms_per_step": t["ms_per_step"],
+                     "value": t["value"]})
+        print(f"[sweep] r={r} stride={stride} {t['ms_per_step']:.4f} ms", file=sys.stderr,
+              flush=True)
     return {"workload": "1024x1024 RGB, T=4, lambda 4, exp weights", "unit": "MPixel/s",
             "rows": rows}
 
@@ -634,6 +639,7 @@ def main():
 
     configs = config_rows(torch, ops, synth, dev, args)
     fused = fused_rows(torch, ops, f, g, p, ws, args.steps)
+    sweep = stride_sweep(torch, ops, synth, dev, args, compact=True)
 
     # Accuracy of this very output against the oracle, and the CPU baseline.
     step()
@@ -732,6 +738,7 @@ def main():
         "cold": {"ms_per_step": round(ms_cold, 5), "value": round(M * N / (ms_cold * 1e-3) / 1e6, 2),
                  "note": "median of single calls, each after a 512 MiB scratch write"},
         "fused_passes": fused,
+        "stride_sweep": sweep,
         "stride3": stride3,
         "ctx": ctx,
         "radius": radius,

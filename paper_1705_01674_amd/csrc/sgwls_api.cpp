@@ -54,6 +54,9 @@ std::mutex& tune_mutex() {
 int size_bucket(int L, int W) {
   return (int)std::lround(2.0 * std::log2((double)L * (double)W));
 }
+// Strided passes are tuned apart from stride-1 ones: their direction field
+// is offset by kStridedDir.
+constexpr int kStridedDir = 4;
 TuneKey tune_key(int r, int cb, int fp64, int kind, int dir, int L, int W) {
   return TuneKey(r, cb, fp64, kind, dir, size_bucket(L, W));
 }
@@ -176,8 +179,10 @@ sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* 
   for (int c0 = 0; c0 < C;) {
     const int cb = channel_block(C - c0);
     int v = variant >= 0 ? variant
-                         : tuned_variant(p.r, cb, p.prec, (int)p.kind, direction, L, W);
-    if (out_t && !variants_of(p.r, cb, p.prec).v[v].D) v = 0;   // variant 0 reads directly
+                         : tuned_variant(p.r, cb, p.prec, (int)p.kind,
+                                         direction + (p.stride != 1 ? kStridedDir : 0), L, W);
+    if (out_t && p.stride == 1 && !variants_of(p.r, cb, p.prec).v[v].D)
+      v = 0;   // variant 0 reads directly
     PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, v);
     pl.one = one;
     PassGeom geo = pass_geom(direction, M, N, pl, p.stride);
@@ -896,10 +901,13 @@ sgwls_status sgwls_tune_pin(int direction, int channel_block, int M, int N,
   p = &pr;
   if (direction != 0 && direction != 1) return SGWLS_E_ARG;
   if (channel_block != 1 && channel_block != 3) return SGWLS_E_ARG;
-  if (variant < 0 || variant >= variants_of(p->r, channel_block, p->prec).n) return SGWLS_E_ARG;
+  const int nv = p->stride == 1 ? variants_of(p->r, channel_block, p->prec).n
+                                 : strided_variant_count(p->r, channel_block, p->prec);
+  if (variant < 0 || variant >= nv) return SGWLS_E_ARG;
   const int L = direction == 0 ? M : N, W = direction == 0 ? N : M;
+  const int kd = direction + (p->stride != 1 ? kStridedDir : 0);
   std::lock_guard<std::mutex> lk(tune_mutex());
-  tune_table()[tune_key(p->r, channel_block, p->prec, (int)p->kind, direction, L, W)] = variant;
+  tune_table()[tune_key(p->r, channel_block, p->prec, (int)p->kind, kd, L, W)] = variant;
   return SGWLS_OK;
 }
 
@@ -908,7 +916,8 @@ int sgwls_tune_query(int direction, int channel_block, int M, int N, const sgwls
   const sgwls_params pr = resolved(*p, 0);
   p = &pr;
   const int L = direction == 0 ? M : N, W = direction == 0 ? N : M;
-  return tuned_variant(p->r, channel_block, p->prec, (int)p->kind, direction, L, W);
+  return tuned_variant(p->r, channel_block, p->prec, (int)p->kind,
+                       direction + (p->stride != 1 ? kStridedDir : 0), L, W);
 }
 
 void sgwls_tune_clear(void) {
@@ -935,7 +944,6 @@ sgwls_status sgwls_autotune(const float* x, const float* g, float* y, int C, int
   void* iface = ws;
   if (chosen)
     for (int i = 0; i < 4; ++i) chosen[i] = -1;
-  if (p->stride != 1) return SGWLS_OK;   // strided passes have a single kernel
   tune_cache_load_once();
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -957,14 +965,21 @@ sgwls_status sgwls_autotune(const float* x, const float* g, float* y, int C, int
       }
       if (c0 < 0) continue;
       const VariantSet vs = variants_of(p->r, cb, p->prec);
+      const bool strided = p->stride != 1;
+      const int nv = strided ? strided_variant_count(p->r, cb, p->prec) : vs.n;
       // With transposed frames the filter runs every pass as a direct column
       // pass storing transposed, over the M x N and the N x M frame, both
-      // under the column-direction key: time exactly that.
-      const bool frames = dir == 0 && frames_supported(C, p->r, p->stride, p->prec);
+      // under the column-direction key: time exactly that.  Strided calls
+      // without saved inputs run as frames too.
+      const bool frames = dir == 0 && (strided || frames_supported(C, p->r, p->stride, p->prec));
+      if (strided && (dir != 0 || nv < 2)) {
+        if (chosen) chosen[dir * 2 + cbi] = 0;
+        continue;
+      }
       int best = 0;
       float best_ms = 0.0f;
-      for (int v = 0; v < vs.n && result == SGWLS_OK; ++v) {
-        if (frames && !vs.v[v].D) continue;
+      for (int v = 0; v < nv && result == SGWLS_OK; ++v) {
+        if (!strided && frames && !vs.v[v].D) continue;
         auto run = [&]() {
           for (int f = 0; f < (frames ? 2 : 1); ++f) {
             const int Mf = f == 0 ? M : N, Nf = f == 0 ? N : M;
@@ -992,7 +1007,8 @@ sgwls_status sgwls_autotune(const float* x, const float* g, float* y, int C, int
       if (result != SGWLS_OK) break;
       {
         std::lock_guard<std::mutex> lk(tune_mutex());
-        tune_table()[tune_key(p->r, cb, p->prec, (int)p->kind, dir, L, W)] = best;
+        tune_table()[tune_key(p->r, cb, p->prec, (int)p->kind, dir + (strided ? kStridedDir : 0),
+                              L, W)] = best;
       }
       if (chosen) chosen[dir * 2 + cbi] = best;
     }

@@ -2188,10 +2188,24 @@ hipError_t launch_kind(const float* x, const float* g, float* y, int c0, const P
                        float lam_host, void* iface, hipStream_t s, int st, const BwdArgs& bw) {
   constexpr VariantSet VS = variants_for(MODE, r, CB, fp64);
   // Strided forward column passes read their chunks directly (no input tile).
-  if (geo.stride != 1)
+  if (geo.stride != 1) {
+    if constexpr (MODE == kModeForward) {
+      constexpr StridedVariant S1v = strided_variant(r, CB, fp64, 1);
+      if (pl.variant == 1)
+        return launch_impl<r, CB, fp64, false, KIND, S1v.R, S1v.Q, MODE, 1>(
+            x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st, bw);
+      constexpr int RH = strided_half_R(r, CB, fp64);
+      if constexpr (RH > 0) {
+        constexpr StridedVariant S2v = strided_variant(r, CB, fp64, 2);
+        if (pl.variant == 2)
+          return launch_impl<r, CB, fp64, false, KIND, S2v.R, S2v.Q, MODE, 1>(
+              x, g, y, c0, geo, pl, wp, lam_dev, lam_host, iface, s, st, bw);
+      }
+    }
     return launch_impl<r, CB, fp64, false, KIND, VS.v[0].R, 1, MODE,
                        MODE == kModeForward ? 1 : 0>(x, g, y, c0, geo, pl, wp, lam_dev, lam_host,
                                                      iface, s, st, bw);
+  }
   return launch_variant<r, CB, fp64, KIND, MODE, 0>(pl.variant, x, g, y, c0, geo, pl, wp,
                                                     lam_dev, lam_host, iface, s, st, bw);
 }

@@ -141,6 +141,29 @@ constexpr VariantSet variants_for(int mode, int r, int cb, int fp64) {
   return mode == kModeBackward ? bwd_variants_of(r, cb, fp64) : variants_of(r, cb, fp64);
 }
 
+// Strided forward passes: variant 0 uses variant 0's R with one chunk (one
+// wave) per block; variant 1 two chunks per block, so the transposed output
+// of a block is 2R rows long instead of R; variant 2 (where R/2 is even)
+// half-height chunks four to a block (more blocks, and 2R rows per block).
+// A variant whose LDS accumulators exceed 64 KiB at the call's stride runs
+// as variant 0.  Strided backward passes have variant 0 only.
+struct StridedVariant {
+  int R, Q;
+};
+constexpr int strided_half_R(int r, int cb, int fp64) {
+  const int R0 = variants_of(r, cb, fp64).v[0].R;
+  return (R0 >= 4 && (R0 / 2) % 2 == 0) ? R0 / 2 : 0;
+}
+constexpr int strided_variant_count(int r, int cb, int fp64, int mode = kModeForward) {
+  return mode != kModeForward ? 1 : strided_half_R(r, cb, fp64) > 0 ? 3 : 2;
+}
+constexpr StridedVariant strided_variant(int r, int cb, int fp64, int v) {
+  const int R0 = variants_of(r, cb, fp64).v[0].R;
+  return v == 1 ? StridedVariant{R0, 2} : v == 2 ? StridedVariant{strided_half_R(r, cb, fp64), 4}
+                                                 : StridedVariant{R0, 1};
+}
+constexpr size_t kStridedLdsMax = 65536;
+
 // Synchronisation area at the start of the workspaces of sgwls_filter and
 // sgwls_filter_nchw: the error word of the fused passes (kSyncErrMagic after
 // a wait gave up; any other value means no error), then two banks of

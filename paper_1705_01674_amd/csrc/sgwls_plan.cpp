@@ -16,12 +16,25 @@ int strip_count(int W, int r, int stride) {
 PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64, int variant, int mode) {
   PassPlan pl{};
   const VariantSet vs = variants_for(mode, r, cb, fp64);
-  if (stride != 1 || variant < 0 || variant >= vs.n) variant = 0;
+  if (variant < 0 || variant >= (stride == 1 ? vs.n : strided_variant_count(r, cb, fp64, mode)))
+    variant = 0;
+  if (stride != 1 && variant > 0) {
+    // LDS accumulators of the strided expand: cb planes of Q R + 2 rows
+    const StridedVariant sv = strided_variant(r, cb, fp64, variant);
+    const int pitch = ((kWave - 1) * stride + 2 * r + 1) | 1;
+    if (sizeof(float) * (size_t)cb * (sv.Q * sv.R + 2) * pitch > kStridedLdsMax) variant = 0;
+  }
   pl.mode = mode;
   pl.nr = mode == kModeBackward ? 2 * cb : cb;
   pl.variant = variant;
-  pl.R = vs.v[variant].R;
-  pl.Q = stride == 1 ? vs.v[variant].Q : 1;
+  if (stride == 1) {
+    pl.R = vs.v[variant].R;
+    pl.Q = vs.v[variant].Q;
+  } else {
+    const StridedVariant sv = strided_variant(r, cb, fp64, variant);
+    pl.R = sv.R;
+    pl.Q = sv.Q;
+  }
   pl.P = (L + pl.R - 1) / pl.R;
   pl.nK = strip_count(W, r, stride);
   pl.OW = stride == 1 ? kWave - 2 * r : (kWave - 2) * stride - 2 * r;
@@ -53,7 +66,8 @@ size_t interface_bytes(const PassPlan& pl) {
 size_t interface_bytes_max(int L, int W, int r, int cb, int stride, int fp64, int mode) {
   const VariantSet vs = variants_for(mode, r, cb, fp64);
   size_t need = 0;
-  for (int v = 0; v < (stride == 1 ? vs.n : 1); ++v)
+  const int nv = stride == 1 ? vs.n : strided_variant_count(r, cb, fp64, mode);
+  for (int v = 0; v < nv; ++v)
     need = std::max(need, interface_bytes(make_plan(L, W, r, cb, stride, fp64, v, mode)));
   return need;
 }

@@ -98,6 +98,32 @@ def test_strided_filter(ops, r, stride, C):
     check(f"filter r{r} s{stride} C{C} fp64", run_filter(ops, f, g, pd, "fp64_pivot"), ref)
 
 
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("r,stride,C", [(1, 2, 3), (1, 3, 3), (1, 3, 1), (2, 3, 3), (2, 5, 1),
+                                        (3, 4, 3), (4, 9, 3)])
+def test_strided_variants_match_oracle(ops, r, stride, C, variant):
+    # the strided forward variants (two chunks per block; half-height chunks
+    # four to a block), pinned on both frames of the filter
+    rng = np.random.default_rng(7500 + 100 * r + 10 * stride + C + variant)
+    ow = 62 * stride - 2 * r
+    M, N = ow + 37 + 5 * r, 2 * ow + 19
+    f = rng.uniform(0, 1, (C, M, N)).astype(np.float32)
+    g = rng.uniform(0, 1, (M, N)).astype(np.float32)
+    pd = pdict(lam=4.0, r=r, iters=2, stride=stride, sigma_r=0.2)
+    p = ops.Params(**pd)
+    try:
+        try:
+            ops.tune_pin(0, C, M, N, p, variant)
+            ops.tune_pin(0, C, N, M, p, variant)
+        except ops.nat.SgwlsError:
+            pytest.skip(f"no strided variant {variant} at r={r}")
+        print(f"[parity] strided variant {variant} r{r} s{stride} C{C} {M}x{N}", flush=True)
+        check(f"strided variant {variant} r{r} s{stride} C{C}", run_filter(ops, f, g, pd),
+              oracle_filter(f, g, pd))
+    finally:
+        ops.tune_clear()
+
+
 @pytest.mark.parametrize("r", [1, 2])
 @pytest.mark.parametrize("C", [1, 3])
 def test_long_lines_use_the_long_run_solver(ops, r, C):
