@@ -1798,6 +1798,13 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
         const int ta = r0 + idx / TB, tb = idx - (ta - r0) * TB;
         smem[acc0 + p * TA * pch + ta * pch + tb] = 0.0f;
       }
+    // Forward: row 0 of accumulator plane 0 (never accumulated) holds the
+    // reciprocal cover count of each owned column, computed once per column.
+    const int ncols = b_hi - b_lo;
+    float* invc = smem + acc0;
+    if constexpr (!BWD)
+      for (int bc = threadIdx.x; bc < ncols; bc += kWave * Q)
+        invc[bc] = 1.0f / float(cover_count(b_lo + bc, geo, r));
     __syncthreads();
     // Sum over the strips covering each pixel, in a fixed order (q = 0..2r).
 #pragma unroll
@@ -1824,20 +1831,23 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
         __syncthreads();
       }
     }
-    const int ncols = b_hi - b_lo;
-    for (int idx = threadIdx.x; idx < arows * ncols; idx += kWave * Q) {
-      // Row-major output walks rows; column-major output (row pass, or a
-      // transposed store, pixel (a, b) at b * L + a) walks columns.
-      int tr, bc;
-      if (geo.sb == 1 && !geo.out_t) {
-        tr = idx / ncols;
-        bc = idx - tr * ncols;
-      } else {
-        bc = idx / arows;
-        tr = idx - bc * arows;
+    // Row-major output walks rows; column-major output (row pass, or a
+    // transposed store, pixel (a, b) at b * L + a) walks columns.  Element
+    // idx = outer * n_in + inner of the walk, for idx = thread, thread + step,
+    // ...: the indices advance by a fixed quotient and remainder.
+    const bool colmajor = !(geo.sb == 1 && !geo.out_t);
+    const int n_in = colmajor ? arows : ncols, n_out = colmajor ? ncols : arows;
+    const int step = kWave * Q, dq = step / n_in, dr = step - dq * n_in;
+    int outer = threadIdx.x / n_in, inner = threadIdx.x - outer * n_in;
+    for (; outer < n_out; outer += dq) {
+      const int tr = colmajor ? inner : outer, bc = colmajor ? outer : inner;
+      inner += dr;
+      if (inner >= n_in) {
+        inner -= n_in;
+        ++outer;
       }
       const int bb = b_lo + bc, a = a_lo + tr;
-      const float inv = BWD ? 1.0f : 1.0f / float(cover_count(bb, geo, r));
+      const float inv = BWD ? 1.0f : invc[bc];
       const float* cell = smem + acc0 + (tr + 1) * pch + (bb - colbase);
       const int o = geo.out_t     ? a + bb * geo.L
                     : geo.sb == 1 ? a * (int)geo.sa + bb

@@ -30,6 +30,9 @@ PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64, int varian
   if (stride == 1) {
     pl.R = vs.v[variant].R;
     pl.Q = vs.v[variant].Q;
+  } else if (variant == 0) {   // the mode's own variant 0 (backward chunks differ)
+    pl.R = vs.v[0].R;
+    pl.Q = 1;
   } else {
     const StridedVariant sv = strided_variant(r, cb, fp64, variant);
     pl.R = sv.R;
