@@ -1141,6 +1141,125 @@ __global__ __launch_bounds__(kWave) void k_interface_pcr(const Acc* __restrict__
   iface_pcr_strip<r, CB, MM, Acc>(zmove_bytes(sum, zi, z), zmove_bytes(U, zi, z), P, m, blockIdx.x);
 }
 
+// Block exchanges between the NL lanes of a workgroup (NL = 64 x waves)
+// through LDS: value f of lane L at xs[f * NL + L].
+template <int n, int m, int NL, typename Acc>
+DEV void lds_put(Acc* xs, int f0, const Acc (&b)[n][m], int L) {
+#pragma unroll
+  for (int i = 0; i < n; ++i)
+#pragma unroll
+    for (int j = 0; j < m; ++j) xs[(f0 + i * m + j) * NL + L] = b[i][j];
+}
+// b = the block of lane src, or 0 where !ok.
+template <int n, int m, int NL, typename Acc>
+DEV void lds_get(const Acc* xs, int f0, Acc (&b)[n][m], int src, bool ok) {
+  const int s = ok ? src : 0;
+#pragma unroll
+  for (int i = 0; i < n; ++i)
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
+      const Acc v = xs[(f0 + i * m + j) * NL + s];
+      b[i][j] = ok ? v : Acc(0);
+    }
+}
+
+// iface_pcr_levels over the NL lanes of a workgroup: the same reduced system
+// and block cyclic reduction (log2 NL levels), with every neighbour exchange
+// through LDS (xs: NL x (3 r^2 + r CB) values).  Called by all NL threads.
+template <int r, int CB, typename Acc, int NL>
+DEV void iface_pcr_levels_mw(const Acc (&S)[r][r], const Acc (&Bt)[r][r], const Acc (&Rr)[r][CB],
+                             const Acc (&TT)[r][r], const Acc (&RT)[r][CB], bool active, int m,
+                             int n, int L, Acc* xs, Acc (&X)[r][CB], Acc (&XT)[r][CB]) {
+  constexpr int RR = r * r, RC = r * CB;
+  Acc A[r][r], B[r][r], Cc[r][r], d[r][CB];
+  {
+    Acc TTn[r][r], RTn[r][CB], Btn[r][r];
+    lds_put<r, r, NL>(xs, 0, TT, L);
+    lds_put<r, CB, NL>(xs, RR, RT, L);
+    lds_put<r, r, NL>(xs, RR + RC, Bt, L);
+    __syncthreads();
+    const bool has = L + 1 < NL;
+    lds_get<r, r, NL>(xs, 0, TTn, L + 1, has);
+    lds_get<r, CB, NL>(xs, RR, RTn, L + 1, has);
+    lds_get<r, r, NL>(xs, RR + RC, Btn, L + 1, has);
+    __syncthreads();
+    const bool nextActive = (L + 1) * m < n;
+#pragma unroll
+    for (int a = 0; a < r; ++a) {
+#pragma unroll
+      for (int c = 0; c < r; ++c) {
+        A[a][c] = active ? Bt[a][c] : Acc(0);
+        B[a][c] = active ? S[a][c] - (nextActive ? TTn[a][c] : Acc(0)) : (a == c ? Acc(1) : Acc(0));
+        Cc[a][c] = (active && nextActive) ? Btn[c][a] : Acc(0);
+      }
+#pragma unroll
+      for (int h = 0; h < CB; ++h) d[a][h] = active ? Rr[a][h] - (nextActive ? RTn[a][h] : Acc(0)) : Acc(0);
+    }
+  }
+  for (int delta = 1; delta < NL; delta *= 2) {
+    Acc Bi[r][r];
+    spd_inverse<r, Acc>(B, Bi);
+    lds_put<r, r, NL>(xs, 0, Bi, L);
+    lds_put<r, r, NL>(xs, RR, A, L);
+    lds_put<r, r, NL>(xs, 2 * RR, Cc, L);
+    lds_put<r, CB, NL>(xs, 3 * RR, d, L);
+    __syncthreads();
+    Acc Bim[r][r], Am[r][r], Cm[r][r], dm[r][CB];
+    Acc Bip[r][r], Ap[r][r], Cp[r][r], dp[r][CB];
+    const bool up = L >= delta, dn = L + delta < NL;
+    lds_get<r, r, NL>(xs, 0, Bim, L - delta, up);
+    lds_get<r, r, NL>(xs, RR, Am, L - delta, up);
+    lds_get<r, r, NL>(xs, 2 * RR, Cm, L - delta, up);
+    lds_get<r, CB, NL>(xs, 3 * RR, dm, L - delta, up);
+    lds_get<r, r, NL>(xs, 0, Bip, L + delta, dn);
+    lds_get<r, r, NL>(xs, RR, Ap, L + delta, dn);
+    lds_get<r, r, NL>(xs, 2 * RR, Cp, L + delta, dn);
+    lds_get<r, CB, NL>(xs, 3 * RR, dp, L + delta, dn);
+    __syncthreads();
+    Acc al[r][r], ga[r][r];
+    mm<r, r, r, Acc>(A, Bim, al);
+    mm<r, r, r, Acc>(Cc, Bip, ga);
+    Acc An[r][r], Cn[r][r], t1[r][r], t2[r][r], e1[r][CB], e2[r][CB];
+    mm<r, r, r, Acc>(al, Am, An);
+    mm<r, r, r, Acc>(ga, Cp, Cn);
+    mm<r, r, r, Acc>(al, Cm, t1);
+    mm<r, r, r, Acc>(ga, Ap, t2);
+    mm<r, r, CB, Acc>(al, dm, e1);
+    mm<r, r, CB, Acc>(ga, dp, e2);
+#pragma unroll
+    for (int a = 0; a < r; ++a) {
+#pragma unroll
+      for (int c = 0; c < r; ++c) {
+        A[a][c] = -An[a][c];
+        Cc[a][c] = -Cn[a][c];
+        B[a][c] = B[a][c] - t1[a][c] - t2[a][c];
+      }
+#pragma unroll
+      for (int h = 0; h < CB; ++h) d[a][h] = d[a][h] - e1[a][h] - e2[a][h];
+    }
+  }
+  {
+    Acc Bc[r][r];
+#pragma unroll
+    for (int a = 0; a < r; ++a)
+#pragma unroll
+      for (int c = 0; c < r; ++c) Bc[a][c] = B[a][c];
+    chol<r, Acc>(Bc);
+#pragma unroll
+    for (int a = 0; a < r; ++a)
+#pragma unroll
+      for (int h = 0; h < CB; ++h) X[a][h] = d[a][h];
+    chol_solve<r, CB, Acc>(Bc, X);
+  }
+  lds_put<r, CB, NL>(xs, 0, X, L);
+  __syncthreads();
+  lds_get<r, CB, NL>(xs, 0, XT, L - 1, L >= 1);
+}
+
+// LDS values per lane of iface_pcr_levels_mw.
+template <int r, int CB>
+constexpr int kMwSlot = 3 * r * r + r * CB;
+
 // Scratch values per separator block kept by iface_pcr_strip_long: the
 // Cholesky factor of the pivot block, the coupling to the next block, the
 // coupling to the previous lane's block and the right-hand side.
@@ -1150,21 +1269,24 @@ constexpr int kLongSlot = 3 * r * r + r * CB;
 // iface_pcr_strip for runs of any length: the same elimination, cyclic
 // reduction and back substitution, with the per-block values of each lane's
 // run kept in global scratch instead of registers (layout: strip ki, block i
-// of the run, value f, lane -> scr[((ki * m + i) * kLongSlot + f) * 64 + lane],
+// of the run, value f, lane -> scr[((ki * m + i) * kLongSlot + f) * NL + lane],
 // so that a wave's accesses are contiguous).  Used when the runs are longer
-// than the register version holds (long lines at r >= 3).
-template <int r, int CB, typename Acc>
+// than the register version holds (long lines at r >= 3).  NL lanes solve one
+// strip: one wave (NL = 64, cyclic reduction by lane shuffles) or a workgroup
+// of NL / 64 waves (cyclic reduction through LDS at xs), which shortens every
+// lane's run where the strips alone leave the GPU underfilled.
+template <int r, int CB, typename Acc, int NL = kWave>
 DEV void iface_pcr_strip_long(const Acc* __restrict__ sum, Acc* __restrict__ U, int P, int m,
-                              int ki, Acc* __restrict__ scr) {
+                              int ki, Acc* __restrict__ scr, Acc* xs = nullptr) {
   using LY = IfaceLayout<r, CB>;
   constexpr int FS = kLongSlot<r, CB>;
-  const int lane = threadIdx.x % kWave;
+  const int lane = NL == kWave ? (int)(threadIdx.x % kWave) : (int)threadIdx.x;
   const int n = P - 1;
   const int s = lane * m, e = min(s + m, n);
   const bool active = s < n;
   SepReader<r, CB, Acc> rd{sum + (size_t)ki * P * LY::F, P};
-  Acc* slots = scr + (size_t)ki * m * FS * kWave + lane;
-  auto at = [&](int i, int f) -> Acc& { return slots[((size_t)i * FS + f) * kWave]; };
+  Acc* slots = scr + (size_t)ki * m * FS * NL + lane;
+  auto at = [&](int i, int f) -> Acc& { return slots[((size_t)i * FS + f) * NL]; };
 
   Acc S[r][r], Bt[r][r], Rr[r][CB], TT[r][r], RT[r][CB];
 #pragma unroll
@@ -1274,7 +1396,10 @@ DEV void iface_pcr_strip_long(const Acc* __restrict__ sum, Acc* __restrict__ U, 
   }
 
   Acc X[r][CB], XT[r][CB];
-  iface_pcr_levels<r, CB, Acc>(S, Bt, Rr, TT, RT, active, m, n, lane, X, XT);
+  if constexpr (NL == kWave)
+    iface_pcr_levels<r, CB, Acc>(S, Bt, Rr, TT, RT, active, m, n, lane, X, XT);
+  else
+    iface_pcr_levels_mw<r, CB, Acc, NL>(S, Bt, Rr, TT, RT, active, m, n, lane, xs, X, XT);
   if (!active) return;
   Acc* out = U + (size_t)ki * n * r * CB;
 #pragma unroll
@@ -1327,14 +1452,16 @@ DEV void iface_pcr_strip_long(const Acc* __restrict__ sum, Acc* __restrict__ U, 
   }
 }
 
-template <int r, int CB, typename Acc>
-__global__ __launch_bounds__(kWave) void k_interface_pcr_long(const Acc* __restrict__ sum,
-                                                              Acc* __restrict__ U,
-                                                              Acc* __restrict__ scr, int P,
-                                                              int m, long long zi) {
+template <int r, int CB, typename Acc, int NL>
+__global__ __launch_bounds__(NL) void k_interface_pcr_long(const Acc* __restrict__ sum,
+                                                           Acc* __restrict__ U,
+                                                           Acc* __restrict__ scr, int P, int m,
+                                                           long long zi) {
+  extern __shared__ float smem[];
   const int z = blockIdx.z;
-  iface_pcr_strip_long<r, CB, Acc>(zmove_bytes(sum, zi, z), zmove_bytes(U, zi, z), P, m,
-                                   blockIdx.x, zmove_bytes(scr, zi, z));
+  iface_pcr_strip_long<r, CB, Acc, NL>(zmove_bytes(sum, zi, z), zmove_bytes(U, zi, z), P, m,
+                                       blockIdx.x, zmove_bytes(scr, zi, z),
+                                       reinterpret_cast<Acc*>(smem));
 }
 
 // ---------------------------------------------------------------------------
@@ -2142,9 +2269,18 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
     } else {
       // Runs longer than the register solver holds: the same wave solver with
       // its per-block values in the scratch part of the interface buffer.
-      const int m = (geo.P - 1 + kWave - 1) / kWave;
-      hipLaunchKernelGGL((k_interface_pcr_long<r, NR, Acc>), dim3(geo.nK, 1, nz), dim3(kWave), 0,
-                         stream, (const Acc*)sum, us, gb, geo.P, m, geo.zi);
+      const int nl = pl.long_nl;
+      const int m = (geo.P - 1 + nl - 1) / nl;
+      const size_t xs = nl > kWave ? sizeof(Acc) * (size_t)nl * kMwSlot<r, NR> : 0;
+      if (nl == 4 * kWave)
+        hipLaunchKernelGGL((k_interface_pcr_long<r, NR, Acc, 4 * kWave>), dim3(geo.nK, 1, nz),
+                           dim3(nl), xs, stream, (const Acc*)sum, us, gb, geo.P, m, geo.zi);
+      else if (nl == 2 * kWave)
+        hipLaunchKernelGGL((k_interface_pcr_long<r, NR, Acc, 2 * kWave>), dim3(geo.nK, 1, nz),
+                           dim3(nl), xs, stream, (const Acc*)sum, us, gb, geo.P, m, geo.zi);
+      else
+        hipLaunchKernelGGL((k_interface_pcr_long<r, NR, Acc, kWave>), dim3(geo.nK, 1, nz),
+                           dim3(kWave), 0, stream, (const Acc*)sum, us, gb, geo.P, m, geo.zi);
     }
   }
   if (stages & kStageExpand) {

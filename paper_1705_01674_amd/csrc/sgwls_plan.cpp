@@ -53,10 +53,26 @@ PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64, int varian
   pl.sum_elems = (size_t)pl.P * F * pl.nK;
   pl.u_elems = (size_t)std::max(n, 1) * r * pl.nr * pl.nK;
   // Runs longer than the register solver holds go to the long-run solver,
-  // whose per-block values (3r^2 + r*nr each, m blocks per lane, 64 lanes
-  // per strip) live in scratch after the separator solutions.
+  // whose per-block values (3r^2 + r*nr each, m blocks per lane, NL lanes
+  // per strip) live in scratch after the separator solutions.  NL: one wave
+  // per strip, or four or two where that still gives at most 2048 waves (the
+  // strips alone leave the GPU underfilled; their runs shorten by as much)
+  // and the exchange fits 64 KiB of LDS.  Measured at 1024x1024 RGB, r = 4:
+  // stride 4 0.97 -> 0.80 ms, stride 9 0.85 -> 0.66 ms; at stride 1 with more
+  // strips than that a single wave per strip is as fast or faster.
+  pl.long_nl = kWave;
+  if (n > 0 && pl.iface_m == 0) {
+    const size_t slot = (size_t)(3 * r * r + r * pl.nr) * pl.acc_bytes;
+    for (int nw : {4, 2}) {
+      if ((long long)pl.nK * nw <= 2048 && (size_t)nw * kWave * slot <= 65536 && n > nw * kWave) {
+        pl.long_nl = nw * kWave;
+        break;
+      }
+    }
+  }
+  const int ml = (n + pl.long_nl - 1) / pl.long_nl;
   pl.g_elems = (n > 0 && pl.iface_m == 0)
-                   ? (size_t)std::max(m, 1) * kWave * (3 * r * r + r * pl.nr) * pl.nK
+                   ? (size_t)std::max(ml, 1) * pl.long_nl * (3 * r * r + r * pl.nr) * pl.nK
                    : 0;
   return pl;
 }

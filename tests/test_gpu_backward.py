@@ -132,6 +132,20 @@ def test_filter_backward_matches_oracle(ops, r, C, iters):
     check(f"grad_lambda {tag}", gl, rl, TOL_G)
 
 
+def test_filter_backward_multiwave_long_run_solver(ops):
+    """700 x 300 at r = 3: the backward's long-run interface solves (six
+    right-hand sides) run with four waves per strip on the column frame and
+    two on the row frame."""
+    M, N = 700, 300
+    f, g, ub = inputs(3, M, N, 4242)
+    pd = pdict(lam=8.0, r=3, iters=1)
+    gf, gg, gl = filter_grads(ops, f, g, pd, ub)
+    rf, rg, rl = oracle_grads(f, g, pd, ub)
+    check("grad_f multi-wave long", gf, rf, TOL_X)
+    check("grad_g multi-wave long", gg, rg, TOL_G)
+    check("grad_lambda multi-wave long", gl, rl, TOL_G)
+
+
 @pytest.mark.parametrize("r,C", [(1, 3), (3, 1)])
 def test_filter_backward_long_lines(ops, r, C):
     """Tall images (4,000 rows): more separator blocks per lane than the

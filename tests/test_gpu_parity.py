@@ -124,6 +124,22 @@ def test_strided_variants_match_oracle(ops, r, stride, C, variant):
         ops.tune_clear()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64_pivot"])
+@pytest.mark.parametrize("r", [3, 4])
+def test_multiwave_long_run_solver(ops, r, prec):
+    # 700 x 300 at r >= 3 (chunks of two rows): the column frame's 294-ish
+    # strips with 349 separators each run the long-run solver with four waves
+    # per strip in float32 (two with FP64 pivots, whose exchange is twice as
+    # large), the row frame's ~694 strips with two waves per strip
+    rng = np.random.default_rng(8100 + r)
+    M, N = 700, 300
+    f = rng.uniform(0, 1, (3, M, N)).astype(np.float32)
+    g = rng.uniform(0, 1, (M, N)).astype(np.float32)
+    pd = pdict(lam=6.0, r=r, iters=1, sigma_r=0.2)
+    print(f"[parity] multi-wave long-run solver r{r} {prec}", flush=True)
+    check(f"multi-wave long r{r} {prec}", run_filter(ops, f, g, pd, prec), oracle_filter(f, g, pd))
+
+
 @pytest.mark.parametrize("r", [1, 2])
 @pytest.mark.parametrize("C", [1, 3])
 def test_long_lines_use_the_long_run_solver(ops, r, C):
