@@ -95,8 +95,10 @@ DEV constexpr int col_of(int m) {  // offset from the centre column k
 }
 
 // Small dense helpers on r x r blocks.  chol leaves a factor that chol_solve
-// applies: the Cholesky factor for n > 1; for n = 1 the reciprocal of the
-// scalar itself (one rcp instead of a square root and two divisions).
+// applies: the Cholesky factor for n > 1 with the reciprocals of its
+// diagonal entries on the diagonal (one division per entry; the solves then
+// multiply); for n = 1 the reciprocal of the scalar itself (one rcp instead
+// of a square root and two divisions).
 template <int n, typename Acc>
 DEV void chol(Acc (&A)[n][n]) {
   if constexpr (n == 1) {
@@ -108,9 +110,8 @@ DEV void chol(Acc (&A)[n][n]) {
     Acc d = A[j][j];
 #pragma unroll
     for (int t = 0; t < j; ++t) d -= A[j][t] * A[j][t];
-    d = sqrt(d);
-    A[j][j] = d;
-    const Acc inv = Acc(1) / d;
+    const Acc inv = Acc(1) / sqrt(d);
+    A[j][j] = inv;
 #pragma unroll
     for (int i = j + 1; i < n; ++i) {
       Acc v = A[i][j];
@@ -135,14 +136,14 @@ DEV void chol_solve(const Acc (&Lc)[n][n], Acc (&B)[n][m]) {
       Acc v = B[i][c];
 #pragma unroll
       for (int t = 0; t < i; ++t) v -= Lc[i][t] * B[t][c];
-      B[i][c] = v / Lc[i][i];
+      B[i][c] = v * Lc[i][i];
     }
 #pragma unroll
     for (int i = n - 1; i >= 0; --i) {
       Acc v = B[i][c];
 #pragma unroll
       for (int t = i + 1; t < n; ++t) v -= Lc[t][i] * B[t][c];
-      B[i][c] = v / Lc[i][i];
+      B[i][c] = v * Lc[i][i];
     }
   }
 }
