@@ -976,172 +976,6 @@ DEV void iface_pcr_levels(const Acc (&S)[r][r], const Acc (&Bt)[r][r], const Acc
   shfl_up_blk<r, CB, Acc>(X, XT, 1, lane);
 }
 
-// k_interface_pcr: one wave per strip, lane l owns separator blocks
-// [l*m, min(l*m + m, P-1)); MM is the compiled maximum of m.
-// U receives the separator solutions strip-major: U[(ki*(P-1) + j)*r*CB + a*CB + h].
-template <int r, int CB, int MM, typename Acc, class Reader, bool COH = false>
-DEV void iface_pcr_run(const Reader& rd, Acc* __restrict__ U, int P, int m, int ki) {
-  const int lane = threadIdx.x % kWave;
-  const int n = P - 1;
-  const int s = lane * m, e = min(s + m, n);
-  const bool active = s < n;
-
-  // Local bordered elimination of blocks s .. e-2 (T = block s-1 of the
-  // previous lane, B = block e-1 is this lane's unknown at the PCR level).
-  Acc Ls[MM][r][r], Ub[MM][r][r], Btb[MM][r][r], Rb[MM][r][CB];
-  Acc S[r][r], Bt[r][r], Rr[r][CB], TT[r][r], RT[r][CB];
-#pragma unroll
-  for (int a = 0; a < r; ++a) {
-#pragma unroll
-    for (int c = 0; c < r; ++c) { TT[a][c] = Acc(0); S[a][c] = Acc(0); Bt[a][c] = Acc(0); }
-#pragma unroll
-    for (int h = 0; h < CB; ++h) { RT[a][h] = Acc(0); Rr[a][h] = Acc(0); }
-  }
-  if (active) {
-    rd.diag(s, S);
-    rd.rhs(s, Rr);
-    if (s > 0) {
-      Acc U0[r][r];
-      rd.off(s - 1, U0);
-#pragma unroll
-      for (int a = 0; a < r; ++a)
-#pragma unroll
-        for (int c = 0; c < r; ++c) Bt[a][c] = U0[c][a];
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < MM - 1; ++i) {
-    const int b = s + i;
-    if (active && b < e - 1) {
-      Acc Lc[r][r];
-#pragma unroll
-      for (int a = 0; a < r; ++a)
-#pragma unroll
-        for (int c = 0; c < r; ++c) Lc[a][c] = S[a][c];
-      chol<r, Acc>(Lc);
-      Acc Uc[r][r];
-      rd.off(b, Uc);
-      Acc V[r][r], Y[r][r], wv[r][CB];
-#pragma unroll
-      for (int a = 0; a < r; ++a) {
-#pragma unroll
-        for (int c = 0; c < r; ++c) { V[a][c] = Uc[a][c]; Y[a][c] = Bt[a][c]; }
-#pragma unroll
-        for (int h = 0; h < CB; ++h) wv[a][h] = Rr[a][h];
-      }
-      chol_solve<r, r, Acc>(Lc, V);    // S^-1 U
-      chol_solve<r, r, Acc>(Lc, Y);    // S^-1 Bt
-      chol_solve<r, CB, Acc>(Lc, wv);  // S^-1 R
-      // TT += Bt^T S^-1 Bt, RT += Bt^T S^-1 R
-#pragma unroll
-      for (int a = 0; a < r; ++a) {
-#pragma unroll
-        for (int c = 0; c < r; ++c) {
-          Acc v = Acc(0);
-#pragma unroll
-          for (int t = 0; t < r; ++t) v += Bt[t][a] * Y[t][c];
-          TT[a][c] += v;
-        }
-#pragma unroll
-        for (int h = 0; h < CB; ++h) {
-          Acc v = Acc(0);
-#pragma unroll
-          for (int t = 0; t < r; ++t) v += Bt[t][a] * wv[t][h];
-          RT[a][h] += v;
-        }
-      }
-#pragma unroll
-      for (int a = 0; a < r; ++a) {
-#pragma unroll
-        for (int c = 0; c < r; ++c) { Ls[i][a][c] = Lc[a][c]; Ub[i][a][c] = Uc[a][c]; Btb[i][a][c] = Bt[a][c]; }
-#pragma unroll
-        for (int h = 0; h < CB; ++h) Rb[i][a][h] = Rr[a][h];
-      }
-      // next block
-      Acc Sn[r][r], Rn[r][CB], Bn[r][r];
-      rd.diag(b + 1, Sn);
-      rd.rhs(b + 1, Rn);
-#pragma unroll
-      for (int a = 0; a < r; ++a)
-#pragma unroll
-        for (int c = 0; c < r; ++c) Bn[a][c] = Acc(0);
-      sub_AtB<r, r, r, Acc>(Uc, V, Sn);
-      sub_AtB<r, r, r, Acc>(Uc, Y, Bn);
-      sub_AtB<r, r, CB, Acc>(Uc, wv, Rn);
-#pragma unroll
-      for (int a = 0; a < r; ++a) {
-#pragma unroll
-        for (int c = 0; c < r; ++c) { S[a][c] = Sn[a][c]; Bt[a][c] = Bn[a][c]; }
-#pragma unroll
-        for (int h = 0; h < CB; ++h) Rr[a][h] = Rn[a][h];
-      }
-    }
-  }
-
-  Acc X[r][CB], XT[r][CB];
-  iface_pcr_levels<r, CB, Acc>(S, Bt, Rr, TT, RT, active, m, n, lane, X, XT);
-  if (!active) return;
-  Acc* out = U + (size_t)ki * n * r * CB;
-#pragma unroll
-  for (int a = 0; a < r; ++a)
-#pragma unroll
-    for (int h = 0; h < CB; ++h) st_if<COH>(out + (size_t)(e - 1) * r * CB + a * CB + h, X[a][h]);
-  // back substitution: x_b = S_b^-1 (R_b - U_b x_{b+1} - Bt_b x_T)
-  Acc xn[r][CB];
-#pragma unroll
-  for (int a = 0; a < r; ++a)
-#pragma unroll
-    for (int h = 0; h < CB; ++h) xn[a][h] = X[a][h];
-#pragma unroll
-  for (int i = MM - 2; i >= 0; --i) {
-    const int b = s + i;
-    if (b < e - 1) {
-      Acc v[r][CB];
-#pragma unroll
-      for (int a = 0; a < r; ++a)
-#pragma unroll
-        for (int h = 0; h < CB; ++h) {
-          Acc t = Rb[i][a][h];
-#pragma unroll
-          for (int c = 0; c < r; ++c) t -= Ub[i][a][c] * xn[c][h] + Btb[i][a][c] * XT[c][h];
-          v[a][h] = t;
-        }
-      chol_solve<r, CB, Acc>(Ls[i], v);
-#pragma unroll
-      for (int a = 0; a < r; ++a)
-#pragma unroll
-        for (int h = 0; h < CB; ++h) {
-          st_if<COH>(out + (size_t)b * r * CB + a * CB + h, v[a][h]);
-          xn[a][h] = v[a][h];
-        }
-    }
-  }
-}
-
-// The solver of one strip: its chunk records prefetched into registers
-// when the lane's run fits (MM + 1 records), else read as needed.
-template <int r, int CB, int MM, typename Acc, bool COH = false>
-DEV void iface_pcr_strip(const Acc* __restrict__ sum, Acc* __restrict__ U, int P, int m, int ki) {
-  using LY = IfaceLayout<r, CB>;
-  const Acc* S = sum + (size_t)ki * P * LY::F;
-  if constexpr ((MM + 1) * LY::F <= 160) {
-    PreReader<r, CB, MM + 1, Acc, COH> rd;
-    rd.load(S, (int)(threadIdx.x % kWave) * m, P, m + 1);
-    iface_pcr_run<r, CB, MM, Acc, PreReader<r, CB, MM + 1, Acc, COH>, COH>(rd, U, P, m, ki);
-  } else {
-    const SepReader<r, CB, Acc, COH> rd{S, P};
-    iface_pcr_run<r, CB, MM, Acc, SepReader<r, CB, Acc, COH>, COH>(rd, U, P, m, ki);
-  }
-}
-
-template <int r, int CB, int MM, typename Acc>
-__global__ __launch_bounds__(kWave) void k_interface_pcr(const Acc* __restrict__ sum,
-                                                         Acc* __restrict__ U, int nK, int P,
-                                                         int m, long long zi) {
-  const int z = blockIdx.z;   // image of a batched launch (interface buffers zi bytes apart)
-  iface_pcr_strip<r, CB, MM, Acc>(zmove_bytes(sum, zi, z), zmove_bytes(U, zi, z), P, m, blockIdx.x);
-}
-
 // Block exchanges between the NL lanes of a workgroup (NL = 64 x waves)
 // through LDS: value f of lane L at xs[f * NL + L].
 template <int n, int m, int NL, typename Acc>
@@ -1260,6 +1094,193 @@ DEV void iface_pcr_levels_mw(const Acc (&S)[r][r], const Acc (&Bt)[r][r], const 
 // LDS values per lane of iface_pcr_levels_mw.
 template <int r, int CB>
 constexpr int kMwSlot = 3 * r * r + r * CB;
+
+// k_interface_pcr: one wave per strip, lane l owns separator blocks
+// [l*m, min(l*m + m, P-1)); MM is the compiled maximum of m.
+// U receives the separator solutions strip-major: U[(ki*(P-1) + j)*r*CB + a*CB + h].
+template <int r, int CB, int MM, typename Acc, class Reader, bool COH = false, int NL = kWave>
+DEV void iface_pcr_run(const Reader& rd, Acc* __restrict__ U, int P, int m, int ki,
+                       Acc* xs = nullptr) {
+  const int lane = NL == kWave ? (int)(threadIdx.x % kWave) : (int)threadIdx.x;
+  const int n = P - 1;
+  const int s = lane * m, e = min(s + m, n);
+  const bool active = s < n;
+
+  // Local bordered elimination of blocks s .. e-2 (T = block s-1 of the
+  // previous lane, B = block e-1 is this lane's unknown at the PCR level).
+  Acc Ls[MM][r][r], Ub[MM][r][r], Btb[MM][r][r], Rb[MM][r][CB];
+  Acc S[r][r], Bt[r][r], Rr[r][CB], TT[r][r], RT[r][CB];
+#pragma unroll
+  for (int a = 0; a < r; ++a) {
+#pragma unroll
+    for (int c = 0; c < r; ++c) { TT[a][c] = Acc(0); S[a][c] = Acc(0); Bt[a][c] = Acc(0); }
+#pragma unroll
+    for (int h = 0; h < CB; ++h) { RT[a][h] = Acc(0); Rr[a][h] = Acc(0); }
+  }
+  if (active) {
+    rd.diag(s, S);
+    rd.rhs(s, Rr);
+    if (s > 0) {
+      Acc U0[r][r];
+      rd.off(s - 1, U0);
+#pragma unroll
+      for (int a = 0; a < r; ++a)
+#pragma unroll
+        for (int c = 0; c < r; ++c) Bt[a][c] = U0[c][a];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < MM - 1; ++i) {
+    const int b = s + i;
+    if (active && b < e - 1) {
+      Acc Lc[r][r];
+#pragma unroll
+      for (int a = 0; a < r; ++a)
+#pragma unroll
+        for (int c = 0; c < r; ++c) Lc[a][c] = S[a][c];
+      chol<r, Acc>(Lc);
+      Acc Uc[r][r];
+      rd.off(b, Uc);
+      Acc V[r][r], Y[r][r], wv[r][CB];
+#pragma unroll
+      for (int a = 0; a < r; ++a) {
+#pragma unroll
+        for (int c = 0; c < r; ++c) { V[a][c] = Uc[a][c]; Y[a][c] = Bt[a][c]; }
+#pragma unroll
+        for (int h = 0; h < CB; ++h) wv[a][h] = Rr[a][h];
+      }
+      chol_solve<r, r, Acc>(Lc, V);    // S^-1 U
+      chol_solve<r, r, Acc>(Lc, Y);    // S^-1 Bt
+      chol_solve<r, CB, Acc>(Lc, wv);  // S^-1 R
+      // TT += Bt^T S^-1 Bt, RT += Bt^T S^-1 R
+#pragma unroll
+      for (int a = 0; a < r; ++a) {
+#pragma unroll
+        for (int c = 0; c < r; ++c) {
+          Acc v = Acc(0);
+#pragma unroll
+          for (int t = 0; t < r; ++t) v += Bt[t][a] * Y[t][c];
+          TT[a][c] += v;
+        }
+#pragma unroll
+        for (int h = 0; h < CB; ++h) {
+          Acc v = Acc(0);
+#pragma unroll
+          for (int t = 0; t < r; ++t) v += Bt[t][a] * wv[t][h];
+          RT[a][h] += v;
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < r; ++a) {
+#pragma unroll
+        for (int c = 0; c < r; ++c) { Ls[i][a][c] = Lc[a][c]; Ub[i][a][c] = Uc[a][c]; Btb[i][a][c] = Bt[a][c]; }
+#pragma unroll
+        for (int h = 0; h < CB; ++h) Rb[i][a][h] = Rr[a][h];
+      }
+      // next block
+      Acc Sn[r][r], Rn[r][CB], Bn[r][r];
+      rd.diag(b + 1, Sn);
+      rd.rhs(b + 1, Rn);
+#pragma unroll
+      for (int a = 0; a < r; ++a)
+#pragma unroll
+        for (int c = 0; c < r; ++c) Bn[a][c] = Acc(0);
+      sub_AtB<r, r, r, Acc>(Uc, V, Sn);
+      sub_AtB<r, r, r, Acc>(Uc, Y, Bn);
+      sub_AtB<r, r, CB, Acc>(Uc, wv, Rn);
+#pragma unroll
+      for (int a = 0; a < r; ++a) {
+#pragma unroll
+        for (int c = 0; c < r; ++c) { S[a][c] = Sn[a][c]; Bt[a][c] = Bn[a][c]; }
+#pragma unroll
+        for (int h = 0; h < CB; ++h) Rr[a][h] = Rn[a][h];
+      }
+    }
+  }
+
+  Acc X[r][CB], XT[r][CB];
+  if constexpr (NL == kWave)
+    iface_pcr_levels<r, CB, Acc>(S, Bt, Rr, TT, RT, active, m, n, lane, X, XT);
+  else
+    iface_pcr_levels_mw<r, CB, Acc, NL>(S, Bt, Rr, TT, RT, active, m, n, lane, xs, X, XT);
+  if (!active) return;
+  Acc* out = U + (size_t)ki * n * r * CB;
+#pragma unroll
+  for (int a = 0; a < r; ++a)
+#pragma unroll
+    for (int h = 0; h < CB; ++h) st_if<COH>(out + (size_t)(e - 1) * r * CB + a * CB + h, X[a][h]);
+  // back substitution: x_b = S_b^-1 (R_b - U_b x_{b+1} - Bt_b x_T)
+  Acc xn[r][CB];
+#pragma unroll
+  for (int a = 0; a < r; ++a)
+#pragma unroll
+    for (int h = 0; h < CB; ++h) xn[a][h] = X[a][h];
+#pragma unroll
+  for (int i = MM - 2; i >= 0; --i) {
+    const int b = s + i;
+    if (b < e - 1) {
+      Acc v[r][CB];
+#pragma unroll
+      for (int a = 0; a < r; ++a)
+#pragma unroll
+        for (int h = 0; h < CB; ++h) {
+          Acc t = Rb[i][a][h];
+#pragma unroll
+          for (int c = 0; c < r; ++c) t -= Ub[i][a][c] * xn[c][h] + Btb[i][a][c] * XT[c][h];
+          v[a][h] = t;
+        }
+      chol_solve<r, CB, Acc>(Ls[i], v);
+#pragma unroll
+      for (int a = 0; a < r; ++a)
+#pragma unroll
+        for (int h = 0; h < CB; ++h) {
+          st_if<COH>(out + (size_t)b * r * CB + a * CB + h, v[a][h]);
+          xn[a][h] = v[a][h];
+        }
+    }
+  }
+}
+
+// The solver of one strip: its chunk records prefetched into registers
+// when the lane's run fits (MM + 1 records), else read as needed.
+template <int r, int CB, int MM, typename Acc, bool COH = false>
+DEV void iface_pcr_strip(const Acc* __restrict__ sum, Acc* __restrict__ U, int P, int m, int ki) {
+  using LY = IfaceLayout<r, CB>;
+  const Acc* S = sum + (size_t)ki * P * LY::F;
+  if constexpr ((MM + 1) * LY::F <= 160) {
+    PreReader<r, CB, MM + 1, Acc, COH> rd;
+    rd.load(S, (int)(threadIdx.x % kWave) * m, P, m + 1);
+    iface_pcr_run<r, CB, MM, Acc, PreReader<r, CB, MM + 1, Acc, COH>, COH>(rd, U, P, m, ki);
+  } else {
+    const SepReader<r, CB, Acc, COH> rd{S, P};
+    iface_pcr_run<r, CB, MM, Acc, SepReader<r, CB, Acc, COH>, COH>(rd, U, P, m, ki);
+  }
+}
+
+template <int r, int CB, int MM, typename Acc>
+__global__ __launch_bounds__(kWave) void k_interface_pcr(const Acc* __restrict__ sum,
+                                                         Acc* __restrict__ U, int nK, int P,
+                                                         int m, long long zi) {
+  const int z = blockIdx.z;   // image of a batched launch (interface buffers zi bytes apart)
+  iface_pcr_strip<r, CB, MM, Acc>(zmove_bytes(sum, zi, z), zmove_bytes(U, zi, z), P, m, blockIdx.x);
+}
+
+// Register solver on a workgroup of NL lanes per strip (cyclic reduction
+// through LDS): for runs too long for one wave's registers (r = 3), where NL
+// lanes cut every lane's run to at most MM blocks, so that no scratch round
+// trip is needed.  Records are read as needed (no prefetch: registers).
+constexpr int kMwMM = 4;
+template <int r, int CB, typename Acc, int NL>
+__global__ __launch_bounds__(NL) void k_interface_pcr_mw(const Acc* __restrict__ sum,
+                                                         Acc* __restrict__ U, int P, int m,
+                                                         long long zi) {
+  using LY = IfaceLayout<r, CB>;
+  extern __shared__ float smem[];
+  const int z = blockIdx.z;
+  const SepReader<r, CB, Acc> rd{zmove_bytes(sum, zi, z) + (size_t)blockIdx.x * P * LY::F, P};
+  iface_pcr_run<r, CB, kMwMM, Acc, SepReader<r, CB, Acc>, false, NL>(
+      rd, zmove_bytes(U, zi, z), P, m, blockIdx.x, reinterpret_cast<Acc*>(smem));
+}
 
 // Scratch values per separator block kept by iface_pcr_strip_long: the
 // Cholesky factor of the pivot block, the coupling to the next block, the
@@ -2267,6 +2288,20 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
       constexpr int MM = VS.MM > 0 ? VS.MM : 1;
       hipLaunchKernelGGL((k_interface_pcr<r, NR, MM, Acc>), dim3(geo.nK, 1, nz), dim3(kWave), 0,
                          stream, (const Acc*)sum, us, geo.nK, geo.P, pl.iface_m, geo.zi);
+    } else if (pl.mw_nl > 0) {
+      if constexpr (r == 3 && fp64 == 0 && MODE == kModeForward) {
+        const int nl = pl.mw_nl;
+        const int m = (geo.P - 1 + nl - 1) / nl;
+        const size_t xs = sizeof(Acc) * (size_t)nl * kMwSlot<r, NR>;
+        if (nl == 4 * kWave)
+          hipLaunchKernelGGL((k_interface_pcr_mw<r, NR, Acc, 4 * kWave>), dim3(geo.nK, 1, nz),
+                             dim3(nl), xs, stream, (const Acc*)sum, us, geo.P, m, geo.zi);
+        else
+          hipLaunchKernelGGL((k_interface_pcr_mw<r, NR, Acc, 2 * kWave>), dim3(geo.nK, 1, nz),
+                             dim3(nl), xs, stream, (const Acc*)sum, us, geo.P, m, geo.zi);
+      } else {
+        return hipErrorInvalidValue;
+      }
     } else {
       // Runs longer than the register solver holds: the same wave solver with
       // its per-block values in the scratch part of the interface buffer.

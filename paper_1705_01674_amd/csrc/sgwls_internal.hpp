@@ -213,6 +213,7 @@ struct PassPlan {
   size_t sum_elems, u_elems;   // interface buffer sizes (elements)
   size_t g_elems;              // scratch of the long-run interface solver (elements)
   int long_nl;                 // lanes per strip of the long-run solver (64, 128 or 256)
+  int mw_nl;                   // > 0: the register solver on mw_nl lanes per strip instead
   int acc_bytes;    // 4 (float) or 8 (double) interface element size
   OneCtl* one;      // set by the caller to allow the one-launch pass
 };

@@ -60,6 +60,17 @@ PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64, int varian
   // and the exchange fits 64 KiB of LDS.  Measured at 1024x1024 RGB, r = 4:
   // stride 4 0.97 -> 0.80 ms, stride 9 0.85 -> 0.66 ms; at stride 1 with more
   // strips than that a single wave per strip is as fast or faster.
+  // Float32 forward passes at r = 3: the register solver on 128 or 256 lanes
+  // per strip (at most 4 blocks per lane, no scratch) where that holds the
+  // runs (lines up to 1025 chunks).
+  pl.mw_nl = 0;
+  if (n > 0 && pl.iface_m == 0 && r == 3 && !fp64 && mode == kModeForward) {
+    for (int nl : {2 * kWave, 4 * kWave})
+      if (n <= 4 * nl) {
+        pl.mw_nl = nl;
+        break;
+      }
+  }
   pl.long_nl = kWave;
   if (n > 0 && pl.iface_m == 0) {
     const size_t slot = (size_t)(3 * r * r + r * pl.nr) * pl.acc_bytes;
