@@ -385,16 +385,19 @@ sgwls_status sgwls_backward(const float* g, const float* saved, const float* gra
  * that group, whose workgroups stride over the work units (image, channel,
  * block of strips and chunks), largest image first.  With SGWLS_P_AUTO each
  * image resolves its own precision (float32 images keep float32 even when
- * others of the batch need FP64 pivots).  Requirements (else
- * SGWLS_E_UNSUPPORTED or SGWLS_E_ARG): every p[b].iters, kind and prec
- * equal; stride 1; r <= 2;
- * each side at most about 64*8 chunks long (2052 pixels for r = 2 and 4104
- * for r = 1 with the default variant).  Images with several channels are
- * filtered channel by channel (the guidance weights are recomputed per
- * channel).  On a non-default stream that is not being captured, the whole
+ * others of the batch need FP64 pivots).  The persistent launches take the
+ * images with stride 1, r <= 2 and sides of at most 4104 pixels (r = 1) or
+ * 2052 (r = 2); every other image of the batch (r = 3 or 4, stride > 1,
+ * longer sides) runs through sgwls_filter in the same call, after them, on
+ * the same stream.  Requirements (else SGWLS_E_ARG, or SGWLS_E_UNSUPPORTED
+ * for SGWLS_P_FP32_DELTA): every p[b].iters, kind and prec equal, and each
+ * image valid for sgwls_filter.  Images with several channels are filtered
+ * channel by channel by the persistent launches (the guidance weights are
+ * recomputed per channel).  On a non-default stream that is not being captured, the whole
  * call (2T passes) is captured once into a hipGraph and replayed by later
  * calls with identical arguments (same stream, workspace, pointers, shapes
- * and parameters); otherwise it is enqueued directly.  u may alias f. */
+ * and parameters); otherwise it is enqueued directly (the single-image-path
+ * images are always enqueued directly).  u may alias f. */
 
 /* One image of a batch: device pointers and its shape. */
 typedef struct {

@@ -604,6 +604,59 @@ void tune_cache_save() {
   if (!arch.empty()) (void)sgwls_tune_save(path, arch.c_str());
 }
 
+// Images the persistent batched kernels take: stride 1, r <= kBatchMaxR and
+// sides whose chunk count the batched wave solver holds with every batched
+// variant's chunk height.  The others of a batch (larger radii, strides > 1,
+// longer sides) run through the single-image filter in the same call.
+constexpr int batch_min_R(int r) {
+  int m = 1 << 20;
+  for (int fp = 0; fp < 2; ++fp)
+    for (int v = 0; v < batch_variant_count(fp); ++v) {
+      const BatchVariant bv = batch_variant(v, fp);
+      const int R = r == 1 ? bv.R1 : bv.R2;
+      m = R < m ? R : m;
+    }
+  return m;
+}
+bool batch_eligible(const sgwls_image& im, const sgwls_params& p) {
+  if (p.stride != 1 || p.r > kBatchMaxR) return false;
+  const int R = batch_min_R(p.r);
+  const int side = std::max(im.M, im.N);
+  return (side + R - 1) / R - 1 <= kWave * kBatchMM;
+}
+
+struct BatchSplit {
+  std::vector<sgwls_image> im;    // persistent-kernel images
+  std::vector<sgwls_params> pp;
+  std::vector<int> rest;          // indices of the single-image-path images
+};
+
+sgwls_status batch_split(const sgwls_image* imgs, const sgwls_params* p, int B, BatchSplit& s) {
+  if (!imgs || !p || B < 1 || B > (1 << 20)) return SGWLS_E_ARG;
+  for (int b = 0; b < B; ++b) {
+    const sgwls_status st = sgwls_validate(imgs[b].C, imgs[b].M, imgs[b].N, &p[b]);
+    if (st != SGWLS_OK) return st;
+    if (p[b].iters != p[0].iters || p[b].kind != p[0].kind || p[b].prec != p[0].prec)
+      return SGWLS_E_ARG;
+    if (p[b].prec == SGWLS_P_FP32_DELTA) return SGWLS_E_UNSUPPORTED;
+    if (batch_eligible(imgs[b], p[b])) {
+      s.im.push_back(imgs[b]);
+      s.pp.push_back(p[b]);
+    } else {
+      s.rest.push_back(b);
+    }
+  }
+  return SGWLS_OK;
+}
+
+// Workspace of the single-image-path images (run one after another).
+size_t batch_rest_bytes(const sgwls_image* imgs, const sgwls_params* p, const BatchSplit& s) {
+  size_t need = 0;
+  for (int b : s.rest)
+    need = std::max(need, sgwls_workspace_bytes(imgs[b].C, imgs[b].M, imgs[b].N, &p[b], 0));
+  return need;
+}
+
 double batch_pixels(const sgwls_image* imgs, int B) {
   double px = 0.0;
   for (int b = 0; b < B; ++b) px += (double)imgs[b].C * imgs[b].M * imgs[b].N;
@@ -1185,7 +1238,8 @@ sgwls_status sgwls_backward_nchw(const float* g, const float* saved, const float
   return SGWLS_OK;
 }
 
-size_t sgwls_batched_workspace_bytes(const sgwls_image* imgs, const sgwls_params* p, int B) {
+// The persistent-kernel part of a batch (every image eligible).
+static size_t batched_core_bytes(const sgwls_image* imgs, const sgwls_params* p, int B) {
   if (!imgs || !p || B < 1) return 0;
   BatchPlan probe;
   if (batch_plan(imgs, p, B, 0, nullptr, probe) != SGWLS_OK) return 0;
@@ -1203,8 +1257,19 @@ int sgwls_batched_variant_count(int prec) {
   return batch_variant_count(prec);
 }
 
-sgwls_status sgwls_filter_batched_variant(const sgwls_image* imgs, const sgwls_params* p, int B,
-                                          int variant, void* ws, size_t ws_bytes, void* stream) {
+size_t sgwls_batched_workspace_bytes(const sgwls_image* imgs, const sgwls_params* p, int B) {
+  BatchSplit sp;
+  if (batch_split(imgs, p, B, sp) != SGWLS_OK) return 0;
+  size_t core = 0;
+  if (!sp.im.empty()) {
+    core = batched_core_bytes(sp.im.data(), sp.pp.data(), (int)sp.im.size());
+    if (core == 0) return 0;
+  }
+  return align_up(core) + batch_rest_bytes(imgs, p, sp);
+}
+
+static sgwls_status batched_core_run(const sgwls_image* imgs, const sgwls_params* p, int B,
+                                     int variant, void* ws, size_t ws_bytes, void* stream) {
   BatchPlan probe;
   sgwls_status st = batch_plan(imgs, p, B, 0, nullptr, probe);
   if (st != SGWLS_OK) return st;
@@ -1215,12 +1280,40 @@ sgwls_status sgwls_filter_batched_variant(const sgwls_image* imgs, const sgwls_p
     variant = it == tune_table().end() ? 0 : it->second;
   }
   if (variant >= batch_variant_count(probe.fp64)) return SGWLS_E_ARG;
-  if (!ws || ws_bytes < sgwls_batched_workspace_bytes(imgs, p, B)) return SGWLS_E_WORKSPACE;
+  if (!ws || ws_bytes < batched_core_bytes(imgs, p, B)) return SGWLS_E_WORKSPACE;
   clear_hip_error();
   BatchPlan plan;
   st = batch_plan(imgs, p, B, variant, ws, plan);
   if (st != SGWLS_OK) return st;
   return batch_run(plan, ws, (hipStream_t)stream);
+}
+
+sgwls_status sgwls_filter_batched_variant(const sgwls_image* imgs, const sgwls_params* p, int B,
+                                          int variant, void* ws, size_t ws_bytes, void* stream) {
+  BatchSplit sp;
+  sgwls_status st = batch_split(imgs, p, B, sp);
+  if (st != SGWLS_OK) return st;
+  for (int b = 0; b < B; ++b)
+    if (!imgs[b].f || !imgs[b].g || !imgs[b].u || (const float*)imgs[b].u == imgs[b].g)
+      return SGWLS_E_ARG;
+  const size_t need = sgwls_batched_workspace_bytes(imgs, p, B);
+  if (need == 0) return SGWLS_E_ARG;
+  if (!ws || ws_bytes < need) return SGWLS_E_WORKSPACE;
+  const size_t core = sp.im.empty() ? 0 : align_up(batched_core_bytes(sp.im.data(), sp.pp.data(),
+                                                                      (int)sp.im.size()));
+  if (!sp.im.empty()) {
+    st = batched_core_run(sp.im.data(), sp.pp.data(), (int)sp.im.size(), variant, ws, core, stream);
+    if (st != SGWLS_OK) return st;
+  } else if (variant >= batch_variant_count(0)) {
+    return SGWLS_E_ARG;
+  }
+  char* rest_ws = reinterpret_cast<char*>(ws) + core;
+  for (int b : sp.rest) {
+    st = sgwls_filter(imgs[b].f, imgs[b].g, imgs[b].u, imgs[b].C, imgs[b].M, imgs[b].N, &p[b],
+                      nullptr, nullptr, rest_ws, ws_bytes - core, stream);
+    if (st != SGWLS_OK) return st;
+  }
+  return SGWLS_OK;
 }
 
 size_t sgwls_interpolate_workspace_bytes(int C, int M, int N, const sgwls_params* p) {
@@ -1263,14 +1356,34 @@ sgwls_status sgwls_filter_batched(const sgwls_image* imgs, const sgwls_params* p
   return sgwls_filter_batched_variant(imgs, p, B, -1, ws, ws_bytes, stream);
 }
 
+static sgwls_status autotune_batched_core(const sgwls_image* imgs, const sgwls_params* p, int B,
+                                          void* ws, size_t ws_bytes, void* stream, int reps,
+                                          int* chosen);
+
 sgwls_status sgwls_autotune_batched(const sgwls_image* imgs, const sgwls_params* p, int B,
                                     void* ws, size_t ws_bytes, void* stream, int reps,
                                     int* chosen) {
+  BatchSplit sp;
+  sgwls_status st = batch_split(imgs, p, B, sp);
+  if (st != SGWLS_OK) return st;
+  if (reps < 1) return SGWLS_E_ARG;
+  if (!ws || ws_bytes < sgwls_batched_workspace_bytes(imgs, p, B)) return SGWLS_E_WORKSPACE;
+  if (sp.im.empty()) {   // nothing for the persistent kernels to tune
+    if (chosen) *chosen = 0;
+    return SGWLS_OK;
+  }
+  return autotune_batched_core(sp.im.data(), sp.pp.data(), (int)sp.im.size(), ws, ws_bytes,
+                               stream, reps, chosen);
+}
+
+static sgwls_status autotune_batched_core(const sgwls_image* imgs, const sgwls_params* p, int B,
+                                          void* ws, size_t ws_bytes, void* stream, int reps,
+                                          int* chosen) {
   BatchPlan probe;
   sgwls_status st = batch_plan(imgs, p, B, 0, nullptr, probe);
   if (st != SGWLS_OK) return st;
   if (reps < 1) return SGWLS_E_ARG;
-  if (!ws || ws_bytes < sgwls_batched_workspace_bytes(imgs, p, B)) return SGWLS_E_WORKSPACE;
+  if (!ws || ws_bytes < batched_core_bytes(imgs, p, B)) return SGWLS_E_WORKSPACE;
   clear_hip_error();
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -219,12 +219,21 @@ def test_batched_workspace_and_validation(nat):
     px = 300 * 500 + 2048 * 256 + 3 * 64 * 64
     assert n >= 4 * px                                   # at least the ping-pong images
     assert lib.sgwls_batched_workspace_bytes(imgs, ps, 0) == 0
-    for bad in ({"iters": 2}, {"stride": 2}, {"r": 3}):
-        imgs, ps, B = batch(nat, [(1, 300, 500), (1, 200, 200, bad)])
-        assert lib.sgwls_batched_workspace_bytes(imgs, ps, B) == 0
-    # a side too long for the wave interface solver of the batched kernels
-    imgs, ps, B = batch(nat, [(1, 8000, 64, {"r": 2})])
-    assert lib.sgwls_batched_workspace_bytes(imgs, ps, B) == 0
+    imgs, ps, B = batch(nat, [(1, 300, 500), (1, 200, 200, {"iters": 2})])
+    assert lib.sgwls_batched_workspace_bytes(imgs, ps, B) == 0       # T differs
+    imgs, ps, B = batch(nat, [(1, 300, 500), (1, 200, 200, {"prec": 2})])
+    assert lib.sgwls_batched_workspace_bytes(imgs, ps, B) == 0       # serial-strip mode
+    # images outside the persistent kernels (stride > 1, r > 2, a side too long
+    # for their wave interface solver) run through the single-image filter:
+    # the workspace holds the persistent part plus the largest single-image one
+    core_imgs, core_ps, _ = batch(nat, [(1, 300, 500)])
+    core = lib.sgwls_batched_workspace_bytes(core_imgs, core_ps, 1)
+    for extra, shape in (({"stride": 2}, (1, 200, 200)), ({"r": 3, "lam": 8.0}, (1, 200, 200)),
+                         ({"r": 4, "stride": 9}, (3, 300, 250)), ({"r": 2}, (1, 8000, 64))):
+        imgs, ps, B = batch(nat, [(1, 300, 500), (*shape, extra)])
+        single = lib.sgwls_workspace_bytes(*shape, ctypes.byref(ps[1]), 0)
+        assert single > 0
+        assert lib.sgwls_batched_workspace_bytes(imgs, ps, B) >= core + single
     assert lib.sgwls_batched_variant_count(0) == 3
     assert lib.sgwls_batched_variant_count(1) == 1
     assert lib.sgwls_batched_variant_count(7) == 0
@@ -235,8 +244,12 @@ def test_batched_error_paths_return_before_any_launch(nat):
     ws = ctypes.c_void_p(0x4000)
     imgs, ps, B = batch(nat, [(1, 300, 500), (1, 200, 200, {"iters": 2})])
     assert lib.sgwls_filter_batched(imgs, ps, B, ws, 1 << 30, None) == 1      # mixed T
+    imgs, ps, B = batch(nat, [(1, 300, 500), (1, 200, 200, {"prec": 2})])
+    assert lib.sgwls_filter_batched(imgs, ps, B, ws, 1 << 30, None) == 1      # mixed precision mode
+    imgs, ps, B = batch(nat, [(1, 300, 500, {"prec": 2}), (1, 200, 200, {"prec": 2})])
+    assert lib.sgwls_filter_batched(imgs, ps, B, ws, 1 << 30, None) == 4      # serial-strip mode
     imgs, ps, B = batch(nat, [(1, 300, 500), (1, 200, 200, {"stride": 3})])
-    assert lib.sgwls_filter_batched(imgs, ps, B, ws, 1 << 30, None) == 4      # unsupported
+    assert lib.sgwls_filter_batched(imgs, ps, B, ws, 1 << 30, None) == 1      # NULL image pointers
     imgs, ps, B = batch(nat, [(1, 300, 500)])
     assert lib.sgwls_filter_batched(imgs, ps, B, ws, 1 << 30, None) == 1      # NULL image pointers
     fake = (nat.SgwlsImage * 1)(nat.SgwlsImage(0x1000, 0x2000, 0x3000, 1, 300, 500))

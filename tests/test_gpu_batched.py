@@ -184,3 +184,37 @@ def test_auto_precision_per_image(ops, variant):
     mixed = run_batch(ops, items, prec="auto", variant=variant)
     alone = run_batch(ops, [items[0]], prec="fp32", variant=variant)
     assert np.array_equal(mixed[0], alone[0])
+
+
+def test_batch_mixing_radii_strides_and_long_sides(ops):
+    # r = 1..4, strides up to 2r+1 and sides past the persistent kernels'
+    # wave interface solver: images the persistent launches do not take run
+    # through the single-image filter in the same call (also when the call
+    # is replayed as a graph on a side stream)
+    rng = np.random.default_rng(44)
+    specs = [((1, 120, 150), 1, 1), ((3, 90, 130), 2, 1), ((1, 100, 140), 3, 1),
+             ((1, 110, 120), 4, 4), ((3, 80, 200), 2, 5), ((1, 130, 90), 1, 3),
+             ((1, 4200, 40), 2, 1), ((1, 4000, 33), 1, 1), ((1, 96, 97), 4, 9)]
+    items = []
+    for (C, M, N), r, stride in specs:
+        f = rng.uniform(0, 1, (C, M, N)).astype(np.float32)
+        g = (f.mean(axis=0) + 0.02 * rng.standard_normal((M, N))).astype(np.float32)
+        pd = dict(lam=float(2.0 ** rng.uniform(-1, 4)), r=r, iters=2, stride=stride, kind="exp",
+                  sigma_s=float(r), sigma_r=0.15, alpha_s=1.2, alpha_r=1.2, eps=1e-4)
+        items.append((f, g, pd))
+    refs = oracle_outs(items)
+    check_all("mixed radii/strides/long sides", run_batch(ops, items, prec="auto"), refs)
+    stream = torch.cuda.Stream()
+    fs = [torch.from_numpy(f).cuda() for f, _, _ in items]
+    gs = [torch.from_numpy(g).cuda() for _, g, _ in items]
+    ps = [ops.Params(**pd, prec="auto") for _, _, pd in items]
+    outs = [torch.empty_like(f) for f in fs]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            ops.sgwls_filter_batched(fs, gs, ps, stream=stream, outs=outs)
+        stream.synchronize()
+        check_all(f"mixed batch on a side stream, call {rep}", [o.cpu().numpy() for o in outs], refs)
