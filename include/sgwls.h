@@ -214,7 +214,8 @@ sgwls_status sgwls_filter(const float* f, const float* g, float* u,
  * sets an error word at the start of ws.  sgwls_filter_status synchronises
  * `stream`, returns SGWLS_E_HIP (and clears the word) if it is set, else
  * SGWLS_OK; ws is the workspace of the filter calls to check.  Every call
- * with fused passes clears the word when it starts. */
+ * with fused passes clears the word when it starts.  sgwls_filter_noalloc
+ * always runs three launches per pass (its workspace is the library's). */
 sgwls_status sgwls_filter_status(void* ws, void* stream);
 
 /* ---- sgwls_filter without a caller workspace ----

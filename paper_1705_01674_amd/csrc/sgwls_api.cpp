@@ -152,7 +152,9 @@ size_t image_bytes(int C, int M, int N) { return align_up(sizeof(float) * (size_
 // the three stage kernels, read at every call from SGWLS_ONE_LAUNCH: unset
 // or 0 = three launches per pass, 1 = one launch, 2 = reduce and interface
 // in one launch, expand in a second.
+thread_local int t_no_fused = 0;
 int one_launch_mode() {
+  if (t_no_fused > 0) return 0;
   const char* e = std::getenv("SGWLS_ONE_LAUNCH");
   return (e && (e[0] == '1' || e[0] == '2')) ? e[0] - '0' : 0;
 }
@@ -664,6 +666,9 @@ double batch_pixels(const sgwls_image* imgs, int B) {
 }
 
 }  // namespace
+
+sgwls::NoFusedScope::NoFusedScope() { ++t_no_fused; }
+sgwls::NoFusedScope::~NoFusedScope() { --t_no_fused; }
 
 extern "C" {
 

@@ -187,6 +187,16 @@ struct OneCtl {
   DEV_HOST_INLINE int bank_words() const { return (int)(2 * counters * kCounterStride); }
   DEV_HOST_INLINE unsigned int* bank_ptr(int b) const { return banks + (size_t)b * bank_words(); }
 };
+// While a NoFusedScope lives, filter calls on this thread run three launches
+// per pass whatever SGWLS_ONE_LAUNCH says (for callers whose workspace the
+// user cannot read the fused passes' error word back from).
+struct NoFusedScope {
+  NoFusedScope();
+  ~NoFusedScope();
+  NoFusedScope(const NoFusedScope&) = delete;
+  NoFusedScope& operator=(const NoFusedScope&) = delete;
+};
+
 // Synchronisation bytes of a call over B images of M x N (strip groups of 64
 // strips across the wider frame).
 inline size_t sync_bytes(int B, int M, int N) {

@@ -45,6 +45,9 @@ extern "C" sgwls_status sgwls_filter_noalloc(const float* f, const float* g, flo
   void* ws = device_scratch();
   if (!ws) return SGWLS_E_HIP;
   // Everything the filter reads from its workspace it writes first in the
-  // same call, so the array needs no clearing between calls.
+  // same call, so the array needs no clearing between calls.  Three
+  // launches per pass: the caller could not read a fused pass's wait error
+  // back from the library's array.
+  const sgwls::NoFusedScope three_launches;
   return sgwls_filter(f, g, u, C, M, N, p, lambda_dev, saved, ws, kScratchBytes, stream);
 }

@@ -83,3 +83,26 @@ def test_fused_wait_error_is_reported(ops, monkeypatch):
     u0 = ops.sgwls_filter_nchw(f, g, p, workspace=ws)
     torch.cuda.synchronize()
     assert (u1 - u0).abs().max().item() <= 2e-6
+
+
+def test_noalloc_ignores_the_fused_switch(ops, monkeypatch):
+    # sgwls_filter_noalloc keeps three launches per pass (its workspace is the
+    # library's, so a wait error could not be read back): with
+    # SGWLS_ONE_LAUNCH=1 it gives exactly the three-launch result
+    import ctypes
+    rng = np.random.default_rng(9)
+    C, M, N = 3, 260, 410
+    f = torch.from_numpy(rng.uniform(0, 1, (C, M, N)).astype(np.float32)).cuda()
+    g = torch.from_numpy(rng.uniform(0, 1, (M, N)).astype(np.float32)).cuda()
+    p = ops.Params(lam=4.0, r=1, iters=2, sigma_r=0.1, prec="fp32")
+    monkeypatch.setenv("SGWLS_ONE_LAUNCH", "0")
+    u0 = ops.sgwls_filter(f, g, p)
+    monkeypatch.setenv("SGWLS_ONE_LAUNCH", "1")
+    u1 = torch.empty_like(f)
+    st = ops.nat.lib.sgwls_filter_noalloc(
+        ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(u1.data_ptr()),
+        C, M, N, ctypes.byref(p.c()), None, None,
+        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    assert st == 0
+    assert torch.equal(u0, u1)
