@@ -102,6 +102,13 @@ def sources_digest():
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_expand_d_rgb1080p_r1_T3_counters.md")
 
 
+def frame_variants(tuned):
+    """The tuned kernel variant of each channel-block width: every pass of a
+    stride-1 filter call is a column pass of a frame (the image or its
+    transpose) and runs the column-direction variant."""
+    return {f"c{cb}": v for (d, cb), v in sorted(tuned.items()) if d == 0}
+
+
 def counted_traffic(tuned):
     """HBM bytes per k_expand_d launch (mean of the column and row frame) from
     the committed counter summary, or None when it is missing, was taken on
@@ -118,10 +125,12 @@ def counted_traffic(tuned):
     if data.get("source_sha256") != sources_digest():
         return None
     per = data.get("bytes_per_launch", {})
-    col, row = per.get(str(tuned.get((0, 3)))), per.get(str(tuned.get((1, 3))))
-    if not col or not row or "col" not in col or "row" not in row:
+    # Every pass of the filter is a column pass of a frame (the image or its
+    # transpose), both run with the column-direction variant.
+    v = per.get(str(tuned.get((0, 3))))
+    if not v or "col" not in v or "row" not in v:
         return None
-    return round((col["col"] + row["row"]) / 2)
+    return round((v["col"] + v["row"]) / 2)
 
 
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_rgb1080p_r1_r2_r3_T3.md")
@@ -172,7 +181,7 @@ def radius_rows(torch, ops, nat, synth, dev, args, counters=False):
         u = torch.empty_like(f)
         ws = torch.empty(ops.workspace_bytes(C, M, N, p), dtype=torch.uint8, device=dev)
         tuned = ops.autotune(f, g, p, reps=10)
-        variants = {f"{'col' if d == 0 else 'row'}_c{cb}": v for (d, cb), v in sorted(tuned.items())}
+        variants = frame_variants(tuned)
 
         def step():
             ops.sgwls_filter(f, g, p, out=u, workspace=ws)
@@ -509,8 +518,7 @@ def main():
         ops.sgwls_filter(f, g, p, out=u, workspace=ws)
 
     if args.counters == "fwd":
-        counter_run(torch, step, args, {"variants": {f"{'col' if d == 0 else 'row'}_c{cb}": v
-                                                     for (d, cb), v in sorted(tuned.items())}})
+        counter_run(torch, step, args, {"variants": frame_variants(tuned)})
         return
     if args.fused:
         print(json.dumps({"fused_passes": fused_rows(torch, ops, f, g, p, ws, args.steps)}),
@@ -703,8 +711,7 @@ def main():
         "config": {"workload": w.name, "M": M, "N": N, "C": C, "r": p.r, "iters": p.iters,
                    "stride": p.stride, "lambda": p.lam, "weight": p.kind,
                    "sigma_s": float(p.r), "sigma_r": p.sigma_r,
-                   "variants": {f"{'col' if d == 0 else 'row'}_c{cb}": v
-                                for (d, cb), v in sorted(tuned.items())}},
+                   "variants": frame_variants(tuned)},
         "roofline": {"bound": "hbm", "kernel": dom,
                      "achieved": round(achieved, 1) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
