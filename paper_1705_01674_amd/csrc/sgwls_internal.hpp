@@ -103,7 +103,9 @@ constexpr int kModeForward = 0, kModeBackward = 1;
 // R shrinks as r, the channel block and the precision grow.
 constexpr VariantSet variants_of(int r, int cb, int fp64) {
   if (fp64) {
-    if (r == 1) return cb == 1 ? VariantSet{2, {{8, 4, 1}, {4, 4}}, 8} : VariantSet{2, {{4, 4, 1}, {4, 2}}, 8};
+    // r = 1, three channels: six-row chunks first (0.290 against 0.315 ms for
+    // four rows on 1080p RGB; eight rows need all 256 VGPRs and are slower)
+    if (r == 1) return cb == 1 ? VariantSet{2, {{8, 4, 1}, {4, 4}}, 8} : VariantSet{3, {{6, 4, 1}, {4, 4, 1}, {4, 2}}, 8};
     if (r == 2) return cb == 1 ? VariantSet{1, {{4, 4, 1}}, 4} : VariantSet{1, {{2, 4, 1}}, 4};
     return VariantSet{1, {{2, 2, 1}}, 0};
   }
