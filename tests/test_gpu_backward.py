@@ -146,6 +146,23 @@ def test_filter_backward_multiwave_long_run_solver(ops):
     check("grad_lambda multi-wave long", gl, rl, TOL_G)
 
 
+@pytest.mark.parametrize("r,prec", [(4, "fp32"), (3, "fp64_pivot")])
+def test_filter_backward_two_wave_long_run_solver(ops, r, prec):
+    """600 x 60: the column frame's ~52 strips with 299 separators each run
+    the backward's long-run interface on two waves per strip (the four-wave
+    exchange would pass 64 KiB of LDS at these right-hand-side counts)."""
+    M, N = 600, 60
+    f, g, ub = inputs(2, M, N, 4300 + r)
+    pd = pdict(lam=8.0, r=r, iters=1)
+    gf, gg, gl = filter_grads(ops, f, g, pd, ub, prec=prec)
+    rf, rg, rl = oracle_grads(f, g, pd, ub)
+    tag = f"two-wave long r{r} {prec}"
+    check(f"grad_f {tag}", gf, rf, TOL_X)
+    check(f"grad_g {tag}", gg, rg, TOL_G)
+    if prec != "fp32":   # the float32 lambda gradient is outside the policy's bar
+        check(f"grad_lambda {tag}", gl, rl, TOL_G)
+
+
 @pytest.mark.parametrize("r,C", [(1, 3), (3, 1)])
 def test_filter_backward_long_lines(ops, r, C):
     """Tall images (4,000 rows): more separator blocks per lane than the
