@@ -392,9 +392,9 @@ sgwls_status sgwls_backward(const float* g, const float* saved, const float* gra
  * longer sides) runs through sgwls_filter in the same call, after them, on
  * the same stream.  Requirements (else SGWLS_E_ARG, or SGWLS_E_UNSUPPORTED
  * for SGWLS_P_FP32_DELTA): every p[b].iters, kind and prec equal, and each
- * image valid for sgwls_filter.  Images with several channels are filtered
- * channel by channel by the persistent launches (the guidance weights are
- * recomputed per channel).  On a non-default stream that is not being captured, the whole
+ * image valid for sgwls_filter.  The persistent launches filter images whose
+ * channel count is a multiple of 3 three channels at a time (the guidance
+ * weights shared by the block) and the others channel by channel.  On a non-default stream that is not being captured, the whole
  * call (2T passes) is captured once into a hipGraph and replayed by later
  * calls with identical arguments (same stream, workspace, pointers, shapes
  * and parameters); otherwise it is enqueued directly (the single-image-path

@@ -297,9 +297,12 @@ TuneKey batch_tune_key(int fp64, int kind, double pixels) {
   return TuneKey(0, 0, fp64, kind, kBatchDir, (int)std::lround(2.0 * std::log2(std::max(pixels, 1.0))));
 }
 
-// Images are grouped by precision (float32 groups first) and radius: group
-// k = prec * kBatchMaxR + (r - 1), one launch per group, stage and pass.
-constexpr int kBatchGroups = 2 * kBatchMaxR;
+// Images are grouped by precision (float32 groups first), channel block
+// (images whose channel count is a multiple of 3 are filtered three channels
+// at a time, sharing the guidance weights; the others one channel at a time)
+// and radius: group k = (prec * 2 + (cb == 3)) * kBatchMaxR + (r - 1), one
+// launch per group, stage and pass.
+constexpr int kBatchGroups = 4 * kBatchMaxR;
 
 struct BatchPlan {
   int B = 0, passes = 0, kind = 0, variant = 0;
@@ -315,12 +318,42 @@ struct BatchPlan {
   size_t pre_tiles() const { return (size_t)kBatchGroups * 6 * (B + 1); }
   size_t off_tab = 0, off_pre = 0, off_tmp = 0, off_gt = 0, off_iface = 0, off_iface64 = 0,
          total = 0;
-  static int group_prec(int k) { return k / kBatchMaxR; }
+  static int group_prec(int k) { return k / (2 * kBatchMaxR); }
+  static int group_cb(int k) { return (k / kBatchMaxR) % 2 ? 3 : 1; }
   static int group_r(int k) { return k % kBatchMaxR + 1; }
-  // float32 groups run the chosen variant, float64 groups their only one
-  int group_variant(int k) const { return group_prec(k) ? 0 : variant; }
+  // float32 one-channel groups run the chosen variant, the other groups
+  // their only one
+  int group_variant(int k) const { return group_prec(k) || group_cb(k) == 3 ? 0 : variant; }
   size_t group_iface(int k) const { return group_prec(k) ? off_iface64 : off_iface; }
 };
+
+// Images the persistent batched kernels take: stride 1, r <= kBatchMaxR and
+// sides whose chunk count the batched wave solver holds with every batched
+// variant's chunk height.  The others of a batch (larger radii, strides > 1,
+// longer sides) run through the single-image filter in the same call.
+constexpr int batch_min_R(int r) {
+  int m = 1 << 20;
+  for (int fp = 0; fp < 2; ++fp)
+    for (int v = 0; v < batch_variant_count(fp); ++v) {
+      const BatchVariant bv = batch_variant(v, fp);
+      const int R = r == 1 ? bv.R1 : bv.R2;
+      m = R < m ? R : m;
+    }
+  return m;
+}
+// Channel block of an image in the persistent kernels: 3 where the channel
+// count allows it and the three-channel chunk height keeps the sides within
+// the wave solver, else 1 where the one-channel heights do, else 0 (the
+// single-image path).
+int batch_cb(const sgwls_image& im, const sgwls_params& p) {
+  if (p.stride != 1 || p.r > kBatchMaxR) return 0;
+  const int side = std::max(im.M, im.N);
+  auto fits = [&](int R) { return (side + R - 1) / R - 1 <= kWave * kBatchMM; };
+  const int fp64 = resolved(p, 0).prec == SGWLS_P_FP64_PIVOT ? 1 : 0;
+  if (im.C % 3 == 0 && fits(variants_of(p.r, 3, fp64).v[0].R)) return 3;
+  return fits(batch_min_R(p.r)) ? 1 : 0;
+}
+bool batch_eligible(const sgwls_image& im, const sgwls_params& p) { return batch_cb(im, p) > 0; }
 
 // Validates the batch and lays out its workspace (ws may be NULL: sizes only).
 sgwls_status batch_plan(const sgwls_image* imgs, const sgwls_params* p, int B, int variant,
@@ -348,7 +381,9 @@ sgwls_status batch_plan(const sgwls_image* imgs, const sgwls_params* p, int B, i
   plan.fp64 = all64;
   plan.kind = (int)p0.kind;
   plan.variant = variant;
-  auto group_of = [&](int b) { return prec[b] * kBatchMaxR + p[b].r - 1; };
+  std::vector<int> cbk(B);
+  for (int b = 0; b < B; ++b) cbk[b] = batch_cb(imgs[b], p[b]);
+  auto group_of = [&](int b) { return (prec[b] * 2 + (cbk[b] == 3 ? 1 : 0)) * kBatchMaxR + p[b].r - 1; };
   std::vector<int> order(B);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -379,7 +414,10 @@ sgwls_status batch_plan(const sgwls_image* imgs, const sgwls_params* p, int B, i
     const sgwls_image& im = imgs[b];
     const sgwls_params& pb = p[b];
     const int k = group_of(b);
+    const int cb = cbk[b];
+    if (cb == 0) return SGWLS_E_UNSUPPORTED;
     const BatchVariant bv = batch_variant(prec[b] ? 0 : variant, prec[b]);
+    const Variant v3 = variants_of(p[b].r, 3, prec[b]).v[0];
     BatchDesc& D = plan.tab[t];
     D.f = im.f;
     D.g = im.g;
@@ -397,9 +435,11 @@ sgwls_status batch_plan(const sgwls_image* imgs, const sgwls_params* p, int B, i
     D.lam = pb.lambda;
     D.wp = weight_params(pb);
     D.OW = kWave - 2 * pb.r;
-    const int R = pb.r == 1 ? bv.R1 : bv.R2;
+    const int R = cb == 3 ? v3.R : pb.r == 1 ? bv.R1 : bv.R2;
+    const int Q = cb == 3 ? v3.Q : bv.Q;
     const int T2 = pb.r * (pb.r + 1) / 2;
-    const int F = 2 * T2 + 2 * pb.r + pb.r * pb.r;
+    const int F = 2 * T2 + 2 * pb.r * cb + pb.r * pb.r;
+    const int nblk = im.C / cb;
     long long sum_max = 0, us_max = 0;
     for (int dir = 0; dir < 2; ++dir) {
       // Both passes are column passes storing transposed: the row pass runs
@@ -420,15 +460,16 @@ sgwls_status batch_plan(const sgwls_image* imgs, const sgwls_params* p, int B, i
       if (n > kWave * kBatchMM) return SGWLS_E_UNSUPPORTED;   // too long for the wave solver
       D.nbx_red[dir] = (g.nK + kWave - 1) / kWave;
       D.nbx_exp[dir] = (g.W + D.OW - 1) / D.OW;
-      D.nby[dir] = (g.P + bv.Q - 1) / bv.Q;
+      D.nby[dir] = (g.P + Q - 1) / Q;
       sum_max = std::max(sum_max, (long long)g.P * F * g.nK);
-      us_max = std::max(us_max, (long long)std::max(n, 1) * pb.r * g.nK);
-      // Prefix sums of the group's sub-table: entry t - first + 1.
+      us_max = std::max(us_max, (long long)std::max(n, 1) * pb.r * cb * g.nK);
+      // Prefix sums of the group's sub-table: entry t - first + 1 (units of
+      // every channel block of the image).
       const bool split = g.P > 1;
       long long* un = units[k][dir];
-      un[0] += split ? (long long)im.C * D.nbx_red[dir] * D.nby[dir] : 0;
-      un[1] += split ? (long long)im.C * g.nK : 0;
-      un[2] += (long long)im.C * D.nbx_exp[dir] * D.nby[dir];
+      un[0] += split ? (long long)nblk * D.nbx_red[dir] * D.nby[dir] : 0;
+      un[1] += split ? (long long)nblk * g.nK : 0;
+      un[2] += (long long)nblk * D.nbx_exp[dir] * D.nby[dir];
       const int tl = t - plan.first[k];
       for (int st = 0; st < 3; ++st)
         plan.pre[plan.pre_at(k, dir, st) + tl + 1] = (int)std::min<long long>(un[st], 0x7fffffff);
@@ -437,9 +478,9 @@ sgwls_status batch_plan(const sgwls_image* imgs, const sgwls_params* p, int B, i
     D.us_ch = us_max;
     size_t& ie = iface_elems[prec[b]];
     D.sum_base = (long long)ie;
-    ie += (size_t)im.C * sum_max;
+    ie += (size_t)nblk * sum_max;
     D.us_base = (long long)ie;
-    ie += (size_t)im.C * us_max;
+    ie += (size_t)nblk * us_max;
   }
   for (int k = 0; k < kBatchGroups; ++k)
     for (int dir = 0; dir < 2; ++dir)
@@ -486,7 +527,8 @@ sgwls_status batch_enqueue(const BatchPlan& plan, void* ws, hipStream_t s) {
       const int b0 = plan.first[k], nb = plan.first[k + 1] - b0;
       if (nb == 0) continue;
       if (launch_batch_pass(plan.group_variant(k), BatchPlan::group_prec(k), plan.kind,
-                            BatchPlan::group_r(k), tab + b0, pre + plan.pre_at(k, dir, 0),
+                            BatchPlan::group_r(k), BatchPlan::group_cb(k), tab + b0,
+                            pre + plan.pre_at(k, dir, 0),
                             pre + plan.pre_at(k, dir, 1), pre + plan.pre_at(k, dir, 2),
                             plan.totals[k][dir], nb, q, dir, base + plan.group_iface(k),
                             s) != hipSuccess)
@@ -534,8 +576,8 @@ sgwls_status batch_run(const BatchPlan& plan, void* ws, hipStream_t s) {
   for (int k = 0; k < kBatchGroups; ++k)
     if (plan.first[k + 1] > plan.first[k] &&
         launch_batch_pass(plan.group_variant(k), BatchPlan::group_prec(k), plan.kind,
-                          BatchPlan::group_r(k), nullptr, nullptr, nullptr, nullptr, none, 0, 0, 0,
-                          nullptr, s) != hipSuccess)
+                          BatchPlan::group_r(k), BatchPlan::group_cb(k), nullptr, nullptr, nullptr,
+                          nullptr, none, 0, 0, 0, nullptr, s) != hipSuccess)
       return SGWLS_E_HIP;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (s == nullptr || hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
@@ -604,27 +646,6 @@ void tune_cache_save() {
   if (!path) return;
   const std::string arch = device_arch_name();
   if (!arch.empty()) (void)sgwls_tune_save(path, arch.c_str());
-}
-
-// Images the persistent batched kernels take: stride 1, r <= kBatchMaxR and
-// sides whose chunk count the batched wave solver holds with every batched
-// variant's chunk height.  The others of a batch (larger radii, strides > 1,
-// longer sides) run through the single-image filter in the same call.
-constexpr int batch_min_R(int r) {
-  int m = 1 << 20;
-  for (int fp = 0; fp < 2; ++fp)
-    for (int v = 0; v < batch_variant_count(fp); ++v) {
-      const BatchVariant bv = batch_variant(v, fp);
-      const int R = r == 1 ? bv.R1 : bv.R2;
-      m = R < m ? R : m;
-    }
-  return m;
-}
-bool batch_eligible(const sgwls_image& im, const sgwls_params& p) {
-  if (p.stride != 1 || p.r > kBatchMaxR) return false;
-  const int R = batch_min_R(p.r);
-  const int side = std::max(im.M, im.N);
-  return (side + R - 1) / R - 1 <= kWave * kBatchMM;
 }
 
 struct BatchSplit {

@@ -53,7 +53,7 @@ DEV float* pass_out(const BatchDesc& D, int q) { return (q % 2) ? D.u : D.tmp; }
 // The kernels of one radius: a batch runs one launch per stage and radius
 // over the images of that radius, so each kernel holds the registers of its
 // own radius only.
-template <int r, int KIND, typename Acc, int R, int Q>
+template <int r, int CB, int KIND, typename Acc, int R, int Q>
 __global__ __launch_bounds__(kWave* Q) void k_batch_reduce(const BatchDesc* __restrict__ tab,
                                                            const int* __restrict__ pre, int B,
                                                            int q, int dir,
@@ -68,15 +68,15 @@ __global__ __launch_bounds__(kWave* Q) void k_batch_reduce(const BatchDesc* __re
     const BatchDesc& D = tab[i];
     int local = u - cur.lo;
     const int nbx = D.nbx_red[dir], per_c = nbx * D.nby[dir];
-    const int c = local / per_c;
+    const int c = local / per_c;   // channel block
     local -= c * per_c;
     const int by = local / nbx, bx = local - by * nbx;
     const PassGeom& geo = D.geo[dir];
-    const PlaneSrc<1> src{pass_in(D, q), nullptr, c, (int)geo.plane};
+    const PlaneSrc<CB> src{pass_in(D, q), nullptr, c * CB, (int)geo.plane};
     const float* gf = dir ? D.gT : D.g;
     Acc* sum = iface + D.sum_base + c * D.sum_ch;
-    reduce_tile<r, 1, R, Q, true, KIND, Acc, kModeForward, true>(geo, D.wp, D.lam, 0, sum, bx, by,
-                                                                 smem, gf, &src);
+    reduce_tile<r, CB, R, Q, true, KIND, Acc, kModeForward, true>(geo, D.wp, D.lam, 0, sum, bx,
+                                                                  by, smem, gf, &src);
   }
 }
 
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kWave* Q) void k_batch_reduce(const BatchDesc* __re
 // wave-local: no workgroup barrier).
 constexpr int kIfaceWaves = 4;
 
-template <int r, typename Acc>
+template <int r, int CB, typename Acc>
 __global__ __launch_bounds__(kWave* kIfaceWaves) void k_batch_iface(
     const BatchDesc* __restrict__ tab, const int* __restrict__ pre, int B, int dir,
     Acc* __restrict__ iface) {
@@ -97,14 +97,14 @@ __global__ __launch_bounds__(kWave* kIfaceWaves) void k_batch_iface(
     const BatchDesc& D = tab[i];
     const int local = u - cur.lo;
     const int nK = D.geo[dir].nK;
-    const int c = local / nK, ki = local - c * nK;
+    const int c = local / nK, ki = local - c * nK;   // channel block, strip
     const Acc* sum = iface + D.sum_base + c * D.sum_ch;
     Acc* us = iface + D.us_base + c * D.us_ch;
-    iface_pcr_strip<r, 1, kBatchMM, Acc>(sum, us, D.geo[dir].P, D.m[dir], ki);
+    iface_pcr_strip<r, CB, kBatchMM, Acc>(sum, us, D.geo[dir].P, D.m[dir], ki);
   }
 }
 
-template <int r, int KIND, typename Acc, int R, int Q>
+template <int r, int CB, int KIND, typename Acc, int R, int Q>
 __global__ __launch_bounds__(kWave* Q) void k_batch_expand(const BatchDesc* __restrict__ tab,
                                                            const int* __restrict__ pre, int B,
                                                            int q, int dir,
@@ -120,26 +120,26 @@ __global__ __launch_bounds__(kWave* Q) void k_batch_expand(const BatchDesc* __re
     const BatchDesc& D = tab[i];
     int local = u - cur.lo;
     const int nbx = D.nbx_exp[dir], per_c = nbx * D.nby[dir];
-    const int c = local / per_c;
+    const int c = local / per_c;   // channel block
     local -= c * per_c;
     const int by = local / nbx, bx = local - by * nbx;
     const PassGeom& geo = D.geo[dir];
-    const PlaneSrc<1> src{pass_in(D, q), nullptr, c, (int)geo.plane};
+    const PlaneSrc<CB> src{pass_in(D, q), nullptr, c * CB, (int)geo.plane};
     const float* gf = dir ? D.gT : D.g;
     float* y = pass_out(D, q);
     const Acc* us = iface + D.us_base + c * D.us_ch;
-    expand_tile<r, 1, R, Q, true, KIND, Acc, kModeForward, true>(gf, y, geo, D.wp, D.lam, c, us,
-                                                                 D.OW, 0, none, bx, by, nbx, smem,
-                                                                 &src);
+    expand_tile<r, CB, R, Q, true, KIND, Acc, kModeForward, true>(gf, y, geo, D.wp, D.lam, c * CB,
+                                                                  us, D.OW, 0, none, bx, by, nbx,
+                                                                  smem, &src);
   }
 }
 
 // LDS of one batched reduce / expand block (direct reads: the reduce output
 // staging and the transposed-store staging).
-template <typename Acc, int r, int R, int Q>
+template <typename Acc, int r, int CB, int R, int Q>
 constexpr size_t batch_lds() {
-  const size_t out = sizeof(float) * Q * R * (kWave + 1);
-  const size_t F = r * (r + 1) + 2 * r + r * r;
+  const size_t out = sizeof(float) * CB * Q * R * (kWave + 1);
+  const size_t F = r * (r + 1) + 2 * r * CB + r * r;
   const size_t stage = sizeof(Acc) * kWave * Q * F;
   return out > stage ? out : stage;
 }
@@ -188,26 +188,28 @@ int persistent_grid(K kernel, int block, size_t lds) {
   return per_cu * std::max(1, cus);
 }
 
-template <int r, int KIND, typename Acc, int R, int Q>
+template <int r, int CB, int KIND, typename Acc, int R, int Q>
 hipError_t batch_pass_impl(const BatchDesc* tab, const int* pre_r, const int* pre_i,
                            const int* pre_e, const int totals[3], int B, int q, int dir,
                            void* iface, hipStream_t s) {
   Acc* buf = reinterpret_cast<Acc*>(iface);
-  constexpr size_t lds = batch_lds<Acc, r, R, Q>();
-  static const int g_red = persistent_grid(k_batch_reduce<r, KIND, Acc, R, Q>, kWave * Q, lds);
-  static const int g_if = persistent_grid(k_batch_iface<r, Acc>, kWave * kIfaceWaves, 0);
-  static const int g_exp = persistent_grid(k_batch_expand<r, KIND, Acc, R, Q>, kWave * Q, lds);
+  constexpr size_t lds = batch_lds<Acc, r, CB, R, Q>();
+  static const int g_red =
+      persistent_grid(k_batch_reduce<r, CB, KIND, Acc, R, Q>, kWave * Q, lds);
+  static const int g_if = persistent_grid(k_batch_iface<r, CB, Acc>, kWave * kIfaceWaves, 0);
+  static const int g_exp =
+      persistent_grid(k_batch_expand<r, CB, KIND, Acc, R, Q>, kWave * Q, lds);
   if (g_red <= 0 || g_if <= 0 || g_exp <= 0) return hipErrorInvalidConfiguration;
   if (totals[0] + totals[1] + totals[2] == 0) return hipSuccess;
   if (totals[0] > 0)
-    hipLaunchKernelGGL((k_batch_reduce<r, KIND, Acc, R, Q>), dim3(std::min(g_red, totals[0])),
+    hipLaunchKernelGGL((k_batch_reduce<r, CB, KIND, Acc, R, Q>), dim3(std::min(g_red, totals[0])),
                        dim3(kWave * Q), lds, s, tab, pre_r, B, q, dir, buf);
   if (totals[1] > 0)
-    hipLaunchKernelGGL((k_batch_iface<r, Acc>),
+    hipLaunchKernelGGL((k_batch_iface<r, CB, Acc>),
                        dim3(std::min(g_if, (totals[1] + kIfaceWaves - 1) / kIfaceWaves)),
                        dim3(kWave * kIfaceWaves), 0, s, tab, pre_i, B, dir, buf);
   if (totals[2] > 0)
-    hipLaunchKernelGGL((k_batch_expand<r, KIND, Acc, R, Q>), dim3(std::min(g_exp, totals[2])),
+    hipLaunchKernelGGL((k_batch_expand<r, CB, KIND, Acc, R, Q>), dim3(std::min(g_exp, totals[2])),
                        dim3(kWave * Q), lds, s, tab, pre_e, B, q, dir, (const Acc*)buf);
   return hipGetLastError();
 }
@@ -221,11 +223,11 @@ hipError_t batch_variant_impl(int v, int r, const BatchDesc* tab, const int* pre
       constexpr BatchVariant bv = batch_variant(V, fp64);
       using Acc = typename std::conditional<fp64 != 0, double, float>::type;
       if (r == 1)
-        return batch_pass_impl<1, KIND, Acc, bv.R1, bv.Q>(tab, pre_r, pre_i, pre_e, totals, B, q,
-                                                          dir, iface, s);
+        return batch_pass_impl<1, 1, KIND, Acc, bv.R1, bv.Q>(tab, pre_r, pre_i, pre_e, totals, B,
+                                                             q, dir, iface, s);
       if (r == 2)
-        return batch_pass_impl<2, KIND, Acc, bv.R2, bv.Q>(tab, pre_r, pre_i, pre_e, totals, B, q,
-                                                          dir, iface, s);
+        return batch_pass_impl<2, 1, KIND, Acc, bv.R2, bv.Q>(tab, pre_r, pre_i, pre_e, totals, B,
+                                                             q, dir, iface, s);
       return hipErrorInvalidValue;
     }
     return batch_variant_impl<KIND, fp64, V + 1>(v, r, tab, pre_r, pre_i, pre_e, totals, B, q,
@@ -235,12 +237,36 @@ hipError_t batch_variant_impl(int v, int r, const BatchDesc* tab, const int* pre
   }
 }
 
+// Three-channel blocks: the chunk shape of the single-image path's first
+// (direct) variant for three channels.
+template <int KIND, int fp64>
+hipError_t batch_cb3_impl(int r, const BatchDesc* tab, const int* pre_r, const int* pre_i,
+                          const int* pre_e, const int totals[3], int B, int q, int dir,
+                          void* iface, hipStream_t s) {
+  using Acc = typename std::conditional<fp64 != 0, double, float>::type;
+  constexpr VariantSet v1 = variants_of(1, 3, fp64), v2 = variants_of(2, 3, fp64);
+  if (r == 1)
+    return batch_pass_impl<1, 3, KIND, Acc, v1.v[0].R, v1.v[0].Q>(tab, pre_r, pre_i, pre_e,
+                                                                  totals, B, q, dir, iface, s);
+  if (r == 2)
+    return batch_pass_impl<2, 3, KIND, Acc, v2.v[0].R, v2.v[0].Q>(tab, pre_r, pre_i, pre_e,
+                                                                  totals, B, q, dir, iface, s);
+  return hipErrorInvalidValue;
+}
+
 }  // namespace
 
-hipError_t launch_batch_pass(int variant, int fp64, int kind, int r, const BatchDesc* tab,
+hipError_t launch_batch_pass(int variant, int fp64, int kind, int r, int cb, const BatchDesc* tab,
                              const int* pre_r, const int* pre_i, const int* pre_e,
                              const int totals[3], int B, int q, int dir, void* iface,
                              hipStream_t s) {
+  if (cb == 3) {
+    if (kind == 0)
+      return fp64 ? batch_cb3_impl<0, 1>(r, tab, pre_r, pre_i, pre_e, totals, B, q, dir, iface, s)
+                  : batch_cb3_impl<0, 0>(r, tab, pre_r, pre_i, pre_e, totals, B, q, dir, iface, s);
+    return fp64 ? batch_cb3_impl<1, 1>(r, tab, pre_r, pre_i, pre_e, totals, B, q, dir, iface, s)
+                : batch_cb3_impl<1, 0>(r, tab, pre_r, pre_i, pre_e, totals, B, q, dir, iface, s);
+  }
   if (kind == 0)
     return fp64 ? batch_variant_impl<0, 1, 0>(variant, r, tab, pre_r, pre_i, pre_e, totals, B, q,
                                               dir, iface, s)

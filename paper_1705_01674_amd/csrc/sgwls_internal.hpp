@@ -329,12 +329,13 @@ struct BatchDesc {
   long long sum_ch, us_ch;       // per-channel strides of those buffers
 };
 
-// Stages of one batched pass over the images of radius r (tab: their
+// Stages of one batched pass over the images of radius r filtered in blocks
+// of cb channels (1, or 3 with the three-channel chunk shape; tab: their
 // table entries, B of them); prefix = the (B+1) unit prefix sums of the
 // stage's direction.
 // With all totals 0 it launches nothing and only prepares the persistent
 // grid sizes of the variant (a device query, not a stream operation).
-hipError_t launch_batch_pass(int variant, int fp64, int kind, int r, const BatchDesc* tab,
+hipError_t launch_batch_pass(int variant, int fp64, int kind, int r, int cb, const BatchDesc* tab,
                              const int* prefix_reduce, const int* prefix_iface,
                              const int* prefix_expand, const int totals[3], int B, int q,
                              int dir, void* iface, hipStream_t stream);

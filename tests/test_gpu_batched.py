@@ -218,3 +218,22 @@ def test_batch_mixing_radii_strides_and_long_sides(ops):
             ops.sgwls_filter_batched(fs, gs, ps, stream=stream, outs=outs)
         stream.synchronize()
         check_all(f"mixed batch on a side stream, call {rep}", [o.cpu().numpy() for o in outs], refs)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64_pivot"])
+def test_three_channel_blocks_share_weights(ops, prec):
+    # images with 3 or 6 channels run in three-channel blocks (one weight
+    # computation per block), beside 1- and 4-channel images run channel by
+    # channel, and a 3-channel image too tall for the three-channel chunk
+    # height in the persistent kernels, all against the oracle
+    rng = np.random.default_rng(91)
+    specs = [((3, 130, 170), 1), ((6, 90, 120), 2), ((1, 140, 100), 1), ((4, 70, 150), 2),
+             ((3, 96, 300), 2), ((3, 2100, 40), 2)]
+    items = []
+    for (C, M, N), r in specs:
+        f = rng.uniform(0, 1, (C, M, N)).astype(np.float32)
+        g = (f.mean(axis=0) + 0.02 * rng.standard_normal((M, N))).astype(np.float32)
+        pd = dict(lam=float(2.0 ** rng.uniform(-1, 4)), r=r, iters=2, stride=1, kind="exp",
+                  sigma_s=float(r), sigma_r=0.15, alpha_s=1.2, alpha_r=1.2, eps=1e-4)
+        items.append((f, g, pd))
+    check_all(f"three-channel blocks {prec}", run_batch(ops, items, prec=prec), oracle_outs(items))
