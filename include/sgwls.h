@@ -142,9 +142,12 @@ sgwls_status sgwls_validate(int C, int M, int N, const sgwls_params* p);
  * request is invalid.  save_for_backward (0 or 1) says whether the filter
  * call will pass `saved`: it decides the precision an SGWLS_P_AUTO call
  * resolves to (the saved pass inputs themselves live in the caller's
- * `saved` buffer).  For
- * SGWLS_P_FP32_DELTA it is sgwls_filter's workspace in that mode (one image
- * plus the eliminated strips of four channels).  Makes no HIP call. */
+ * `saved` buffer).  The filter's workspace starts with a synchronisation
+ * area (the fused passes' error word and counters, see SGWLS_ONE_LAUNCH
+ * below), then one intermediate image, the transposed guidance and the
+ * interface buffers.  For SGWLS_P_FP32_DELTA it is sgwls_filter's workspace
+ * in that mode (the synchronisation area, one image plus the eliminated
+ * strips of four channels).  Makes no HIP call. */
 size_t sgwls_workspace_bytes(int C, int M, int N, const sgwls_params* p, int save_for_backward);
 
 /* The precision a call with parameters p runs in: p->prec itself unless it
