@@ -13,9 +13,11 @@ Prints ONE JSON line:
              duration (HIP events around launches of that kernel alone), vs
              the 8 TB/s HBM peak
   cpu_baseline  the FP64 oracle on the host cores, same workload
-  fwd_bwd    one forward call that saves the pass inputs plus the backward call
-             (gradients for f, g and lambda) for a fixed output gradient, as
-             MPixel/s and algorithmic bytes / time vs 8 TB/s
+  fwd_bwd    one forward call that saves the pass inputs (and every pass's
+             separator solutions) plus the backward call (gradients for f, g
+             and lambda) for a fixed output gradient, as MPixel/s and
+             algorithmic bytes / time vs 8 TB/s; also the same pair without
+             saved separators
   fp64_pivot the same forward call with float64 pivots and recurrences
   fp32_delta the same forward call in the cancellation-free float32 mode
              (one serial solve per strip, pivots carried as their excess)
@@ -560,6 +562,9 @@ def main():
     saved = torch.empty((2 * p.iters, C, M, N), dtype=torch.float32, device=dev)
     ws_b = torch.empty(ops.backward_workspace_bytes(C, M, N, p), dtype=torch.uint8, device=dev)
     ws_s = torch.empty(ops.workspace_bytes(C, M, N, p, True), dtype=torch.uint8, device=dev)
+    # the forward also keeps every pass's separator solutions, so that each
+    # backward pass solves only the adjoint's separator systems
+    seps = torch.empty(ops.separator_bytes_nchw(1, C, M, N, p), dtype=torch.uint8, device=dev)
     ops.sgwls_filter(f, g, p, saved=saved, out=u, workspace=ws_s)
     tgt = torch.from_numpy(synth.image(M, N, C, 200, 0.0, 1000, sinus=True)).to(dev)
     ubar = (2.0 / u.numel()) * (u - tgt)
@@ -568,6 +573,11 @@ def main():
     grad_l = torch.empty(1, dtype=torch.float64, device=dev)
 
     def step_fb():
+        ops.sgwls_filter(f, g, p, saved=saved, out=u, workspace=ws_s, seps=seps)
+        ops.sgwls_backward(g, saved, ubar, p, grad_f=grad_f, grad_g=grad_g, grad_lambda=grad_l,
+                           workspace=ws_b, seps=seps)
+
+    def step_fb_plain():
         ops.sgwls_filter(f, g, p, saved=saved, out=u, workspace=ws_s)
         ops.sgwls_backward(g, saved, ubar, p, grad_f=grad_f, grad_g=grad_g, grad_lambda=grad_l,
                            workspace=ws_b)
@@ -579,6 +589,9 @@ def main():
         step_fb()
     torch.cuda.synchronize()
     ms_fb = time_events(torch, step_fb, args.steps)
+    for _ in range(args.warmup):
+        step_fb_plain()
+    ms_fb_plain = time_events(torch, step_fb_plain, args.steps)
     fb_bytes = ((8 * C + 4) + (12 * C + 8)) * M * N * 2 * p.iters
     step_fb()
     torch.cuda.synchronize()
@@ -592,11 +605,12 @@ def main():
     grad_f32, grad_g32 = torch.empty_like(f), torch.empty_like(g)
     grad_l32 = torch.empty(1, dtype=torch.float64, device=dev)
     u32 = torch.empty_like(f)
+    seps32 = torch.empty(ops.separator_bytes_nchw(1, C, M, N, p32), dtype=torch.uint8, device=dev)
 
     def step_fb32():
-        ops.sgwls_filter(f, g, p32, saved=saved, out=u32, workspace=ws_s32)
+        ops.sgwls_filter(f, g, p32, saved=saved, out=u32, workspace=ws_s32, seps=seps32)
         ops.sgwls_backward(g, saved, ubar, p32, grad_f=grad_f32, grad_g=grad_g32,
-                           grad_lambda=grad_l32, workspace=ws_b32)
+                           grad_lambda=grad_l32, workspace=ws_b32, seps=seps32)
 
     for _ in range(args.warmup):
         step_fb32()
@@ -731,6 +745,10 @@ def main():
                     "alg_bytes": fb_bytes,
                     "alg_GBps": round(fb_bytes / (ms_fb * 1e-3) / 1e9, 1),
                     "hbm_frac": round(fb_bytes / (ms_fb * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "saved_separators": True,
+                    "without_saved_separators": {
+                        "ms_per_step": round(ms_fb_plain, 5),
+                        "value": round(M * N / (ms_fb_plain * 1e-3) / 1e6, 2)},
                     "max_rel_err_vs_oracle": grad_err},
         "fwd_bwd_fp32": {"value": round(M * N / (ms_fb32 * 1e-3) / 1e6, 2),
                          "ms_per_step": round(ms_fb32, 5),

@@ -27,7 +27,8 @@ EXPORTS = ["sgwls_status_str", "sgwls_version", "sgwls_validate", "sgwls_workspa
            "sgwls_wls2d_workspace_bytes", "sgwls_wls2d", "sgwls_resolve_precision",
            "sgwls_filter_noalloc", "sgwls_filter_status", "sgwls_workspace_bytes_nchw",
            "sgwls_filter_nchw",
-           "sgwls_backward_workspace_bytes_nchw", "sgwls_backward_nchw"]
+           "sgwls_backward_workspace_bytes_nchw", "sgwls_backward_nchw",
+           "sgwls_separator_bytes_nchw", "sgwls_filter_nchw_seps", "sgwls_backward_nchw_seps"]
 
 
 class SgwlsParams(ctypes.Structure):
@@ -72,6 +73,13 @@ def _load():
     lib.sgwls_backward_workspace_bytes_nchw.argtypes = [i, i, i, i, P]
     lib.sgwls_backward_nchw.restype = i
     lib.sgwls_backward_nchw.argtypes = [vp, vp, vp, vp, vp, vp, i, i, i, i, P, vp, vp, sz, vp]
+    lib.sgwls_separator_bytes_nchw.restype = sz
+    lib.sgwls_separator_bytes_nchw.argtypes = [i, i, i, i, P]
+    lib.sgwls_filter_nchw_seps.restype = i
+    lib.sgwls_filter_nchw_seps.argtypes = [vp, vp, vp, i, i, i, i, P, vp, vp, vp, sz, vp, sz, vp]
+    lib.sgwls_backward_nchw_seps.restype = i
+    lib.sgwls_backward_nchw_seps.argtypes = [vp, vp, vp, sz, vp, vp, vp, vp, i, i, i, i, P, vp, vp,
+                                             sz, vp]
     lib.sgwls_filter_noalloc.restype = i
     lib.sgwls_filter_noalloc.argtypes = [vp, vp, vp, i, i, i, P, vp, vp, vp]
     lib.sgwls_filter_status.restype = i

@@ -170,11 +170,61 @@ unsigned int one_launch_spin_limit() {
 // left by an earlier, unrelated runtime call of the thread: clear it first.
 void clear_hip_error() { (void)hipGetLastError(); }
 
+// ---------------------------------------------------------------------------
+// Saved separators.  A forward pass cut into the backward's chunks (variant 0
+// of the backward table) solves, at the chunk separators, exactly the values
+// the backward's recomputation of that pass needs; a filter call that keeps
+// them lets every backward pass eliminate and solve only the adjoint system
+// (one right-hand side per channel instead of two).  Buffer layout per image:
+// pass q in order, then its channel blocks in order, each block the
+// separator solutions of a forward interface buffer (r x cb values per
+// separator, strip after strip) rounded up to 256 bytes.
+
+// The forward variant whose chunks are the backward's, -1 when none is.
+int seps_variant(int r, int cb, int fp64) {
+  if (fp64 != 0 && fp64 != 1) return -1;
+  const VariantSet fw = variants_of(r, cb, fp64), bw = bwd_variants_of(r, cb, fp64);
+  if (!bw.v[0].D) return -1;
+  for (int v = 0; v < fw.n; ++v)
+    if (fw.v[v].D && fw.v[v].R == bw.v[0].R) return v;
+  return -1;
+}
+
+// Pass q of a stride-1 filter call runs as a column pass of an L x W frame:
+// the image for even q, its transpose for odd q.
+size_t seps_pass_bytes(int q, int C, int M, int N, const sgwls_params& p) {
+  const int L = q % 2 == 0 ? M : N, W = q % 2 == 0 ? N : M;
+  size_t b = 0;
+  for (int c0 = 0; c0 < C;) {
+    const int cb = channel_block(C - c0);
+    const PassPlan pl = make_plan(L, W, p.r, cb, 1, p.prec, seps_variant(p.r, cb, p.prec));
+    b += align_up(pl.u_elems * pl.acc_bytes);
+    c0 += cb;
+  }
+  return b;
+}
+
+// Per-image bytes of the separator buffer, 0 when the case has no saved-
+// separator path (p resolved, validated).
+size_t seps_image_bytes(int C, int M, int N, const sgwls_params& p) {
+  if (p.stride != 1 || (p.prec != SGWLS_P_FP32 && p.prec != SGWLS_P_FP64_PIVOT)) return 0;
+  if (!frames_supported(C, p.r, 1, p.prec)) return 0;
+  for (int c0 = 0; c0 < C;) {
+    const int cb = channel_block(C - c0);
+    if (seps_variant(p.r, cb, p.prec) < 0) return 0;
+    c0 += cb;
+  }
+  size_t b = 0;
+  for (int q = 0; q < 2 * p.iters; ++q) b += seps_pass_bytes(q, C, M, N, p);
+  return b;
+}
+
 // variant < 0: the tuned variant of the case (variant 0 when none is tuned).
 sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* y, int C, int M,
                           int N, const sgwls_params& p, const float* lam_dev, void* iface,
                           hipStream_t stream, int stages = kStageAll, int variant = -1,
-                          const Batch* bt = nullptr, OneCtl* one = nullptr) {
+                          const Batch* bt = nullptr, OneCtl* one = nullptr,
+                          char* useps = nullptr, long long zseps = 0) {
   const int L = direction == 0 ? M : N, W = direction == 0 ? N : M;
   const WeightParams wp = weight_params(p);
   const int out_t = (stages & kStageTransposeOut) ? 1 : 0;
@@ -185,11 +235,18 @@ sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* 
                                          direction + (p.stride != 1 ? kStridedDir : 0), L, W);
     if (out_t && p.stride == 1 && !variants_of(p.r, cb, p.prec).v[v].D)
       v = 0;   // variant 0 reads directly
+    if (useps) v = seps_variant(p.r, cb, p.prec);   // the backward's chunks
     PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, v);
-    pl.one = one;
+    pl.one = useps ? nullptr : one;
     PassGeom geo = pass_geom(direction, M, N, pl, p.stride);
     geo.out_t = out_t;
     if (bt) set_batch(geo, *bt);
+    if (useps) {
+      // the separator solutions go to the caller's buffer (kept for the backward)
+      pl.us_out = useps;
+      geo.zu = zseps;
+      useps += align_up(pl.u_elems * pl.acc_bytes);
+    }
     stages &= kStageAll;
     hipError_t e = launch_pass(p.r, cb, p.prec, x, g, y, c0, geo, pl, wp, lam_dev, p.lambda,
                                iface, stream, stages);
@@ -216,6 +273,9 @@ BwdLayout bwd_layout(int C, int M, int N, const sgwls_params& p, int B = 1) {
     for (int c0 = 0; c0 < C;) {
       const int cb = channel_block(C - c0);
       iface = std::max(iface, interface_bytes_max(L, W, p.r, cb, p.stride, p.prec, kModeBackward));
+      if (p.stride == 1)   // the adjoint's own buffers (saved separators)
+        iface = std::max(iface, interface_bytes(make_plan(L, W, p.r, cb, 1, p.prec, 0,
+                                                          kModeAdjoint)));
       const VariantSet vs = variants_for(kModeBackward, p.r, cb, p.prec);
       for (int v = 0; v < (p.stride == 1 ? vs.n : 1); ++v) {
         const PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, v, kModeBackward);
@@ -250,7 +310,8 @@ sgwls_status enqueue_pass_backward(int direction, const float* x, const float* g
                                    const sgwls_params& p, const float* lam_dev, void* ws,
                                    const BwdLayout& lay, hipStream_t stream, bool& first,
                                    bool* gfirst = nullptr, int out_t = 0,
-                                   const Batch* bt = nullptr) {
+                                   const Batch* bt = nullptr, const char* useps = nullptr,
+                                   long long zseps = 0) {
   const int L = direction == 0 ? M : N, W = direction == 0 ? N : M;
   const WeightParams wp = weight_params(p);
   char* base = reinterpret_cast<char*>(ws);
@@ -261,7 +322,7 @@ sgwls_status enqueue_pass_backward(int direction, const float* x, const float* g
   bw.lpart = grad_lambda ? reinterpret_cast<double*>(base + lay.lpart_off) : nullptr;
   for (int c0 = 0; c0 < C;) {
     const int cb = channel_block(C - c0);
-    const PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, 0, kModeBackward);
+    PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, 0, kModeBackward);
     PassGeom geo = pass_geom(direction, M, N, pl, p.stride);
     geo.out_t = out_t;
     if (bt) {
@@ -275,8 +336,34 @@ sgwls_status enqueue_pass_backward(int direction, const float* x, const float* g
     }
     bool& gf = gfirst ? *gfirst : first;   // first write of this guidance-gradient buffer
     bw.gacc = gf ? 0 : 1;
+    char* iface = base + lay.iface_off;
+    int stages = kStageAll;
+    if (useps) {
+      // The pass solution's separators come from the forward: chunk
+      // elimination and separator systems of the adjoint alone (output
+      // gradient over the cover counts, one right-hand side per channel),
+      // then the re-solve of both with the adjoint's separators after its
+      // summaries in the interface buffer.
+      const PassPlan pa = make_plan(L, W, p.r, cb, p.stride, p.prec, 0, kModeAdjoint);
+      if (interface_bytes(pa) > lay.iface_img) return SGWLS_E_WORKSPACE;
+      PassGeom ga = pass_geom(direction, M, N, pa, p.stride);
+      if (bt) {
+        Batch b = *bt;
+        b.x = bt->x2;
+        b.iface = (long long)lay.iface_img;
+        set_batch(ga, b);
+      }
+      hipError_t e = launch_pass(p.r, cb, p.prec, ybar, g, nullptr, c0, ga, pa, wp, lam_dev,
+                                 p.lambda, iface, stream, kStageReduce | kStageInterface, nullptr);
+      if (e != hipSuccess) return SGWLS_E_HIP;
+      pl.us_out = iface + pa.sum_elems * pa.acc_bytes;
+      bw.useps = useps;
+      bw.zseps = zseps;
+      useps += align_up(pa.u_elems * pa.acc_bytes);
+      stages = kStageExpand;
+    }
     hipError_t e = launch_pass(p.r, cb, p.prec, x, g, xbar, c0, geo, pl, wp, lam_dev, p.lambda,
-                               base + lay.iface_off, stream, kStageAll, &bw);
+                               iface, stream, stages, &bw);
     if (e != hipSuccess) return SGWLS_E_HIP;
     e = launch_bwd_fixup(bw.side, gbar, geo, bw.lpart, expand_blocks(geo, pl), grad_lambda,
                          first ? 0 : 1, stream);
@@ -829,9 +916,12 @@ sgwls_status sgwls_filter_status(void* ws, void* stream) {
   return SGWLS_E_HIP;
 }
 
-sgwls_status sgwls_filter_nchw(const float* f, const float* g, float* u, int B, int C, int M,
-                               int N, const sgwls_params* p, const float* lambda_dev,
-                               float* saved, void* ws, size_t ws_bytes, void* stream) {
+// sgwls_filter_nchw, with the separator solutions of every pass written to
+// seps (B images, per-image layout of seps_image_bytes) when it is non-NULL.
+static sgwls_status filter_nchw_core(const float* f, const float* g, float* u, int B, int C,
+                                     int M, int N, const sgwls_params* p,
+                                     const float* lambda_dev, float* saved, char* seps,
+                                     void* ws, size_t ws_bytes, void* stream) {
   sgwls_status st = sgwls_validate(C, M, N, p);
   if (st != SGWLS_OK) return st;
   if (B < 1) return SGWLS_E_SHAPE;
@@ -923,7 +1013,8 @@ sgwls_status sgwls_filter_nchw(const float* f, const float* g, float* u, int B, 
     OneCtl one{};
     OneCtl* onep = nullptr;
     int nzero = 0;
-    const int fuse = one_launch_mode();
+    const int fuse = seps ? 0 : one_launch_mode();
+    const long long zseps = seps ? (long long)seps_image_bytes(C, M, N, *p) : 0;
     if (fuse && p->stride == 1) {
       one.full = fuse == 1;
       one.err = sync;
@@ -938,17 +1029,21 @@ sgwls_status sgwls_filter_nchw(const float* f, const float* g, float* u, int B, 
     if (launch_transpose(g, gT, M, N, s, B, 0, onep ? sync : nullptr, nzero) != hipSuccess)
       return SGWLS_E_HIP;
     const float* x = saved ? saved : f;
+    size_t soff = 0;
     for (int q = 0; q < passes; ++q) {
       const bool even = q % 2 == 0;
       float* y = q == passes - 1 ? u : saved ? saved + (size_t)(q + 1) * plane : even ? tmp : u;
       const Batch bt = batch(x, y);
       st = enqueue_pass(0, x, even ? g : gT, y, C, even ? M : N, even ? N : M, *p, lambda_dev,
-                        iface, s, kStageAll | kStageTransposeOut, -1, &bt, onep);
+                        iface, s, kStageAll | kStageTransposeOut, -1, &bt, onep,
+                        seps ? seps + soff : nullptr, zseps);
       if (st != SGWLS_OK) return st;
+      if (seps) soff += seps_pass_bytes(q, C, M, N, *p);
       x = y;
     }
     return SGWLS_OK;
   }
+  if (seps) return SGWLS_E_UNSUPPORTED;
   // Pass q reads x_q and writes x_{q+1}; x_0 = f and x_{2T} = u.  With saved,
   // x_q lives in saved[q] (q < 2T); otherwise passes ping-pong between tmp
   // and u so that the last one lands in u.
@@ -964,6 +1059,33 @@ sgwls_status sgwls_filter_nchw(const float* f, const float* g, float* u, int B, 
     x = y;
   }
   return SGWLS_OK;
+}
+
+sgwls_status sgwls_filter_nchw(const float* f, const float* g, float* u, int B, int C, int M,
+                               int N, const sgwls_params* p, const float* lambda_dev,
+                               float* saved, void* ws, size_t ws_bytes, void* stream) {
+  return filter_nchw_core(f, g, u, B, C, M, N, p, lambda_dev, saved, nullptr, ws, ws_bytes,
+                          stream);
+}
+
+size_t sgwls_separator_bytes_nchw(int B, int C, int M, int N, const sgwls_params* p) {
+  if (B < 1 || validate_partitioned(C, M, N, p) != SGWLS_OK) return 0;
+  return (size_t)B * seps_image_bytes(C, M, N, resolved(*p, 1));
+}
+
+sgwls_status sgwls_filter_nchw_seps(const float* f, const float* g, float* u, int B, int C,
+                                    int M, int N, const sgwls_params* p,
+                                    const float* lambda_dev, float* saved, void* seps,
+                                    size_t seps_bytes, void* ws, size_t ws_bytes, void* stream) {
+  sgwls_status st = validate_partitioned(C, M, N, p);
+  if (st != SGWLS_OK) return st;
+  if (B < 1) return SGWLS_E_SHAPE;
+  if (!saved || !seps) return SGWLS_E_ARG;
+  const size_t need = seps_image_bytes(C, M, N, resolved(*p, 1));
+  if (need == 0) return SGWLS_E_UNSUPPORTED;
+  if (seps_bytes < (size_t)B * need) return SGWLS_E_WORKSPACE;
+  return filter_nchw_core(f, g, u, B, C, M, N, p, lambda_dev, saved,
+                          reinterpret_cast<char*>(seps), ws, ws_bytes, stream);
 }
 
 int sgwls_variant_count(int r, int channel_block, int prec) {
@@ -1189,14 +1311,18 @@ sgwls_status sgwls_backward(const float* g, const float* saved, const float* gra
                              lambda_dev, ws, ws_bytes, stream);
 }
 
-sgwls_status sgwls_backward_nchw(const float* g, const float* saved, const float* grad_u,
-                                 float* grad_f, float* grad_g, double* grad_lambda, int B, int C,
-                                 int M, int N, const sgwls_params* p, const float* lambda_dev,
-                                 void* ws, size_t ws_bytes, void* stream) {
+// sgwls_backward_nchw; with seps (written by sgwls_filter_nchw_seps) the
+// passes take the pass solutions' separators from it and run in the
+// precision that call ran in.
+static sgwls_status backward_nchw_core(const float* g, const float* saved, const char* seps,
+                                       const float* grad_u, float* grad_f, float* grad_g,
+                                       double* grad_lambda, int B, int C, int M, int N,
+                                       const sgwls_params* p, const float* lambda_dev, void* ws,
+                                       size_t ws_bytes, void* stream) {
   sgwls_status st = validate_partitioned(C, M, N, p);
   if (st != SGWLS_OK) return st;
   if (B < 1) return SGWLS_E_SHAPE;
-  const sgwls_params pr = resolved(*p, grad_lambda != nullptr);
+  const sgwls_params pr = resolved(*p, seps ? 1 : grad_lambda != nullptr);
   p = &pr;
   if (!g || !saved || !grad_u || !grad_f || (const float*)grad_f == g ||
       (const float*)grad_f == saved)
@@ -1239,19 +1365,25 @@ sgwls_status sgwls_backward_nchw(const float* g, const float* saved, const float
       return SGWLS_E_HIP;
     const float* ybar = yT;
     bool gfirst[2] = {true, true};
+    const long long zseps = seps ? (long long)seps_image_bytes(C, M, N, *p) : 0;
+    size_t soff = 0;
+    for (int q = 0; seps && q < passes - 1; ++q) soff += seps_pass_bytes(q, C, M, N, *p);
     for (int q = passes - 1; q >= 0; --q) {
       const bool odd = q % 2 == 1;
       float* xbar = (q % 2 == 0) ? grad_f : tmp;
       st = enqueue_pass_backward(0, saved + (size_t)q * plane, odd ? gT : g, ybar, xbar,
                                  grad_g ? (odd ? gTacc : grad_g) : nullptr, grad_lambda, C,
                                  odd ? N : M, odd ? M : N, *p, lambda_dev, ws, lay, s, first,
-                                 &gfirst[odd ? 1 : 0], q > 0 ? 1 : 0, &bt);
+                                 &gfirst[odd ? 1 : 0], q > 0 ? 1 : 0, &bt,
+                                 seps ? seps + soff : nullptr, zseps);
       if (st != SGWLS_OK) return st;
+      if (seps && q > 0) soff -= seps_pass_bytes(q - 1, C, M, N, *p);
       ybar = xbar;
     }
     if (grad_g && launch_transpose(gTacc, grad_g, N, M, s, B, 1) != hipSuccess) return SGWLS_E_HIP;
     return SGWLS_OK;
   }
+  if (seps) return SGWLS_E_UNSUPPORTED;
   const float* ybar = grad_u;
   for (int q = passes - 1; q >= 0; --q) {
     float* xbar = (q % 2 == 0) ? grad_f : tmp;
@@ -1265,6 +1397,31 @@ sgwls_status sgwls_backward_nchw(const float* g, const float* saved, const float
 }
 
 // The persistent-kernel part of a batch (every image eligible).
+sgwls_status sgwls_backward_nchw(const float* g, const float* saved, const float* grad_u,
+                                 float* grad_f, float* grad_g, double* grad_lambda, int B, int C,
+                                 int M, int N, const sgwls_params* p, const float* lambda_dev,
+                                 void* ws, size_t ws_bytes, void* stream) {
+  return backward_nchw_core(g, saved, nullptr, grad_u, grad_f, grad_g, grad_lambda, B, C, M, N,
+                            p, lambda_dev, ws, ws_bytes, stream);
+}
+
+sgwls_status sgwls_backward_nchw_seps(const float* g, const float* saved, const void* seps,
+                                      size_t seps_bytes, const float* grad_u, float* grad_f,
+                                      float* grad_g, double* grad_lambda, int B, int C, int M,
+                                      int N, const sgwls_params* p, const float* lambda_dev,
+                                      void* ws, size_t ws_bytes, void* stream) {
+  sgwls_status st = validate_partitioned(C, M, N, p);
+  if (st != SGWLS_OK) return st;
+  if (B < 1) return SGWLS_E_SHAPE;
+  if (!seps) return SGWLS_E_ARG;
+  const size_t need = seps_image_bytes(C, M, N, resolved(*p, 1));
+  if (need == 0) return SGWLS_E_UNSUPPORTED;
+  if (seps_bytes < (size_t)B * need) return SGWLS_E_WORKSPACE;
+  return backward_nchw_core(g, saved, reinterpret_cast<const char*>(seps), grad_u, grad_f,
+                            grad_g, grad_lambda, B, C, M, N, p, lambda_dev, ws, ws_bytes,
+                            stream);
+}
+
 static size_t batched_core_bytes(const sgwls_image* imgs, const sgwls_params* p, int B) {
   if (!imgs || !p || B < 1) return 0;
   BatchPlan probe;

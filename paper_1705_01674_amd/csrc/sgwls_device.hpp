@@ -679,10 +679,11 @@ DEV void reduce_tile(const PassGeom& geo, const WeightParams& wp, float lam, int
     float lw[E + r][r];
     chunk_weights<r, KIND>(cv, wp, lamS, lw);
     float ic[2 * r + 1];
-    if constexpr (MODE == kModeBackward) inv_counts<r, S1>(k, geo, ic);
+    if constexpr (MODE != kModeForward) inv_counts<r, S1>(k, geo, ic);
     auto fval = [&](int m, int c) -> Acc {   // 0 outside the subsystem
       const float v = DIRECT ? fpre[DIRECT ? m : 0][c] : cv.f(m, c);
-      if (MODE == kModeBackward && c >= CB) return Acc(v * ic[col_of<r>(m) + r]);
+      if ((MODE == kModeBackward && c >= CB) || MODE == kModeAdjoint)
+        return Acc(v * ic[col_of<r>(m) + r]);
       return Acc(v);
     };
 #pragma unroll
@@ -1260,9 +1261,9 @@ DEV void iface_pcr_strip(const Acc* __restrict__ sum, Acc* __restrict__ U, int P
 template <int r, int CB, int MM, typename Acc>
 __global__ __launch_bounds__(kWave) void k_interface_pcr(const Acc* __restrict__ sum,
                                                          Acc* __restrict__ U, int nK, int P,
-                                                         int m, long long zi) {
-  const int z = blockIdx.z;   // image of a batched launch (interface buffers zi bytes apart)
-  iface_pcr_strip<r, CB, MM, Acc>(zmove_bytes(sum, zi, z), zmove_bytes(U, zi, z), P, m, blockIdx.x);
+                                                         int m, long long zi, long long zu) {
+  const int z = blockIdx.z;   // image of a batched launch (summaries zi, solutions zu bytes apart)
+  iface_pcr_strip<r, CB, MM, Acc>(zmove_bytes(sum, zi, z), zmove_bytes(U, zu, z), P, m, blockIdx.x);
 }
 
 // Register solver on a workgroup of NL lanes per strip (cyclic reduction
@@ -1273,13 +1274,13 @@ constexpr int kMwMM = 4;
 template <int r, int CB, typename Acc, int NL>
 __global__ __launch_bounds__(NL) void k_interface_pcr_mw(const Acc* __restrict__ sum,
                                                          Acc* __restrict__ U, int P, int m,
-                                                         long long zi) {
+                                                         long long zi, long long zu) {
   using LY = IfaceLayout<r, CB>;
   extern __shared__ float smem[];
   const int z = blockIdx.z;
   const SepReader<r, CB, Acc> rd{zmove_bytes(sum, zi, z) + (size_t)blockIdx.x * P * LY::F, P};
   iface_pcr_run<r, CB, kMwMM, Acc, SepReader<r, CB, Acc>, false, NL>(
-      rd, zmove_bytes(U, zi, z), P, m, blockIdx.x, reinterpret_cast<Acc*>(smem));
+      rd, zmove_bytes(U, zu, z), P, m, blockIdx.x, reinterpret_cast<Acc*>(smem));
 }
 
 // Scratch values per separator block kept by iface_pcr_strip_long: the
@@ -1478,10 +1479,10 @@ template <int r, int CB, typename Acc, int NL>
 __global__ __launch_bounds__(NL) void k_interface_pcr_long(const Acc* __restrict__ sum,
                                                            Acc* __restrict__ U,
                                                            Acc* __restrict__ scr, int P, int m,
-                                                           long long zi) {
+                                                           long long zi, long long zu) {
   extern __shared__ float smem[];
   const int z = blockIdx.z;
-  iface_pcr_strip_long<r, CB, Acc, NL>(zmove_bytes(sum, zi, z), zmove_bytes(U, zi, z), P, m,
+  iface_pcr_strip_long<r, CB, Acc, NL>(zmove_bytes(sum, zi, z), zmove_bytes(U, zu, z), P, m,
                                        blockIdx.x, zmove_bytes(scr, zi, z),
                                        reinterpret_cast<Acc*>(smem));
 }
@@ -1614,14 +1615,37 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
   if (active) {
     // Separator values first: their loads are the head of the dependency chain.
     const int n_sep = geo.P - 1;
-    const Acc* us = Us + (size_t)ki * n_sep * r * NR;
+    bool split = false;
+    if constexpr (BWD) {
+      if (bw.useps) {
+        // the pass solution's separators saved by the forward, the adjoint's
+        // from this pass's own interface (r x CB each)
+        split = true;
+        const Acc* uf = reinterpret_cast<const Acc*>(bw.useps) + (size_t)ki * n_sep * r * CB;
+        const Acc* ua = Us + (size_t)ki * n_sep * r * CB;
 #pragma unroll
-    for (int a = 0; a < r; ++a)
+        for (int a = 0; a < r; ++a)
 #pragma unroll
-      for (int h = 0; h < NR; ++h) {
-        uT[a][h] = hasT ? ld_if<COH>(us + (size_t)(j - 1) * r * NR + a * NR + h) : Acc(0);
-        uB[a][h] = hasB ? ld_if<COH>(us + (size_t)j * r * NR + a * NR + h) : Acc(0);
+          for (int h = 0; h < CB; ++h) {
+            const size_t oT = (size_t)(j - 1) * r * CB + a * CB + h;
+            const size_t oB = (size_t)j * r * CB + a * CB + h;
+            uT[a][h] = hasT ? uf[oT] : Acc(0);
+            uB[a][h] = hasB ? uf[oB] : Acc(0);
+            uT[a][CB + h] = hasT ? ua[oT] : Acc(0);
+            uB[a][CB + h] = hasB ? ua[oB] : Acc(0);
+          }
       }
+    }
+    if (!split) {
+      const Acc* us = Us + (size_t)ki * n_sep * r * NR;
+#pragma unroll
+      for (int a = 0; a < r; ++a)
+#pragma unroll
+        for (int h = 0; h < NR; ++h) {
+          uT[a][h] = hasT ? ld_if<COH>(us + (size_t)(j - 1) * r * NR + a * NR + h) : Acc(0);
+          uB[a][h] = hasB ? ld_if<COH>(us + (size_t)j * r * NR + a * NR + h) : Acc(0);
+        }
+    }
     typename std::conditional<DIRECT, GlobalChunk<r, R, NR>, CV>::type cv;
     if constexpr (DIRECT) {
       cv.init(G, *src, geo, j * R, k);
@@ -2057,6 +2081,7 @@ DEV BwdArgs bwd_at(BwdArgs bw, const PassGeom& geo, int z) {
   bw.gbar = zmove(bw.gbar, geo.zgb, z);
   bw.side = zmove(bw.side, geo.zside, z);
   bw.lpart = zmove(bw.lpart, (long long)geo.zlpart, z);
+  bw.useps = zmove_bytes(bw.useps, bw.zseps, z);
   return bw;
 }
 
@@ -2073,7 +2098,7 @@ __global__ __launch_bounds__(kWave* Q) void k_expand_d(
   xcd_block(bx, by);
   expand_tile<r, CB, R, Q, S1, KIND, Acc, MODE, true>(
       zmove(G, geo.zg, z), zmove(Y, geo.zy, z), geo, wp, load_lambda(lam_dev, lam_host), c0,
-      zmove_bytes(Us, geo.zi, z), OW, pitch, bz, bx, by, gridDim.x, smem, &src);
+      zmove_bytes(Us, geo.zu, z), OW, pitch, bz, bx, by, gridDim.x, smem, &src);
 }
 
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE>
@@ -2085,7 +2110,7 @@ __global__ __launch_bounds__(kWave* Q) void k_expand(
   const int z = blockIdx.z;
   expand_block<r, CB, R, Q, S1, KIND, Acc, MODE>(
       zmove(X, geo.zx, z), zmove(G, geo.zg, z), zmove(Y, geo.zy, z), geo, wp,
-      load_lambda(lam_dev, lam_host), c0, zmove_bytes(Us, geo.zi, z), OW, pitch,
+      load_lambda(lam_dev, lam_host), c0, zmove_bytes(Us, geo.zu, z), OW, pitch,
       bwd_at(bw, geo, z), blockIdx.x, blockIdx.y, gridDim.x, smem);
 }
 
@@ -2149,7 +2174,7 @@ __global__ __launch_bounds__(kWave* Q) void k_pass_one(
   const float* Xz = zmove(X, geo.zx, z);
   const float* Gz = zmove(G, geo.zg, z);
   Acc* sumz = zmove_bytes(sum, geo.zi, z);
-  Acc* Usz = zmove_bytes(Us, geo.zi, z);
+  Acc* Usz = zmove_bytes(Us, geo.zu, z);
   const PlaneSrc<CB> src{Xz, nullptr, c0, (int)geo.plane};
   const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int nred = geo.P > 1 ? gx * gy : 0;
@@ -2211,8 +2236,8 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
   constexpr VariantSet VS = variants_for(MODE, r, CB, fp64);
   using LY = IfaceLayout<r, NR>;
   Acc* sum = reinterpret_cast<Acc*>(iface);
-  Acc* us = sum + pl.sum_elems;
-  Acc* gb = us + pl.u_elems;
+  Acc* us = pl.us_out ? reinterpret_cast<Acc*>(pl.us_out) : sum + pl.sum_elems;
+  Acc* gb = sum + pl.sum_elems + pl.u_elems;
   const size_t tile = sizeof(float) * (size_t)(NR + 1) * (Q * R + 2) * pl.pitch;
   const size_t stage_out = sizeof(Acc) * (size_t)kWave * Q * LY::F;
   const int gy = (geo.P + Q - 1) / Q;
@@ -2278,16 +2303,19 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
                            lam_host, c0, sum);
       }
     }
-    if (!direct)
+    if constexpr (MODE == kModeAdjoint) {
+      if (!direct) return hipErrorInvalidValue;   // direct stride-1 chunks only
+    } else if (!direct) {
       hipLaunchKernelGGL((k_reduce<r, CB, R, Q, S1, KIND, Acc, MODE>), dim3(gx, gy, nz),
                          dim3(kWave * Q), std::max(tile, stage_out), stream, x, bw.ybar, g, geo,
                          wp, lam_dev, lam_host, c0, pl.pitch, sum);
+    }
   }
   if (geo.P > 1 && (stages & kStageInterface)) {
     if (VS.MM > 0 && pl.iface_m > 0 && pl.iface_m <= VS.MM) {
       constexpr int MM = VS.MM > 0 ? VS.MM : 1;
       hipLaunchKernelGGL((k_interface_pcr<r, NR, MM, Acc>), dim3(geo.nK, 1, nz), dim3(kWave), 0,
-                         stream, (const Acc*)sum, us, geo.nK, geo.P, pl.iface_m, geo.zi);
+                         stream, (const Acc*)sum, us, geo.nK, geo.P, pl.iface_m, geo.zi, geo.zu);
     } else if (pl.mw_nl > 0) {
       if constexpr (r == 3 && fp64 == 0 && MODE == kModeForward) {
         const int nl = pl.mw_nl;
@@ -2295,10 +2323,10 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
         const size_t xs = sizeof(Acc) * (size_t)nl * kMwSlot<r, NR>;
         if (nl == 4 * kWave)
           hipLaunchKernelGGL((k_interface_pcr_mw<r, NR, Acc, 4 * kWave>), dim3(geo.nK, 1, nz),
-                             dim3(nl), xs, stream, (const Acc*)sum, us, geo.P, m, geo.zi);
+                             dim3(nl), xs, stream, (const Acc*)sum, us, geo.P, m, geo.zi, geo.zu);
         else
           hipLaunchKernelGGL((k_interface_pcr_mw<r, NR, Acc, 2 * kWave>), dim3(geo.nK, 1, nz),
-                             dim3(nl), xs, stream, (const Acc*)sum, us, geo.P, m, geo.zi);
+                             dim3(nl), xs, stream, (const Acc*)sum, us, geo.P, m, geo.zi, geo.zu);
       } else {
         return hipErrorInvalidValue;
       }
@@ -2310,15 +2338,16 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
       const size_t xs = nl > kWave ? sizeof(Acc) * (size_t)nl * kMwSlot<r, NR> : 0;
       if (nl == 4 * kWave)
         hipLaunchKernelGGL((k_interface_pcr_long<r, NR, Acc, 4 * kWave>), dim3(geo.nK, 1, nz),
-                           dim3(nl), xs, stream, (const Acc*)sum, us, gb, geo.P, m, geo.zi);
+                           dim3(nl), xs, stream, (const Acc*)sum, us, gb, geo.P, m, geo.zi, geo.zu);
       else if (nl == 2 * kWave)
         hipLaunchKernelGGL((k_interface_pcr_long<r, NR, Acc, 2 * kWave>), dim3(geo.nK, 1, nz),
-                           dim3(nl), xs, stream, (const Acc*)sum, us, gb, geo.P, m, geo.zi);
+                           dim3(nl), xs, stream, (const Acc*)sum, us, gb, geo.P, m, geo.zi, geo.zu);
       else
         hipLaunchKernelGGL((k_interface_pcr_long<r, NR, Acc, kWave>), dim3(geo.nK, 1, nz),
-                           dim3(kWave), 0, stream, (const Acc*)sum, us, gb, geo.P, m, geo.zi);
+                           dim3(kWave), 0, stream, (const Acc*)sum, us, gb, geo.P, m, geo.zi, geo.zu);
     }
   }
+  if constexpr (MODE != kModeAdjoint) {
   if (stages & kStageExpand) {
     const int ex = (geo.W + pl.OW - 1) / pl.OW;
     bool direct = false;
@@ -2341,6 +2370,7 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
                          dim3(kWave * Q), tile, stream, x, g, y, geo, wp, lam_dev, lam_host, c0,
                          (const Acc*)us, pl.OW, pl.pitch, bw);
     }
+  }
   }
   return hipGetLastError();
 }
@@ -2369,8 +2399,10 @@ hipError_t launch_kind(const float* x, const float* g, float* y, int c0, const P
                        const PassPlan& pl, const WeightParams& wp, const float* lam_dev,
                        float lam_host, void* iface, hipStream_t s, int st, const BwdArgs& bw) {
   constexpr VariantSet VS = variants_for(MODE, r, CB, fp64);
-  // Strided forward column passes read their chunks directly (no input tile).
-  if (geo.stride != 1) {
+  if constexpr (MODE == kModeAdjoint) {
+    if (geo.stride != 1) return hipErrorInvalidValue;   // stride-1 frames only
+  } else if (geo.stride != 1) {
+    // Strided forward column passes read their chunks directly (no input tile).
     if constexpr (MODE == kModeForward) {
       constexpr StridedVariant S1v = strided_variant(r, CB, fp64, 1);
       if (pl.variant == 1)
@@ -2424,6 +2456,9 @@ hipError_t launch_r(int cb, int fp64, const float* x, const float* g, float* y, 
     return launch_mode<r, kModeBackward>(cb, fp64, x, g, y, c0, geo, pl, wp, lam_dev, lam_host,
                                          iface, s, st, *bw);
   const BwdArgs none{};
+  if (pl.mode == kModeAdjoint)
+    return launch_mode<r, kModeAdjoint>(cb, fp64, x, g, y, c0, geo, pl, wp, lam_dev, lam_host,
+                                        iface, s, st, none);
   return launch_mode<r, kModeForward>(cb, fp64, x, g, y, c0, geo, pl, wp, lam_dev, lam_host,
                                       iface, s, st, none);
 }

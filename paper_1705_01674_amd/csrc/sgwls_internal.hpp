@@ -50,6 +50,8 @@ struct PassGeom {
   int nimg;
   long long zx, zx2, zy, zg, zgb, zside, zi;
   int zlpart;
+  long long zu;     // bytes between images of the separator solutions (zi unless
+                    // they are written to a buffer of their own)
 };
 
 // Image z of a batched launch: p moved by z * stride elements (or bytes).
@@ -78,6 +80,7 @@ DEV_HOST_INLINE void set_batch(PassGeom& geo, const Batch& b) {
   geo.zgb = b.gb;
   geo.zside = b.side;
   geo.zi = b.iface;
+  geo.zu = b.iface;
   geo.zlpart = b.lpart;
 }
 
@@ -98,6 +101,11 @@ struct VariantSet {
 // Kernels of a pass: the forward solve, or its adjoint (two right-hand sides
 // per channel: the recomputed pass solution and the adjoint solve).
 constexpr int kModeForward = 0, kModeBackward = 1;
+// The adjoint half of a backward pass on its own: chunk elimination and
+// separator systems of the output gradient divided by the cover counts (one
+// right-hand side per channel), in the backward's chunk shape; the backward
+// re-solve then takes the pass solution's separators from the forward.
+constexpr int kModeAdjoint = 2;
 
 // The expand kernel keeps (r + CB) values per chunk element in registers, so
 // R shrinks as r, the channel block and the precision grow.
@@ -140,7 +148,7 @@ constexpr VariantSet bwd_variants_of(int r, int cb, int fp64) {
 }
 
 constexpr VariantSet variants_for(int mode, int r, int cb, int fp64) {
-  return mode == kModeBackward ? bwd_variants_of(r, cb, fp64) : variants_of(r, cb, fp64);
+  return mode == kModeForward ? variants_of(r, cb, fp64) : bwd_variants_of(r, cb, fp64);
 }
 
 // Strided forward passes: variant 0 uses variant 0's R with one chunk (one
@@ -228,6 +236,7 @@ struct PassPlan {
   int mw_nl;                   // > 0: the register solver on mw_nl lanes per strip instead
   int acc_bytes;    // 4 (float) or 8 (double) interface element size
   OneCtl* one;      // set by the caller to allow the one-launch pass
+  void* us_out;     // non-NULL: separator solutions here instead of after the summaries
 };
 
 // Cancellation-free float32 mode at r = 1 (sgwls_delta.hip): one serial
@@ -270,6 +279,12 @@ struct BwdArgs {
                        // boundaries, for the pixels of the chunk above
   double* lpart;       // one partial lambda gradient per expand block (NULL: not wanted)
   int gacc;            // 1: add to gbar, 0: overwrite it
+  // Separators of the pass solution saved by the forward (layout of a forward
+  // interface buffer's solutions, r x CB per separator), or NULL: then the
+  // pass solves them itself (2 CB right-hand sides); with them the
+  // interface buffer holds the adjoint's separators only (r x CB).
+  const void* useps;
+  long long zseps;     // bytes between the images of an NCHW batch in useps
 };
 
 // Enqueue the stages in `stages` of one pass for channels [c0, c0+cb) of x

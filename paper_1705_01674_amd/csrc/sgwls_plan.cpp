@@ -50,6 +50,7 @@ PassPlan make_plan(int L, int W, int r, int cb, int stride, int fp64, int varian
   const int F = 2 * T2 + 2 * r * pl.nr + r * r;
   pl.acc_bytes = fp64 ? 8 : 4;
   pl.one = nullptr;
+  pl.us_out = nullptr;
   pl.sum_elems = (size_t)pl.P * F * pl.nK;
   pl.u_elems = (size_t)std::max(n, 1) * r * pl.nr * pl.nK;
   // Runs longer than the register solver holds go to the long-run solver,
@@ -122,6 +123,7 @@ hipError_t launch_pass(int r, int cb, int fp64, const float* x, const float* g, 
                        const WeightParams& wp, const float* lam_dev, float lam_host,
                        void* iface, hipStream_t stream, int st, const BwdArgs* bw) {
   if (plan.mode == kModeBackward && !bw) return hipErrorInvalidValue;
+  if (plan.mode == kModeAdjoint && (st & kStageExpand)) return hipErrorInvalidValue;
   switch (r) {
     case 1: return launch_pass_r1(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface, stream, st, bw);
     case 2: return launch_pass_r2(cb, fp64, x, g, y, c0, geo, plan, wp, lam_dev, lam_host, iface, stream, st, bw);

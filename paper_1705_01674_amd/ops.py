@@ -10,6 +10,7 @@ Eq. (2).
 from __future__ import annotations
 
 import ctypes
+import os
 from dataclasses import dataclass, replace
 from typing import Optional
 
@@ -118,15 +119,23 @@ def _workspace(nbytes: int, dev) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=dev)
 
 
+def _seps_buffer(seps: torch.Tensor, dev) -> None:
+    if seps.dtype != torch.uint8 or seps.device != dev or not seps.is_contiguous():
+        raise ValueError("seps must be a contiguous uint8 tensor on the device of the images")
+
+
 def sgwls_filter(f: torch.Tensor, g: torch.Tensor, p: Params, *,
                  lambda_dev: Optional[torch.Tensor] = None,
                  saved: Optional[torch.Tensor] = None,
                  out: Optional[torch.Tensor] = None,
-                 workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+                 workspace: Optional[torch.Tensor] = None,
+                 seps: Optional[torch.Tensor] = None) -> torch.Tensor:
     """SG-WLS filter of f (C x M x N or M x N) guided by g (M x N), Sec. 2.3.
 
     ``saved`` (optional, 2T x C x M x N float32) receives every pass input for
-    the backward call.  ``out`` may be f itself (in-place filtering)."""
+    the backward call.  ``out`` may be f itself (in-place filtering).
+    ``seps`` (optional, with saved; uint8, separator_bytes_nchw(1, C, M, N, p)
+    bytes) receives every pass's separator solutions for the backward."""
     C, M, N = _image(f, "f")
     dev = f.device
     _guidance(g, M, N, dev)
@@ -144,6 +153,14 @@ def sgwls_filter(f: torch.Tensor, g: torch.Tensor, p: Params, *,
     if ws.numel() < nbytes or ws.device != dev:
         raise ValueError("workspace too small")
     cp = p.c()
+    if seps is not None:
+        _seps_buffer(seps, dev)
+        nat.check(nat.lib.sgwls_filter_nchw_seps(_ptr(f), _ptr(g), _ptr(out), 1, C, M, N,
+                                                 ctypes.byref(cp), _ptr(lam), _ptr(saved),
+                                                 _ptr(seps), seps.numel(), _ptr(ws), ws.numel(),
+                                                 _stream(dev)),
+                  "sgwls_filter_nchw_seps")
+        return out
     nat.check(nat.lib.sgwls_filter(_ptr(f), _ptr(g), _ptr(out), C, M, N, ctypes.byref(cp),
                                    _ptr(lam), _ptr(saved), _ptr(ws), ws.numel(), _stream(dev)),
               "sgwls_filter")
@@ -311,9 +328,11 @@ def sgwls_backward(g: torch.Tensor, saved: torch.Tensor, grad_u: torch.Tensor, p
                    want_lambda: bool = True, grad_f: Optional[torch.Tensor] = None,
                    grad_g: Optional[torch.Tensor] = None,
                    grad_lambda: Optional[torch.Tensor] = None,
-                   workspace: Optional[torch.Tensor] = None):
+                   workspace: Optional[torch.Tensor] = None,
+                   seps: Optional[torch.Tensor] = None):
     """Adjoint of ``sgwls_filter`` given the pass inputs it saved: returns
-    (grad_f, grad_g or None, grad_lambda (float64 device tensor) or None)."""
+    (grad_f, grad_g or None, grad_lambda (float64 device tensor) or None).
+    ``seps``: the separators that filter call kept (p must be its p)."""
     C, M, N = _image(grad_u, "grad_u")
     dev = grad_u.device
     _guidance(g, M, N, dev)
@@ -340,6 +359,14 @@ def sgwls_backward(g: torch.Tensor, saved: torch.Tensor, grad_u: torch.Tensor, p
     ws = workspace if workspace is not None else _workspace(nbytes, dev)
     if ws.numel() < nbytes or ws.device != dev:
         raise ValueError("workspace too small")
+    if seps is not None:
+        _seps_buffer(seps, dev)
+        nat.check(nat.lib.sgwls_backward_nchw_seps(_ptr(g), _ptr(saved), _ptr(seps), seps.numel(),
+                                                   _ptr(grad_u), _ptr(grad_f), _ptr(gbar),
+                                                   _ptr(glam), 1, C, M, N, ctypes.byref(p.c()),
+                                                   _ptr(lam), _ptr(ws), ws.numel(), _stream(dev)),
+                  "sgwls_backward_nchw_seps")
+        return grad_f, gbar, glam
     nat.check(nat.lib.sgwls_backward(_ptr(g), _ptr(saved), _ptr(grad_u), _ptr(grad_f), _ptr(gbar),
                                      _ptr(glam), C, M, N, ctypes.byref(p.c()), _ptr(lam), _ptr(ws),
                                      ws.numel(), _stream(dev)),
@@ -364,13 +391,22 @@ def workspace_bytes_nchw(B: int, C: int, M: int, N: int, p: Params,
     return int(n)
 
 
+def separator_bytes_nchw(B: int, C: int, M: int, N: int, p: Params) -> int:
+    """Bytes of the saved-separator buffer of B images of C x M x N (0: the
+    case has no saved-separator path)."""
+    return int(nat.lib.sgwls_separator_bytes_nchw(B, C, M, N, ctypes.byref(p.c())))
+
+
 def sgwls_filter_nchw(f: torch.Tensor, g: torch.Tensor, p: Params, *,
                       lambda_dev: Optional[torch.Tensor] = None,
                       saved: Optional[torch.Tensor] = None,
+                      seps: Optional[torch.Tensor] = None,
                       out: Optional[torch.Tensor] = None,
                       workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
     """The filter of B equal-shape images in each launch: f (B, C, M, N), g
-    (B, M, N); saved (optional) B x 2T x C x M x N."""
+    (B, M, N); saved (optional) B x 2T x C x M x N; seps (optional, with
+    saved): a uint8 device tensor of separator_bytes_nchw bytes that receives
+    every pass's separator solutions for sgwls_backward_nchw."""
     B, C, M, N = _batch4(f, "f")
     dev = f.device
     if g.shape != (B, M, N) or not g.is_contiguous() or g.dtype != torch.float32 or g.device != dev:
@@ -388,6 +424,14 @@ def sgwls_filter_nchw(f: torch.Tensor, g: torch.Tensor, p: Params, *,
     ws = workspace if workspace is not None else _workspace(nbytes, dev)
     if ws.numel() < nbytes or ws.device != dev:
         raise ValueError("workspace too small")
+    if seps is not None:
+        _seps_buffer(seps, dev)
+        nat.check(nat.lib.sgwls_filter_nchw_seps(_ptr(f), _ptr(g), _ptr(out), B, C, M, N,
+                                                 ctypes.byref(p.c()), _ptr(lam), _ptr(saved),
+                                                 _ptr(seps), seps.numel(), _ptr(ws), ws.numel(),
+                                                 _stream(dev)),
+                  "sgwls_filter_nchw_seps")
+        return out
     nat.check(nat.lib.sgwls_filter_nchw(_ptr(f), _ptr(g), _ptr(out), B, C, M, N, ctypes.byref(p.c()),
                                         _ptr(lam), _ptr(saved), _ptr(ws), ws.numel(), _stream(dev)),
               "sgwls_filter_nchw")
@@ -396,10 +440,12 @@ def sgwls_filter_nchw(f: torch.Tensor, g: torch.Tensor, p: Params, *,
 
 def sgwls_backward_nchw(g: torch.Tensor, saved: torch.Tensor, grad_u: torch.Tensor, p: Params, *,
                         lambda_dev: Optional[torch.Tensor] = None, want_g: bool = True,
-                        want_lambda: bool = True, workspace: Optional[torch.Tensor] = None):
+                        want_lambda: bool = True, workspace: Optional[torch.Tensor] = None,
+                        seps: Optional[torch.Tensor] = None):
     """Adjoint of sgwls_filter_nchw: returns (grad_f (B, C, M, N), grad_g
     (B, M, N) or None, grad_lambda summed over the batch (float64 device
-    tensor) or None)."""
+    tensor) or None).  seps: the separators the forward kept (then p must be
+    the forward's, and the call runs in the forward's precision)."""
     B, C, M, N = _batch4(grad_u, "grad_u")
     dev = grad_u.device
     lam = _lambda(lambda_dev, dev)
@@ -410,6 +456,14 @@ def sgwls_backward_nchw(g: torch.Tensor, saved: torch.Tensor, grad_u: torch.Tens
     ws = workspace if workspace is not None else _workspace(nbytes, dev)
     if ws.numel() < nbytes or ws.device != dev:
         raise ValueError("workspace too small")
+    if seps is not None:
+        _seps_buffer(seps, dev)
+        nat.check(nat.lib.sgwls_backward_nchw_seps(_ptr(g), _ptr(saved), _ptr(seps), seps.numel(),
+                                                   _ptr(grad_u), _ptr(grad_f), _ptr(gbar),
+                                                   _ptr(glam), B, C, M, N, ctypes.byref(p.c()),
+                                                   _ptr(lam), _ptr(ws), ws.numel(), _stream(dev)),
+                  "sgwls_backward_nchw_seps")
+        return grad_f, gbar, glam
     nat.check(nat.lib.sgwls_backward_nchw(_ptr(g), _ptr(saved), _ptr(grad_u), _ptr(grad_f), _ptr(gbar),
                                           _ptr(glam), B, C, M, N, ctypes.byref(p.c()), _ptr(lam),
                                           _ptr(ws), ws.numel(), _stream(dev)),
@@ -422,9 +476,12 @@ class SGWLSFunction(torch.autograd.Function):
 
     f: (C, M, N) or (B, C, M, N) float32; g: (M, N) or (B, M, N) float32;
     lam: one-element float32 tensor on the device (a learnable scalar).  The
-    forward pass saves every pass input (2T images per image); the backward
-    pass runs the adjoint kernels, which recompute the weights from g.  A
-    batch runs as one NCHW call each way (every launch covers all images)."""
+    forward pass saves every pass input (2T images per image) and, where the
+    case has that path, every pass's separator solutions; the backward pass
+    runs the adjoint kernels, which recompute the weights from g (and, with
+    saved separators, solve only the adjoint's separator systems).  A batch
+    runs as one NCHW call each way (every launch covers all images).  The
+    environment variable SGWLS_SAVE_SEPARATORS=0 turns the separators off."""
 
     @staticmethod
     def forward(ctx, f, g, lam, p: Params):
@@ -442,21 +499,28 @@ class SGWLSFunction(torch.autograd.Function):
             p = p.with_(lam=max(float(lam_dev.item()), 0.0))
             p = p.with_(prec=resolve_precision(p, bool(ctx.needs_input_grad[2])))
         saved = torch.empty((B, 2 * p.iters, C, M, N), dtype=torch.float32, device=f.device)
-        out = sgwls_filter_nchw(fb, gb, p, lambda_dev=lam_dev, saved=saved)
+        nsep = separator_bytes_nchw(B, C, M, N, p) if os.environ.get("SGWLS_SAVE_SEPARATORS", "1") != "0" else 0
+        seps = torch.empty(nsep, dtype=torch.uint8, device=f.device) if nsep > 0 else None
+        out = sgwls_filter_nchw(fb, gb, p, lambda_dev=lam_dev, saved=saved, seps=seps)
         ctx.p = p
         ctx.batched = batched
         ctx.lam_shape = lam.shape
-        ctx.save_for_backward(gb, saved, lam_dev)
+        ctx.has_seps = seps is not None
+        if seps is None:
+            ctx.save_for_backward(gb, saved, lam_dev)
+        else:
+            ctx.save_for_backward(gb, saved, lam_dev, seps)
         return out if batched else out[0]
 
     @staticmethod
     def backward(ctx, grad_out):
-        gb, saved, lam_dev = ctx.saved_tensors
+        gb, saved, lam_dev = ctx.saved_tensors[:3]
+        seps = ctx.saved_tensors[3] if ctx.has_seps else None
         p = ctx.p
         go = grad_out.contiguous() if ctx.batched else grad_out.contiguous().unsqueeze(0)
         want_f, want_g, want_l = ctx.needs_input_grad[0], ctx.needs_input_grad[1], ctx.needs_input_grad[2]
         grad_f, grad_g, glam = sgwls_backward_nchw(gb, saved, go, p, lambda_dev=lam_dev,
-                                                   want_g=want_g, want_lambda=want_l)
+                                                   want_g=want_g, want_lambda=want_l, seps=seps)
         gl_out = glam.to(torch.float32).reshape(ctx.lam_shape) if want_l else None
         if not ctx.batched:
             grad_f = grad_f[0]

@@ -371,3 +371,47 @@ def test_nchw_workspaces_and_errors(nat):
                                  ws, big, None) == 4
     assert lib.sgwls_filter_nchw(f, g, u, 2, 3, 64, 64, p, None, None, ws, 16, None) == 3
     assert lib.sgwls_backward_nchw(g, u, u, f, None, None, 0, 3, 64, 64, p, None, ws, big, None) == 2
+
+
+def test_separator_bytes_and_errors(nat):
+    lib = nat.lib
+    def sb(B, C, M, N, **kw):
+        return lib.sgwls_separator_bytes_nchw(B, C, M, N, ctypes.byref(P(nat, **kw)))
+    # r = 1, three channels, float32: the backward cuts 6-row chunks, so a
+    # pass holds (ceil(L/6) - 1) separators x (W - 2) strips x 3 floats
+    def blk(L, W, R, acc):
+        n = -(-L // R) - 1
+        return -(-(n * 3 * (W - 2) * acc) // 256) * 256
+    one = sb(1, 3, 100, 120, r=1, iters=1, prec=0)
+    assert one == blk(100, 120, 6, 4) + blk(120, 100, 6, 4)
+    assert sb(3, 3, 100, 120, r=1, iters=1, prec=0) == 3 * one
+    assert sb(1, 3, 100, 120, r=1, iters=2, prec=0) == 2 * one
+    # FP64 pivots: four-row chunks, double separators
+    assert sb(1, 3, 100, 120, r=1, iters=1, prec=1) == blk(100, 120, 4, 8) + blk(120, 100, 4, 8)
+    # AUTO resolves as for the lambda gradient (FP64 pivots)
+    assert sb(1, 3, 100, 120, r=1, iters=1, prec=3) == sb(1, 3, 100, 120, r=1, iters=1, prec=1)
+    # no such path: strided, serial strips, no matching forward chunks, invalid
+    assert sb(1, 3, 100, 120, r=1, iters=1, prec=0, stride=2) == 0
+    assert sb(1, 3, 100, 120, r=1, iters=1, prec=2) == 0
+    assert sb(1, 1, 100, 120, r=3, iters=1, prec=0) == 0
+    assert sb(1, 1, 100, 120, r=2, iters=1, prec=1) == 0
+    assert sb(1, 3, 100, 120, r=3, iters=1, prec=0) > 0
+    assert sb(0, 3, 100, 120, r=1, iters=1, prec=0) == 0
+    f, g, u, s, ws = (ctypes.c_void_p(a) for a in (0x1000, 0x2000, 0x3000, 0x5000, 0x4000))
+    big = 1 << 34
+    p = ctypes.byref(P(nat, r=1, iters=1, prec=0))
+    pr3 = ctypes.byref(P(nat, r=3, iters=1, prec=0))
+    assert lib.sgwls_filter_nchw_seps(f, g, u, 1, 3, 100, 120, p, None, None, s, big, ws, big,
+                                      None) == 1
+    assert lib.sgwls_filter_nchw_seps(f, g, u, 1, 3, 100, 120, p, None, u, None, big, ws, big,
+                                      None) == 1
+    assert lib.sgwls_filter_nchw_seps(f, g, u, 1, 3, 100, 120, p, None, u, s, one - 1, ws, big,
+                                      None) == 3
+    assert lib.sgwls_filter_nchw_seps(f, g, u, 1, 1, 100, 120, pr3, None, u, s, big, ws, big,
+                                      None) == 4
+    assert lib.sgwls_backward_nchw_seps(g, u, None, big, u, f, None, None, 1, 3, 100, 120, p, None,
+                                        ws, big, None) == 1
+    assert lib.sgwls_backward_nchw_seps(g, u, s, one - 1, u, f, None, None, 1, 3, 100, 120, p,
+                                        None, ws, big, None) == 3
+    assert lib.sgwls_backward_nchw_seps(g, u, s, big, u, f, None, None, 1, 1, 100, 120, pr3, None,
+                                        ws, big, None) == 4
