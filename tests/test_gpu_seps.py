@@ -75,6 +75,15 @@ CASES = [
     (1, 3, 50, 90, 3, "fp32", 1),
     (1, 1, 60, 80, 4, "fp64_pivot", 1),
     (1, 3, 44, 70, 4, "fp32", 1),
+    # edges: one chunk per column (no separators in that frame), the
+    # minimum height 2r+1 (one strip in the row frame), five channels (blocks
+    # 3, 1, 1), and lines long enough for the scratch-backed long-run
+    # interface (more than 512 separators) in the forward and the adjoint
+    (1, 2, 5, 200, 1, "fp32", 1),
+    (1, 3, 3, 64, 1, "fp64_pivot", 1),
+    (1, 5, 40, 90, 1, "fp64_pivot", 1),
+    (1, 3, 3300, 40, 1, "fp32", 1),
+    (1, 1, 40, 2100, 2, "fp32", 1),
 ]
 
 
