@@ -261,8 +261,9 @@ sgwls_status sgwls_backward_nchw(const float* g, const float* saved, const float
  * A backward pass recomputes its pass solution (Sec. 2.3) alongside the
  * adjoint solve.  sgwls_filter_nchw_seps is sgwls_filter_nchw with `saved`
  * required that also keeps, in the device buffer seps, the solution of every
- * pass at its chunk separators (the interface values of Sec. 2.3, steps 2-3),
- * the pass cut into the backward's chunks; sgwls_backward_nchw_seps is
+ * pass at the chunk separators of the backward's cut (the interface values
+ * of Sec. 2.3, steps 2-3, for the backward's chunks; the forward keeps its
+ * own chunks and stores them from its re-solve); sgwls_backward_nchw_seps is
  * sgwls_backward_nchw that takes them from seps, so each of its passes
  * eliminates and solves the separator systems of the adjoint alone (one
  * right-hand side per channel instead of two) before re-solving both.
@@ -272,13 +273,12 @@ sgwls_status sgwls_backward_nchw(const float* g, const float* saved, const float
  * the forward's p, B, C, M, N and its seps unchanged.
  * sgwls_separator_bytes_nchw: bytes of seps for B images, 0 when the case
  * has no such path (then both calls return SGWLS_E_UNSUPPORTED and enqueue
- * nothing): stride 1 with the forward's column-pass kernels reading their
- * chunks directly, the partitioned precisions, and a forward variant cut
- * like the backward (not r = 3 with one channel in float32 nor r = 2 with one
- * channel with FP64 pivots).  Layout per image (image b at b times the
- * per-image bytes): pass 0 .. 2T-1, within a pass its channel blocks (three
- * channels, then single channels), each block its separator solutions
- * rounded up to 256 bytes.  SGWLS_E_WORKSPACE when seps_bytes is too small;
+ * nothing): stride 1 with the column-pass kernels reading their chunks
+ * directly, and the partitioned precisions.  Layout per image (image b at b
+ * times the per-image bytes): pass 0 .. 2T-1, within a pass its channel
+ * blocks (three channels, then single channels), each block its separator
+ * solutions (r x cb values per separator, strip after strip) rounded up to
+ * 256 bytes.  SGWLS_E_WORKSPACE when seps_bytes is too small;
  * the workspaces are those of the plain calls.  The fused passes
  * (SGWLS_ONE_LAUNCH) do not apply to sgwls_filter_nchw_seps. */
 size_t sgwls_separator_bytes_nchw(int B, int C, int M, int N, const sgwls_params* p);

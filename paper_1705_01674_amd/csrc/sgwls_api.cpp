@@ -171,23 +171,24 @@ unsigned int one_launch_spin_limit() {
 void clear_hip_error() { (void)hipGetLastError(); }
 
 // ---------------------------------------------------------------------------
-// Saved separators.  A forward pass cut into the backward's chunks (variant 0
-// of the backward table) solves, at the chunk separators, exactly the values
-// the backward's recomputation of that pass needs; a filter call that keeps
-// them lets every backward pass eliminate and solve only the adjoint system
-// (one right-hand side per channel instead of two).  Buffer layout per image:
-// pass q in order, then its channel blocks in order, each block the
-// separator solutions of a forward interface buffer (r x cb values per
-// separator, strip after strip) rounded up to 256 bytes.
+// Saved separators.  The backward's recomputation of a pass needs the pass
+// solution at the separators of the backward's chunks (variant 0 of the
+// backward table); a filter call that keeps them lets every backward pass
+// eliminate and solve only the adjoint system (one right-hand side per
+// channel instead of two).  Where a forward variant is cut like the backward,
+// the forward runs it and its interface writes its separator solutions
+// straight to the buffer; otherwise the forward keeps its own chunks and its
+// re-solve stores the last r elements of every subsystem row that ends a
+// backward chunk (slower per pass: the stores sit in the re-solve).  Buffer
+// layout per image: pass q in order, then its channel blocks in order, each
+// block the separator solutions in the backward's interface layout (r x cb
+// values per separator, strip after strip) rounded up to 256 bytes.
 
-// The forward variant whose chunks are the backward's, -1 when none is.
-int seps_variant(int r, int cb, int fp64) {
-  if (fp64 != 0 && fp64 != 1) return -1;
-  const VariantSet fw = variants_of(r, cb, fp64), bw = bwd_variants_of(r, cb, fp64);
-  if (!bw.v[0].D) return -1;
-  for (int v = 0; v < fw.n; ++v)
-    if (fw.v[v].D && fw.v[v].R == bw.v[0].R) return v;
-  return -1;
+
+// The backward's cut of a pass over an L x W frame (one channel block), with
+// one right-hand side per channel: the layout of its separator solutions.
+PassPlan seps_plan(int L, int W, int cb, const sgwls_params& p) {
+  return make_plan(L, W, p.r, cb, 1, p.prec, 0, kModeAdjoint);
 }
 
 // Pass q of a stride-1 filter call runs as a column pass of an L x W frame:
@@ -197,7 +198,7 @@ size_t seps_pass_bytes(int q, int C, int M, int N, const sgwls_params& p) {
   size_t b = 0;
   for (int c0 = 0; c0 < C;) {
     const int cb = channel_block(C - c0);
-    const PassPlan pl = make_plan(L, W, p.r, cb, 1, p.prec, seps_variant(p.r, cb, p.prec));
+    const PassPlan pl = seps_plan(L, W, cb, p);
     b += align_up(pl.u_elems * pl.acc_bytes);
     c0 += cb;
   }
@@ -205,15 +206,11 @@ size_t seps_pass_bytes(int q, int C, int M, int N, const sgwls_params& p) {
 }
 
 // Per-image bytes of the separator buffer, 0 when the case has no saved-
-// separator path (p resolved, validated).
+// separator path (p resolved, validated): stride-1 frames with direct
+// forward and backward kernels, the partitioned precisions.
 size_t seps_image_bytes(int C, int M, int N, const sgwls_params& p) {
   if (p.stride != 1 || (p.prec != SGWLS_P_FP32 && p.prec != SGWLS_P_FP64_PIVOT)) return 0;
   if (!frames_supported(C, p.r, 1, p.prec)) return 0;
-  for (int c0 = 0; c0 < C;) {
-    const int cb = channel_block(C - c0);
-    if (seps_variant(p.r, cb, p.prec) < 0) return 0;
-    c0 += cb;
-  }
   size_t b = 0;
   for (int q = 0; q < 2 * p.iters; ++q) b += seps_pass_bytes(q, C, M, N, p);
   return b;
@@ -235,21 +232,32 @@ sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* 
                                          direction + (p.stride != 1 ? kStridedDir : 0), L, W);
     if (out_t && p.stride == 1 && !variants_of(p.r, cb, p.prec).v[v].D)
       v = 0;   // variant 0 reads directly
-    if (useps) v = seps_variant(p.r, cb, p.prec);   // the backward's chunks
+    const int sv = useps ? forward_variant_cut_like_backward(p.r, cb, p.prec) : -1;
+    if (sv >= 0) v = sv;   // cut like the backward
     PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, v);
     pl.one = useps ? nullptr : one;
     PassGeom geo = pass_geom(direction, M, N, pl, p.stride);
     geo.out_t = out_t;
     if (bt) set_batch(geo, *bt);
+    BwdArgs keep{};
     if (useps) {
-      // the separator solutions go to the caller's buffer (kept for the backward)
-      pl.us_out = useps;
-      geo.zu = zseps;
-      useps += align_up(pl.u_elems * pl.acc_bytes);
+      const PassPlan sp = seps_plan(L, W, cb, p);
+      if (sv >= 0) {
+        // the interface writes its separator solutions to the buffer
+        pl.us_out = useps;
+        geo.zu = zseps;
+      } else {
+        // the re-solve stores the solution at the backward's separators
+        keep.seps_out = useps;
+        keep.zseps = zseps;
+        keep.seps_R = sp.R;
+        keep.seps_n = sp.P - 1;
+      }
+      useps += align_up(sp.u_elems * sp.acc_bytes);
     }
     stages &= kStageAll;
     hipError_t e = launch_pass(p.r, cb, p.prec, x, g, y, c0, geo, pl, wp, lam_dev, p.lambda,
-                               iface, stream, stages);
+                               iface, stream, stages, keep.seps_out ? &keep : nullptr);
     if (e != hipSuccess) return SGWLS_E_HIP;
     c0 += cb;
   }

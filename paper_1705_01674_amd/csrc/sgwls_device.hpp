@@ -1505,7 +1505,7 @@ __global__ __launch_bounds__(NL) void k_interface_pcr_long(const Acc* __restrict
 // the block owns (a strip is solved by the two blocks whose columns it
 // touches, and owned by the first).
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE,
-          bool DIRECT = false, bool COH = false>
+          bool DIRECT = false, bool COH = false, bool KEEP = false>
 DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const PassGeom& geo,
                      const WeightParams& wp, float lam_in, int c0, const Acc* __restrict__ Us,
                      int OW, int pch, const BwdArgs& bw, int bx, int by, int nbx, float* smem,
@@ -1577,7 +1577,7 @@ DEV void store_transposed(const float* smem, float* __restrict__ Yc, const float
 // The solve and output of a block whose tile is in LDS (see expand_block), or,
 // with DIRECT, whose chunks are read from global memory (stride-1 column pass).
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE, bool DIRECT,
-          bool COH>
+          bool COH, bool KEEP>
 DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const PassGeom& geo,
                      const WeightParams& wp, float lam_in, int c0, const Acc* __restrict__ Us,
                      int OW, int pch, const BwdArgs& bw, int bx, int by, int nbx, float* smem,
@@ -1852,6 +1852,14 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
       inv = __builtin_amdgcn_rcpf(float(max(cnt, 1)));
     }
     if constexpr (ROWWISE) {
+      // KEEP: separators of another cut (seps_R rows per chunk) kept for the
+      // backward: the last r elements of every subsystem row that ends one of
+      // its chunks, stored by the block that owns the strip.
+      bool keep_seps = false;
+      if constexpr (KEEP) {
+        const int ki_next = bx + 1 < nbx ? expand_first_strip(bx + 1, OW, geo, r) : geo.nK;
+        keep_seps = bw.seps_out != nullptr && active && ki < ki_next;
+      }
 #pragma unroll
       for (int rho = R - 1; rho >= 0; --rho) {
         if (active) {
@@ -1867,6 +1875,17 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
                 Z[m][h] = v;
               }
             }
+          }
+        }
+        if (KEEP && keep_seps) {
+          const int rows_to = j * R + rho + 1;   // subsystem rows up to this one
+          const int js = rows_to / bw.seps_R - 1;
+          if (rows_to % bw.seps_R == 0 && js < bw.seps_n) {
+            Acc* o = reinterpret_cast<Acc*>(bw.seps_out) + ((size_t)ki * bw.seps_n + js) * r * CB;
+#pragma unroll
+            for (int a = 0; a < r; ++a)
+#pragma unroll
+              for (int h = 0; h < CB; ++h) o[a * CB + h] = Z[rho * w + w - r + a][h];
           }
         }
         float orow[NO];
@@ -2082,10 +2101,12 @@ DEV BwdArgs bwd_at(BwdArgs bw, const PassGeom& geo, int z) {
   bw.side = zmove(bw.side, geo.zside, z);
   bw.lpart = zmove(bw.lpart, (long long)geo.zlpart, z);
   bw.useps = zmove_bytes(bw.useps, bw.zseps, z);
+  bw.seps_out = zmove_bytes(bw.seps_out, bw.zseps, z);
   return bw;
 }
 
-template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE>
+template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE,
+          bool KEEP = false>
 __global__ __launch_bounds__(kWave* Q) void k_expand_d(
     const float* __restrict__ X, const float* __restrict__ G, float* __restrict__ Y,
     PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
@@ -2096,7 +2117,7 @@ __global__ __launch_bounds__(kWave* Q) void k_expand_d(
   const PlaneSrc<CB> src{zmove(X, geo.zx, z), bz.ybar, c0, (int)geo.plane};
   int bx, by;
   xcd_block(bx, by);
-  expand_tile<r, CB, R, Q, S1, KIND, Acc, MODE, true>(
+  expand_tile<r, CB, R, Q, S1, KIND, Acc, MODE, true, false, KEEP>(
       zmove(G, geo.zg, z), zmove(Y, geo.zy, z), geo, wp, load_lambda(lam_dev, lam_host), c0,
       zmove_bytes(Us, geo.zu, z), OW, pitch, bz, bx, by, gridDim.x, smem, &src);
 }
@@ -2351,6 +2372,22 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
   if (stages & kStageExpand) {
     const int ex = (geo.W + pl.OW - 1) / pl.OW;
     bool direct = false;
+    // Kept separators of the backward's cut: the row-wise stores of the direct
+    // stride-1 forward, compiled only where no forward variant is cut like
+    // the backward (elsewhere the interface writes them).
+    constexpr bool KEEP = MODE == kModeForward && D && S1 && !forward_cut_like_backward(r, CB, fp64);
+    if (bw.seps_out) {
+      if constexpr (KEEP) {
+        if (geo.sb != 1) return hipErrorInvalidValue;
+        const size_t lds = geo.out_t ? sizeof(float) * CB * Q * R * (kWave + 1) : 0;
+        hipLaunchKernelGGL((k_expand_d<r, CB, R, Q, S1, KIND, Acc, MODE, true>), dim3(ex, gy, nz),
+                           dim3(kWave * Q), lds, stream, x, g, y, geo, wp, lam_dev, lam_host, c0,
+                           (const Acc*)us, pl.OW, pl.pitch, bw);
+        return hipGetLastError();
+      } else {
+        return hipErrorInvalidValue;
+      }
+    }
     if constexpr (D) {
       if (geo.sb == 1) {
         // Stride 1: LDS only to stage a transposed store.  Strided: LDS
@@ -2456,6 +2493,9 @@ hipError_t launch_r(int cb, int fp64, const float* x, const float* g, float* y, 
     return launch_mode<r, kModeBackward>(cb, fp64, x, g, y, c0, geo, pl, wp, lam_dev, lam_host,
                                          iface, s, st, *bw);
   const BwdArgs none{};
+  if (pl.mode == kModeForward && bw)   // a forward that keeps separators
+    return launch_mode<r, kModeForward>(cb, fp64, x, g, y, c0, geo, pl, wp, lam_dev, lam_host,
+                                        iface, s, st, *bw);
   if (pl.mode == kModeAdjoint)
     return launch_mode<r, kModeAdjoint>(cb, fp64, x, g, y, c0, geo, pl, wp, lam_dev, lam_host,
                                         iface, s, st, none);

@@ -147,6 +147,18 @@ constexpr VariantSet bwd_variants_of(int r, int cb, int fp64) {
   return VariantSet{1, {{2, 2, 1}}, 0};
 }
 
+// A forward variant reading its chunks directly and cut like variant 0 of the
+// backward (whose interface then solves the backward's separators).
+constexpr int forward_variant_cut_like_backward(int r, int cb, int fp64) {
+  const VariantSet fw = variants_of(r, cb, fp64), bw = bwd_variants_of(r, cb, fp64);
+  for (int v = 0; v < fw.n; ++v)
+    if (fw.v[v].D && fw.v[v].R == bw.v[0].R) return v;
+  return -1;
+}
+constexpr bool forward_cut_like_backward(int r, int cb, int fp64) {
+  return forward_variant_cut_like_backward(r, cb, fp64) >= 0;
+}
+
 constexpr VariantSet variants_for(int mode, int r, int cb, int fp64) {
   return mode == kModeForward ? variants_of(r, cb, fp64) : bwd_variants_of(r, cb, fp64);
 }
@@ -284,7 +296,12 @@ struct BwdArgs {
   // pass solves them itself (2 CB right-hand sides); with them the
   // interface buffer holds the adjoint's separators only (r x CB).
   const void* useps;
-  long long zseps;     // bytes between the images of an NCHW batch in useps
+  long long zseps;     // bytes between the images of an NCHW batch in useps / seps_out
+  // Forward passes: non-NULL to also store the pass solution at the chunk
+  // separators of another cut of the subsystems (seps_R rows per chunk,
+  // seps_n separators per strip), in the layout useps reads.
+  void* seps_out;
+  int seps_R, seps_n;
 };
 
 // Enqueue the stages in `stages` of one pass for channels [c0, c0+cb) of x

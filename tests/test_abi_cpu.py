@@ -390,17 +390,20 @@ def test_separator_bytes_and_errors(nat):
     assert sb(1, 3, 100, 120, r=1, iters=1, prec=1) == blk(100, 120, 4, 8) + blk(120, 100, 4, 8)
     # AUTO resolves as for the lambda gradient (FP64 pivots)
     assert sb(1, 3, 100, 120, r=1, iters=1, prec=3) == sb(1, 3, 100, 120, r=1, iters=1, prec=1)
-    # no such path: strided, serial strips, no matching forward chunks, invalid
+    # r = 2 grey with FP64 pivots: the backward's two-row chunks (the
+    # forward's own are four rows), double separators of two values
+    n2 = lambda L: -(-L // 2) - 1
+    assert sb(1, 1, 100, 120, r=2, iters=1, prec=1) == (
+        -(-(n2(100) * 2 * 116 * 8) // 256) * 256 + -(-(n2(120) * 2 * 96 * 8) // 256) * 256)
+    assert sb(1, 1, 100, 120, r=3, iters=1, prec=0) > 0
+    # no such path: strided, serial strips, invalid
     assert sb(1, 3, 100, 120, r=1, iters=1, prec=0, stride=2) == 0
     assert sb(1, 3, 100, 120, r=1, iters=1, prec=2) == 0
-    assert sb(1, 1, 100, 120, r=3, iters=1, prec=0) == 0
-    assert sb(1, 1, 100, 120, r=2, iters=1, prec=1) == 0
-    assert sb(1, 3, 100, 120, r=3, iters=1, prec=0) > 0
     assert sb(0, 3, 100, 120, r=1, iters=1, prec=0) == 0
     f, g, u, s, ws = (ctypes.c_void_p(a) for a in (0x1000, 0x2000, 0x3000, 0x5000, 0x4000))
     big = 1 << 34
     p = ctypes.byref(P(nat, r=1, iters=1, prec=0))
-    pr3 = ctypes.byref(P(nat, r=3, iters=1, prec=0))
+    pr3 = ctypes.byref(P(nat, r=1, iters=1, prec=0, stride=2))   # strided: no such path
     assert lib.sgwls_filter_nchw_seps(f, g, u, 1, 3, 100, 120, p, None, None, s, big, ws, big,
                                       None) == 1
     assert lib.sgwls_filter_nchw_seps(f, g, u, 1, 3, 100, 120, p, None, u, None, big, ws, big,

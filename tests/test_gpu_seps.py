@@ -2,9 +2,10 @@
 sgwls_backward_nchw_seps) against the FP64 CPU oracle's adjoint, and against
 the plain forward/backward pair at the full differentiation workload.
 
-The forward keeps every pass's solution at the chunk separators (cut as the
-backward cuts its chunks); each backward pass then eliminates only the
-adjoint's right-hand sides and re-solves both with the forward's separators.
+The forward keeps every pass's solution at the separators of the backward's
+chunks (stored by its re-solve, whatever its own chunks); each backward pass
+then eliminates only the adjoint's right-hand sides and re-solves both with
+the forward's separators.
 Same tolerances as the plain backward: the arithmetic per chunk is the same,
 in the same precision.  Error measure: normwise relative, max|gpu - ref| /
 max|ref|.
@@ -84,6 +85,11 @@ CASES = [
     (1, 5, 40, 90, 1, "fp64_pivot", 1),
     (1, 3, 3300, 40, 1, "fp32", 1),
     (1, 1, 40, 2100, 2, "fp32", 1),
+    # forward chunks taller than the backward's (separators stored from
+    # inside the forward's chunks): r = 3 grey in float32, r = 2 grey with
+    # FP64 pivots
+    (1, 1, 70, 110, 3, "fp32", 1),
+    (1, 1, 66, 98, 2, "fp64_pivot", 2),
 ]
 
 
