@@ -90,6 +90,11 @@ CASES = [
     # FP64 pivots
     (1, 1, 70, 110, 3, "fp32", 1),
     (1, 1, 66, 98, 2, "fp64_pivot", 2),
+    # the same stores in a batch (per-image offsets), and four channels at
+    # r = 3 (the three-channel block through the interface, the single
+    # channel through the re-solve, in one call)
+    (2, 1, 58, 84, 3, "fp32", 1),
+    (1, 4, 50, 90, 3, "fp32", 1),
 ]
 
 
