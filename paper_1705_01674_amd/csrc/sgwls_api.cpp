@@ -184,7 +184,6 @@ void clear_hip_error() { (void)hipGetLastError(); }
 // block the separator solutions in the backward's interface layout (r x cb
 // values per separator, strip after strip) rounded up to 256 bytes.
 
-
 // The backward's cut of a pass over an L x W frame (one channel block), with
 // one right-hand side per channel: the layout of its separator solutions.
 PassPlan seps_plan(int L, int W, int cb, const sgwls_params& p) {
@@ -352,7 +351,7 @@ sgwls_status enqueue_pass_backward(int direction, const float* x, const float* g
       // gradient over the cover counts, one right-hand side per channel),
       // then the re-solve of both with the adjoint's separators after its
       // summaries in the interface buffer.
-      const PassPlan pa = make_plan(L, W, p.r, cb, p.stride, p.prec, 0, kModeAdjoint);
+      const PassPlan pa = seps_plan(L, W, cb, p);   // the adjoint's own plan
       if (interface_bytes(pa) > lay.iface_img) return SGWLS_E_WORKSPACE;
       PassGeom ga = pass_geom(direction, M, N, pa, p.stride);
       if (bt) {
