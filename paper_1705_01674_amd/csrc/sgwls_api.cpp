@@ -220,7 +220,8 @@ sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* 
                           int N, const sgwls_params& p, const float* lam_dev, void* iface,
                           hipStream_t stream, int stages = kStageAll, int variant = -1,
                           const Batch* bt = nullptr, OneCtl* one = nullptr,
-                          char* useps = nullptr, long long zseps = 0) {
+                          char* useps = nullptr, long long zseps = 0,
+                          float* gT_out = nullptr) {
   const int L = direction == 0 ? M : N, W = direction == 0 ? N : M;
   const WeightParams wp = weight_params(p);
   const int out_t = (stages & kStageTransposeOut) ? 1 : 0;
@@ -254,9 +255,19 @@ sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* 
       }
       useps += align_up(sp.u_elems * sp.acc_bytes);
     }
+    if (gT_out && c0 == 0) {
+      // the first block's re-solve transposes g when its staged tile, one
+      // plane larger, still fits 64 KiB of LDS; else a transpose of its own
+      const size_t lds = sizeof(float) * (size_t)(cb + 1) * pl.Q * pl.R * (kWave + 1);
+      if (lds <= 65536)
+        keep.gT_out = gT_out;
+      else if (launch_transpose(g, gT_out, M, N, stream, bt ? bt->n : 1) != hipSuccess)
+        return SGWLS_E_HIP;
+    }
     stages &= kStageAll;
     hipError_t e = launch_pass(p.r, cb, p.prec, x, g, y, c0, geo, pl, wp, lam_dev, p.lambda,
-                               iface, stream, stages, keep.seps_out ? &keep : nullptr);
+                               iface, stream, stages,
+                               (keep.seps_out || keep.gT_out) ? &keep : nullptr);
     if (e != hipSuccess) return SGWLS_E_HIP;
     c0 += cb;
   }
@@ -1033,7 +1044,15 @@ static sgwls_status filter_nchw_core(const float* f, const float* g, float* u, i
       nzero = (int)(kSyncHead / sizeof(unsigned int)) + 2 * one.bank_words();
       onep = &one;
     }
-    if (launch_transpose(g, gT, M, N, s, B, 0, onep ? sync : nullptr, nzero) != hipSuccess)
+    // The guidance transposed for the row passes: by pass 0's re-solve, from
+    // the tile it stages for its transposed store (stride 1, three launches
+    // per pass, and no separators stored by that re-solve); else by a
+    // transpose of its own, which also clears the fused passes' words.
+    const bool gt_pass0 =
+        !onep && p->stride == 1 &&
+        (!seps || forward_cut_like_backward(p->r, channel_block(C), p->prec));
+    if (!gt_pass0 &&
+        launch_transpose(g, gT, M, N, s, B, 0, onep ? sync : nullptr, nzero) != hipSuccess)
       return SGWLS_E_HIP;
     const float* x = saved ? saved : f;
     size_t soff = 0;
@@ -1043,7 +1062,7 @@ static sgwls_status filter_nchw_core(const float* f, const float* g, float* u, i
       const Batch bt = batch(x, y);
       st = enqueue_pass(0, x, even ? g : gT, y, C, even ? M : N, even ? N : M, *p, lambda_dev,
                         iface, s, kStageAll | kStageTransposeOut, -1, &bt, onep,
-                        seps ? seps + soff : nullptr, zseps);
+                        seps ? seps + soff : nullptr, zseps, gt_pass0 && q == 0 ? gT : nullptr);
       if (st != SGWLS_OK) return st;
       if (seps) soff += seps_pass_bytes(q, C, M, N, *p);
       x = y;

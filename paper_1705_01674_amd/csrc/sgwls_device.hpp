@@ -1505,7 +1505,7 @@ __global__ __launch_bounds__(NL) void k_interface_pcr_long(const Acc* __restrict
 // the block owns (a strip is solved by the two blocks whose columns it
 // touches, and owned by the first).
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE,
-          bool DIRECT = false, bool COH = false, bool KEEP = false>
+          bool DIRECT = false, bool COH = false, bool KEEP = false, bool GT = false>
 DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const PassGeom& geo,
                      const WeightParams& wp, float lam_in, int c0, const Acc* __restrict__ Us,
                      int OW, int pch, const BwdArgs& bw, int bx, int by, int nbx, float* smem,
@@ -1543,14 +1543,17 @@ DEV void expand_block(const float* __restrict__ X, const float* __restrict__ G,
 // contiguous in the output, so consecutive threads take consecutive rows of
 // one column (the block's Q waves share the work): four rows per 16-byte
 // store when the runs are 16-byte aligned (a_lo is a multiple of QR), one row
-// per store otherwise.
-template <int CB, int Q, int R>
+// per store otherwise.  GTP: staged plane CB holds the guidance, which goes to
+// gT[bb*L + a_lo + tr].
+template <int CB, int Q, int R, bool GTP = false>
 DEV void store_transposed(const float* smem, float* __restrict__ Yc, const float* Ybase, int plane,
-                          int L, int a_lo, int arows, int b_lo, int b_hi, int colbase) {
+                          int L, int a_lo, int arows, int b_lo, int b_hi, int colbase,
+                          float* __restrict__ gT = nullptr) {
   constexpr int RP = kWave + 1, QR = Q * R, nthr = kWave * Q;
   const int ncols = b_hi - b_lo;
   if (QR % 4 == 0 && L % 4 == 0 && arows % 4 == 0 && plane % 4 == 0 &&
-      (reinterpret_cast<uintptr_t>(Ybase) & 15) == 0) {
+      (reinterpret_cast<uintptr_t>(Ybase) & 15) == 0 &&
+      (!GTP || (reinterpret_cast<uintptr_t>(gT) & 15) == 0)) {
     const int q4 = arows / 4;
     for (int idx = threadIdx.x; idx < q4 * ncols; idx += nthr) {
       const int bc = idx / q4, tr = 4 * (idx - bc * q4);
@@ -1562,6 +1565,11 @@ DEV void store_transposed(const float* smem, float* __restrict__ Yc, const float
         *reinterpret_cast<float4*>(Yc + h * plane + (size_t)bb * L + a_lo + tr) =
             make_float4(c[0], c[RP], c[2 * RP], c[3 * RP]);
       }
+      if constexpr (GTP) {
+        const float* c = cell + CB * QR * RP;
+        *reinterpret_cast<float4*>(gT + (size_t)bb * L + a_lo + tr) =
+            make_float4(c[0], c[RP], c[2 * RP], c[3 * RP]);
+      }
     }
   } else {
     for (int idx = threadIdx.x; idx < arows * ncols; idx += nthr) {
@@ -1570,6 +1578,7 @@ DEV void store_transposed(const float* smem, float* __restrict__ Yc, const float
       const float* cell = smem + tr * RP + (bb - colbase);
 #pragma unroll
       for (int h = 0; h < CB; ++h) Yc[h * plane + (size_t)bb * L + a_lo + tr] = cell[h * QR * RP];
+      if constexpr (GTP) gT[(size_t)bb * L + a_lo + tr] = cell[CB * QR * RP];
     }
   }
 }
@@ -1577,7 +1586,7 @@ DEV void store_transposed(const float* smem, float* __restrict__ Yc, const float
 // The solve and output of a block whose tile is in LDS (see expand_block), or,
 // with DIRECT, whose chunks are read from global memory (stride-1 column pass).
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE, bool DIRECT,
-          bool COH, bool KEEP>
+          bool COH, bool KEEP, bool GT>
 DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const PassGeom& geo,
                      const WeightParams& wp, float lam_in, int c0, const Acc* __restrict__ Us,
                      int OW, int pch, const BwdArgs& bw, int bx, int by, int nbx, float* smem,
@@ -1900,6 +1909,11 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
         if (geo.out_t) {           // stage the row for the transposed store below
 #pragma unroll
           for (int h = 0; h < CB; ++h) smem[(h * Q * R + wq * R + rho) * (kWave + 1) + lane] = orow[h];
+          if constexpr (GT) {      // and the guidance at the lane's output column
+            const int row = j * R + rho;
+            smem[(CB * Q * R + wq * R + rho) * (kWave + 1) + lane] =
+                (row < geo.L && b < geo.W) ? G[(size_t)row * geo.sa + b] : 0.0f;
+          }
         } else if (own && rho < rows) {
           const int o = (j * R + rho) * (int)geo.sa + b;
 #pragma unroll
@@ -1908,7 +1922,8 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
       }
       if (geo.out_t) {
         __syncthreads();
-        store_transposed<CB, Q, R>(smem, Yc, Y, plane, geo.L, a_lo, arows, b_lo, b_hi, colbase);
+        store_transposed<CB, Q, R, GT>(smem, Yc, Y, plane, geo.L, a_lo, arows, b_lo, b_hi,
+                                       colbase, bw.gT_out);
       }
       return;
     }
@@ -2102,11 +2117,12 @@ DEV BwdArgs bwd_at(BwdArgs bw, const PassGeom& geo, int z) {
   bw.lpart = zmove(bw.lpart, (long long)geo.zlpart, z);
   bw.useps = zmove_bytes(bw.useps, bw.zseps, z);
   bw.seps_out = zmove_bytes(bw.seps_out, bw.zseps, z);
+  bw.gT_out = zmove(bw.gT_out, geo.zg, z);
   return bw;
 }
 
 template <int r, int CB, int R, int Q, bool S1, int KIND, typename Acc, int MODE,
-          bool KEEP = false>
+          bool KEEP = false, bool GT = false>
 __global__ __launch_bounds__(kWave* Q) void k_expand_d(
     const float* __restrict__ X, const float* __restrict__ G, float* __restrict__ Y,
     PassGeom geo, WeightParams wp, const float* __restrict__ lam_dev, float lam_host, int c0,
@@ -2117,7 +2133,7 @@ __global__ __launch_bounds__(kWave* Q) void k_expand_d(
   const PlaneSrc<CB> src{zmove(X, geo.zx, z), bz.ybar, c0, (int)geo.plane};
   int bx, by;
   xcd_block(bx, by);
-  expand_tile<r, CB, R, Q, S1, KIND, Acc, MODE, true, false, KEEP>(
+  expand_tile<r, CB, R, Q, S1, KIND, Acc, MODE, true, false, KEEP, GT>(
       zmove(G, geo.zg, z), zmove(Y, geo.zy, z), geo, wp, load_lambda(lam_dev, lam_host), c0,
       zmove_bytes(Us, geo.zu, z), OW, pitch, bz, bx, by, gridDim.x, smem, &src);
 }
@@ -2376,6 +2392,19 @@ hipError_t launch_impl(const float* x, const float* g, float* y, int c0, const P
     // stride-1 forward, compiled only where no forward variant is cut like
     // the backward (elsewhere the interface writes them).
     constexpr bool KEEP = MODE == kModeForward && D && S1 && !forward_cut_like_backward(r, CB, fp64);
+    if (bw.gT_out) {
+      // pass 0 of a filter call: the guidance transposed from the staged tile
+      if constexpr (MODE == kModeForward && D && S1) {
+        if (geo.sb != 1 || !geo.out_t || bw.seps_out) return hipErrorInvalidValue;
+        const size_t lds = sizeof(float) * (CB + 1) * Q * R * (kWave + 1);
+        hipLaunchKernelGGL((k_expand_d<r, CB, R, Q, S1, KIND, Acc, MODE, false, true>),
+                           dim3(ex, gy, nz), dim3(kWave * Q), lds, stream, x, g, y, geo, wp,
+                           lam_dev, lam_host, c0, (const Acc*)us, pl.OW, pl.pitch, bw);
+        return hipGetLastError();
+      } else {
+        return hipErrorInvalidValue;
+      }
+    }
     if (bw.seps_out) {
       if constexpr (KEEP) {
         if (geo.sb != 1) return hipErrorInvalidValue;

@@ -302,6 +302,9 @@ struct BwdArgs {
   // seps_n separators per strip), in the layout useps reads.
   void* seps_out;
   int seps_R, seps_n;
+  // Forward column passes storing transposed: non-NULL to also store the
+  // guidance transposed here (W x L, image z at z * zg floats).
+  float* gT_out;
 };
 
 // Enqueue the stages in `stages` of one pass for channels [c0, c0+cb) of x
