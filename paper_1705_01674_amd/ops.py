@@ -494,10 +494,14 @@ class SGWLSFunction(torch.autograd.Function):
         lam_dev = lam.detach().reshape(1).to(torch.float32).contiguous()
         if p.prec == "auto":
             # The automatic precision is decided here, once for the forward and
-            # the backward, from lambda (one host sync) and from whether lambda
-            # needs a gradient (which asks for FP64 pivots in both calls).
-            p = p.with_(lam=max(float(lam_dev.item()), 0.0))
-            p = p.with_(prec=resolve_precision(p, bool(ctx.needs_input_grad[2])))
+            # the backward.  A lambda that needs a gradient asks for FP64 pivots
+            # in both calls whatever its value (no host sync); otherwise the
+            # bound on lambda * omega decides, from lambda read back once.
+            if ctx.needs_input_grad[2]:
+                p = p.with_(prec="fp64_pivot")
+            else:
+                p = p.with_(lam=max(float(lam_dev.item()), 0.0))
+                p = p.with_(prec=resolve_precision(p, False))
         saved = torch.empty((B, 2 * p.iters, C, M, N), dtype=torch.float32, device=f.device)
         nsep = separator_bytes_nchw(B, C, M, N, p) if os.environ.get("SGWLS_SAVE_SEPARATORS", "1") != "0" else 0
         seps = torch.empty(nsep, dtype=torch.uint8, device=f.device) if nsep > 0 else None
