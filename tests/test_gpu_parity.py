@@ -292,6 +292,31 @@ def test_every_kernel_variant_matches_oracle(ops, r, C, direction):
         ops.tune_clear()
 
 
+@pytest.mark.parametrize("r,C", [(1, 3), (1, 1), (2, 3)])
+def test_filter_with_every_pinned_variant_matches_oracle(ops, r, C):
+    # The filter with each kernel variant pinned for both frames: pass 0's
+    # re-solve also stores the guidance transposed for the row passes (or,
+    # for a tile too large for the extra plane, a transpose kernel does).
+    rng = np.random.default_rng(100 + 10 * r + C)
+    M, N = 133, 157
+    f = rng.uniform(0, 1, (C, M, N)).astype(np.float32)
+    g = rng.uniform(0, 1, (M, N)).astype(np.float32)
+    pd = pdict(lam=6.0, r=r, sigma_r=0.2, iters=2)
+    p = ops.Params(**pd, prec="fp32")
+    ref = oracle.filter(f.astype(np.float64), g.astype(np.float64), oracle.OracleParams(**pd))
+    ft, gt = torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda()
+    try:
+        for v in range(ops.variant_count(r, C)):
+            ops.tune_pin(0, C, M, N, p, v)
+            ops.tune_pin(0, C, N, M, p, v)
+            print(f"[parity] filter, variant {v} pinned, r{r} C{C}", flush=True)
+            out = ops.sgwls_filter(ft, gt, p)
+            torch.cuda.synchronize()
+            check(f"filter variant {v} r{r} C{C}", out.cpu().numpy(), ref)
+    finally:
+        ops.tune_clear()
+
+
 def test_autotune_picks_a_variant_and_keeps_parity(ops):
     w = synth.single("t", 300, 420, 3, 40, 0.05, 21, 4.0, 1, 2)
     p = ops.Params(**w.params)
