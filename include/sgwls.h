@@ -274,11 +274,13 @@ sgwls_status sgwls_backward_nchw(const float* g, const float* saved, const float
  * sgwls_separator_bytes_nchw: bytes of seps for B images, 0 when the case
  * has no such path (then both calls return SGWLS_E_UNSUPPORTED and enqueue
  * nothing): stride 1 with the column-pass kernels reading their chunks
- * directly, and the partitioned precisions.  Layout per image (image b at b
- * times the per-image bytes): pass 0 .. 2T-1, within a pass its channel
- * blocks (three channels, then single channels), each block its separator
- * solutions (r x cb values per separator, strip after strip) rounded up to
- * 256 bytes.  SGWLS_E_WORKSPACE when seps_bytes is too small;
+ * directly, and the partitioned precisions.  Layout: the B guidance planes
+ * transposed (N x M each, written by the forward, read by the backward
+ * instead of transposing g again, so g must be the forward's, unchanged),
+ * rounded up to 256 bytes; then per image (image b at b times the per-image
+ * bytes): pass 0 .. 2T-1, within a pass its channel blocks (three channels,
+ * then single channels), each block its separator solutions (r x cb values
+ * per separator, strip after strip) rounded up to 256 bytes.  SGWLS_E_WORKSPACE when seps_bytes is too small;
  * the workspaces are those of the plain calls.  The fused passes
  * (SGWLS_ONE_LAUNCH) do not apply to sgwls_filter_nchw_seps. */
 size_t sgwls_separator_bytes_nchw(int B, int C, int M, int N, const sgwls_params* p);

@@ -179,10 +179,13 @@ void clear_hip_error() { (void)hipGetLastError(); }
 // the forward runs it and its interface writes its separator solutions
 // straight to the buffer; otherwise the forward keeps its own chunks and its
 // re-solve stores the last r elements of every subsystem row that ends a
-// backward chunk (slower per pass: the stores sit in the re-solve).  Buffer
-// layout per image: pass q in order, then its channel blocks in order, each
-// block the separator solutions in the backward's interface layout (r x cb
-// values per separator, strip after strip) rounded up to 256 bytes.
+// backward chunk (slower per pass: the stores sit in the re-solve).  The
+// forward's transposed guidance goes to the buffer too, so that the backward
+// need not transpose g again.  Buffer layout: the B transposed guidance
+// planes (N x M each) rounded up to 256 bytes, then per image: pass q in
+// order, then its channel blocks in order, each block the separator solutions
+// in the backward's interface layout (r x cb values per separator, strip
+// after strip) rounded up to 256 bytes.
 
 // The backward's cut of a pass over an L x W frame (one channel block), with
 // one right-hand side per channel: the layout of its separator solutions.
@@ -204,7 +207,12 @@ size_t seps_pass_bytes(int q, int C, int M, int N, const sgwls_params& p) {
   return b;
 }
 
-// Per-image bytes of the separator buffer, 0 when the case has no saved-
+// Bytes of the transposed guidance planes at the start of the buffer.
+size_t seps_guidance_bytes(int B, int M, int N) {
+  return align_up(sizeof(float) * (size_t)B * M * N);
+}
+
+// Per-image bytes of the separator regions, 0 when the case has no saved-
 // separator path (p resolved, validated): stride-1 frames with direct
 // forward and backward kernels, the partitioned precisions.
 size_t seps_image_bytes(int C, int M, int N, const sgwls_params& p) {
@@ -213,6 +221,12 @@ size_t seps_image_bytes(int C, int M, int N, const sgwls_params& p) {
   size_t b = 0;
   for (int q = 0; q < 2 * p.iters; ++q) b += seps_pass_bytes(q, C, M, N, p);
   return b;
+}
+
+// The whole buffer for B images, 0 when the case has no such path.
+size_t seps_total_bytes(int B, int C, int M, int N, const sgwls_params& p) {
+  const size_t per = seps_image_bytes(C, M, N, p);
+  return per ? seps_guidance_bytes(B, M, N) + (size_t)B * per : 0;
 }
 
 // variant < 0: the tuned variant of the case (variant 0 when none is tuned).
@@ -1033,6 +1047,11 @@ static sgwls_status filter_nchw_core(const float* f, const float* g, float* u, i
     int nzero = 0;
     const int fuse = seps ? 0 : one_launch_mode();
     const long long zseps = seps ? (long long)seps_image_bytes(C, M, N, *p) : 0;
+    char* sepr = nullptr;   // the separator regions, after the transposed guidance
+    if (seps) {
+      gT = reinterpret_cast<float*>(seps);
+      sepr = seps + seps_guidance_bytes(B, M, N);
+    }
     if (fuse && p->stride == 1) {
       one.full = fuse == 1;
       one.err = sync;
@@ -1062,7 +1081,7 @@ static sgwls_status filter_nchw_core(const float* f, const float* g, float* u, i
       const Batch bt = batch(x, y);
       st = enqueue_pass(0, x, even ? g : gT, y, C, even ? M : N, even ? N : M, *p, lambda_dev,
                         iface, s, kStageAll | kStageTransposeOut, -1, &bt, onep,
-                        seps ? seps + soff : nullptr, zseps, gt_pass0 && q == 0 ? gT : nullptr);
+                        seps ? sepr + soff : nullptr, zseps, gt_pass0 && q == 0 ? gT : nullptr);
       if (st != SGWLS_OK) return st;
       if (seps) soff += seps_pass_bytes(q, C, M, N, *p);
       x = y;
@@ -1096,7 +1115,7 @@ sgwls_status sgwls_filter_nchw(const float* f, const float* g, float* u, int B, 
 
 size_t sgwls_separator_bytes_nchw(int B, int C, int M, int N, const sgwls_params* p) {
   if (B < 1 || validate_partitioned(C, M, N, p) != SGWLS_OK) return 0;
-  return (size_t)B * seps_image_bytes(C, M, N, resolved(*p, 1));
+  return seps_total_bytes(B, C, M, N, resolved(*p, 1));
 }
 
 sgwls_status sgwls_filter_nchw_seps(const float* f, const float* g, float* u, int B, int C,
@@ -1107,9 +1126,9 @@ sgwls_status sgwls_filter_nchw_seps(const float* f, const float* g, float* u, in
   if (st != SGWLS_OK) return st;
   if (B < 1) return SGWLS_E_SHAPE;
   if (!saved || !seps) return SGWLS_E_ARG;
-  const size_t need = seps_image_bytes(C, M, N, resolved(*p, 1));
+  const size_t need = seps_total_bytes(B, C, M, N, resolved(*p, 1));
   if (need == 0) return SGWLS_E_UNSUPPORTED;
-  if (seps_bytes < (size_t)B * need) return SGWLS_E_WORKSPACE;
+  if (seps_bytes < need) return SGWLS_E_WORKSPACE;
   return filter_nchw_core(f, g, u, B, C, M, N, p, lambda_dev, saved,
                           reinterpret_cast<char*>(seps), ws, ws_bytes, stream);
 }
@@ -1383,15 +1402,19 @@ static sgwls_status backward_nchw_core(const float* g, const float* saved, const
     // i.e. in the frame of pass q-1; pass 0 stores it as the image.  The
     // guidance gradient of odd passes accumulates transposed and is added to
     // grad_g at the end.
-    float* gT = reinterpret_cast<float*>(base + lay.gt_off);
+    // With saved separators the forward's transposed guidance is in seps.
+    const float* gT = seps ? reinterpret_cast<const float*>(seps)
+                           : reinterpret_cast<float*>(base + lay.gt_off);
     float* gTacc = reinterpret_cast<float*>(base + lay.gtacc_off);
     float* yT = reinterpret_cast<float*>(base + lay.yt_off);
-    if (launch_transpose(g, gT, M, N, s, B) != hipSuccess ||
+    if ((!seps && launch_transpose(g, reinterpret_cast<float*>(base + lay.gt_off), M, N, s, B) !=
+                      hipSuccess) ||
         launch_transpose(grad_u, yT, M, N, s, B * C) != hipSuccess)
       return SGWLS_E_HIP;
     const float* ybar = yT;
     bool gfirst[2] = {true, true};
     const long long zseps = seps ? (long long)seps_image_bytes(C, M, N, *p) : 0;
+    const char* sepr = seps ? seps + seps_guidance_bytes(B, M, N) : nullptr;
     size_t soff = 0;
     for (int q = 0; seps && q < passes - 1; ++q) soff += seps_pass_bytes(q, C, M, N, *p);
     for (int q = passes - 1; q >= 0; --q) {
@@ -1401,7 +1424,7 @@ static sgwls_status backward_nchw_core(const float* g, const float* saved, const
                                  grad_g ? (odd ? gTacc : grad_g) : nullptr, grad_lambda, C,
                                  odd ? N : M, odd ? M : N, *p, lambda_dev, ws, lay, s, first,
                                  &gfirst[odd ? 1 : 0], q > 0 ? 1 : 0, &bt,
-                                 seps ? seps + soff : nullptr, zseps);
+                                 seps ? sepr + soff : nullptr, zseps);
       if (st != SGWLS_OK) return st;
       if (seps && q > 0) soff -= seps_pass_bytes(q - 1, C, M, N, *p);
       ybar = xbar;
@@ -1440,9 +1463,9 @@ sgwls_status sgwls_backward_nchw_seps(const float* g, const float* saved, const 
   if (st != SGWLS_OK) return st;
   if (B < 1) return SGWLS_E_SHAPE;
   if (!seps) return SGWLS_E_ARG;
-  const size_t need = seps_image_bytes(C, M, N, resolved(*p, 1));
+  const size_t need = seps_total_bytes(B, C, M, N, resolved(*p, 1));
   if (need == 0) return SGWLS_E_UNSUPPORTED;
-  if (seps_bytes < (size_t)B * need) return SGWLS_E_WORKSPACE;
+  if (seps_bytes < need) return SGWLS_E_WORKSPACE;
   return backward_nchw_core(g, saved, reinterpret_cast<const char*>(seps), grad_u, grad_f,
                             grad_g, grad_lambda, B, C, M, N, p, lambda_dev, ws, ws_bytes,
                             stream);

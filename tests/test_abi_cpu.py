@@ -382,18 +382,23 @@ def test_separator_bytes_and_errors(nat):
     def blk(L, W, R, acc):
         n = -(-L // R) - 1
         return -(-(n * 3 * (W - 2) * acc) // 256) * 256
+    # the buffer starts with the B transposed guidance planes
+    def gplanes(B, M, N):
+        return -(-(4 * B * M * N) // 256) * 256
+    per = blk(100, 120, 6, 4) + blk(120, 100, 6, 4)
     one = sb(1, 3, 100, 120, r=1, iters=1, prec=0)
-    assert one == blk(100, 120, 6, 4) + blk(120, 100, 6, 4)
-    assert sb(3, 3, 100, 120, r=1, iters=1, prec=0) == 3 * one
-    assert sb(1, 3, 100, 120, r=1, iters=2, prec=0) == 2 * one
+    assert one == gplanes(1, 100, 120) + per
+    assert sb(3, 3, 100, 120, r=1, iters=1, prec=0) == gplanes(3, 100, 120) + 3 * per
+    assert sb(1, 3, 100, 120, r=1, iters=2, prec=0) == gplanes(1, 100, 120) + 2 * per
     # FP64 pivots: four-row chunks, double separators
-    assert sb(1, 3, 100, 120, r=1, iters=1, prec=1) == blk(100, 120, 4, 8) + blk(120, 100, 4, 8)
+    assert sb(1, 3, 100, 120, r=1, iters=1, prec=1) == (
+        gplanes(1, 100, 120) + blk(100, 120, 4, 8) + blk(120, 100, 4, 8))
     # AUTO resolves as for the lambda gradient (FP64 pivots)
     assert sb(1, 3, 100, 120, r=1, iters=1, prec=3) == sb(1, 3, 100, 120, r=1, iters=1, prec=1)
     # r = 2 grey with FP64 pivots: the backward's two-row chunks (the
     # forward's own are four rows), double separators of two values
     n2 = lambda L: -(-L // 2) - 1
-    assert sb(1, 1, 100, 120, r=2, iters=1, prec=1) == (
+    assert sb(1, 1, 100, 120, r=2, iters=1, prec=1) == gplanes(1, 100, 120) + (
         -(-(n2(100) * 2 * 116 * 8) // 256) * 256 + -(-(n2(120) * 2 * 96 * 8) // 256) * 256)
     assert sb(1, 1, 100, 120, r=3, iters=1, prec=0) > 0
     # no such path: strided, serial strips, invalid
