@@ -575,7 +575,7 @@ def main():
     def step_fb():
         ops.sgwls_filter(f, g, p, saved=saved, out=u, workspace=ws_s, seps=seps)
         ops.sgwls_backward(g, saved, ubar, p, grad_f=grad_f, grad_g=grad_g, grad_lambda=grad_l,
-                           workspace=ws_b, seps=seps)
+                           workspace=ws_b, seps=seps, f=f)
 
     def step_fb_plain():
         ops.sgwls_filter(f, g, p, saved=saved, out=u, workspace=ws_s)
@@ -610,7 +610,7 @@ def main():
     def step_fb32():
         ops.sgwls_filter(f, g, p32, saved=saved, out=u32, workspace=ws_s32, seps=seps32)
         ops.sgwls_backward(g, saved, ubar, p32, grad_f=grad_f32, grad_g=grad_g32,
-                           grad_lambda=grad_l32, workspace=ws_b32, seps=seps32)
+                           grad_lambda=grad_l32, workspace=ws_b32, seps=seps32, f=f)
 
     for _ in range(args.warmup):
         step_fb32()

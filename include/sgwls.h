@@ -260,13 +260,17 @@ sgwls_status sgwls_backward_nchw(const float* g, const float* saved, const float
 /* ---- Saved separators (not in the paper) ----
  * A backward pass recomputes its pass solution (Sec. 2.3) alongside the
  * adjoint solve.  sgwls_filter_nchw_seps is sgwls_filter_nchw with `saved`
- * required that also keeps, in the device buffer seps, the solution of every
- * pass at the chunk separators of the backward's cut (the interface values
- * of Sec. 2.3, steps 2-3, for the backward's chunks; the forward keeps its
- * own chunks and stores them from its re-solve); sgwls_backward_nchw_seps is
- * sgwls_backward_nchw that takes them from seps, so each of its passes
- * eliminates and solves the separator systems of the adjoint alone (one
- * right-hand side per channel instead of two) before re-solving both.
+ * required (entries 1 .. 2T-1 are written; entry 0, pass 0's input, is f
+ * itself and is left unwritten, so u must not alias f) that also keeps, in
+ * the device buffer seps, the solution of every pass at the chunk
+ * separators of the backward's cut (the interface values of Sec. 2.3,
+ * steps 2-3, for the backward's chunks; where the forward keeps its own
+ * chunks its re-solve stores them).
+ * sgwls_backward_nchw_seps is sgwls_backward_nchw that takes them from seps
+ * and pass 0's input from f (the forward's f, unchanged; grad_f and grad_g
+ * must not alias it), so each of its passes eliminates and solves the
+ * separator systems of the adjoint alone (one right-hand side per channel
+ * instead of two) before re-solving both.
  * Results agree with the plain pair to rounding.  Both calls run in the
  * precision sgwls_resolve_precision(p, 1) gives (AUTO: as for the lambda
  * gradient, whether or not grad_lambda is wanted), so the backward must get
@@ -288,8 +292,9 @@ sgwls_status sgwls_filter_nchw_seps(const float* f, const float* g, float* u, in
                                     int M, int N, const sgwls_params* p,
                                     const float* lambda_dev, float* saved, void* seps,
                                     size_t seps_bytes, void* ws, size_t ws_bytes, void* stream);
-sgwls_status sgwls_backward_nchw_seps(const float* g, const float* saved, const void* seps,
-                                      size_t seps_bytes, const float* grad_u, float* grad_f,
+sgwls_status sgwls_backward_nchw_seps(const float* g, const float* f, const float* saved,
+                                      const void* seps, size_t seps_bytes,
+                                      const float* grad_u, float* grad_f,
                                       float* grad_g, double* grad_lambda, int B, int C, int M,
                                       int N, const sgwls_params* p, const float* lambda_dev,
                                       void* ws, size_t ws_bytes, void* stream);

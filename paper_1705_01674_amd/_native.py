@@ -78,8 +78,8 @@ def _load():
     lib.sgwls_filter_nchw_seps.restype = i
     lib.sgwls_filter_nchw_seps.argtypes = [vp, vp, vp, i, i, i, i, P, vp, vp, vp, sz, vp, sz, vp]
     lib.sgwls_backward_nchw_seps.restype = i
-    lib.sgwls_backward_nchw_seps.argtypes = [vp, vp, vp, sz, vp, vp, vp, vp, i, i, i, i, P, vp, vp,
-                                             sz, vp]
+    lib.sgwls_backward_nchw_seps.argtypes = [vp, vp, vp, vp, sz, vp, vp, vp, vp, i, i, i, i, P,
+                                             vp, vp, sz, vp]
     lib.sgwls_filter_noalloc.restype = i
     lib.sgwls_filter_noalloc.argtypes = [vp, vp, vp, i, i, i, P, vp, vp, vp]
     lib.sgwls_filter_status.restype = i

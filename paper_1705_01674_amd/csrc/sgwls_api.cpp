@@ -1029,7 +1029,9 @@ static sgwls_status filter_nchw_core(const float* f, const float* g, float* u, i
     b.iface = (long long)iface_img;
     return b;
   };
-  if (saved && hipMemcpy2DAsync(saved, sizeof(float) * ss, f, sizeof(float) * plane,
+  // Pass 0's input is f itself; with saved separators the backward takes f,
+  // so saved[0] is not written.
+  if (saved && !seps && hipMemcpy2DAsync(saved, sizeof(float) * ss, f, sizeof(float) * plane,
                                 sizeof(float) * plane, nb, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return SGWLS_E_HIP;
   // Strided forward calls without saved inputs also run as frames: their
@@ -1073,7 +1075,7 @@ static sgwls_status filter_nchw_core(const float* f, const float* g, float* u, i
     if (!gt_pass0 &&
         launch_transpose(g, gT, M, N, s, B, 0, onep ? sync : nullptr, nzero) != hipSuccess)
       return SGWLS_E_HIP;
-    const float* x = saved ? saved : f;
+    const float* x = saved && !seps ? saved : f;
     size_t soff = 0;
     for (int q = 0; q < passes; ++q) {
       const bool even = q % 2 == 0;
@@ -1125,7 +1127,7 @@ sgwls_status sgwls_filter_nchw_seps(const float* f, const float* g, float* u, in
   sgwls_status st = validate_partitioned(C, M, N, p);
   if (st != SGWLS_OK) return st;
   if (B < 1) return SGWLS_E_SHAPE;
-  if (!saved || !seps) return SGWLS_E_ARG;
+  if (!saved || !seps || (const float*)u == f) return SGWLS_E_ARG;   // f is kept as pass 0's input
   const size_t need = seps_total_bytes(B, C, M, N, resolved(*p, 1));
   if (need == 0) return SGWLS_E_UNSUPPORTED;
   if (seps_bytes < need) return SGWLS_E_WORKSPACE;
@@ -1359,8 +1361,10 @@ sgwls_status sgwls_backward(const float* g, const float* saved, const float* gra
 // sgwls_backward_nchw; with seps (written by sgwls_filter_nchw_seps) the
 // passes take the pass solutions' separators from it and run in the
 // precision that call ran in.
-static sgwls_status backward_nchw_core(const float* g, const float* saved, const char* seps,
-                                       const float* grad_u, float* grad_f, float* grad_g,
+// f0: pass 0's input (the forward's f) when saved[0] was not written.
+static sgwls_status backward_nchw_core(const float* g, const float* f0, const float* saved,
+                                       const char* seps, const float* grad_u, float* grad_f,
+                                       float* grad_g,
                                        double* grad_lambda, int B, int C, int M, int N,
                                        const sgwls_params* p, const float* lambda_dev, void* ws,
                                        size_t ws_bytes, void* stream) {
@@ -1370,8 +1374,9 @@ static sgwls_status backward_nchw_core(const float* g, const float* saved, const
   const sgwls_params pr = resolved(*p, seps ? 1 : grad_lambda != nullptr);
   p = &pr;
   if (!g || !saved || !grad_u || !grad_f || (const float*)grad_f == g ||
-      (const float*)grad_f == saved)
+      (const float*)grad_f == saved || (const float*)grad_f == f0)
     return SGWLS_E_ARG;
+  if (f0 && grad_g && (const float*)grad_g == f0) return SGWLS_E_ARG;
   if (grad_g && ((const float*)grad_g == g || grad_g == grad_f || (const float*)grad_g == grad_u ||
                  (const float*)grad_g == saved))
     return SGWLS_E_ARG;
@@ -1420,10 +1425,16 @@ static sgwls_status backward_nchw_core(const float* g, const float* saved, const
     for (int q = passes - 1; q >= 0; --q) {
       const bool odd = q % 2 == 1;
       float* xbar = (q % 2 == 0) ? grad_f : tmp;
-      st = enqueue_pass_backward(0, saved + (size_t)q * plane, odd ? gT : g, ybar, xbar,
+      Batch bq = bt;
+      const float* xq = saved + (size_t)q * plane;
+      if (f0 && q == 0) {   // pass 0's input is f (C*M*N floats per image)
+        xq = f0;
+        bq.x = (long long)plane;
+      }
+      st = enqueue_pass_backward(0, xq, odd ? gT : g, ybar, xbar,
                                  grad_g ? (odd ? gTacc : grad_g) : nullptr, grad_lambda, C,
                                  odd ? N : M, odd ? M : N, *p, lambda_dev, ws, lay, s, first,
-                                 &gfirst[odd ? 1 : 0], q > 0 ? 1 : 0, &bt,
+                                 &gfirst[odd ? 1 : 0], q > 0 ? 1 : 0, &bq,
                                  seps ? sepr + soff : nullptr, zseps);
       if (st != SGWLS_OK) return st;
       if (seps && q > 0) soff -= seps_pass_bytes(q - 1, C, M, N, *p);
@@ -1450,23 +1461,24 @@ sgwls_status sgwls_backward_nchw(const float* g, const float* saved, const float
                                  float* grad_f, float* grad_g, double* grad_lambda, int B, int C,
                                  int M, int N, const sgwls_params* p, const float* lambda_dev,
                                  void* ws, size_t ws_bytes, void* stream) {
-  return backward_nchw_core(g, saved, nullptr, grad_u, grad_f, grad_g, grad_lambda, B, C, M, N,
-                            p, lambda_dev, ws, ws_bytes, stream);
+  return backward_nchw_core(g, nullptr, saved, nullptr, grad_u, grad_f, grad_g, grad_lambda, B,
+                            C, M, N, p, lambda_dev, ws, ws_bytes, stream);
 }
 
-sgwls_status sgwls_backward_nchw_seps(const float* g, const float* saved, const void* seps,
-                                      size_t seps_bytes, const float* grad_u, float* grad_f,
+sgwls_status sgwls_backward_nchw_seps(const float* g, const float* f, const float* saved,
+                                      const void* seps, size_t seps_bytes,
+                                      const float* grad_u, float* grad_f,
                                       float* grad_g, double* grad_lambda, int B, int C, int M,
                                       int N, const sgwls_params* p, const float* lambda_dev,
                                       void* ws, size_t ws_bytes, void* stream) {
   sgwls_status st = validate_partitioned(C, M, N, p);
   if (st != SGWLS_OK) return st;
   if (B < 1) return SGWLS_E_SHAPE;
-  if (!seps) return SGWLS_E_ARG;
+  if (!seps || !f) return SGWLS_E_ARG;
   const size_t need = seps_total_bytes(B, C, M, N, resolved(*p, 1));
   if (need == 0) return SGWLS_E_UNSUPPORTED;
   if (seps_bytes < need) return SGWLS_E_WORKSPACE;
-  return backward_nchw_core(g, saved, reinterpret_cast<const char*>(seps), grad_u, grad_f,
+  return backward_nchw_core(g, f, saved, reinterpret_cast<const char*>(seps), grad_u, grad_f,
                             grad_g, grad_lambda, B, C, M, N, p, lambda_dev, ws, ws_bytes,
                             stream);
 }

@@ -135,7 +135,9 @@ def sgwls_filter(f: torch.Tensor, g: torch.Tensor, p: Params, *,
     ``saved`` (optional, 2T x C x M x N float32) receives every pass input for
     the backward call.  ``out`` may be f itself (in-place filtering).
     ``seps`` (optional, with saved; uint8, separator_bytes_nchw(1, C, M, N, p)
-    bytes) receives every pass's separator solutions for the backward."""
+    bytes) receives every pass's separator solutions for the backward; then
+    saved[0] is not written (the backward takes f itself, so ``out`` must
+    not be f)."""
     C, M, N = _image(f, "f")
     dev = f.device
     _guidance(g, M, N, dev)
@@ -329,10 +331,11 @@ def sgwls_backward(g: torch.Tensor, saved: torch.Tensor, grad_u: torch.Tensor, p
                    grad_g: Optional[torch.Tensor] = None,
                    grad_lambda: Optional[torch.Tensor] = None,
                    workspace: Optional[torch.Tensor] = None,
-                   seps: Optional[torch.Tensor] = None):
+                   seps: Optional[torch.Tensor] = None, f: Optional[torch.Tensor] = None):
     """Adjoint of ``sgwls_filter`` given the pass inputs it saved: returns
     (grad_f, grad_g or None, grad_lambda (float64 device tensor) or None).
-    ``seps``: the separators that filter call kept (p must be its p)."""
+    ``seps``: the separators that filter call kept (p must be its p), with
+    ``f`` its input (pass 0's input, which that call did not copy)."""
     C, M, N = _image(grad_u, "grad_u")
     dev = grad_u.device
     _guidance(g, M, N, dev)
@@ -361,10 +364,13 @@ def sgwls_backward(g: torch.Tensor, saved: torch.Tensor, grad_u: torch.Tensor, p
         raise ValueError("workspace too small")
     if seps is not None:
         _seps_buffer(seps, dev)
-        nat.check(nat.lib.sgwls_backward_nchw_seps(_ptr(g), _ptr(saved), _ptr(seps), seps.numel(),
-                                                   _ptr(grad_u), _ptr(grad_f), _ptr(gbar),
-                                                   _ptr(glam), 1, C, M, N, ctypes.byref(p.c()),
-                                                   _ptr(lam), _ptr(ws), ws.numel(), _stream(dev)),
+        if f is None or f.shape != grad_u.shape or f.dtype != torch.float32 or not f.is_contiguous():
+            raise ValueError("f (the filter call's input) must come with seps")
+        nat.check(nat.lib.sgwls_backward_nchw_seps(_ptr(g), _ptr(f), _ptr(saved), _ptr(seps),
+                                                   seps.numel(), _ptr(grad_u), _ptr(grad_f),
+                                                   _ptr(gbar), _ptr(glam), 1, C, M, N,
+                                                   ctypes.byref(p.c()), _ptr(lam), _ptr(ws),
+                                                   ws.numel(), _stream(dev)),
                   "sgwls_backward_nchw_seps")
         return grad_f, gbar, glam
     nat.check(nat.lib.sgwls_backward(_ptr(g), _ptr(saved), _ptr(grad_u), _ptr(grad_f), _ptr(gbar),
@@ -406,7 +412,9 @@ def sgwls_filter_nchw(f: torch.Tensor, g: torch.Tensor, p: Params, *,
     """The filter of B equal-shape images in each launch: f (B, C, M, N), g
     (B, M, N); saved (optional) B x 2T x C x M x N; seps (optional, with
     saved): a uint8 device tensor of separator_bytes_nchw bytes that receives
-    every pass's separator solutions for sgwls_backward_nchw."""
+    every pass's separator solutions for sgwls_backward_nchw (saved[:, 0] is
+    then not written: the backward takes f itself, so ``out`` must not be
+    f)."""
     B, C, M, N = _batch4(f, "f")
     dev = f.device
     if g.shape != (B, M, N) or not g.is_contiguous() or g.dtype != torch.float32 or g.device != dev:
@@ -441,11 +449,12 @@ def sgwls_filter_nchw(f: torch.Tensor, g: torch.Tensor, p: Params, *,
 def sgwls_backward_nchw(g: torch.Tensor, saved: torch.Tensor, grad_u: torch.Tensor, p: Params, *,
                         lambda_dev: Optional[torch.Tensor] = None, want_g: bool = True,
                         want_lambda: bool = True, workspace: Optional[torch.Tensor] = None,
-                        seps: Optional[torch.Tensor] = None):
+                        seps: Optional[torch.Tensor] = None, f: Optional[torch.Tensor] = None):
     """Adjoint of sgwls_filter_nchw: returns (grad_f (B, C, M, N), grad_g
     (B, M, N) or None, grad_lambda summed over the batch (float64 device
     tensor) or None).  seps: the separators the forward kept (then p must be
-    the forward's, and the call runs in the forward's precision)."""
+    the forward's, the call runs in the forward's precision, and f is the
+    forward's input, pass 0's input, which that call did not copy)."""
     B, C, M, N = _batch4(grad_u, "grad_u")
     dev = grad_u.device
     lam = _lambda(lambda_dev, dev)
@@ -458,10 +467,13 @@ def sgwls_backward_nchw(g: torch.Tensor, saved: torch.Tensor, grad_u: torch.Tens
         raise ValueError("workspace too small")
     if seps is not None:
         _seps_buffer(seps, dev)
-        nat.check(nat.lib.sgwls_backward_nchw_seps(_ptr(g), _ptr(saved), _ptr(seps), seps.numel(),
-                                                   _ptr(grad_u), _ptr(grad_f), _ptr(gbar),
-                                                   _ptr(glam), B, C, M, N, ctypes.byref(p.c()),
-                                                   _ptr(lam), _ptr(ws), ws.numel(), _stream(dev)),
+        if f is None or f.shape != grad_u.shape or f.dtype != torch.float32 or not f.is_contiguous():
+            raise ValueError("f (the filter call's input) must come with seps")
+        nat.check(nat.lib.sgwls_backward_nchw_seps(_ptr(g), _ptr(f), _ptr(saved), _ptr(seps),
+                                                   seps.numel(), _ptr(grad_u), _ptr(grad_f),
+                                                   _ptr(gbar), _ptr(glam), B, C, M, N,
+                                                   ctypes.byref(p.c()), _ptr(lam), _ptr(ws),
+                                                   ws.numel(), _stream(dev)),
                   "sgwls_backward_nchw_seps")
         return grad_f, gbar, glam
     nat.check(nat.lib.sgwls_backward_nchw(_ptr(g), _ptr(saved), _ptr(grad_u), _ptr(grad_f), _ptr(gbar),
@@ -513,18 +525,21 @@ class SGWLSFunction(torch.autograd.Function):
         if seps is None:
             ctx.save_for_backward(gb, saved, lam_dev)
         else:
-            ctx.save_for_backward(gb, saved, lam_dev, seps)
+            # pass 0's input is f itself (not copied into saved)
+            ctx.save_for_backward(gb, saved, lam_dev, seps, fb)
         return out if batched else out[0]
 
     @staticmethod
     def backward(ctx, grad_out):
         gb, saved, lam_dev = ctx.saved_tensors[:3]
         seps = ctx.saved_tensors[3] if ctx.has_seps else None
+        fb = ctx.saved_tensors[4] if ctx.has_seps else None
         p = ctx.p
         go = grad_out.contiguous() if ctx.batched else grad_out.contiguous().unsqueeze(0)
         want_f, want_g, want_l = ctx.needs_input_grad[0], ctx.needs_input_grad[1], ctx.needs_input_grad[2]
         grad_f, grad_g, glam = sgwls_backward_nchw(gb, saved, go, p, lambda_dev=lam_dev,
-                                                   want_g=want_g, want_lambda=want_l, seps=seps)
+                                                   want_g=want_g, want_lambda=want_l, seps=seps,
+                                                   f=fb)
         gl_out = glam.to(torch.float32).reshape(ctx.lam_shape) if want_l else None
         if not ctx.batched:
             grad_f = grad_f[0]

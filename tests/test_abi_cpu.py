@@ -417,9 +417,15 @@ def test_separator_bytes_and_errors(nat):
                                       None) == 3
     assert lib.sgwls_filter_nchw_seps(f, g, u, 1, 1, 100, 120, pr3, None, u, s, big, ws, big,
                                       None) == 4
-    assert lib.sgwls_backward_nchw_seps(g, u, None, big, u, f, None, None, 1, 3, 100, 120, p, None,
-                                        ws, big, None) == 1
-    assert lib.sgwls_backward_nchw_seps(g, u, s, one - 1, u, f, None, None, 1, 3, 100, 120, p,
+    x0 = ctypes.c_void_p(0x6000)
+    assert lib.sgwls_backward_nchw_seps(g, x0, u, None, big, u, f, None, None, 1, 3, 100, 120, p,
+                                        None, ws, big, None) == 1
+    assert lib.sgwls_backward_nchw_seps(g, None, u, s, big, u, f, None, None, 1, 3, 100, 120, p,
+                                        None, ws, big, None) == 1
+    assert lib.sgwls_backward_nchw_seps(g, x0, u, s, one - 1, u, f, None, None, 1, 3, 100, 120, p,
                                         None, ws, big, None) == 3
-    assert lib.sgwls_backward_nchw_seps(g, u, s, big, u, f, None, None, 1, 1, 100, 120, pr3, None,
-                                        ws, big, None) == 4
+    assert lib.sgwls_backward_nchw_seps(g, x0, u, s, big, u, f, None, None, 1, 1, 100, 120, pr3,
+                                        None, ws, big, None) == 4
+    # the filter with separators keeps f as pass 0's input: no in-place output
+    assert lib.sgwls_filter_nchw_seps(f, g, f, 1, 3, 100, 120, p, None, u, s, big, ws, big,
+                                      None) == 1

@@ -55,8 +55,10 @@ def run_seps(ops, f, g, ub, p):
     seps = torch.empty(nsep, dtype=torch.uint8, device="cuda")
     saved = torch.empty((B, 2 * p.iters, C, M, N), device="cuda")
     lam = torch.tensor([p.lam], device="cuda")
-    u = ops.sgwls_filter_nchw(cuda(f), cuda(g), p, lambda_dev=lam, saved=saved, seps=seps)
-    gf, gg, gl = ops.sgwls_backward_nchw(cuda(g), saved, cuda(ub), p, lambda_dev=lam, seps=seps)
+    ft = cuda(f)
+    u = ops.sgwls_filter_nchw(ft, cuda(g), p, lambda_dev=lam, saved=saved, seps=seps)
+    gf, gg, gl = ops.sgwls_backward_nchw(cuda(g), saved, cuda(ub), p, lambda_dev=lam, seps=seps,
+                                         f=ft)
     torch.cuda.synchronize()
     return u.cpu().numpy(), gf.cpu().numpy(), gg.cpu().numpy(), gl.item()
 
