@@ -293,6 +293,7 @@ sgwls_status enqueue_pass(int direction, const float* x, const float* g, float* 
 // chunk-boundary edges (P x W floats) and the per-block lambda partials.
 struct BwdLayout {
   size_t img_off, iface_off, side_off, lpart_off, total;
+  size_t side_set, lpart_set;         // floats / doubles of one side / partials set
   size_t gt_off, gtacc_off, yt_off;   // transposed-frame buffers (frames only)
   size_t iface_img, side_img;         // per-image strides: bytes, floats
 };
@@ -300,6 +301,8 @@ struct BwdLayout {
 // B images (an NCHW batch): every buffer holds B per-image parts.
 BwdLayout bwd_layout(int C, int M, int N, const sgwls_params& p, int B = 1) {
   size_t iface = 0, side = 0, blocks = 0;
+  int nblk = 0;   // channel blocks
+  for (int c0 = 0; c0 < C; c0 += channel_block(C - c0)) ++nblk;
   for (int dir = 0; dir < 2; ++dir) {
     const int L = dir == 0 ? M : N, W = dir == 0 ? N : M;
     for (int c0 = 0; c0 < C;) {
@@ -324,18 +327,34 @@ BwdLayout bwd_layout(int C, int M, int N, const sgwls_params& p, int B = 1) {
   l.side_img = align_up(side * sizeof(float)) / sizeof(float);
   l.img_off = 0;
   l.iface_off = l.img_off + align_up(nb * sizeof(float) * C * M * N);
+  // Side terms: one set per (frame parity, channel block); lambda partials:
+  // one set per (pass, channel block).  A backward call over all passes
+  // accumulates each set and applies them once at the end (set 0 alone when
+  // every pass is fixed up by itself).
+  l.side_set = nb * l.side_img;
+  l.lpart_set = nb * blocks;
+  const size_t nsides = 2 * (size_t)nblk, nparts = 2 * (size_t)p.iters * nblk;
   l.side_off = l.iface_off + nb * l.iface_img;
-  l.lpart_off = l.side_off + nb * l.side_img * sizeof(float);
-  l.gt_off = l.lpart_off + align_up(nb * blocks * sizeof(double));
+  l.lpart_off = l.side_off + align_up(nsides * l.side_set * sizeof(float));
+  l.gt_off = l.lpart_off + align_up(nparts * l.lpart_set * sizeof(double));
   l.gtacc_off = l.gt_off + align_up(nb * sizeof(float) * M * N);
   l.yt_off = l.gtacc_off + align_up(nb * sizeof(float) * M * N);
   l.total = l.yt_off + align_up(nb * sizeof(float) * C * M * N);
   return l;
 }
 
+// Fix-ups deferred to the end of a backward call: the side terms of pass q,
+// channel block b go to set side_set + b (added to the set when side_first
+// is false), its lambda partials to the partials from lpart_off on.
+struct BwdDefer {
+  int side_set;
+  bool side_first;
+  size_t lpart_off;   // doubles from the start of the partials region
+};
+
 // One backward pass over all channel blocks.  `first` is true for the first
 // launch of a backward call: it overwrites gbar and *grad_lambda, later
-// launches add to them.
+// launches add to them.  With dfr the fix-ups are left to the caller.
 sgwls_status enqueue_pass_backward(int direction, const float* x, const float* g,
                                    const float* ybar, float* xbar, float* gbar,
                                    double* grad_lambda, int C, int M, int N,
@@ -343,16 +362,18 @@ sgwls_status enqueue_pass_backward(int direction, const float* x, const float* g
                                    const BwdLayout& lay, hipStream_t stream, bool& first,
                                    bool* gfirst = nullptr, int out_t = 0,
                                    const Batch* bt = nullptr, const char* useps = nullptr,
-                                   long long zseps = 0) {
+                                   long long zseps = 0, BwdDefer* dfr = nullptr) {
   const int L = direction == 0 ? M : N, W = direction == 0 ? N : M;
   const WeightParams wp = weight_params(p);
   char* base = reinterpret_cast<char*>(ws);
   BwdArgs bw{};
   bw.ybar = ybar;
   bw.gbar = gbar;
-  bw.side = reinterpret_cast<float*>(base + lay.side_off);
-  bw.lpart = grad_lambda ? reinterpret_cast<double*>(base + lay.lpart_off) : nullptr;
-  for (int c0 = 0; c0 < C;) {
+  float* const side0 = reinterpret_cast<float*>(base + lay.side_off);
+  double* const lpart0 = reinterpret_cast<double*>(base + lay.lpart_off);
+  bw.side = side0;
+  bw.lpart = grad_lambda ? lpart0 : nullptr;
+  for (int c0 = 0, blk = 0; c0 < C; ++blk) {
     const int cb = channel_block(C - c0);
     PassPlan pl = make_plan(L, W, p.r, cb, p.stride, p.prec, 0, kModeBackward);
     PassGeom geo = pass_geom(direction, M, N, pl, p.stride);
@@ -368,6 +389,12 @@ sgwls_status enqueue_pass_backward(int direction, const float* x, const float* g
     }
     bool& gf = gfirst ? *gfirst : first;   // first write of this guidance-gradient buffer
     bw.gacc = gf ? 0 : 1;
+    if (dfr) {
+      bw.side = side0 + (size_t)(dfr->side_set + blk) * lay.side_set;
+      bw.sacc = dfr->side_first ? 0 : 1;
+      bw.lpart = grad_lambda ? lpart0 + dfr->lpart_off : nullptr;
+      dfr->lpart_off += (size_t)(bt ? bt->n : 1) * expand_blocks(geo, pl);
+    }
     char* iface = base + lay.iface_off;
     int stages = kStageAll;
     if (useps) {
@@ -397,9 +424,11 @@ sgwls_status enqueue_pass_backward(int direction, const float* x, const float* g
     hipError_t e = launch_pass(p.r, cb, p.prec, x, g, xbar, c0, geo, pl, wp, lam_dev, p.lambda,
                                iface, stream, stages, &bw);
     if (e != hipSuccess) return SGWLS_E_HIP;
-    e = launch_bwd_fixup(bw.side, gbar, geo, bw.lpart, expand_blocks(geo, pl), grad_lambda,
-                         first ? 0 : 1, stream);
-    if (e != hipSuccess) return SGWLS_E_HIP;
+    if (!dfr) {
+      e = launch_bwd_fixup(bw.side, gbar, geo, bw.lpart, expand_blocks(geo, pl), grad_lambda,
+                           first ? 0 : 1, stream);
+      if (e != hipSuccess) return SGWLS_E_HIP;
+    }
     first = false;
     gf = false;
     c0 += cb;
@@ -1422,9 +1451,16 @@ static sgwls_status backward_nchw_core(const float* g, const float* f0, const fl
     const char* sepr = seps ? seps + seps_guidance_bytes(B, M, N) : nullptr;
     size_t soff = 0;
     for (int q = 0; seps && q < passes - 1; ++q) soff += seps_pass_bytes(q, C, M, N, *p);
+    // The fix-ups wait for the end: side terms accumulate per frame parity
+    // and channel block, lambda partials stay per pass (see below).
+    int nblk = 0;
+    for (int c0 = 0; c0 < C; c0 += channel_block(C - c0)) ++nblk;
+    bool side_first[2] = {true, true};
+    size_t lpart_end = 0;
     for (int q = passes - 1; q >= 0; --q) {
       const bool odd = q % 2 == 1;
       float* xbar = (q % 2 == 0) ? grad_f : tmp;
+      BwdDefer dfr{odd ? nblk : 0, side_first[odd ? 1 : 0], lpart_end};
       Batch bq = bt;
       const float* xq = saved + (size_t)q * plane;
       if (f0 && q == 0) {   // pass 0's input is f (C*M*N floats per image)
@@ -1435,10 +1471,40 @@ static sgwls_status backward_nchw_core(const float* g, const float* f0, const fl
                                  grad_g ? (odd ? gTacc : grad_g) : nullptr, grad_lambda, C,
                                  odd ? N : M, odd ? M : N, *p, lambda_dev, ws, lay, s, first,
                                  &gfirst[odd ? 1 : 0], q > 0 ? 1 : 0, &bq,
-                                 seps ? sepr + soff : nullptr, zseps);
+                                 seps ? sepr + soff : nullptr, zseps, &dfr);
       if (st != SGWLS_OK) return st;
+      lpart_end = dfr.lpart_off;
+      side_first[odd ? 1 : 0] = false;
       if (seps && q > 0) soff -= seps_pass_bytes(q - 1, C, M, N, *p);
       ybar = xbar;
+    }
+    // Deferred fix-ups: each parity's accumulated side terms into its
+    // guidance gradient (odd: the transposed accumulator, before it is added
+    // to grad_g), then every lambda partial of the call in one fixed-order
+    // reduction.
+    float* side0 = reinterpret_cast<float*>(base + lay.side_off);
+    for (int par = 0; grad_g && par < 2; ++par) {
+      const int L = par ? N : M, W = par ? M : N;   // the frame of the parity's passes
+      for (int c0 = 0, blk = 0; c0 < C; ++blk) {
+        const int cb = channel_block(C - c0);
+        const PassPlan pl = make_plan(L, W, p->r, cb, 1, p->prec, 0, kModeBackward);
+        PassGeom geo = pass_geom(0, L, W, pl, 1);
+        Batch b = bt;
+        b.side = (long long)lay.side_img;
+        set_batch(geo, b);
+        if (launch_bwd_fixup(side0 + (size_t)(par * nblk + blk) * lay.side_set,
+                             par ? gTacc : grad_g, geo, nullptr, 0, nullptr, 0, s) != hipSuccess)
+          return SGWLS_E_HIP;
+        c0 += cb;
+      }
+    }
+    if (grad_lambda) {
+      PassGeom one_image{};
+      one_image.P = 1;
+      if (launch_bwd_fixup(nullptr, nullptr, one_image,
+                           reinterpret_cast<const double*>(base + lay.lpart_off), (int)lpart_end,
+                           grad_lambda, 0, s) != hipSuccess)
+        return SGWLS_E_HIP;
     }
     if (grad_g && launch_transpose(gTacc, grad_g, N, M, s, B, 1) != hipSuccess) return SGWLS_E_HIP;
     return SGWLS_OK;

@@ -1946,7 +1946,10 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
         float sacc = Gv[0];
 #pragma unroll
         for (int i = 1; i < r; ++i) sacc = Gv[i] + lane_shr1(sacc);
-        if (own && hasT) bw.side[(size_t)j * geo.W + b] = sacc;
+        if (own && hasT) {
+          float* sp = bw.side + (size_t)j * geo.W + b;
+          *sp = bw.sacc ? *sp + sacc : sacc;
+        }
       }
     }
     if (geo.sb == 1) {   // column pass: lanes write consecutive columns of each row
@@ -2067,9 +2070,11 @@ DEV void expand_tile(const float* __restrict__ G, float* __restrict__ Y, const P
     }
     if constexpr (BWD) {
       if (wantg && j0 > 0 && j0 < geo.P)
-        for (int bc = threadIdx.x; bc < ncols; bc += kWave * Q)
-          bw.side[(size_t)j0 * geo.W + b_lo + bc] =
-              smem[acc0 + (NO - 1) * TA * pch + (b_lo + bc - colbase)];
+        for (int bc = threadIdx.x; bc < ncols; bc += kWave * Q) {
+          float* sp = bw.side + (size_t)j0 * geo.W + b_lo + bc;
+          const float v = smem[acc0 + (NO - 1) * TA * pch + (b_lo + bc - colbase)];
+          *sp = bw.sacc ? *sp + v : v;
+        }
     }
   }
 }

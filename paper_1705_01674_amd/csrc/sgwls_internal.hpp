@@ -291,6 +291,7 @@ struct BwdArgs {
                        // boundaries, for the pixels of the chunk above
   double* lpart;       // one partial lambda gradient per expand block (NULL: not wanted)
   int gacc;            // 1: add to gbar, 0: overwrite it
+  int sacc;            // 1: add to side (terms of several passes), 0: overwrite it
   // Separators of the pass solution saved by the forward (layout of a forward
   // interface buffer's solutions, r x CB per separator), or NULL: then the
   // pass solves them itself (2 CB right-hand sides); with them the
